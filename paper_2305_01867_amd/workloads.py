@@ -1,0 +1,136 @@
+"""Seeded synthetic inputs: triangle meshes and segment rays.
+
+This module only draws numbers.  It holds none of the intersection method's
+arithmetic, and both the GPU path's tests and the CPU oracle's tests take their
+inputs from it.  Every array is drawn in binary64 with numpy's PCG64 generator
+(``numpy.random.default_rng(seed)``) and rounded to float32 at the end;
+triangle indices are int32.
+
+Stand-ins: the paper measures on a surface of 14,874 vertices / 29,260
+triangles and 1e7 rays produced by a script that is not available (paper:
+Performance section, and Case Study 2).  The heightfields below have the same
+scale (a 128 x 128 grid gives 32,258 triangles) and the ray sets the same count.
+
+Heightfield H(n, seed): vertex (i, j) at x = i/(n-1), y = j/(n-1), vertex id
+j*n + i, z = sum_k 0.1 sin(2 pi (f_k0 x + f_k1 y) + phi_k) over 4 waves with
+f ~ U[1, 6], phi ~ U[0, 2 pi), plus N(0, 0.005^2) noise per vertex.  Cell (i, j)
+with c = j(n-1) + i holds triangles 2c = (v(i,j), v(i+1,j), v(i+1,j+1)) and
+2c+1 = (v(i,j), v(i+1,j+1), v(i,j+1)).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "heightfield",
+    "rays_crossing_mix",
+    "rays_in_box",
+    "appendix_scene",
+    "tiny_config",
+    "paper_scale_config",
+    "HEADLINE_SEEDS",
+]
+
+# seeds of the two named workloads: (mesh, rays)
+TINY_SEEDS = (11, 12)
+HEADLINE_SEEDS = (21, 22)
+
+
+def heightfield(n: int, seed: int):
+    """Return (V float32 [n*n, 3], F int32 [2(n-1)^2, 3]) for H(n, seed)."""
+    if n < 2:
+        raise ValueError("a heightfield needs n >= 2")
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(1.0, 6.0, size=(4, 2))
+    phi = rng.uniform(0.0, 2.0 * np.pi, size=4)
+    g = np.arange(n, dtype=np.float64) / (n - 1)
+    x, y = np.meshgrid(g, g, indexing="xy")  # x varies along i (columns), y along j (rows)
+    z = np.zeros_like(x)
+    for k in range(4):
+        z += 0.1 * np.sin(2.0 * np.pi * (f[k, 0] * x + f[k, 1] * y) + phi[k])
+    z += rng.normal(0.0, 0.005, size=z.shape)
+    V = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(np.float32)
+
+    i, j = np.meshgrid(np.arange(n - 1), np.arange(n - 1), indexing="xy")
+    i = i.ravel()
+    j = j.ravel()
+    v00 = j * n + i
+    v10 = j * n + i + 1
+    v11 = (j + 1) * n + i + 1
+    v01 = (j + 1) * n + i
+    F = np.empty((2 * (n - 1) ** 2, 3), dtype=np.int64)
+    F[0::2] = np.stack([v00, v10, v11], axis=1)
+    F[1::2] = np.stack([v00, v11, v01], axis=1)
+    return V, F.astype(np.int32)
+
+
+def rays_crossing_mix(n_rays: int, seed: int, p_cross: float = 0.5):
+    """Segments over [0,1]^2 in x, y: with probability p_cross the start lies at
+    z = 0.5 + U(0, 0.3) and the end at z = -U(0, 0.3); otherwise both ends are
+    drawn from one side's law (above or below, each with probability 0.5).  The
+    x, y of each end point are drawn independently, so segments are oblique."""
+    rng = np.random.default_rng(seed)
+    xy0 = rng.uniform(0.0, 1.0, size=(n_rays, 2))
+    xy1 = rng.uniform(0.0, 1.0, size=(n_rays, 2))
+    above0 = 0.5 + rng.uniform(0.0, 0.3, size=n_rays)
+    below1 = -rng.uniform(0.0, 0.3, size=n_rays)
+    above1 = 0.5 + rng.uniform(0.0, 0.3, size=n_rays)
+    below0 = -rng.uniform(0.0, 0.3, size=n_rays)
+    cross = rng.uniform(size=n_rays) < p_cross
+    side_above = rng.uniform(size=n_rays) < 0.5
+    z0 = np.where(cross, above0, np.where(side_above, above0, below0))
+    z1 = np.where(cross, below1, np.where(side_above, above1, below1))
+    O = np.concatenate([xy0, z0[:, None]], axis=1).astype(np.float32)
+    E = np.concatenate([xy1, z1[:, None]], axis=1).astype(np.float32)
+    return O, E
+
+
+def rays_in_box(n_rays: int, seed: int, lo, hi, inflate: float = 1.1, chunk: int = 1 << 22):
+    """Segments whose two end points are i.i.d. uniform in the box [lo, hi]
+    scaled by `inflate` about its centre."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    c = 0.5 * (lo + hi)
+    h = 0.5 * (hi - lo) * inflate
+    rng = np.random.default_rng(seed)
+    O = np.empty((n_rays, 3), np.float32)
+    E = np.empty((n_rays, 3), np.float32)
+    for s in range(0, n_rays, chunk):
+        m = min(chunk, n_rays - s)
+        O[s:s + m] = (c + h * rng.uniform(-1.0, 1.0, size=(m, 3))).astype(np.float32)
+        E[s:s + m] = (c + h * rng.uniform(-1.0, 1.0, size=(m, 3))).astype(np.float32)
+    return O, E
+
+
+def appendix_scene():
+    """The 4-triangle / 8-ray scene of the paper's Case Study 1 (its figure is
+    not available).  The mesh is the one the printed leaf boxes and hit points
+    determine: a unit square in x, y fanned around its centre.  Rays 1, 2, 4, 7
+    are vertical segments through the printed hit points' x, y; rays 0, 3, 5, 6
+    are constructed misses (outside the footprint, stopping above the surface,
+    horizontal above it, outside).  Returns (V, F, O, E)."""
+    V = np.array([[12.0, 2.0, 1.0], [13.0, 2.0, 1.2], [12.0, 3.0, 1.2],
+                  [13.0, 3.0, 1.3], [12.5, 2.5, 1.1]], dtype=np.float32)
+    F = np.array([[0, 1, 4], [1, 3, 4], [2, 3, 4], [0, 2, 4]], dtype=np.int32)
+    O = np.array([[11.5, 2.5, 5.0], [12.7, 2.2, 5.0], [12.9, 2.4, 5.0], [12.5, 2.25, 5.0],
+                  [12.6, 2.9, 5.0], [11.0, 2.5, 2.0], [13.5, 2.5, 5.0], [12.2, 2.4, 5.0]],
+                 dtype=np.float32)
+    E = np.array([[11.5, 2.5, -5.0], [12.7, 2.2, -5.0], [12.9, 2.4, -5.0], [12.5, 2.25, 1.5],
+                  [12.6, 2.9, -5.0], [14.0, 2.5, 2.0], [13.5, 2.5, -5.0], [12.2, 2.4, -5.0]],
+                 dtype=np.float32)
+    return V, F, O, E
+
+
+def tiny_config():
+    """64 x 64 heightfield (7,938 triangles) and 10,000 crossing-mix rays."""
+    V, F = heightfield(64, TINY_SEEDS[0])
+    O, E = rays_crossing_mix(10_000, TINY_SEEDS[1])
+    return V, F, O, E
+
+
+def paper_scale_config(n_rays: int = 10_000_000):
+    """128 x 128 heightfield (32,258 triangles) and n_rays segments with end
+    points uniform in the mesh bounding box inflated by 10%."""
+    V, F = heightfield(128, HEADLINE_SEEDS[0])
+    O, E = rays_in_box(n_rays, HEADLINE_SEEDS[1], V.min(axis=0), V.max(axis=0))
+    return V, F, O, E
