@@ -1,0 +1,215 @@
+/*
+ * rsi.h -- line-segment / triangle-mesh intersection on AMD gfx950 (MI355X).
+ *
+ * The operation (paper: Background section, problem statement): N_r line
+ * segments l_i = (r_i_start, r_i_end) are tested against a surface of N_t
+ * triangles, each a triplet of indices into N_v vertices.  The mesh is indexed
+ * by a bounding volume hierarchy: Morton codes of the triangles, sorted, then a
+ * binary radix tree (Karras 2012) whose node boxes are filled bottom-up; a tree
+ * search per segment finds candidate triangles and a Moller-Trumbore test
+ * decides (Background; Case Studies 1 and 2 show the tree's contents).  The
+ * three results are those of the paper's operating modes (Background): a
+ * boolean per segment, and the nearest hit's triangle with its barycentric
+ * coordinates and segment parameter (from which distance and point follow).
+ *
+ * What counts as a hit (the reading this library implements exactly):
+ *   the closed segment {O + t (E - O) : 0 <= t <= 1} meets the closed triangle
+ *   {(1-u-v) A + u B + v C : u, v >= 0, u + v <= 1}, A, B, C = the triangle's
+ *   vertices in index order, and the segment is not parallel to the plane.
+ *   "Nearest" is the smallest t; equal t goes to the smaller triangle index.
+ *   In RSI_PRECISION_CERTIFIED every decision equals the one a binary64
+ *   evaluation of the Moller-Trumbore predicates makes (the paper's Epilogue
+ *   offers binary64 for near-parallel rays whose binary32 result can be wrong).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers (hipMalloc / hipMallocAsync / a
+ *     torch CUDA tensor on a ROCm build), owned by the caller, 4-byte aligned
+ *     and densely packed; host pointers are rejected with RSI_E_ARG.
+ *   - Floating-point inputs are IEEE binary32; indices are int32 (the paper's
+ *     Case Study 1: a 64-bit index array read through an int32 pointer
+ *     silently drops triangles -- this interface only takes int32).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is queued on it and the call returns without waiting unless stated.
+ *   - A call returns a status and never throws or aborts.  Argument errors are
+ *     found before any GPU work is queued.  A HIP error (including one left by
+ *     earlier asynchronous work) is returned as RSI_E_HIP.  rsi_last_error()
+ *     gives a message for the calling thread's last failure.
+ *   - Calls that share one mesh handle may run concurrently only if they are
+ *     ordered on the GPU (same stream or events); the handle itself is not
+ *     changed by rsi_intersect.
+ */
+#ifndef RSI_H
+#define RSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSI_ABI_VERSION 1
+
+typedef struct rsi_mesh_s *rsi_mesh; /* opaque; owned by the library until rsi_destroy */
+
+typedef enum rsi_status {
+    RSI_OK = 0,
+    RSI_E_ARG = 1,      /* NULL / host / misaligned pointer, negative count, unknown option */
+    RSI_E_RANGE = 2,    /* a triangle index outside [0, N_v) (only with check_indices) */
+    RSI_E_NOMEM = 3,    /* device memory allocation failed */
+    RSI_E_HIP = 4,      /* HIP runtime error, possibly from earlier asynchronous work */
+    RSI_E_STATE = 5,    /* no usable gfx950 device, or a destroyed / invalid handle */
+    RSI_E_CAPACITY = 6  /* a size beyond a documented limit */
+} rsi_status;
+
+typedef enum rsi_mode {
+    RSI_MODE_BOOLEAN = 0,     /* paper's mode=boolean: one flag per segment */
+    RSI_MODE_FIRST_HIT = 1,   /* index of the nearest hit triangle */
+    RSI_MODE_BARYCENTRIC = 2  /* paper's mode=barycentric: nearest hit + (u, v, t) */
+} rsi_mode;
+
+typedef enum rsi_precision {
+    RSI_PRECISION_PLAIN = 0,     /* binary32 test; rare near-degenerate pairs may differ
+                                    from the binary64 decision (paper's Epilogue) */
+    RSI_PRECISION_CERTIFIED = 1  /* binary32 test with a proven error bound; pairs and
+                                    orderings inside the bound are re-decided in binary64
+                                    on the GPU, so results equal the binary64 decisions */
+} rsi_precision;
+
+/* Build options; pass NULL for defaults. */
+typedef struct rsi_build_opts {
+    int32_t morton_bits;   /* 30 (10 bits per axis, 32-bit keys) or 63 (21 bits per
+                              axis, 64-bit keys, as the paper's uint64 codes); 0 = 30 */
+    int32_t check_indices; /* nonzero: wait for the build and return RSI_E_RANGE if any
+                              index is outside [0, N_v).  Without it such triangles are
+                              never hit and the build does not wait. */
+} rsi_build_opts;
+
+/* Intersection options; pass NULL for defaults. */
+typedef struct rsi_intersect_opts {
+    int32_t precision;    /* rsi_precision; default RSI_PRECISION_PLAIN */
+    int32_t block;        /* threads per workgroup: 64, 128 or 256; 0 = 256 */
+    int32_t stack_depth;  /* traversal stack entries per lane in LDS, 1..64; 0 = 24.
+                             Deeper paths are finished exactly by a second pass. */
+    int32_t ray_sort;     /* 0 = rays processed in input order (the only value so far) */
+    int32_t proposal;     /* 0 = no learned proposal (the only value so far) */
+} rsi_intersect_opts;
+
+/* Output buffers (device pointers, caller-owned).  Required per mode:
+ *   BOOLEAN:     hit
+ *   FIRST_HIT:   tri_id            (hit filled too when not NULL)
+ *   BARYCENTRIC: tri_id and uvt    (hit filled too when not NULL)
+ * Results are written at the segment's input index. */
+typedef struct rsi_outputs {
+    uint8_t *hit;       /* [N_r] 1 if the segment meets the surface, else 0 */
+    int32_t *tri_id;    /* [N_r] input index of the nearest hit triangle, -1 on a miss */
+    float *uvt;         /* [N_r][3] u, v (weights of the triangle's 2nd and 3rd vertex)
+                           and t of that hit, rounded from binary64 in CERTIFIED
+                           precision; NaN on a miss */
+    uint64_t *counters; /* optional [4]: [0] segments re-decided in binary64, [1] segments
+                           that outgrew the LDS stack, [2], [3] reserved (0).  Zeroed by
+                           the call before it counts. */
+} rsi_outputs;
+
+/*
+ * rsi_build -- build the bounding volume hierarchy of a triangle mesh.
+ *   vertices   [n_vertices][3] float, x y z of each vertex
+ *   triangles  [n_triangles][3] int32, vertex indices of each triangle
+ *   opts       NULL or build options
+ *   stream     queue for the build
+ *   out        receives the handle (set to NULL on failure)
+ * Steps (paper: Background; Specific changes; Case Studies 1-2): mesh extent,
+ * Morton key of every triangle centroid normalised to the extent, a stable
+ * LDS radix sort of (key, index), the Karras binary radix tree over the sorted
+ * keys, and a bottom-up pass (one thread per leaf, an atomic counter per
+ * internal node: the second child to arrive merges both boxes and climbs).
+ * The library keeps copies of what it needs (the inputs may be freed once the
+ * stream passes the call) and allocates about 64 N_t + 48 N_t + 12 N_v + 12 N_t
+ * + 24 N_t bytes of device memory, stream-ordered on `stream`.
+ * Limits: n_triangles < 2^30, n_vertices < 2^31.  n_triangles == 0 gives a
+ * mesh no segment hits.
+ */
+rsi_status rsi_build(const float *vertices, int64_t n_vertices,
+                     const int32_t *triangles, int64_t n_triangles,
+                     const rsi_build_opts *opts, void *stream, rsi_mesh *out);
+
+/*
+ * rsi_intersect -- test n_rays segments against a built mesh.
+ *   rays_from, rays_to  [n_rays][3] float: start and end point of each segment
+ *   mode                rsi_mode
+ *   opts                NULL or intersection options
+ *   out                 output buffers (see rsi_outputs)
+ * Per segment (paper: Background -- tree search for candidates, then the
+ * Moller-Trumbore test): traverse the tree from the root, nearer child first,
+ * skipping children whose box (conservatively widened, so no binary64 hit is
+ * ever culled) the segment misses; test each reached triangle.  Boolean mode
+ * stops at the first hit; the other modes keep the nearest and skip boxes that
+ * begin beyond it.  n_rays == 0 does nothing.  Limit: n_rays < 2^31.
+ * Temporary device memory (4 n_rays + 64 bytes) is allocated and freed
+ * stream-ordered on `stream`.
+ */
+rsi_status rsi_intersect(rsi_mesh mesh, const float *rays_from, const float *rays_to,
+                         int64_t n_rays, int32_t mode, const rsi_intersect_opts *opts,
+                         const rsi_outputs *out, void *stream);
+
+/* rsi_destroy -- free a mesh (stream-ordered on the stream it was built on).
+ * NULL is accepted and ignored. */
+rsi_status rsi_destroy(rsi_mesh mesh);
+
+/* Host-side description of a built mesh. */
+typedef struct rsi_mesh_info {
+    int64_t n_vertices;
+    int64_t n_triangles;
+    int32_t morton_bits;
+    int32_t root;            /* root reference: 0 (internal node 0), ~0 (single leaf), or
+                                INT32_MIN for an empty mesh */
+    int64_t device_bytes;    /* device memory held by the mesh */
+} rsi_mesh_info;
+
+rsi_status rsi_mesh_info_get(rsi_mesh mesh, rsi_mesh_info *info);
+
+/* What rsi_mesh_export copies (for inspection and tests, in the spirit of the
+ * paper's device-memory debugging of the BVH, Case Study 1). */
+typedef enum rsi_export_what {
+    RSI_EXPORT_SORTED_KEYS = 0, /* uint64 [N_t]  Morton keys in sorted order (widened)   */
+    RSI_EXPORT_SORTED_IDS = 1,  /* int32  [N_t]  triangle index at each sorted position   */
+    RSI_EXPORT_NODES = 2,       /* 16 x 32-bit words per internal node, [N_t - 1]:
+                                   words 0-3  left  box x lo, x hi, y lo, y hi
+                                   words 4-7  right box x lo, x hi, y lo, y hi
+                                   words 8-11 left z lo, z hi, right z lo, z hi
+                                   word 12, 13 left / right child: >= 0 internal node,
+                                   < 0 leaf at sorted position ~ref; words 14-15 zero   */
+    RSI_EXPORT_PARENTS = 3,     /* int32 [2 N_t - 1]: parent of internal node i at [i]
+                                   (-1 for the root), of leaf k at [N_t - 1 + k]        */
+    RSI_EXPORT_COUNTERS = 4,    /* int32 [N_t - 1]: arrivals counted at each internal
+                                   node by the bottom-up pass (2 when complete)          */
+    RSI_EXPORT_LEAVES = 5,      /* 12 x 32-bit words per sorted leaf, [N_t]: A.xyz,
+                                   triangle index (int32), B-A xyz, 0, C-A xyz, 0        */
+    RSI_EXPORT_BOUNDS = 6       /* float [8]: mesh lo xyz, hi xyz, coordinate scale
+                                   (largest |coordinate|), 0                              */
+} rsi_export_what;
+
+/* Copy one internal array into dst (device or host memory of dst_bytes bytes,
+ * at least the size stated above).  Queued on `stream`; with a host dst the
+ * call waits for the copy. */
+rsi_status rsi_mesh_export(rsi_mesh mesh, int32_t what, void *dst, int64_t dst_bytes, void *stream);
+
+/*
+ * rsi_traversal_stats -- per-segment work of the same traversal rsi_intersect
+ * runs with these arguments (an instrumented copy of the kernel; results are
+ * not written).  node_visits[i] counts internal nodes fetched, leaf_tests[i]
+ * triangles tested; both uint32 [n_rays] device arrays.  Segments finished by
+ * the second (deep-stack) pass report the first pass's counts.
+ */
+rsi_status rsi_traversal_stats(rsi_mesh mesh, const float *rays_from, const float *rays_to,
+                               int64_t n_rays, int32_t mode, const rsi_intersect_opts *opts,
+                               uint32_t *node_visits, uint32_t *leaf_tests, void *stream);
+
+const char *rsi_status_string(rsi_status status);
+const char *rsi_last_error(void);   /* message of this thread's last failure, "" if none */
+int32_t rsi_abi_version(void);      /* RSI_ABI_VERSION of the built library */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSI_H */

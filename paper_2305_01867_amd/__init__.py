@@ -1,0 +1,262 @@
+"""Python binding of librsi.so (include/rsi.h): segment / triangle-mesh
+intersection on AMD gfx950.
+
+Argument marshalling only: tensors must already be on the GPU, float32
+coordinates and int32 indices (the paper's Case Study 1 is about a 64-bit
+index array read as 32-bit; an int64 array is refused here, never converted).
+Every step of the computation runs in the library's HIP kernels; this module
+has no CPU fallback and raises if the library is not built.
+
+Names follow the C ABI: rsi_build, rsi_intersect, rsi_destroy,
+rsi_mesh_info_get, rsi_mesh_export, rsi_traversal_stats.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # imported first so the library binds to the HIP runtime torch loaded
+
+__all__ = [
+    "RSIError", "Mesh", "lib", "library_path", "rsi_build", "rsi_intersect", "rsi_destroy",
+    "rsi_mesh_info_get", "rsi_mesh_export", "rsi_traversal_stats", "MODES", "PRECISIONS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "librsi.so")
+
+MODES = {"boolean": 0, "first_hit": 1, "barycentric": 2}
+PRECISIONS = {"plain": 0, "certified": 1}
+EXPORTS = {"sorted_keys": 0, "sorted_ids": 1, "nodes": 2, "parents": 3, "counters": 4, "leaves": 5, "bounds": 6}
+STATUS = {0: "RSI_OK", 1: "RSI_E_ARG", 2: "RSI_E_RANGE", 3: "RSI_E_NOMEM", 4: "RSI_E_HIP",
+          5: "RSI_E_STATE", 6: "RSI_E_CAPACITY"}
+
+
+class RSIError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _BuildOpts(ctypes.Structure):
+    _fields_ = [("morton_bits", ctypes.c_int32), ("check_indices", ctypes.c_int32)]
+
+
+class _IntersectOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("block", ctypes.c_int32), ("stack_depth", ctypes.c_int32),
+                ("ray_sort", ctypes.c_int32), ("proposal", ctypes.c_int32)]
+
+
+class _Outputs(ctypes.Structure):
+    _fields_ = [("hit", ctypes.c_void_p), ("tri_id", ctypes.c_void_p), ("uvt", ctypes.c_void_p),
+                ("counters", ctypes.c_void_p)]
+
+
+class _MeshInfo(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64), ("morton_bits", ctypes.c_int32),
+                ("root", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librsi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise ImportError(f"{library_path} is missing: build it with paper_2305_01867_amd/build_lib.py "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(library_path)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.rsi_build.argtypes = [P, I64, P, I64, ctypes.POINTER(_BuildOpts), P, ctypes.POINTER(P)]
+    L.rsi_intersect.argtypes = [P, P, P, I64, I32, ctypes.POINTER(_IntersectOpts), ctypes.POINTER(_Outputs), P]
+    L.rsi_destroy.argtypes = [P]
+    L.rsi_mesh_info_get.argtypes = [P, ctypes.POINTER(_MeshInfo)]
+    L.rsi_mesh_export.argtypes = [P, I32, P, I64, P]
+    L.rsi_traversal_stats.argtypes = [P, P, P, I64, I32, ctypes.POINTER(_IntersectOpts), P, P, P]
+    for f in ("rsi_build", "rsi_intersect", "rsi_destroy", "rsi_mesh_info_get", "rsi_mesh_export",
+              "rsi_traversal_stats"):
+        getattr(L, f).restype = ctypes.c_int
+    L.rsi_status_string.argtypes = [ctypes.c_int]
+    L.rsi_status_string.restype = ctypes.c_char_p
+    L.rsi_last_error.argtypes = []
+    L.rsi_last_error.restype = ctypes.c_char_p
+    L.rsi_abi_version.argtypes = []
+    L.rsi_abi_version.restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise RSIError(status, lib().rsi_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _need(t: torch.Tensor, name: str, dtype, shape_tail=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and (t.dim() != 2 or t.shape[1] != shape_tail):
+        raise ValueError(f"{name} must have shape [N, {shape_tail}]")
+    return t
+
+
+class Mesh:
+    """A built BVH (owns the library handle)."""
+
+    def __init__(self, handle, n_vertices, n_triangles, morton_bits, stream):
+        self._h = handle
+        self.n_vertices = n_vertices
+        self.n_triangles = n_triangles
+        self.morton_bits = morton_bits
+        self._stream = stream
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RSIError(5, "mesh destroyed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            _check(lib().rsi_destroy(h))
+
+    def __del__(self):
+        try:
+            if self._h is not None and _lib is not None:
+                _lib.rsi_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def rsi_build(vertices: torch.Tensor, triangles: torch.Tensor, morton_bits: int = 30,
+              check_indices: bool = False, stream=None) -> Mesh:
+    """Build the BVH of a mesh: vertices float32 [N_v, 3], triangles int32 [N_t, 3]."""
+    for t, name, dt in ((vertices, "vertices", torch.float32), (triangles, "triangles", torch.int32)):
+        if isinstance(t, torch.Tensor) and t.dtype != dt:
+            raise TypeError(f"{name} must be {dt}, got {t.dtype}")
+    _need(vertices, "vertices", torch.float32, 3)
+    _need(triangles, "triangles", torch.int32, 3)
+    opts = _BuildOpts(int(morton_bits), int(bool(check_indices)))
+    h = ctypes.c_void_p()
+    s = _stream_handle(stream)
+    _check(lib().rsi_build(ctypes.c_void_p(vertices.data_ptr()), vertices.shape[0],
+                           ctypes.c_void_p(triangles.data_ptr()), triangles.shape[0],
+                           ctypes.byref(opts), s, ctypes.byref(h)))
+    return Mesh(h, vertices.shape[0], triangles.shape[0], morton_bits, stream)
+
+
+def rsi_destroy(mesh: Mesh):
+    mesh.close()
+
+
+def _iopts(precision, block, stack_depth):
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+    return _IntersectOpts(PRECISIONS[precision], int(block), int(stack_depth), 0, 0)
+
+
+def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
+                  precision: str = "plain", block: int = 0, stack_depth: int = 0, out: dict | None = None,
+                  stream=None) -> dict:
+    """Test segments [N, 3] float32 against the mesh.  Returns a dict with the
+    outputs of the mode ("hit" uint8, "tri_id" int32, "uvt" float32 [N, 3]) and
+    "counters" uint64 [4] (re-decided in binary64, past the LDS stack, 0, 0).
+    `out` may supply preallocated tensors under the same keys."""
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {list(MODES)}")
+    _need(rays_from, "rays_from", torch.float32, 3)
+    _need(rays_to, "rays_to", torch.float32, 3)
+    if rays_from.shape != rays_to.shape:
+        raise ValueError("rays_from and rays_to must have the same shape")
+    n = rays_from.shape[0]
+    dev = rays_from.device
+    out = dict(out or {})
+    if mode == "boolean":
+        out.setdefault("hit", torch.empty(n, dtype=torch.uint8, device=dev))
+    else:
+        out.setdefault("tri_id", torch.empty(n, dtype=torch.int32, device=dev))
+    if mode == "barycentric":
+        out.setdefault("uvt", torch.empty((n, 3), dtype=torch.float32, device=dev))
+    out.setdefault("counters", torch.zeros(4, dtype=torch.int64, device=dev))
+    spec = {"hit": (torch.uint8, None), "tri_id": (torch.int32, None), "uvt": (torch.float32, 3),
+            "counters": (torch.int64, None)}
+    for k, t in out.items():
+        if k not in spec:
+            raise ValueError(f"unknown output {k}")
+        _need(t, f"out[{k!r}]", spec[k][0], spec[k][1])
+        if k != "counters" and t.shape[0] < n:
+            raise ValueError(f"out[{k!r}] is too small")
+        if k == "counters" and t.numel() < 4:
+            raise ValueError("out['counters'] needs 4 entries")
+
+    def ptr(k):
+        return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()
+
+    o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"))
+    opts = _iopts(precision, block, stack_depth)
+    _check(lib().rsi_intersect(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
+                               ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
+                               ctypes.byref(o), _stream_handle(stream)))
+    return out
+
+
+def rsi_traversal_stats(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
+                        precision: str = "plain", block: int = 0, stack_depth: int = 0, stream=None):
+    """Per-segment (node visits, leaf tests) of the traversal, uint32 -> int64 tensors."""
+    _need(rays_from, "rays_from", torch.float32, 3)
+    _need(rays_to, "rays_to", torch.float32, 3)
+    n = rays_from.shape[0]
+    visits = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
+    tests = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
+    opts = _iopts(precision, block, stack_depth)
+    _check(lib().rsi_traversal_stats(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
+                                     ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
+                                     ctypes.c_void_p(visits.data_ptr()), ctypes.c_void_p(tests.data_ptr()),
+                                     _stream_handle(stream)))
+    return visits, tests
+
+
+def rsi_mesh_info_get(mesh: Mesh) -> dict:
+    info = _MeshInfo()
+    _check(lib().rsi_mesh_info_get(mesh.handle, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in _MeshInfo._fields_}
+
+
+def rsi_mesh_export(mesh: Mesh, what: str, stream=None) -> torch.Tensor:
+    """Copy one internal array to a new GPU tensor (layouts in include/rsi.h)."""
+    nt = mesh.n_triangles
+    shapes = {
+        "sorted_keys": ((nt,), torch.int64), "sorted_ids": ((nt,), torch.int32),
+        "nodes": ((max(nt - 1, 0), 16), torch.int32), "parents": ((max(2 * nt - 1, 0),), torch.int32),
+        "counters": ((max(nt - 1, 0),), torch.int32), "leaves": ((nt, 12), torch.int32),
+        "bounds": ((8 if nt > 0 else 0,), torch.float32),
+    }
+    if what not in shapes:
+        raise ValueError(f"what must be one of {list(shapes)}")
+    shape, dtype = shapes[what]
+    dst = torch.empty(shape, dtype=dtype, device="cuda")
+    _check(lib().rsi_mesh_export(mesh.handle, EXPORTS[what], ctypes.c_void_p(dst.data_ptr()),
+                                 dst.numel() * dst.element_size(), _stream_handle(stream)))
+    return dst

@@ -1,0 +1,418 @@
+// build.hip -- bounding volume hierarchy construction on gfx950.
+//
+// Steps (paper: Background -- Morton codes, spatial sort, binary radix tree of
+// Karras 2012; Specific changes -- Morton kernel, 64-bit codes; Case Studies
+// 1-2 -- sorted int32 triangle ids, bottom-up node filling with one atomic
+// counter per internal node, N_t - 1 internal nodes, a launch sized by N_t):
+//   1. mesh extent            one workgroup, min / max over all vertices
+//   2. Morton keys            one lane per triangle
+//   3. LDS radix sort         stable LSD, 8-bit digits: tile histograms,
+//                             one device-wide scan, stable tile scatter
+//   4. radix tree             one lane per internal node (Karras section 3)
+//   5. leaves + bottom-up     one lane per leaf; counters at agent scope
+#include "rsi_internal.h"
+
+namespace rsi {
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 2048 keys per tile
+constexpr int kRadix = 256;
+
+// ---------------------------------------------------------------- 1. extent
+__global__ __launch_bounds__(1024) void k_mesh_bounds(const float *__restrict__ V, int64_t nv,
+                                                      float *__restrict__ bounds) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = threadIdx.x; i < nv; i += blockDim.x) {
+        for (int a = 0; a < 3; ++a) {
+            float x = V[3 * i + a];
+            lo[a] = fminf(lo[a], x);
+            hi[a] = fmaxf(hi[a], x);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off));
+        }
+    __shared__ float red[16][6];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int a = 0; a < 3; ++a) {
+            red[w][a] = lo[a];
+            red[w][3 + a] = hi[a];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 1; k < nw; ++k)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fminf(lo[a], red[k][a]);
+                hi[a] = fmaxf(hi[a], red[k][3 + a]);
+            }
+        float scale = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            bounds[a] = lo[a];
+            bounds[3 + a] = hi[a];
+            scale = fmaxf(scale, fmaxf(fabsf(lo[a]), fabsf(hi[a])));
+        }
+        bounds[6] = scale;
+        bounds[7] = 0.0f;
+    }
+}
+
+// ---------------------------------------------------------- 2. Morton keys
+// Spread the low 10 (or 21) bits of x so that bit k lands on bit 3k.
+__device__ __forceinline__ uint32_t spread3(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+__device__ __forceinline__ uint64_t spread3(uint64_t x) {
+    x &= 0x1fffffull;
+    x = (x | (x << 32)) & 0x001f00000000ffffull;
+    x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// Quantise one centroid coordinate: n = (c - lo) / ext (0 for a flat axis),
+// q = floor(min(n 2^b, 2^b - 1)), 0 for n <= 0 or NaN.  Single float32 ops,
+// no contraction.
+__device__ __forceinline__ uint32_t quantise(float c, float lo, float ext, float two_b, float top) {
+#pragma clang fp contract(off)
+    float n = ext > 0.0f ? (c - lo) / ext : 0.0f;
+    float x = n * two_b;
+    return x > 0.0f ? (uint32_t)floorf(fminf(x, top)) : 0u;
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_morton(const float *__restrict__ V, int64_t nv,
+                                                const int32_t *__restrict__ F, int64_t nt,
+                                                const float *__restrict__ bounds, K *__restrict__ keys,
+                                                int32_t *__restrict__ ids, int32_t *__restrict__ flags) {
+#pragma clang fp contract(off)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt)
+        return;
+    constexpr int b = sizeof(K) == 4 ? 10 : 21;
+    const int32_t i0 = F[3 * t], i1 = F[3 * t + 1], i2 = F[3 * t + 2];
+    ids[t] = (int32_t)t;
+    if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
+        atomicOr(flags, 1);
+        keys[t] = (K)0;
+        return;
+    }
+    float c[3];
+    for (int a = 0; a < 3; ++a)
+        c[a] = ((V[3 * (int64_t)i0 + a] + V[3 * (int64_t)i1 + a]) + V[3 * (int64_t)i2 + a]) / 3.0f;
+    const float two_b = (float)(1u << b), top = (float)((1u << b) - 1u);
+    K key = 0;
+    for (int a = 2; a >= 0; --a) {  // z, then y, then x: z lands on the top bit of each triple
+        const float lo = bounds[a], ext = bounds[3 + a] - bounds[a];
+        key = (K)(key << 1) | spread3((K)quantise(c[a], lo, ext, two_b, top));
+    }
+    keys[t] = key;
+}
+
+// ---------------------------------------------------------- 3. radix sort
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K *__restrict__ keys, int64_t n, int shift,
+                                                            int ntiles, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[kRadix];
+    const int tid = threadIdx.x, tile = blockIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)tile * kSortTile;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t idx = base + r * kSortThreads + tid;
+        if (idx < n)
+            atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 0xffu], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * ntiles + tile] = h[tid];
+}
+
+// Exclusive scan of hist[0..len) in place, one workgroup of 1024 lanes.
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ hist, int64_t len) {
+    __shared__ uint32_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (len + 1023) / 1024;
+    const int64_t beg = tid * chunk, end = beg + chunk < len ? beg + chunk : len;
+    uint32_t s = 0;
+    for (int64_t i = beg; i < end; ++i)
+        s += hist[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - s;  // exclusive prefix of this chunk
+    for (int64_t i = beg; i < end; ++i) {
+        uint32_t v = hist[i];
+        hist[i] = run;
+        run += v;
+    }
+}
+
+// Stable scatter of one tile.  Rounds of 256 consecutive keys are ranked in
+// order: inside a wave by matching the 8 digit bits with ballots, across the
+// four waves and earlier rounds through per-digit LDS counts.
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const K *__restrict__ kin,
+                                                               const int32_t *__restrict__ iin,
+                                                               K *__restrict__ kout, int32_t *__restrict__ iout,
+                                                               int64_t n, int shift, int ntiles,
+                                                               const uint32_t *__restrict__ offs) {
+    __shared__ uint32_t run[kRadix];
+    __shared__ uint32_t base[kRadix];
+    __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
+    const int tid = threadIdx.x, tile = blockIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    run[tid] = 0;
+    base[tid] = offs[(int64_t)tid * ntiles + tile];
+    for (int w = 0; w < kSortThreads / 64; ++w)
+        wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t t0 = (int64_t)tile * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t idx = t0 + r * kSortThreads + tid;
+        const bool valid = idx < n;
+        K key = 0;
+        int32_t id = 0;
+        uint32_t digit = 0;
+        if (valid) {
+            key = kin[idx];
+            id = iin[idx];
+            digit = (uint32_t)(key >> shift) & 0xffu;
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (digit >> bit) & 1u;
+            const uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0)
+            wcnt[wave][digit] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[digit] + run[digit] + rank;
+            for (int w = 0; w < wave; ++w)
+                pos += wcnt[w][digit];
+            kout[pos] = key;
+            iout[pos] = id;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < kSortThreads / 64; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------- 4. radix tree
+// Length of the common prefix of key_i || i and key_j || j; -1 outside [0, n).
+template <typename K>
+__device__ __forceinline__ int prefix(const K *__restrict__ k, int n, int i, K ki, int j) {
+    if (j < 0 || j >= n)
+        return -1;
+    const K kj = k[j];
+    if (ki != kj) {
+        if constexpr (sizeof(K) == 8)
+            return __builtin_clzll((unsigned long long)(ki ^ kj));
+        else
+            return __builtin_clz((unsigned)(ki ^ kj));
+    }
+    return (int)(8 * sizeof(K)) + __builtin_clz((unsigned)(i ^ j));
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_radix_tree(const K *__restrict__ keys, int n, Node *__restrict__ nodes,
+                                                    int32_t *__restrict__ parent, int32_t *__restrict__ counters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1)
+        return;
+    const K ki = keys[i];
+    const int d = prefix(keys, n, i, ki, i + 1) > prefix(keys, n, i, ki, i - 1) ? 1 : -1;
+    const int below = prefix(keys, n, i, ki, i - d);
+    int len_max = 2;
+    while (prefix(keys, n, i, ki, i + len_max * d) > below)
+        len_max <<= 1;
+    int len = 0;
+    for (int step = len_max >> 1; step >= 1; step >>= 1)
+        if (prefix(keys, n, i, ki, i + (len + step) * d) > below)
+            len += step;
+    const int j = i + len * d;
+    const int node_prefix = prefix(keys, n, i, ki, j);
+    int s = 0;
+    for (int div = 2;; div <<= 1) {
+        const int step = (len + div - 1) / div;
+        if (prefix(keys, n, i, ki, i + (s + step) * d) > node_prefix)
+            s += step;
+        if (step <= 1)
+            break;
+    }
+    const int split = i + s * d + (d < 0 ? -1 : 0);
+    const int lo = min(i, j), hi = max(i, j);
+    const int left = (lo == split) ? ~split : split;
+    const int right = (hi == split + 1) ? ~(split + 1) : split + 1;
+    nodes[i].refs = make_int4(left, right, 0, 0);
+    parent[left >= 0 ? left : (n - 1) + ~left] = i;
+    parent[right >= 0 ? right : (n - 1) + ~right] = i;
+    counters[i] = 0;
+    if (i == 0)
+        parent[0] = -1;
+}
+
+// ------------------------------------------------- 5. leaves and bottom-up
+// One lane per sorted leaf: write its triangle, then climb.  At each internal
+// node the lane stores its subtree's box in its slot and increments the node's
+// counter (acquire-release at agent scope, so boxes written on another XCD are
+// visible); the first arrival stops, the second merges both boxes and goes on.
+__global__ __launch_bounds__(256) void k_leaves_bottom_up(const float *__restrict__ V, int64_t nv,
+                                                          const int32_t *__restrict__ F,
+                                                          const int32_t *__restrict__ ids, int n,
+                                                          Tri *__restrict__ tris, Node *nodes,
+                                                          const int32_t *__restrict__ parent, int32_t *counters) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n)
+        return;
+    int t = ids[k];
+    const bool t_ok = t >= 0 && t < n;  // always true for a correct sort; guards the loads below
+    if (!t_ok)
+        t = 0;
+    const int32_t i0 = F[3 * (int64_t)t], i1 = F[3 * (int64_t)t + 1], i2 = F[3 * (int64_t)t + 2];
+    float lo[3], hi[3];
+    Tri tri;
+    if (!t_ok || i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
+        // an invalid triangle is never hit and does not widen any box
+        tri.a = make_float4(NAN, NAN, NAN, __int_as_float(t));
+        tri.e1 = make_float4(NAN, NAN, NAN, 0.0f);
+        tri.e2 = make_float4(NAN, NAN, NAN, 0.0f);
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = INFINITY;
+            hi[a] = -INFINITY;
+        }
+    } else {
+        float A[3], B[3], C[3];
+        for (int a = 0; a < 3; ++a) {
+            A[a] = V[3 * (int64_t)i0 + a];
+            B[a] = V[3 * (int64_t)i1 + a];
+            C[a] = V[3 * (int64_t)i2 + a];
+            lo[a] = fminf(A[a], fminf(B[a], C[a]));
+            hi[a] = fmaxf(A[a], fmaxf(B[a], C[a]));
+        }
+        tri.a = make_float4(A[0], A[1], A[2], __int_as_float(t));
+        tri.e1 = make_float4(B[0] - A[0], B[1] - A[1], B[2] - A[2], 0.0f);
+        tri.e2 = make_float4(C[0] - A[0], C[1] - A[1], C[2] - A[2], 0.0f);
+    }
+    tris[k] = tri;
+    if (n < 2)
+        return;
+    int self = ~k;
+    int p = parent[(n - 1) + k];
+    // a radix tree is at most 97 levels deep; the bound only guards the loop
+    for (int level = 0; p >= 0 && p < n - 1 && level < kDeepStack; ++level) {
+        Node *node = nodes + p;
+        const bool is_left = node->refs.x == self;
+        if (is_left) {
+            node->xy_left = make_float4(lo[0], hi[0], lo[1], hi[1]);
+            *reinterpret_cast<float2 *>(&node->z_both.x) = make_float2(lo[2], hi[2]);
+        } else {
+            node->xy_right = make_float4(lo[0], hi[0], lo[1], hi[1]);
+            *reinterpret_cast<float2 *>(&node->z_both.z) = make_float2(lo[2], hi[2]);
+        }
+        const int before = __hip_atomic_fetch_add(counters + p, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (before == 0)
+            return;  // the sibling subtree is not finished; its last lane continues
+        float4 xy;
+        float2 z;
+        if (is_left) {
+            xy = node->xy_right;
+            z = *reinterpret_cast<const float2 *>(&node->z_both.z);
+        } else {
+            xy = node->xy_left;
+            z = *reinterpret_cast<const float2 *>(&node->z_both.x);
+        }
+        lo[0] = fminf(lo[0], xy.x);
+        hi[0] = fmaxf(hi[0], xy.y);
+        lo[1] = fminf(lo[1], xy.z);
+        hi[1] = fmaxf(hi[1], xy.w);
+        lo[2] = fminf(lo[2], z.x);
+        hi[2] = fmaxf(hi[2], z.y);
+        self = p;
+        p = parent[p];
+    }
+}
+
+__global__ void k_zero_i32(int32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0;
+}
+
+inline int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
+
+template <typename K>
+hipError_t build_typed(MeshDev &m, hipStream_t s) {
+    const int64_t nt = m.nt;
+    K *keys = static_cast<K *>(m.keys);
+    K *keys_tmp = static_cast<K *>(m.sort_tmp);
+    int32_t *ids_tmp = reinterpret_cast<int32_t *>(keys_tmp + nt);
+    const int ntiles = blocks_for(nt, kSortTile);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ids_tmp + nt);
+
+    k_morton<K><<<blocks_for(nt, 256), 256, 0, s>>>(m.V, m.nv, m.F, nt, m.bounds, keys, m.ids, m.flags);
+
+    const int key_bits = m.morton_bits;
+    K *src_k = keys, *dst_k = keys_tmp;
+    int32_t *src_i = m.ids, *dst_i = ids_tmp;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        k_sort_hist<K><<<ntiles, kSortThreads, 0, s>>>(src_k, nt, shift, ntiles, hist);
+        k_sort_scan<<<1, 1024, 0, s>>>(hist, (int64_t)kRadix * ntiles);
+        k_sort_scatter<K><<<ntiles, kSortThreads, 0, s>>>(src_k, src_i, dst_k, dst_i, nt, shift, ntiles, hist);
+        K *tk = src_k; src_k = dst_k; dst_k = tk;
+        int32_t *ti = src_i; src_i = dst_i; dst_i = ti;
+    }
+    // 4 or 8 passes: the sorted data is back in (keys, ids)
+    if (nt >= 2)
+        k_radix_tree<K><<<blocks_for(nt - 1, 256), 256, 0, s>>>(keys, (int)nt, m.nodes, m.parent, m.counters);
+    k_leaves_bottom_up<<<blocks_for(nt, 256), 256, 0, s>>>(m.V, m.nv, m.F, m.ids, (int)nt, m.tris, m.nodes,
+                                                           m.parent, m.counters);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t sort_tmp_bytes(int64_t nt, int morton_bits) {
+    const size_t kb = morton_bits > 32 ? 8 : 4;
+    const int64_t ntiles = (nt + kSortTile - 1) / kSortTile;
+    return kb * nt + 4 * nt + 4 * (size_t)kRadix * ntiles + 256;
+}
+
+hipError_t launch_build(MeshDev &m, const float *, const int32_t *, hipStream_t s, size_t) {
+    k_zero_i32<<<1, 64, 0, s>>>(m.flags, 4);
+    k_mesh_bounds<<<1, 1024, 0, s>>>(m.V, m.nv, m.bounds);
+    if (m.morton_bits > 32)
+        return build_typed<uint64_t>(m, s);
+    return build_typed<uint32_t>(m, s);
+}
+
+}  // namespace rsi

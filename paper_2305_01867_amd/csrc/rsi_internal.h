@@ -1,0 +1,76 @@
+// rsi_internal.h -- types and launchers shared by the library's own sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsi {
+
+// Internal node: the boxes of both children plus the two child references
+// (>= 0 internal node, < 0 leaf at sorted position ~ref).  One node is 64 B,
+// fetched as four 16-byte loads; keeping the children's boxes in the parent
+// lets one fetch decide both children.
+struct alignas(16) Node {
+    float4 xy_left;   // left  x lo, x hi, y lo, y hi
+    float4 xy_right;  // right x lo, x hi, y lo, y hi
+    float4 z_both;    // left z lo, z hi, right z lo, z hi
+    int4 refs;        // left ref, right ref, 0, 0
+};
+static_assert(sizeof(Node) == 64, "node must be 64 bytes");
+
+// Leaf triangle in sorted order: first corner, the two edge vectors from it
+// (rounded once, exactly as computing them on the fly would) and the input
+// triangle index.  48 B, three 16-byte loads.
+struct alignas(16) Tri {
+    float4 a;   // A.xyz, triangle index (bit pattern of an int32)
+    float4 e1;  // (B - A).xyz, 0
+    float4 e2;  // (C - A).xyz, 0
+};
+static_assert(sizeof(Tri) == 48, "leaf triangle must be 48 bytes");
+
+constexpr int kDeepStack = 128;  // exceeds the radix tree's largest possible depth (97)
+
+// Device state of one built mesh.
+struct MeshDev {
+    int64_t nv = 0, nt = 0;
+    int morton_bits = 30;
+    int root = 0;
+    float *V = nullptr;        // [nv][3] copy of the vertices
+    int32_t *F = nullptr;      // [nt][3] copy of the triangles
+    void *keys = nullptr;      // [nt] sorted keys (uint32 or uint64)
+    int32_t *ids = nullptr;    // [nt] triangle index at each sorted position
+    Node *nodes = nullptr;     // [nt-1]
+    int32_t *parent = nullptr; // [2nt-1]
+    int32_t *counters = nullptr; // [nt-1]
+    Tri *tris = nullptr;       // [nt]
+    float *bounds = nullptr;   // [8]
+    int32_t *flags = nullptr;  // [4]: [0] bad-index flag
+    void *sort_tmp = nullptr;  // key/id ping-pong + histograms
+    int64_t bytes = 0;
+};
+
+// Build steps (build.hip).  All asynchronous on `s`.
+hipError_t launch_build(MeshDev &m, const float *V, const int32_t *F, hipStream_t s, size_t sort_tmp_bytes);
+size_t sort_tmp_bytes(int64_t nt, int morton_bits);
+
+// Intersection (traverse.hip).
+struct TraverseArgs {
+    const float *from = nullptr, *to = nullptr;
+    int64_t n = 0;
+    int mode = 0;
+    int certified = 0;
+    int block = 256;
+    int stack = 24;
+    uint8_t *hit = nullptr;
+    int32_t *tri_id = nullptr;
+    float *uvt = nullptr;
+    uint64_t *counters = nullptr;  // [4] device
+    int32_t *queue = nullptr;      // [n] device
+    uint32_t *queue_len = nullptr; // [1] device (inside counters workspace)
+    uint32_t *visits = nullptr;    // stats only
+    uint32_t *tests = nullptr;     // stats only
+};
+hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
+hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
+
+}  // namespace rsi

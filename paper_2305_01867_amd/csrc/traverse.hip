@@ -1,0 +1,600 @@
+// traverse.hip -- tree search and Moller-Trumbore leaf tests on gfx950.
+//
+// Paper: Background -- a tree search gathers the candidate triangles of each
+// segment and the Moller-Trumbore test (Moller & Trumbore 1997) decides; the
+// operating modes boolean / barycentric; Epilogue -- binary32 can misjudge
+// near-parallel rays, binary64 intermediates fix it.
+//
+// Pass 1 (k_traverse): one lane per segment, stack of pending subtrees in LDS
+// (stack_depth entries per lane), nearer child first, binary32 arithmetic.
+//   PLAIN      the binary32 predicates decide.
+//   CERTIFIED  each predicate X comes with a proven bound B(X) on its distance
+//              from the exact value and from the binary64 value; |X| > B(X)
+//              fixes the sign of the binary64 result, so the pair is a sure
+//              hit or a sure miss.  Otherwise the pair is "unsure".  Nearest-hit
+//              choice uses proven intervals around the binary64 t.
+// A segment whose result is unsure, or whose path outgrows the LDS stack, is
+// appended to a queue and finished by pass 2 (k_finish): a deep private stack
+// and, in CERTIFIED precision, the binary64 test with the oracle's operation
+// order (no contraction, correctly rounded division) on every candidate.
+//
+// Box test: the slab test on each child box widened by eta = 2^-20 max(|coord|)
+// of the segment and mesh.  That margin exceeds every rounding of the slab
+// arithmetic, so a point within eta/4 of a box is never culled -- in
+// particular any binary64 hit of a non-grazing segment.
+#include "rsi_internal.h"
+
+namespace rsi {
+namespace {
+
+constexpr float kEtaRel = 0x1p-20f;
+constexpr float kBoundK = 12.0f * 0x1p-24f;  // >= 8 u32 (binary32) + 8 u64 (binary64) with slack
+constexpr float kBoundTiny = 0x1p-140f;      // absorbs underflow in the products
+constexpr int kMiss = 0, kHit = 1, kUnsure = 2;
+enum { MODE_BOOL = 0, MODE_FIRST = 1, MODE_BARY = 2 };
+
+struct Ray {
+    float3 o, d;   // start point, direction E - O (rounded)
+    float3 inv;    // 1 / direction (components below eta/4 raised to eta/4)
+    float3 nra;    // -(O + eta) * inv   (lower box faces)
+    float3 nrb;    // -(O - eta) * inv   (upper box faces)
+};
+
+__device__ __forceinline__ bool finite3(float3 v) {
+    return __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z);
+}
+
+__device__ __forceinline__ float widen_dir(float d, float dmin) {
+    return fabsf(d) < dmin ? copysignf(dmin, d) : d;
+}
+
+// Returns false for segments whose setup is not finite.
+__device__ __forceinline__ bool setup_ray(const float *__restrict__ from, const float *__restrict__ to,
+                                          int64_t i, float scale, Ray &r) {
+    r.o = make_float3(from[3 * i], from[3 * i + 1], from[3 * i + 2]);
+    const float3 e = make_float3(to[3 * i], to[3 * i + 1], to[3 * i + 2]);
+    r.d = make_float3(e.x - r.o.x, e.y - r.o.y, e.z - r.o.z);
+    float m = fmaxf(scale, fmaxf(fmaxf(fabsf(r.o.x), fabsf(r.o.y)), fabsf(r.o.z)));
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(e.x), fabsf(e.y)), fabsf(e.z)));
+    const float eta = m * kEtaRel;
+    const float dmin = 0.25f * eta;
+    r.inv = make_float3(1.0f / widen_dir(r.d.x, dmin), 1.0f / widen_dir(r.d.y, dmin), 1.0f / widen_dir(r.d.z, dmin));
+    r.nra = make_float3(-((r.o.x + eta) * r.inv.x), -((r.o.y + eta) * r.inv.y), -((r.o.z + eta) * r.inv.z));
+    r.nrb = make_float3(-((r.o.x - eta) * r.inv.x), -((r.o.y - eta) * r.inv.y), -((r.o.z - eta) * r.inv.z));
+    return finite3(r.o) && finite3(e) && finite3(r.d) && finite3(r.inv) && finite3(r.nra) && finite3(r.nrb) &&
+           __builtin_isfinite(eta);
+}
+
+// Widened slab test of one box against t in [0, tlimit]; returns the entry t.
+__device__ __forceinline__ bool slab(float xlo, float xhi, float ylo, float yhi, float zlo, float zhi,
+                                     const Ray &r, float tlimit, float &tenter) {
+    const float tx0 = fmaf(xlo, r.inv.x, r.nra.x), tx1 = fmaf(xhi, r.inv.x, r.nrb.x);
+    const float ty0 = fmaf(ylo, r.inv.y, r.nra.y), ty1 = fmaf(yhi, r.inv.y, r.nrb.y);
+    const float tz0 = fmaf(zlo, r.inv.z, r.nra.z), tz1 = fmaf(zhi, r.inv.z, r.nrb.z);
+    const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+    const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tlimit));
+    tenter = tmin;
+    return tmin <= tmax;
+}
+
+struct MT32 {
+    float det, U, W, T;
+    float3 s;
+};
+
+// Binary32 Moller-Trumbore quantities (contraction allowed: the bound below
+// holds for any grouping into fused operations).
+__device__ __forceinline__ MT32 mt32(const Tri &tri, const Ray &r) {
+    MT32 m;
+    const float3 e1 = make_float3(tri.e1.x, tri.e1.y, tri.e1.z);
+    const float3 e2 = make_float3(tri.e2.x, tri.e2.y, tri.e2.z);
+    m.s = make_float3(r.o.x - tri.a.x, r.o.y - tri.a.y, r.o.z - tri.a.z);
+    const float px = r.d.y * e2.z - r.d.z * e2.y;
+    const float py = r.d.z * e2.x - r.d.x * e2.z;
+    const float pz = r.d.x * e2.y - r.d.y * e2.x;
+    const float qx = m.s.y * e1.z - m.s.z * e1.y;
+    const float qy = m.s.z * e1.x - m.s.x * e1.z;
+    const float qz = m.s.x * e1.y - m.s.y * e1.x;
+    m.det = e1.x * px + e1.y * py + e1.z * pz;
+    m.U = m.s.x * px + m.s.y * py + m.s.z * pz;
+    m.W = r.d.x * qx + r.d.y * qy + r.d.z * qz;
+    m.T = e2.x * qx + e2.y * qy + e2.z * qz;
+    return m;
+}
+
+// The binary32 decision, same predicates as the definition.
+__device__ __forceinline__ bool decide32(const MT32 &m) {
+    if (!(m.det != 0.0f))
+        return false;
+    const float g = m.det > 0.0f ? 1.0f : -1.0f;
+    const float a = g * m.U, b = g * m.W, tt = g * m.T, D = g * m.det;
+    return a >= 0.0f && b >= 0.0f && a + b <= D && tt >= 0.0f && tt <= D;
+}
+
+// Certified classification.  Every binary32 quantity X (det, U, W, T) is a sum
+// of six signed products of three rounded differences, formed with at most 8
+// roundings per product; so |X32 - X| <= gamma_8 M(X) with M(X) the same sum
+// over absolute values, and the binary64 evaluation obeys the same form with
+// unit roundoff 2^-53.  B(X) = 12 * 2^-24 * M(X) covers both with room for the
+// roundings of M itself.  For a hit the interval [tlo, thi] holds the exact t
+// and the binary64 t.
+__device__ __forceinline__ int classify(const MT32 &m, const Tri &tri, const Ray &r, float &tlo, float &thi) {
+    const float adx = fabsf(r.d.x), ady = fabsf(r.d.y), adz = fabsf(r.d.z);
+    const float asx = fabsf(m.s.x), asy = fabsf(m.s.y), asz = fabsf(m.s.z);
+    const float a1x = fabsf(tri.e1.x), a1y = fabsf(tri.e1.y), a1z = fabsf(tri.e1.z);
+    const float a2x = fabsf(tri.e2.x), a2y = fabsf(tri.e2.y), a2z = fabsf(tri.e2.z);
+    const float Pmx = ady * a2z + adz * a2y, Pmy = adz * a2x + adx * a2z, Pmz = adx * a2y + ady * a2x;
+    const float Qmx = asy * a1z + asz * a1y, Qmy = asz * a1x + asx * a1z, Qmz = asx * a1y + asy * a1x;
+    const float Bd = fmaf(kBoundK, a1x * Pmx + a1y * Pmy + a1z * Pmz, kBoundTiny);
+    const float BU = fmaf(kBoundK, asx * Pmx + asy * Pmy + asz * Pmz, kBoundTiny);
+    const float BW = fmaf(kBoundK, adx * Qmx + ady * Qmy + adz * Qmz, kBoundTiny);
+    const float BT = fmaf(kBoundK, a2x * Qmx + a2y * Qmy + a2z * Qmz, kBoundTiny);
+    const float aD = fabsf(m.det);
+    // a hit needs |U|, |W|, |T| <= |det| in binary64; a sure excess is a sure miss
+    const float cap = aD + Bd;
+    if (fabsf(m.U) - BU > cap || fabsf(m.W) - BW > cap || fabsf(m.T) - BT > cap)
+        return kMiss;
+    if (!(aD > Bd))
+        return kUnsure;  // sign of det (or det == 0) not certain; also NaN
+    const float g = m.det > 0.0f ? 1.0f : -1.0f;
+    const float a = g * m.U, b = g * m.W, tt = g * m.T;
+    const float w = g * ((m.det - m.U) - m.W);  // D - a - b
+    const float z = g * (m.det - m.T);          // D - tt
+    const float Bw = Bd + BU + BW + 0x1p-22f * (aD + fabsf(m.U) + fabsf(m.W));
+    const float Bz = Bd + BT + 0x1p-22f * (aD + fabsf(m.T));
+    if (a < -BU || b < -BW || w < -Bw || tt < -BT || z < -Bz)
+        return kMiss;
+    if (a > BU && b > BW && w > Bw && tt > BT && z > Bz) {
+        tlo = (tt - BT) / (aD + Bd) * (1.0f - 0x1p-21f);
+        thi = (tt + BT) / (aD - Bd) * (1.0f + 0x1p-21f);
+        return kHit;
+    }
+    return kUnsure;
+}
+
+// Binary64 test in the definition's operation order: differences, cross
+// products, dot products summed left to right, no fused operations, correctly
+// rounded division.
+struct MT64 {
+    bool hit;
+    double u, v, t;
+};
+
+__device__ __forceinline__ MT64 mt64(double ox, double oy, double oz, double ex, double ey, double ez,
+                                     const float *__restrict__ V, const int32_t *__restrict__ F, int t) {
+#pragma clang fp contract(off)
+    const int32_t i0 = F[3 * (int64_t)t], i1 = F[3 * (int64_t)t + 1], i2 = F[3 * (int64_t)t + 2];
+    const double Ax = V[3 * (int64_t)i0], Ay = V[3 * (int64_t)i0 + 1], Az = V[3 * (int64_t)i0 + 2];
+    const double Bx = V[3 * (int64_t)i1], By = V[3 * (int64_t)i1 + 1], Bz = V[3 * (int64_t)i1 + 2];
+    const double Cx = V[3 * (int64_t)i2], Cy = V[3 * (int64_t)i2 + 1], Cz = V[3 * (int64_t)i2 + 2];
+    const double dx = ex - ox, dy = ey - oy, dz = ez - oz;
+    const double e1x = Bx - Ax, e1y = By - Ay, e1z = Bz - Az;
+    const double e2x = Cx - Ax, e2y = Cy - Ay, e2z = Cz - Az;
+    const double sx = ox - Ax, sy = oy - Ay, sz = oz - Az;
+    const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    const double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    const double det = (e1x * px + e1y * py) + e1z * pz;
+    const double U = (sx * px + sy * py) + sz * pz;
+    const double W = (dx * qx + dy * qy) + dz * qz;
+    const double T = (e2x * qx + e2y * qy) + e2z * qz;
+    MT64 r{false, 0.0, 0.0, 0.0};
+    if (det == 0.0)
+        return r;
+    const double g = det > 0.0 ? 1.0 : -1.0;
+    const double a = g * U, b = g * W, tt = g * T, D = g * det;
+    if (a >= 0.0 && b >= 0.0 && a + b <= D && tt >= 0.0 && tt <= D) {
+        r.hit = true;
+        r.u = U / det;
+        r.v = W / det;
+        r.t = T / det;
+    }
+    return r;
+}
+
+__device__ __forceinline__ bool valid_tri(const int32_t *__restrict__ F, int64_t nv, int t) {
+    const int32_t i0 = F[3 * (int64_t)t], i1 = F[3 * (int64_t)t + 1], i2 = F[3 * (int64_t)t + 2];
+    return i0 >= 0 && i1 >= 0 && i2 >= 0 && i0 < nv && i1 < nv && i2 < nv;
+}
+
+struct Outs {
+    uint8_t *hit;
+    int32_t *id;
+    float *uvt;
+};
+
+__device__ __forceinline__ void write_out(const Outs &o, int64_t i, int mode, int id, float u, float v, float t) {
+    if (o.hit)
+        o.hit[i] = id >= 0 ? 1 : 0;
+    if (mode != MODE_BOOL)
+        o.id[i] = id;
+    if (mode == MODE_BARY) {
+        o.uvt[3 * i] = id >= 0 ? u : NAN;
+        o.uvt[3 * i + 1] = id >= 0 ? v : NAN;
+        o.uvt[3 * i + 2] = id >= 0 ? t : NAN;
+    }
+}
+
+struct TravParams {
+    const Node *__restrict__ nodes;
+    const Tri *__restrict__ tris;
+    const float *__restrict__ V;
+    const int32_t *__restrict__ F;
+    const float *__restrict__ bounds;
+    int64_t nv;
+    int64_t nt;
+    int root;
+    const float *__restrict__ from;
+    const float *__restrict__ to;
+    int64_t n;
+    Outs out;
+    int stack_depth;
+    int32_t *queue;
+    uint32_t *queue_len;
+    unsigned long long *counters;
+    uint32_t *visits;
+    uint32_t *tests;
+};
+
+__device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why) {
+    const uint32_t slot = atomicAdd(p.queue_len, 1u);
+    p.queue[slot] = (int32_t)i;
+    atomicAdd(p.counters + why, 1ull);
+}
+
+// ------------------------------------------------------------------ pass 1
+template <int MODE, bool CERT, bool STATS>
+__global__ __launch_bounds__(256) void k_traverse(TravParams p) {
+    extern __shared__ int lds_stack[];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n)
+        return;
+    Ray r;
+    const bool ok = setup_ray(p.from, p.to, i, p.bounds[6], r);
+    if (!ok) {
+        if (STATS) {
+            p.visits[i] = 0;
+            p.tests[i] = 0;
+        } else if (CERT) {
+            enqueue(p, i, 0);
+        } else {
+            write_out(p.out, i, MODE, -1, 0.0f, 0.0f, 0.0f);
+        }
+        return;
+    }
+    const int stride = blockDim.x;
+    int *stk = lds_stack + threadIdx.x;
+    int sp = 0;
+    int ref = p.root;
+    float tlimit = 1.0f;
+    bool found = false, unsure = false, flagged = false, overflow = false;
+    int best_id = -1, best_leaf = -1;
+    float best_t = INFINITY, best_lo = INFINITY, best_hi = INFINITY, best_u = 0.0f, best_v = 0.0f;
+    uint32_t n_nodes = 0, n_tests = 0;
+    // every node is reached at most once per segment; the bound only guards the loop
+    const int64_t max_steps = 2 * p.nt + 8;
+    const int n_internal = (int)p.nt - 1;
+
+    for (int64_t steps = 0;; ++steps) {
+        if (steps > max_steps || ref >= n_internal || ~ref >= p.nt) {
+            overflow = true;  // cannot happen for a well-formed tree
+            break;
+        }
+        if (ref >= 0) {
+            const Node *nd = p.nodes + ref;
+            const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
+            const int4 refs = nd->refs;
+            if (STATS)
+                ++n_nodes;
+            float tl, tr;
+            const bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, r, tlimit, tl);
+            const bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, r, tlimit, tr);
+            if (hl && hr) {
+                if (sp >= p.stack_depth) {
+                    overflow = true;
+                    break;
+                }
+                const bool left_first = tl <= tr;
+                stk[sp * stride] = left_first ? refs.y : refs.x;
+                ++sp;
+                ref = left_first ? refs.x : refs.y;
+                continue;
+            }
+            if (hl || hr) {
+                ref = hl ? refs.x : refs.y;
+                continue;
+            }
+        } else {
+            const int leaf = ~ref;
+            const Tri tri = p.tris[leaf];
+            if (STATS)
+                ++n_tests;
+            const MT32 m = mt32(tri, r);
+            const int id = __float_as_int(tri.a.w);
+            if (!CERT) {
+                if (decide32(m)) {
+                    if (MODE == MODE_BOOL) {
+                        found = true;
+                        break;
+                    }
+                    const float t = m.T / m.det;
+                    if (t < best_t || (t == best_t && id < best_id)) {
+                        best_t = t;
+                        best_id = id;
+                        best_leaf = leaf;
+                        if (MODE == MODE_BARY) {
+                            best_u = m.U / m.det;
+                            best_v = m.W / m.det;
+                        }
+                        tlimit = best_t;
+                    }
+                }
+            } else {
+                float lo = 0.0f, hi = 0.0f;
+                const int c = classify(m, tri, r, lo, hi);
+                if (MODE == MODE_BOOL) {
+                    if (c == kHit) {
+                        found = true;
+                        break;
+                    }
+                    if (c == kUnsure)
+                        unsure = true;
+                } else {
+                    if (c == kUnsure) {
+                        flagged = true;
+                        break;
+                    }
+                    if (c == kHit) {
+                        if (best_id < 0 || hi < best_lo) {
+                            best_lo = lo;
+                            best_hi = hi;
+                            best_id = id;
+                            best_leaf = leaf;
+                            tlimit = fminf(tlimit, hi * (1.0f + 0x1p-20f));
+                        } else if (!(lo > best_hi)) {
+                            flagged = true;  // intervals overlap: order not certain
+                            break;
+                        }
+                    }
+                }
+            }
+        }
+        if (sp == 0)
+            break;
+        --sp;
+        ref = stk[sp * stride];
+    }
+
+    if (STATS) {
+        p.visits[i] = n_nodes;
+        p.tests[i] = n_tests;
+        return;
+    }
+    if (MODE == MODE_BOOL) {
+        if (found) {
+            p.out.hit[i] = 1;
+            return;
+        }
+        if (overflow) {
+            enqueue(p, i, 1);
+            return;
+        }
+        if (CERT && unsure) {
+            enqueue(p, i, 0);
+            return;
+        }
+        p.out.hit[i] = 0;
+        return;
+    }
+    if (overflow) {
+        enqueue(p, i, 1);
+        return;
+    }
+    if (CERT && flagged) {
+        enqueue(p, i, 0);
+        return;
+    }
+    if (CERT && MODE == MODE_BARY && best_id >= 0) {
+        const float *o = p.from + 3 * i, *e = p.to + 3 * i;
+        const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, best_id);
+        write_out(p.out, i, MODE, best_id, (float)h.u, (float)h.v, (float)h.t);
+        return;
+    }
+    (void)best_leaf;
+    write_out(p.out, i, MODE, best_id, best_u, best_v, best_t);
+}
+
+// ------------------------------------------------------------------ pass 2
+// Segments from the queue, one per lane, with a private stack deep enough for
+// any radix tree.  CERTIFIED: binary64 decides every candidate; a segment whose
+// binary32 setup is not finite is tested against every triangle.
+template <int MODE, bool CERT>
+__global__ __launch_bounds__(64) void k_finish(TravParams p) {
+    const uint32_t count = *p.queue_len;
+    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < count; qi += gridDim.x * blockDim.x) {
+        const int64_t i = p.queue[qi];
+        Ray r;
+        const bool ok = setup_ray(p.from, p.to, i, p.bounds[6], r);
+        const float *o = p.from + 3 * i, *e = p.to + 3 * i;
+        const double ox = o[0], oy = o[1], oz = o[2], ex = e[0], ey = e[1], ez = e[2];
+        int best_id = -1;
+        double bu = 0.0, bv = 0.0, bt = 0.0;
+        float best_t32 = INFINITY, bu32 = 0.0f, bv32 = 0.0f;
+        float tlimit = 1.0f;
+        bool done = false;
+
+        auto test_leaf = [&](int leaf) {
+            const Tri tri = p.tris[leaf];
+            const int id = __float_as_int(tri.a.w);
+            if (CERT) {
+                MT64 h{false, 0.0, 0.0, 0.0};
+                if (valid_tri(p.F, p.nv, id))
+                    h = mt64(ox, oy, oz, ex, ey, ez, p.V, p.F, id);
+                if (h.hit) {
+                    const double u = h.u, v = h.v, t = h.t;
+                    if (MODE == MODE_BOOL) {
+                        best_id = id;
+                        done = true;
+                        return;
+                    }
+                    if (best_id < 0 || t < bt || (t == bt && id < best_id)) {
+                        best_id = id;
+                        bu = u;
+                        bv = v;
+                        bt = t;
+                        // round up, then widen: no box holding a hit at t <= bt is culled
+                        tlimit = fminf(tlimit, __double2float_ru(t) * (1.0f + 0x1p-20f));
+                    }
+                }
+            } else {
+                const MT32 m = mt32(tri, r);
+                if (decide32(m)) {
+                    if (MODE == MODE_BOOL) {
+                        best_id = id;
+                        done = true;
+                        return;
+                    }
+                    const float t = m.T / m.det;
+                    if (t < best_t32 || (t == best_t32 && id < best_id)) {
+                        best_t32 = t;
+                        best_id = id;
+                        bu32 = m.U / m.det;
+                        bv32 = m.W / m.det;
+                        tlimit = t;
+                    }
+                }
+            }
+        };
+
+        if (!ok) {
+            if (CERT) {
+                // brute force over every leaf: the box test is not reliable here
+                for (int64_t leaf = 0; leaf < p.nt && !done; ++leaf)
+                    test_leaf((int)leaf);
+            }
+        } else {
+            int stack[kDeepStack];
+            int sp = 0;
+            int ref = p.root;
+            const int64_t max_steps = 2 * p.nt + 8;
+            const int n_internal = (int)p.nt - 1;
+            for (int64_t steps = 0; steps <= max_steps && ref < n_internal && ~ref < p.nt; ++steps) {
+                if (ref >= 0) {
+                    const Node *nd = p.nodes + ref;
+                    const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
+                    const int4 refs = nd->refs;
+                    float tl, tr;
+                    const bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, r, tlimit, tl);
+                    const bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, r, tlimit, tr);
+                    if (hl && hr) {
+                        const bool left_first = tl <= tr;
+                        if (sp < kDeepStack)
+                            stack[sp++] = left_first ? refs.y : refs.x;
+                        ref = left_first ? refs.x : refs.y;
+                        continue;
+                    }
+                    if (hl || hr) {
+                        ref = hl ? refs.x : refs.y;
+                        continue;
+                    }
+                } else {
+                    test_leaf(~ref);
+                    if (done)
+                        break;
+                }
+                if (sp == 0)
+                    break;
+                ref = stack[--sp];
+            }
+        }
+        if (CERT)
+            write_out(p.out, i, MODE, best_id, (float)bu, (float)bv, (float)bt);
+        else
+            write_out(p.out, i, MODE, best_id, bu32, bv32, best_t32);
+    }
+}
+
+__global__ void k_reset(uint32_t *queue_len, unsigned long long *counters) {
+    if (threadIdx.x == 0)
+        queue_len[0] = 0;
+    if (threadIdx.x < 4)
+        counters[threadIdx.x] = 0;
+}
+
+__global__ void k_fill_miss(Outs out, int64_t n, int mode) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        write_out(out, i, mode, -1, 0.0f, 0.0f, 0.0f);
+}
+
+template <int MODE, bool CERT, bool STATS>
+void launch_pass1(const TravParams &p, int block, hipStream_t s) {
+    const int grid = (int)((p.n + block - 1) / block);
+    const size_t lds = (size_t)p.stack_depth * block * sizeof(int);
+    k_traverse<MODE, CERT, STATS><<<grid, block, lds, s>>>(p);
+}
+
+template <bool STATS>
+void dispatch_pass1(const TravParams &p, int mode, bool cert, int block, hipStream_t s) {
+    if (mode == MODE_BOOL)
+        cert ? launch_pass1<MODE_BOOL, true, STATS>(p, block, s) : launch_pass1<MODE_BOOL, false, STATS>(p, block, s);
+    else if (mode == MODE_FIRST)
+        cert ? launch_pass1<MODE_FIRST, true, STATS>(p, block, s) : launch_pass1<MODE_FIRST, false, STATS>(p, block, s);
+    else
+        cert ? launch_pass1<MODE_BARY, true, STATS>(p, block, s) : launch_pass1<MODE_BARY, false, STATS>(p, block, s);
+}
+
+TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
+    TravParams p;
+    p.nodes = m.nodes;
+    p.tris = m.tris;
+    p.V = m.V;
+    p.F = m.F;
+    p.bounds = m.bounds;
+    p.nv = m.nv;
+    p.nt = m.nt;
+    p.root = m.root;
+    p.from = a.from;
+    p.to = a.to;
+    p.n = a.n;
+    p.out = Outs{a.hit, a.tri_id, a.uvt};
+    p.stack_depth = a.stack;
+    p.queue = a.queue;
+    p.queue_len = a.queue_len;
+    p.counters = reinterpret_cast<unsigned long long *>(a.counters);
+    p.visits = a.visits;
+    p.tests = a.tests;
+    return p;
+}
+
+}  // namespace
+
+hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t s) {
+    TravParams p = make_params(m, a);
+    k_reset<<<1, 64, 0, s>>>(a.queue_len, p.counters);
+    if (a.n == 0)
+        return hipGetLastError();
+    if (m.nt == 0) {
+        k_fill_miss<<<(int)((a.n + 255) / 256), 256, 0, s>>>(p.out, a.n, a.mode);
+        return hipGetLastError();
+    }
+    dispatch_pass1<false>(p, a.mode, a.certified != 0, a.block, s);
+    const int64_t want = (a.n + 63) / 64;
+    const int grid2 = (int)(want < 4096 ? want : 4096);
+    if (a.mode == MODE_BOOL)
+        a.certified ? k_finish<MODE_BOOL, true><<<grid2, 64, 0, s>>>(p) : k_finish<MODE_BOOL, false><<<grid2, 64, 0, s>>>(p);
+    else if (a.mode == MODE_FIRST)
+        a.certified ? k_finish<MODE_FIRST, true><<<grid2, 64, 0, s>>>(p) : k_finish<MODE_FIRST, false><<<grid2, 64, 0, s>>>(p);
+    else
+        a.certified ? k_finish<MODE_BARY, true><<<grid2, 64, 0, s>>>(p) : k_finish<MODE_BARY, false><<<grid2, 64, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s) {
+    TravParams p = make_params(m, a);
+    if (m.nt == 0 || a.n == 0)
+        return hipSuccess;
+    dispatch_pass1<true>(p, a.mode, a.certified != 0, a.block, s);
+    return hipGetLastError();
+}
+
+}  // namespace rsi

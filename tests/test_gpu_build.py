@@ -1,0 +1,142 @@
+"""GPU build vs the oracle, bit for bit: Morton keys, stable sort order, radix
+tree topology, child boxes, completion counters (the paper's Case Study 2
+bar: every internal node reached twice), parents, leaf triangles, extent."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2305_01867_amd as rsi
+from paper_2305_01867_amd import workloads
+from gpu_helpers import decode_nodes, dev, export, say
+
+pytestmark = pytest.mark.gpu
+
+
+def triangle_soup(n_tri, seed, n_vert=600, clustered=False):
+    rng = np.random.default_rng(seed)
+    V = rng.uniform(-1.0, 1.0, size=(n_vert, 3))
+    if clustered:
+        V = np.round(V * 4) / 4  # many identical centroids -> duplicate keys
+    F = rng.integers(0, n_vert, size=(n_tri, 3))
+    return V.astype(np.float32), F.astype(np.int32)
+
+
+def check_structure(V, F, bits):
+    nt = F.shape[0]
+    say(f"[build] n_tri={nt} n_vert={V.shape[0]} bits={bits}")
+    want = oracle.build_structure(V, F, bits)
+    with rsi.rsi_build(dev(V), dev(F), morton_bits=bits) as mesh:
+        info = rsi.rsi_mesh_info_get(mesh)
+        assert info["n_triangles"] == nt and info["morton_bits"] == bits
+        keys = export(mesh, "sorted_keys").view(np.uint64)
+        assert np.array_equal(keys, want["sorted_keys"]), "sorted keys differ"
+        ids = export(mesh, "sorted_ids")
+        assert np.array_equal(ids, want["order"]), "sort order differs"
+
+        leaves = export(mesh, "leaves")
+        lf = leaves.view(np.float32)
+        order = want["order"].astype(np.int64)
+        A = V[F[order, 0]]
+        B = V[F[order, 1]]
+        C = V[F[order, 2]]
+        assert np.array_equal(lf[:, 0:3], A)
+        assert np.array_equal(leaves[:, 3], want["order"])
+        assert np.array_equal(lf[:, 4:7], B - A)
+        assert np.array_equal(lf[:, 8:11], C - A)
+
+        bounds = export(mesh, "bounds")
+        lo, hi = oracle.mesh_bounds(V)
+        assert np.array_equal(bounds[:3], lo) and np.array_equal(bounds[3:6], hi)
+        assert bounds[6] == np.max(np.abs(np.concatenate([lo, hi])))
+
+        if nt < 2:
+            assert info["root"] == -1
+            return
+        assert info["root"] == 0
+        words = export(mesh, "nodes")
+        lref, rref, lbox, rbox = decode_nodes(words)
+        t = want["tree"]
+        want_l = np.where(t["left_leaf"] == 1, ~t["left"], t["left"])
+        want_r = np.where(t["right_leaf"] == 1, ~t["right"], t["right"])
+        assert np.array_equal(lref, want_l), "left children differ"
+        assert np.array_equal(rref, want_r), "right children differ"
+
+        def child_boxes(idx, is_leaf):
+            return np.where(is_leaf[:, None] == 1, want["leaf_boxes"][idx], want["node_boxes"][np.minimum(idx, nt - 2)])
+
+        assert np.array_equal(lbox, child_boxes(t["left"], t["left_leaf"])), "left boxes differ"
+        assert np.array_equal(rbox, child_boxes(t["right"], t["right_leaf"])), "right boxes differ"
+
+        counters = export(mesh, "counters")
+        assert np.all(counters == 2), f"{np.sum(counters != 2)} internal nodes not completed"
+
+        parents = export(mesh, "parents")
+        want_par = np.full(2 * nt - 1, -7, np.int64)
+        want_par[0] = -1
+        for i in range(nt - 1):
+            for c, leaf in ((t["left"][i], t["left_leaf"][i]), (t["right"][i], t["right_leaf"][i])):
+                want_par[(nt - 1 + c) if leaf else c] = i
+        assert np.array_equal(parents, want_par)
+
+
+def test_case_study_1_scene_structure():
+    V, F, _, _ = workloads.appendix_scene()
+    for bits in (30, 63):
+        check_structure(V, F, bits)
+
+
+@pytest.mark.parametrize("n_tri", [1, 2, 3, 63, 64, 65, 1023, 1024, 1025, 2047, 2048, 2049, 29260])
+def test_soup_sizes(n_tri):
+    V, F = triangle_soup(n_tri, n_tri)
+    check_structure(V, F, 30)
+    check_structure(V, F, 63)
+
+
+@pytest.mark.parametrize("n_side", [2, 3, 33, 64, 128, 256])
+def test_heightfields(n_side):
+    V, F = workloads.heightfield(n_side, 100 + n_side)
+    check_structure(V, F, 30 if n_side % 2 == 0 else 63)
+
+
+def test_duplicate_keys_and_degenerate_triangles():
+    V, F = triangle_soup(5000, 3, n_vert=300, clustered=True)
+    F[::7, 1] = F[::7, 0]  # repeated index: zero-area triangle
+    check_structure(V, F, 30)
+    check_structure(V, F, 63)
+    # every triangle with the same centroid: all keys equal
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 1]], np.float32)
+    F = np.tile(np.array([[0, 1, 2]], np.int32), (777, 1))
+    check_structure(V, F, 30)
+
+
+def test_build_is_deterministic():
+    V, F = workloads.heightfield(96, 7)
+    outs = []
+    for _ in range(3):
+        with rsi.rsi_build(dev(V), dev(F)) as mesh:
+            outs.append([export(mesh, w).tobytes() for w in ("sorted_keys", "sorted_ids", "nodes", "parents",
+                                                              "counters", "leaves", "bounds")])
+    assert outs[0] == outs[1] == outs[2]
+
+
+def test_index_check_and_invalid_triangles():
+    V, F = workloads.heightfield(8, 1)
+    bad = F.copy()
+    bad[5, 2] = V.shape[0]  # one past the end
+    with pytest.raises(rsi.RSIError) as e:
+        rsi.rsi_build(dev(V), dev(bad), check_indices=True)
+    assert e.value.status == 2
+    bad[6, 0] = -3
+    with rsi.rsi_build(dev(V), dev(bad)) as mesh:  # unchecked: the bad triangles are never hit
+        counters = export(mesh, "counters")
+        assert np.all(counters == 2)
+
+
+def test_host_pointer_rejected():
+    import ctypes
+    V = np.zeros((3, 3), np.float32)
+    F = np.array([[0, 1, 2]], np.int32)
+    h = ctypes.c_void_p()
+    st = rsi.lib().rsi_build(V.ctypes.data_as(ctypes.c_void_p), 3, F.ctypes.data_as(ctypes.c_void_p), 1, None,
+                             None, ctypes.byref(h))
+    assert st == 1 and b"device pointer" in rsi.lib().rsi_last_error()
