@@ -41,11 +41,50 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB buffer 3 times (reference for the HBM byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of known size: 1 GiB read + 1 GiB written
+    per launch.  Its FETCH_SIZE / WRITE_SIZE readings scale the counters of
+    the other kernels to bytes."""
+    import torch
+
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": a.numel() * 4, "copy_bytes_written_per_launch": b.numel() * 4,
+                      "launches": 3}), flush=True)
+
+
+def measured_traffic(mode, precision):
+    """HBM bytes per traversal launch from the committed rocprofv3 counter
+    summary, or None when the traversal source changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(f"{mode}_{precision}")
+    if not rec:
+        return None
+    src = open(os.path.join(ROOT, "paper_2305_01867_amd", "csrc", "traverse.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["traverse_hip_sha256"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
               "the path shards by segments with the BVH replicated, and no multi-GPU run is part of this build",
@@ -129,7 +168,8 @@ def main():
     achieved_gbs = n * bytes_per_ray / (intersect_avg * 1e-3) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.mode, args.precision),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": "k_traverse (+ k_reset, k_finish in the same event pair)",
         "bytes_per_ray": round(bytes_per_ray, 1), "mean_node_visits": round(mean_visits, 2),
         "p50_node_visits": p50_visits, "p99_node_visits": p99_visits, "mean_leaf_tests": round(mean_tests, 2),
