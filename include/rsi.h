@@ -88,7 +88,7 @@ typedef struct rsi_build_opts {
 typedef struct rsi_intersect_opts {
     int32_t precision;    /* rsi_precision; default RSI_PRECISION_PLAIN */
     int32_t block;        /* threads per workgroup: 64, 128 or 256; 0 = 256 */
-    int32_t stack_depth;  /* traversal stack entries per lane in LDS, 1..64; 0 = 24.
+    int32_t stack_depth;  /* traversal stack entries per lane in LDS, 1..64; 0 = 20.
                              Deeper paths are finished exactly by a second pass. */
     int32_t ray_sort;     /* 0 = rays processed in input order (the only value so far) */
     int32_t proposal;     /* 0 = no learned proposal (the only value so far) */

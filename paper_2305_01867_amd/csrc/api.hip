@@ -97,7 +97,7 @@ bool valid_mesh(rsi_mesh m) { return m != nullptr && m->magic == kMagic; }
 rsi_status parse_intersect_opts(const rsi_intersect_opts *opts, int &precision, int &block, int &stack) {
     precision = RSI_PRECISION_PLAIN;
     block = 256;
-    stack = 24;
+    stack = 20;
     if (!opts)
         return RSI_OK;
     if (opts->precision != RSI_PRECISION_PLAIN && opts->precision != RSI_PRECISION_CERTIFIED)

@@ -51,8 +51,11 @@ __device__ __forceinline__ float widen_dir(float d, float dmin) {
 // Returns false for segments whose setup is not finite.
 __device__ __forceinline__ bool setup_ray(const float *__restrict__ from, const float *__restrict__ to,
                                           int64_t i, float scale, Ray &r) {
-    r.o = make_float3(from[3 * i], from[3 * i + 1], from[3 * i + 2]);
-    const float3 e = make_float3(to[3 * i], to[3 * i + 1], to[3 * i + 2]);
+    // streamed once: non-temporal, so the segments do not push the tree out of L2
+    r.o = make_float3(__builtin_nontemporal_load(from + 3 * i), __builtin_nontemporal_load(from + 3 * i + 1),
+                      __builtin_nontemporal_load(from + 3 * i + 2));
+    const float3 e = make_float3(__builtin_nontemporal_load(to + 3 * i), __builtin_nontemporal_load(to + 3 * i + 1),
+                                 __builtin_nontemporal_load(to + 3 * i + 2));
     r.d = make_float3(e.x - r.o.x, e.y - r.o.y, e.z - r.o.z);
     float m = fmaxf(scale, fmaxf(fmaxf(fabsf(r.o.x), fabsf(r.o.y)), fabsf(r.o.z)));
     m = fmaxf(m, fmaxf(fmaxf(fabsf(e.x), fabsf(e.y)), fabsf(e.z)));
@@ -230,6 +233,7 @@ struct TravParams {
     int stack_depth;
     int32_t *queue;
     uint32_t *queue_len;
+    uint32_t *next_ray;
     unsigned long long *counters;
     uint32_t *visits;
     uint32_t *tests;
@@ -242,165 +246,221 @@ __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why)
 }
 
 // ------------------------------------------------------------------ pass 1
+// Persistent waves.  Each wave owns a contiguous range of segments; a lane
+// whose segment is finished is refilled from that range while the others go
+// on, so a wave's time follows the mean cost of a segment instead of the
+// slowest of its 64 (no atomics: a shared counter across eight XCDs costs more
+// than the imbalance of ~1e3 segments per wave).  Leaf tests are postponed: a lane keeps one leaf
+// aside and continues with internal nodes; the leaf phase runs when half the
+// wave is waiting on a leaf, so the leaf code runs for many lanes at once.
+constexpr int kRefillMin = 8;     // refill when at least this many lanes idle
+constexpr int kDone = INT32_MIN;  // nothing left for the lane's segment
+
 template <int MODE, bool CERT, bool STATS>
 __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
     extern __shared__ int lds_stack[];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n)
-        return;
-    Ray r;
-    const bool ok = setup_ray(p.from, p.to, i, p.bounds[6], r);
-    if (!ok) {
-        if (STATS) {
-            p.visits[i] = 0;
-            p.tests[i] = 0;
-        } else if (CERT) {
-            enqueue(p, i, 0);
-        } else {
-            write_out(p.out, i, MODE, -1, 0.0f, 0.0f, 0.0f);
-        }
-        return;
-    }
-    const int stride = blockDim.x;
     int *stk = lds_stack + threadIdx.x;
-    int sp = 0;
-    int ref = p.root;
-    float tlimit = 1.0f;
-    bool found = false, unsure = false, flagged = false, overflow = false;
-    int best_id = -1, best_leaf = -1;
-    float best_t = INFINITY, best_lo = INFINITY, best_hi = INFINITY, best_u = 0.0f, best_v = 0.0f;
-    uint32_t n_nodes = 0, n_tests = 0;
-    // every node is reached at most once per segment; the bound only guards the loop
-    const int64_t max_steps = 2 * p.nt + 8;
+    const int stride = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const float scale = p.bounds[6];
     const int n_internal = (int)p.nt - 1;
+    const int64_t max_steps = 2 * p.nt + 8;
 
-    for (int64_t steps = 0;; ++steps) {
-        if (steps > max_steps || ref >= n_internal || ~ref >= p.nt) {
-            overflow = true;  // cannot happen for a well-formed tree
-            break;
-        }
-        if (ref >= 0) {
-            const Node *nd = p.nodes + ref;
-            const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
-            const int4 refs = nd->refs;
-            if (STATS)
-                ++n_nodes;
-            float tl, tr;
-            const bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, r, tlimit, tl);
-            const bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, r, tlimit, tr);
-            if (hl && hr) {
-                if (sp >= p.stack_depth) {
-                    overflow = true;
-                    break;
-                }
-                const bool left_first = tl <= tr;
-                stk[sp * stride] = left_first ? refs.y : refs.x;
-                ++sp;
-                ref = left_first ? refs.x : refs.y;
-                continue;
-            }
-            if (hl || hr) {
-                ref = hl ? refs.x : refs.y;
-                continue;
-            }
-        } else {
-            const int leaf = ~ref;
-            const Tri tri = p.tris[leaf];
-            if (STATS)
-                ++n_tests;
-            const MT32 m = mt32(tri, r);
-            const int id = __float_as_int(tri.a.w);
-            if (!CERT) {
-                if (decide32(m)) {
-                    if (MODE == MODE_BOOL) {
-                        found = true;
-                        break;
-                    }
-                    const float t = m.T / m.det;
-                    if (t < best_t || (t == best_t && id < best_id)) {
-                        best_t = t;
-                        best_id = id;
-                        best_leaf = leaf;
-                        if (MODE == MODE_BARY) {
-                            best_u = m.U / m.det;
-                            best_v = m.W / m.det;
+    // each wave owns a contiguous range of segments; its lanes draw from it
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    int64_t cursor = p.n * wave_id / waves;        // the same in every lane of the wave
+    const int64_t range_end = p.n * (wave_id + 1) / waves;
+
+    int64_t ray = -1;
+    Ray r;
+    int ref = kDone, pend = -1, sp = 0;
+    float tlimit = 1.0f;
+    int best_id = -1;
+    float best_t = INFINITY, best_lo = INFINITY, best_hi = INFINITY, best_u = 0.0f, best_v = 0.0f;
+    bool found = false, unsure = false, flagged = false, overflow = false;
+    uint32_t n_nodes = 0, n_tests = 0;
+    int64_t steps = 0;
+
+    auto pop = [&]() -> int { return sp > 0 ? stk[--sp * stride] : kDone; };
+
+    for (;;) {
+        // ---- refill idle lanes
+        const uint64_t idle = __ballot(ray < 0);
+        if (cursor < range_end && idle && (__popcll(idle) >= kRefillMin || idle == ~0ull)) {
+            const int cnt = __popcll(idle);
+            const int64_t base = cursor;
+            cursor = base + cnt < range_end ? base + cnt : range_end;
+            if (ray < 0) {
+                const int64_t idx = base + __popcll(idle & lt_mask);
+                if (idx < range_end) {
+                    ray = idx;
+                    ref = p.root;
+                    pend = -1;
+                    sp = 0;
+                    tlimit = 1.0f;
+                    best_id = -1;
+                    best_t = best_lo = best_hi = INFINITY;
+                    best_u = best_v = 0.0f;
+                    found = unsure = flagged = overflow = false;
+                    n_nodes = n_tests = 0;
+                    steps = 0;
+                    if (!setup_ray(p.from, p.to, ray, scale, r)) {
+                        if (STATS) {
+                            p.visits[ray] = 0;
+                            p.tests[ray] = 0;
+                        } else if (CERT) {
+                            enqueue(p, ray, 0);
+                        } else {
+                            write_out(p.out, ray, MODE, -1, 0.0f, 0.0f, 0.0f);
                         }
-                        tlimit = best_t;
+                        ray = -1;
                     }
                 }
-            } else {
-                float lo = 0.0f, hi = 0.0f;
-                const int c = classify(m, tri, r, lo, hi);
-                if (MODE == MODE_BOOL) {
-                    if (c == kHit) {
-                        found = true;
-                        break;
-                    }
-                    if (c == kUnsure)
-                        unsure = true;
+            }
+        }
+        const uint64_t active = __ballot(ray >= 0);
+        if (!active) {
+            if (cursor >= range_end)
+                break;
+            continue;
+        }
+
+        // ---- node phase
+        for (;;) {
+            if (ray >= 0 && pend < 0 && ref < 0 && ref != kDone) {
+                pend = ~ref;
+                ref = pop();
+            }
+            const bool want = ray >= 0 && ref >= 0;
+            const uint64_t w = __ballot(want);
+            if (!w)
+                break;
+            const uint64_t waiting = active & ~w;
+            if (2 * __popcll(waiting) > __popcll(active))
+                break;
+            if (want) {
+                if (++steps > max_steps || ref >= n_internal) {
+                    overflow = true;  // cannot happen for a well-formed tree
+                    ref = kDone;
+                    pend = -1;
                 } else {
-                    if (c == kUnsure) {
-                        flagged = true;
-                        break;
+                    const Node *nd = p.nodes + ref;
+                    const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
+                    const int4 refs = nd->refs;
+                    if (STATS)
+                        ++n_nodes;
+                    float tl, tr;
+                    const bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, r, tlimit, tl);
+                    const bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, r, tlimit, tr);
+                    if (hl && hr) {
+                        if (sp >= p.stack_depth) {
+                            overflow = true;
+                            ref = kDone;
+                            pend = -1;
+                        } else {
+                            const bool left_first = tl <= tr;
+                            stk[sp * stride] = left_first ? refs.y : refs.x;
+                            ++sp;
+                            ref = left_first ? refs.x : refs.y;
+                        }
+                    } else if (hl || hr) {
+                        ref = hl ? refs.x : refs.y;
+                    } else {
+                        ref = pop();
                     }
-                    if (c == kHit) {
+                }
+            }
+        }
+
+        // ---- leaf phase
+        if (ray >= 0 && pend >= 0) {
+            const int leaf = pend;
+            pend = -1;
+            if (leaf >= p.nt) {
+                overflow = true;  // cannot happen for a well-formed tree
+                ref = kDone;
+            } else {
+                const Tri tri = p.tris[leaf];
+                if (STATS)
+                    ++n_tests;
+                const MT32 m = mt32(tri, r);
+                const int id = __float_as_int(tri.a.w);
+                if (!CERT) {
+                    if (decide32(m)) {
+                        if (MODE == MODE_BOOL) {
+                            found = true;
+                            ref = kDone;
+                        } else {
+                            const float t = m.T / m.det;
+                            if (t < best_t || (t == best_t && id < best_id)) {
+                                best_t = t;
+                                best_id = id;
+                                if (MODE == MODE_BARY) {
+                                    best_u = m.U / m.det;
+                                    best_v = m.W / m.det;
+                                }
+                                tlimit = best_t;
+                            }
+                        }
+                    }
+                } else {
+                    float lo = 0.0f, hi = 0.0f;
+                    const int c = classify(m, tri, r, lo, hi);
+                    if (MODE == MODE_BOOL) {
+                        if (c == kHit) {
+                            found = true;
+                            ref = kDone;
+                        } else if (c == kUnsure) {
+                            unsure = true;
+                        }
+                    } else if (c == kUnsure) {
+                        flagged = true;
+                        ref = kDone;
+                    } else if (c == kHit) {
                         if (best_id < 0 || hi < best_lo) {
                             best_lo = lo;
                             best_hi = hi;
                             best_id = id;
-                            best_leaf = leaf;
                             tlimit = fminf(tlimit, hi * (1.0f + 0x1p-20f));
                         } else if (!(lo > best_hi)) {
                             flagged = true;  // intervals overlap: order not certain
-                            break;
+                            ref = kDone;
                         }
                     }
                 }
             }
         }
-        if (sp == 0)
-            break;
-        --sp;
-        ref = stk[sp * stride];
-    }
 
-    if (STATS) {
-        p.visits[i] = n_nodes;
-        p.tests[i] = n_tests;
-        return;
-    }
-    if (MODE == MODE_BOOL) {
-        if (found) {
-            p.out.hit[i] = 1;
-            return;
+        // ---- finish lanes whose segment is decided
+        if (ray >= 0 && ref == kDone && pend < 0) {
+            if (STATS) {
+                p.visits[ray] = n_nodes;
+                p.tests[ray] = n_tests;
+            } else if (MODE == MODE_BOOL) {
+                if (found)
+                    p.out.hit[ray] = 1;
+                else if (overflow)
+                    enqueue(p, ray, 1);
+                else if (CERT && unsure)
+                    enqueue(p, ray, 0);
+                else
+                    p.out.hit[ray] = 0;
+            } else if (overflow) {
+                enqueue(p, ray, 1);
+            } else if (CERT && flagged) {
+                enqueue(p, ray, 0);
+            } else if (CERT && MODE == MODE_BARY && best_id >= 0) {
+                const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
+                const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, best_id);
+                write_out(p.out, ray, MODE, best_id, (float)h.u, (float)h.v, (float)h.t);
+            } else {
+                write_out(p.out, ray, MODE, best_id, best_u, best_v, best_t);
+            }
+            ray = -1;
         }
-        if (overflow) {
-            enqueue(p, i, 1);
-            return;
-        }
-        if (CERT && unsure) {
-            enqueue(p, i, 0);
-            return;
-        }
-        p.out.hit[i] = 0;
-        return;
     }
-    if (overflow) {
-        enqueue(p, i, 1);
-        return;
-    }
-    if (CERT && flagged) {
-        enqueue(p, i, 0);
-        return;
-    }
-    if (CERT && MODE == MODE_BARY && best_id >= 0) {
-        const float *o = p.from + 3 * i, *e = p.to + 3 * i;
-        const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, best_id);
-        write_out(p.out, i, MODE, best_id, (float)h.u, (float)h.v, (float)h.t);
-        return;
-    }
-    (void)best_leaf;
-    write_out(p.out, i, MODE, best_id, best_u, best_v, best_t);
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -514,8 +574,8 @@ __global__ __launch_bounds__(64) void k_finish(TravParams p) {
 }
 
 __global__ void k_reset(uint32_t *queue_len, unsigned long long *counters) {
-    if (threadIdx.x == 0)
-        queue_len[0] = 0;
+    if (threadIdx.x < 2)
+        queue_len[threadIdx.x] = 0;  // queue length, next segment of pass 1
     if (threadIdx.x < 4)
         counters[threadIdx.x] = 0;
 }
@@ -528,8 +588,17 @@ __global__ void k_fill_miss(Outs out, int64_t n, int mode) {
 
 template <int MODE, bool CERT, bool STATS>
 void launch_pass1(const TravParams &p, int block, hipStream_t s) {
-    const int grid = (int)((p.n + block - 1) / block);
     const size_t lds = (size_t)p.stack_depth * block * sizeof(int);
+    int dev = 0, cus = 256, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_traverse<MODE, CERT, STATS>),
+                                                       block, lds);
+    if (per_cu < 1)
+        per_cu = 1;
+    const int64_t want = (p.n + block - 1) / block;
+    const int64_t resident = (int64_t)cus * per_cu;
+    const int grid = (int)(want < resident ? want : resident);
     k_traverse<MODE, CERT, STATS><<<grid, block, lds, s>>>(p);
 }
 
@@ -560,6 +629,7 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.stack_depth = a.stack;
     p.queue = a.queue;
     p.queue_len = a.queue_len;
+    p.next_ray = a.queue_len + 1;
     p.counters = reinterpret_cast<unsigned long long *>(a.counters);
     p.visits = a.visits;
     p.tests = a.tests;
@@ -591,8 +661,9 @@ hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t
 
 hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s) {
     TravParams p = make_params(m, a);
+    k_reset<<<1, 64, 0, s>>>(a.queue_len, p.counters);
     if (m.nt == 0 || a.n == 0)
-        return hipSuccess;
+        return hipGetLastError();
     dispatch_pass1<true>(p, a.mode, a.certified != 0, a.block, s);
     return hipGetLastError();
 }
