@@ -464,11 +464,17 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
 }
 
 // ------------------------------------------------------------------ pass 2
-// Segments from the queue, one per lane, with a private stack deep enough for
-// any radix tree.  CERTIFIED: binary64 decides every candidate; a segment whose
-// binary32 setup is not finite is tested against every triangle.
+// Segments from the queue, one per lane, with an LDS stack deep enough for any
+// radix tree (128 entries).  CERTIFIED: a candidate the binary32 bound already
+// proves a miss is skipped; every other candidate is decided in binary64 in
+// the oracle's operation order.  A segment whose binary32 setup is not finite
+// is tested against every triangle.
+constexpr int kFinishThreads = 64;
+
 template <int MODE, bool CERT>
-__global__ __launch_bounds__(64) void k_finish(TravParams p) {
+__global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
+    __shared__ int deep[kDeepStack * kFinishThreads];
+    int *stk = deep + threadIdx.x;
     const uint32_t count = *p.queue_len;
     for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < count; qi += gridDim.x * blockDim.x) {
         const int64_t i = p.queue[qi];
@@ -485,42 +491,42 @@ __global__ __launch_bounds__(64) void k_finish(TravParams p) {
         auto test_leaf = [&](int leaf) {
             const Tri tri = p.tris[leaf];
             const int id = __float_as_int(tri.a.w);
+            const MT32 m = mt32(tri, r);
             if (CERT) {
+                float lo, hi;
+                if (classify(m, tri, r, lo, hi) == kMiss)
+                    return;  // the bound proves the binary64 test misses too
                 MT64 h{false, 0.0, 0.0, 0.0};
                 if (valid_tri(p.F, p.nv, id))
                     h = mt64(ox, oy, oz, ex, ey, ez, p.V, p.F, id);
                 if (h.hit) {
-                    const double u = h.u, v = h.v, t = h.t;
                     if (MODE == MODE_BOOL) {
                         best_id = id;
                         done = true;
                         return;
                     }
-                    if (best_id < 0 || t < bt || (t == bt && id < best_id)) {
+                    if (best_id < 0 || h.t < bt || (h.t == bt && id < best_id)) {
                         best_id = id;
-                        bu = u;
-                        bv = v;
-                        bt = t;
+                        bu = h.u;
+                        bv = h.v;
+                        bt = h.t;
                         // round up, then widen: no box holding a hit at t <= bt is culled
-                        tlimit = fminf(tlimit, __double2float_ru(t) * (1.0f + 0x1p-20f));
+                        tlimit = fminf(tlimit, __double2float_ru(h.t) * (1.0f + 0x1p-20f));
                     }
                 }
-            } else {
-                const MT32 m = mt32(tri, r);
-                if (decide32(m)) {
-                    if (MODE == MODE_BOOL) {
-                        best_id = id;
-                        done = true;
-                        return;
-                    }
-                    const float t = m.T / m.det;
-                    if (t < best_t32 || (t == best_t32 && id < best_id)) {
-                        best_t32 = t;
-                        best_id = id;
-                        bu32 = m.U / m.det;
-                        bv32 = m.W / m.det;
-                        tlimit = t;
-                    }
+            } else if (decide32(m)) {
+                if (MODE == MODE_BOOL) {
+                    best_id = id;
+                    done = true;
+                    return;
+                }
+                const float t = m.T / m.det;
+                if (t < best_t32 || (t == best_t32 && id < best_id)) {
+                    best_t32 = t;
+                    best_id = id;
+                    bu32 = m.U / m.det;
+                    bv32 = m.W / m.det;
+                    tlimit = t;
                 }
             }
         };
@@ -532,7 +538,6 @@ __global__ __launch_bounds__(64) void k_finish(TravParams p) {
                     test_leaf((int)leaf);
             }
         } else {
-            int stack[kDeepStack];
             int sp = 0;
             int ref = p.root;
             const int64_t max_steps = 2 * p.nt + 8;
@@ -548,7 +553,7 @@ __global__ __launch_bounds__(64) void k_finish(TravParams p) {
                     if (hl && hr) {
                         const bool left_first = tl <= tr;
                         if (sp < kDeepStack)
-                            stack[sp++] = left_first ? refs.y : refs.x;
+                            stk[(sp++) * kFinishThreads] = left_first ? refs.y : refs.x;
                         ref = left_first ? refs.x : refs.y;
                         continue;
                     }
@@ -563,7 +568,7 @@ __global__ __launch_bounds__(64) void k_finish(TravParams p) {
                 }
                 if (sp == 0)
                     break;
-                ref = stack[--sp];
+                ref = stk[(--sp) * kFinishThreads];
             }
         }
         if (CERT)
@@ -648,14 +653,14 @@ hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t
         return hipGetLastError();
     }
     dispatch_pass1<false>(p, a.mode, a.certified != 0, a.block, s);
-    const int64_t want = (a.n + 63) / 64;
-    const int grid2 = (int)(want < 4096 ? want : 4096);
+    const int64_t want = (a.n + kFinishThreads - 1) / kFinishThreads;
+    const int grid2 = (int)(want < 1024 ? want : 1024);
     if (a.mode == MODE_BOOL)
-        a.certified ? k_finish<MODE_BOOL, true><<<grid2, 64, 0, s>>>(p) : k_finish<MODE_BOOL, false><<<grid2, 64, 0, s>>>(p);
+        a.certified ? k_finish<MODE_BOOL, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_BOOL, false><<<grid2, kFinishThreads, 0, s>>>(p);
     else if (a.mode == MODE_FIRST)
-        a.certified ? k_finish<MODE_FIRST, true><<<grid2, 64, 0, s>>>(p) : k_finish<MODE_FIRST, false><<<grid2, 64, 0, s>>>(p);
+        a.certified ? k_finish<MODE_FIRST, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_FIRST, false><<<grid2, kFinishThreads, 0, s>>>(p);
     else
-        a.certified ? k_finish<MODE_BARY, true><<<grid2, 64, 0, s>>>(p) : k_finish<MODE_BARY, false><<<grid2, 64, 0, s>>>(p);
+        a.certified ? k_finish<MODE_BARY, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_BARY, false><<<grid2, kFinishThreads, 0, s>>>(p);
     return hipGetLastError();
 }
 
