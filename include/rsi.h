@@ -91,7 +91,8 @@ typedef struct rsi_intersect_opts {
     int32_t stack_depth;  /* traversal stack entries per lane in LDS, 1..64; 0 = 20.
                              Deeper paths are finished exactly by a second pass. */
     int32_t ray_sort;     /* 0 = rays processed in input order (the only value so far) */
-    int32_t proposal;     /* 0 = no learned proposal (the only value so far) */
+    int32_t proposal;     /* 1 = visit the learned proposal's bucket first (needs a
+                             trained or loaded proposal); 0 = plain order */
 } rsi_intersect_opts;
 
 /* Output buffers (device pointers, caller-owned).  Required per mode:
@@ -106,8 +107,9 @@ typedef struct rsi_outputs {
                            and t of that hit, rounded from binary64 in CERTIFIED
                            precision; NaN on a miss */
     uint64_t *counters; /* optional [4]: [0] segments re-decided in binary64, [1] segments
-                           that outgrew the LDS stack, [2], [3] reserved (0).  Zeroed by
-                           the call before it counts. */
+                           that outgrew the LDS stack, [2] hitting segments whose answer
+                           was not in the proposed bucket (proposal misses), [3] reserved
+                           (0).  Zeroed by the call before it counts. */
 } rsi_outputs;
 
 /*
@@ -203,6 +205,76 @@ rsi_status rsi_mesh_export(rsi_mesh mesh, int32_t what, void *dst, int64_t dst_b
 rsi_status rsi_traversal_stats(rsi_mesh mesh, const float *rays_from, const float *rays_to,
                                int64_t n_rays, int32_t mode, const rsi_intersect_opts *opts,
                                uint32_t *node_visits, uint32_t *leaf_tests, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned subtree proposal.  A small MLP predicts, per segment, the depth-8
+ * subtree ("bucket") of the tree that holds its first hit; rsi_intersect with
+ * opts->proposal = 1 traverses that subtree first (and, in boolean mode, stops
+ * at a sure hit there), then the rest of the tree without it.  The exact
+ * traversal and test decide every result, so results are identical to
+ * proposal = 0; only the amount of work changes.
+ * Network: inputs = the 6 end-point coordinates normalised to [-1, 1] over the
+ * mesh box and sin/cos(pi f_k x) of each for f_k = 2^(k/2), k = 0..15 (198,
+ * padded to 224); three hidden layers of 256 with ReLU; 256 logits, one per
+ * frontier bucket (buckets past the frontier's size are masked).  bf16 weights
+ * and activations, fp32 accumulation on the matrix cores, fp32 master weights
+ * and Adam for training.  Parameters are one fp32 vector of RSI_MLP_PARAMS:
+ * W1 [256][224], W2, W3, W4 [256][256] (row = output unit), then b1..b4 [256].
+ * All proposal calls need a mesh with at least one triangle.
+ * ---------------------------------------------------------------------- */
+#define RSI_MLP_PARAMS 254976
+#define RSI_MLP_INPUTS 224
+#define RSI_MLP_BUCKETS 256
+
+typedef struct rsi_train_opts {
+    int32_t epochs;   /* passes over the labelled segments; 0 = 2 */
+    int32_t batch;    /* segments per Adam step, 64..65536; 0 = 4096 */
+    float lr;         /* Adam learning rate; 0 = 1e-3 */
+    int32_t reinit;   /* nonzero: draw fresh initial weights even if trained */
+    uint64_t seed;    /* initial-weight seed */
+} rsi_train_opts;
+
+/* Train on segments the method labels itself: a CERTIFIED first-hit pass over
+ * (from, to) gives each hitting segment's triangle, hence its bucket; then
+ * `epochs` passes of minibatch Adam on cross-entropy.  epoch_loss (device
+ * float [epochs], may be NULL) receives the mean loss of each epoch;
+ * *n_labelled (host, may be NULL) the number of hitting segments used.
+ * Waits for the stream (the label count sets the batch schedule). */
+rsi_status rsi_proposal_train(rsi_mesh mesh, const float *rays_from, const float *rays_to, int64_t n_rays,
+                              const rsi_train_opts *opts, float *epoch_loss, int64_t *n_labelled, void *stream);
+
+/* Bucket per segment (device uint8 [n_rays]) from the fused inference kernel. */
+rsi_status rsi_proposal_predict(rsi_mesh mesh, const float *rays_from, const float *rays_to, int64_t n_rays,
+                                uint8_t *bucket, void *stream);
+
+/* what = 0: copy the fp32 parameters to buf; what = 1: replace them with buf
+ * (bf16 copies refreshed, Adam state reset).  buf: device float [RSI_MLP_PARAMS]. */
+rsi_status rsi_proposal_params(rsi_mesh mesh, int32_t what, float *buf, void *stream);
+
+/* One minibatch without an update, for checking the kernels: segments
+ * (from, to) [n_rays <= 65536] with labels (device int32 [n_rays], bucket
+ * index).  Writes the gradient of the mean cross-entropy (device float
+ * [RSI_MLP_PARAMS]), the logits (device float [n_rays][256]) and the mean loss
+ * (device float [1]). */
+rsi_status rsi_proposal_gradient(rsi_mesh mesh, const float *rays_from, const float *rays_to,
+                                 const int32_t *labels, int64_t n_rays, float *grad, float *logits, float *loss,
+                                 void *stream);
+
+/* The network inputs of each segment: device bf16 bit patterns [n_rays][224]. */
+rsi_status rsi_proposal_features(rsi_mesh mesh, const float *rays_from, const float *rays_to, int64_t n_rays,
+                                 uint16_t *features, void *stream);
+
+/* The frontier: node reference of each bucket (>= 0 internal node, < 0 leaf
+ * ~k), first sorted leaf of each bucket (device int32 [256] each, unused
+ * entries untouched), and the bucket count (host). */
+rsi_status rsi_proposal_frontier(rsi_mesh mesh, int32_t *bucket_ref, int32_t *bucket_first, int32_t *n_buckets,
+                                 void *stream);
+
+/* Save / load the parameters and Adam state (raw little-endian binary with a
+ * header: magic, layer sizes, parameter count, step, triangle count, bucket
+ * count).  Loading checks the header against this mesh.  Both wait. */
+rsi_status rsi_proposal_save(rsi_mesh mesh, const char *path);
+rsi_status rsi_proposal_load(rsi_mesh mesh, const char *path);
 
 const char *rsi_status_string(rsi_status status);
 const char *rsi_last_error(void);   /* message of this thread's last failure, "" if none */

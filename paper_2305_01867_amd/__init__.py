@@ -8,7 +8,8 @@ Every step of the computation runs in the library's HIP kernels; this module
 has no CPU fallback and raises if the library is not built.
 
 Names follow the C ABI: rsi_build, rsi_intersect, rsi_destroy,
-rsi_mesh_info_get, rsi_mesh_export, rsi_traversal_stats.
+rsi_mesh_info_get, rsi_mesh_export, rsi_traversal_stats and the
+rsi_proposal_* calls of the learned subtree proposal.
 """
 from __future__ import annotations
 
@@ -20,6 +21,9 @@ import torch  # imported first so the library binds to the HIP runtime torch loa
 __all__ = [
     "RSIError", "Mesh", "lib", "library_path", "rsi_build", "rsi_intersect", "rsi_destroy",
     "rsi_mesh_info_get", "rsi_mesh_export", "rsi_traversal_stats", "MODES", "PRECISIONS",
+    "rsi_proposal_train", "rsi_proposal_predict", "rsi_proposal_params", "rsi_proposal_gradient",
+    "rsi_proposal_features", "rsi_proposal_frontier", "rsi_proposal_save", "rsi_proposal_load",
+    "MLP_PARAMS", "MLP_INPUTS", "MLP_BUCKETS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -52,6 +56,16 @@ class _Outputs(ctypes.Structure):
                 ("counters", ctypes.c_void_p)]
 
 
+class _TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("reinit", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+MLP_PARAMS = 254976
+MLP_INPUTS = 224
+MLP_BUCKETS = 256
+
+
 class _MeshInfo(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64), ("morton_bits", ctypes.c_int32),
                 ("root", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
@@ -76,8 +90,18 @@ def lib():
     L.rsi_mesh_info_get.argtypes = [P, ctypes.POINTER(_MeshInfo)]
     L.rsi_mesh_export.argtypes = [P, I32, P, I64, P]
     L.rsi_traversal_stats.argtypes = [P, P, P, I64, I32, ctypes.POINTER(_IntersectOpts), P, P, P]
+    L.rsi_proposal_train.argtypes = [P, P, P, I64, ctypes.POINTER(_TrainOpts), P, ctypes.POINTER(I64), P]
+    L.rsi_proposal_predict.argtypes = [P, P, P, I64, P, P]
+    L.rsi_proposal_params.argtypes = [P, I32, P, P]
+    L.rsi_proposal_gradient.argtypes = [P, P, P, P, I64, P, P, P, P]
+    L.rsi_proposal_features.argtypes = [P, P, P, I64, P, P]
+    L.rsi_proposal_frontier.argtypes = [P, P, P, ctypes.POINTER(I32), P]
+    L.rsi_proposal_save.argtypes = [P, ctypes.c_char_p]
+    L.rsi_proposal_load.argtypes = [P, ctypes.c_char_p]
     for f in ("rsi_build", "rsi_intersect", "rsi_destroy", "rsi_mesh_info_get", "rsi_mesh_export",
-              "rsi_traversal_stats"):
+              "rsi_traversal_stats", "rsi_proposal_train", "rsi_proposal_predict", "rsi_proposal_params",
+              "rsi_proposal_gradient", "rsi_proposal_features", "rsi_proposal_frontier", "rsi_proposal_save",
+              "rsi_proposal_load"):
         getattr(L, f).restype = ctypes.c_int
     L.rsi_status_string.argtypes = [ctypes.c_int]
     L.rsi_status_string.restype = ctypes.c_char_p
@@ -171,15 +195,15 @@ def rsi_destroy(mesh: Mesh):
     mesh.close()
 
 
-def _iopts(precision, block, stack_depth):
+def _iopts(precision, block, stack_depth, proposal=False):
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")
-    return _IntersectOpts(PRECISIONS[precision], int(block), int(stack_depth), 0, 0)
+    return _IntersectOpts(PRECISIONS[precision], int(block), int(stack_depth), 0, int(bool(proposal)))
 
 
 def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
                   precision: str = "plain", block: int = 0, stack_depth: int = 0, out: dict | None = None,
-                  stream=None) -> dict:
+                  stream=None, proposal: bool = False) -> dict:
     """Test segments [N, 3] float32 against the mesh.  Returns a dict with the
     outputs of the mode ("hit" uint8, "tri_id" int32, "uvt" float32 [N, 3]) and
     "counters" uint64 [4] (re-decided in binary64, past the LDS stack, 0, 0).
@@ -215,7 +239,7 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
         return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()
 
     o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"))
-    opts = _iopts(precision, block, stack_depth)
+    opts = _iopts(precision, block, stack_depth, proposal)
     _check(lib().rsi_intersect(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
                                ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
                                ctypes.byref(o), _stream_handle(stream)))
@@ -223,14 +247,15 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
 
 
 def rsi_traversal_stats(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
-                        precision: str = "plain", block: int = 0, stack_depth: int = 0, stream=None):
+                        precision: str = "plain", block: int = 0, stack_depth: int = 0, stream=None,
+                        proposal: bool = False):
     """Per-segment (node visits, leaf tests) of the traversal, uint32 -> int64 tensors."""
     _need(rays_from, "rays_from", torch.float32, 3)
     _need(rays_to, "rays_to", torch.float32, 3)
     n = rays_from.shape[0]
     visits = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
     tests = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
-    opts = _iopts(precision, block, stack_depth)
+    opts = _iopts(precision, block, stack_depth, proposal)
     _check(lib().rsi_traversal_stats(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
                                      ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
                                      ctypes.c_void_p(visits.data_ptr()), ctypes.c_void_p(tests.data_ptr()),
@@ -260,3 +285,90 @@ def rsi_mesh_export(mesh: Mesh, what: str, stream=None) -> torch.Tensor:
     _check(lib().rsi_mesh_export(mesh.handle, EXPORTS[what], ctypes.c_void_p(dst.data_ptr()),
                                  dst.numel() * dst.element_size(), _stream_handle(stream)))
     return dst
+
+
+# --------------------------------------------------------------- learned proposal
+def _rays(rays_from, rays_to):
+    _need(rays_from, "rays_from", torch.float32, 3)
+    _need(rays_to, "rays_to", torch.float32, 3)
+    if rays_from.shape != rays_to.shape:
+        raise ValueError("rays_from and rays_to must have the same shape")
+    return rays_from.shape[0]
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def rsi_proposal_train(mesh: Mesh, rays_from, rays_to, epochs: int = 2, batch: int = 4096, lr: float = 1e-3,
+                       seed: int = 1, reinit: bool = False, stream=None):
+    """Train the proposal on segments labelled by the exact first-hit pass.
+    Returns (mean loss per epoch as a CPU tensor, number of labelled segments)."""
+    n = _rays(rays_from, rays_to)
+    loss = torch.zeros(max(int(epochs), 1), dtype=torch.float32, device=rays_from.device)
+    nl = ctypes.c_int64(0)
+    opts = _TrainOpts(int(epochs), int(batch), float(lr), int(bool(reinit)), int(seed))
+    _check(lib().rsi_proposal_train(mesh.handle, _p(rays_from), _p(rays_to), n, ctypes.byref(opts), _p(loss),
+                                    ctypes.byref(nl), _stream_handle(stream)))
+    torch.cuda.synchronize()
+    return loss.cpu(), int(nl.value)
+
+
+def rsi_proposal_predict(mesh: Mesh, rays_from, rays_to, stream=None) -> torch.Tensor:
+    n = _rays(rays_from, rays_to)
+    out = torch.empty(n, dtype=torch.uint8, device=rays_from.device)
+    _check(lib().rsi_proposal_predict(mesh.handle, _p(rays_from), _p(rays_to), n, _p(out), _stream_handle(stream)))
+    return out
+
+
+def rsi_proposal_params(mesh: Mesh, new: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Get (new=None) or set the fp32 parameter vector [MLP_PARAMS]."""
+    if new is None:
+        buf = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        _check(lib().rsi_proposal_params(mesh.handle, 0, _p(buf), _stream_handle(stream)))
+        return buf
+    _need(new, "params", torch.float32)
+    if new.numel() != MLP_PARAMS:
+        raise ValueError(f"params must have {MLP_PARAMS} entries")
+    _check(lib().rsi_proposal_params(mesh.handle, 1, _p(new), _stream_handle(stream)))
+    return new
+
+
+def rsi_proposal_gradient(mesh: Mesh, rays_from, rays_to, labels: torch.Tensor, stream=None):
+    """(gradient [MLP_PARAMS], logits [n, 256], mean loss [1]) of one batch."""
+    n = _rays(rays_from, rays_to)
+    _need(labels, "labels", torch.int32)
+    if labels.numel() != n:
+        raise ValueError("one label per segment")
+    dev = rays_from.device
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=dev)
+    logits = torch.empty((n, MLP_BUCKETS), dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    _check(lib().rsi_proposal_gradient(mesh.handle, _p(rays_from), _p(rays_to), _p(labels), n, _p(grad), _p(logits),
+                                       _p(loss), _stream_handle(stream)))
+    return grad, logits, loss
+
+
+def rsi_proposal_features(mesh: Mesh, rays_from, rays_to, stream=None) -> torch.Tensor:
+    """Network inputs [n, 224] as bfloat16."""
+    n = _rays(rays_from, rays_to)
+    X = torch.empty((n, MLP_INPUTS), dtype=torch.int16, device=rays_from.device)
+    _check(lib().rsi_proposal_features(mesh.handle, _p(rays_from), _p(rays_to), n, _p(X), _stream_handle(stream)))
+    return X.view(torch.bfloat16)
+
+
+def rsi_proposal_frontier(mesh: Mesh, stream=None):
+    """(bucket node references [nb], first sorted leaf of each bucket [nb])."""
+    ref = torch.zeros(MLP_BUCKETS, dtype=torch.int32, device="cuda")
+    first = torch.zeros(MLP_BUCKETS, dtype=torch.int32, device="cuda")
+    nb = ctypes.c_int32(0)
+    _check(lib().rsi_proposal_frontier(mesh.handle, _p(ref), _p(first), ctypes.byref(nb), _stream_handle(stream)))
+    return ref[: nb.value], first[: nb.value]
+
+
+def rsi_proposal_save(mesh: Mesh, path: str):
+    _check(lib().rsi_proposal_save(mesh.handle, os.fsencode(path)))
+
+
+def rsi_proposal_load(mesh: Mesh, path: str):
+    _check(lib().rsi_proposal_load(mesh.handle, os.fsencode(path)))

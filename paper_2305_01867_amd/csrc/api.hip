@@ -115,8 +115,8 @@ rsi_status parse_intersect_opts(const rsi_intersect_opts *opts, int &precision, 
     }
     if (opts->ray_sort != 0)
         return fail(RSI_E_ARG, "ray_sort: only 0 (input order) is available");
-    if (opts->proposal != 0)
-        return fail(RSI_E_ARG, "proposal: only 0 (none) is available");
+    if (opts->proposal != 0 && opts->proposal != 1)
+        return fail(RSI_E_ARG, "proposal must be 0 or 1");
     return RSI_OK;
 }
 
@@ -273,8 +273,13 @@ rsi_status rsi_destroy(rsi_mesh mesh) {
         return fail(RSI_E_STATE, "invalid or destroyed mesh handle");
     mesh->magic = kDead;
     hipError_t e = hipSuccess;
-    if (mesh->block)
-        e = hipFreeAsync(mesh->block, mesh->stream);
+    if (mesh->dev.prop.block)
+        e = hipFreeAsync(mesh->dev.prop.block, mesh->stream);
+    if (mesh->block) {
+        hipError_t e2 = hipFreeAsync(mesh->block, mesh->stream);
+        if (e == hipSuccess)
+            e = e2;
+    }
     delete mesh;
     if (e != hipSuccess)
         return fail_hip(e, "rsi_destroy");
@@ -291,6 +296,9 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     int precision, block, stack;
     if ((st = parse_intersect_opts(opts, precision, block, stack)) != RSI_OK)
         return st;
+    const bool use_prop = opts && opts->proposal == 1 && n > 0 && mesh->dev.nt > 0;
+    if (use_prop && !mesh->dev.prop.ready)
+        return fail(RSI_E_STATE, "proposal = 1 needs a trained or loaded proposal (rsi_proposal_train / _load)");
     if (!stats) {
         if (!out)
             return fail(RSI_E_ARG, "out must not be NULL");
@@ -334,7 +342,7 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *ws = nullptr;
-    const size_t ws_bytes = 4 * (size_t)n + 64;
+    const size_t ws_bytes = 4 * (size_t)n + 64 + (use_prop ? (size_t)n + 256 : 0);
     hipError_t e = hipMallocAsync(&ws, ws_bytes, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -352,6 +360,16 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     uint64_t *ws_counters = reinterpret_cast<uint64_t *>(static_cast<char *>(ws));
     a.queue_len = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + 32);
     a.queue = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + 64);
+    if (use_prop) {
+        uint8_t *bucket = static_cast<uint8_t *>(ws) + 64 + 4 * (size_t)n;
+        e = rsi::proposal_predict(mesh->dev, mesh->dev.prop, from, to, n, mesh->dev.prop.n_buckets, bucket, s);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(ws, s);
+            return fail_hip(e, "proposal inference");
+        }
+        a.bucket = bucket;
+        a.bucket_ref = mesh->dev.prop.bucket_ref;
+    }
     if (stats) {
         a.visits = visits;
         a.tests = tests;
@@ -451,6 +469,362 @@ rsi_status rsi_mesh_export(rsi_mesh mesh, int32_t what, void *dst, int64_t dst_b
         e = hipStreamSynchronize(s);
     if (e != hipSuccess)
         return fail_hip(e, "rsi_mesh_export");
+    return RSI_OK;
+}
+
+// ------------------------------------------------------------------ proposal
+static rsi_status ensure_proposal(rsi_mesh mesh, hipStream_t s, uint64_t seed, bool reinit) {
+    rsi::MeshDev &d = mesh->dev;
+    rsi::Proposal &pr = d.prop;
+    if (d.nt < 1)
+        return fail(RSI_E_STATE, "the proposal needs a mesh with at least one triangle");
+    if (!pr.block) {
+        const size_t f = round_up(4 * (size_t)rsi::kMlpParams);
+        const size_t wb = round_up(2 * (size_t)rsi::kMlpWeights);
+        const size_t small = round_up(4 * 256) * 2 + 256;
+        const size_t rk = round_up(4 * (size_t)d.nt);
+        hipError_t e = hipMallocAsync(&pr.block, 4 * f + wb + small + rk, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            pr.block = nullptr;
+            return fail(RSI_E_NOMEM, std::string("proposal allocation: ") + hipGetErrorString(e));
+        }
+        char *p = static_cast<char *>(pr.block);
+        pr.P = reinterpret_cast<float *>(p); p += f;
+        pr.G = reinterpret_cast<float *>(p); p += f;
+        pr.m1 = reinterpret_cast<float *>(p); p += f;
+        pr.m2 = reinterpret_cast<float *>(p); p += f;
+        pr.Wb = reinterpret_cast<__bf16 *>(p); p += wb;
+        pr.bucket_ref = reinterpret_cast<int32_t *>(p); p += round_up(4 * 256);
+        pr.bucket_first = reinterpret_cast<int32_t *>(p); p += round_up(4 * 256);
+        pr.dev_n_buckets = reinterpret_cast<int32_t *>(p); p += 256;
+        pr.rank = reinterpret_cast<int32_t *>(p);
+        e = rsi::proposal_frontier(d, pr, s);
+        int32_t nb = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&nb, pr.dev_n_buckets, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return fail_hip(e, "proposal frontier");
+        pr.n_buckets = nb;
+    }
+    if (!pr.ready || reinit) {
+        hipError_t e = rsi::proposal_init(pr, seed, s);
+        if (e != hipSuccess)
+            return fail_hip(e, "proposal init");
+        pr.ready = true;
+        pr.step = 0;
+    }
+    return RSI_OK;
+}
+
+static rsi_status prop_args(rsi_mesh mesh, const float *from, const float *to, int64_t n) {
+    if (!valid_mesh(mesh))
+        return fail(RSI_E_STATE, "invalid or destroyed mesh handle");
+    if (mesh->dev.nt < 1)
+        return fail(RSI_E_STATE, "the proposal needs a mesh with at least one triangle");
+    if (n < 0)
+        return fail(RSI_E_ARG, "n_rays must be >= 0");
+    if (n >= (int64_t(1) << 31))
+        return fail(RSI_E_CAPACITY, "n_rays must be < 2^31");
+    if (n > 0 && (!from || !to || !aligned4(from) || !aligned4(to)))
+        return fail(RSI_E_ARG, "rays_from / rays_to must be non-NULL and 4-byte aligned");
+    rsi_status st = check_device();
+    if (st != RSI_OK)
+        return st;
+    if (n > 0 && ((st = check_dev_ptr(from, "rays_from")) != RSI_OK || (st = check_dev_ptr(to, "rays_to")) != RSI_OK))
+        return st;
+    return pending_error("before a proposal call");
+}
+
+rsi_status rsi_proposal_train(rsi_mesh mesh, const float *rays_from, const float *rays_to, int64_t n_rays,
+                              const rsi_train_opts *opts, float *epoch_loss, int64_t *n_labelled, void *stream) {
+    g_error.clear();
+    rsi_status st = prop_args(mesh, rays_from, rays_to, n_rays);
+    if (st != RSI_OK)
+        return st;
+    int epochs = 2, batch = 4096, reinit = 0;
+    float lr = 1e-3f;
+    uint64_t seed = 1;
+    if (opts) {
+        if (opts->epochs < 0 || opts->batch < 0 || opts->lr < 0.0f)
+            return fail(RSI_E_ARG, "epochs, batch and lr must be >= 0");
+        if (opts->batch != 0 && (opts->batch < 64 || opts->batch > 65536))
+            return fail(RSI_E_ARG, "batch must be in 64..65536");
+        if (opts->epochs)
+            epochs = opts->epochs;
+        if (opts->batch)
+            batch = opts->batch;
+        if (opts->lr > 0.0f)
+            lr = opts->lr;
+        reinit = opts->reinit;
+        seed = opts->seed;
+    }
+    if (epoch_loss && (st = check_dev_ptr(epoch_loss, "epoch_loss")) != RSI_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = ensure_proposal(mesh, s, seed, reinit != 0)) != RSI_OK)
+        return st;
+    rsi::Proposal &pr = mesh->dev.prop;
+    // labels from the exact first-hit pass
+    void *tmp = nullptr;
+    const size_t scratch = rsi::proposal_batch_scratch(batch);
+    const size_t tmp_bytes = round_up(12 * (size_t)n_rays + 64) + scratch + round_up(4 * (size_t)epochs + 4);
+    hipError_t e = hipMallocAsync(&tmp, tmp_bytes, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RSI_E_NOMEM, std::string("training scratch: ") + hipGetErrorString(e));
+    }
+    char *t = static_cast<char *>(tmp);
+    int32_t *tri = reinterpret_cast<int32_t *>(t);
+    int32_t *seg = tri + n_rays;
+    int32_t *lab = seg + n_rays;
+    uint32_t *count = reinterpret_cast<uint32_t *>(lab + n_rays);
+    char *ws = t + round_up(12 * (size_t)n_rays + 64);
+    float *loss_sink = reinterpret_cast<float *>(ws + scratch);
+    auto bail = [&](rsi_status code) {
+        (void)hipFreeAsync(tmp, s);
+        return code;
+    };
+    rsi_intersect_opts io{RSI_PRECISION_CERTIFIED, 0, 0, 0, 0};
+    rsi_outputs out{nullptr, tri, nullptr, nullptr};
+    if ((st = rsi_intersect(mesh, rays_from, rays_to, n_rays, RSI_MODE_FIRST_HIT, &io, &out, stream)) != RSI_OK)
+        return bail(st);
+    uint32_t n_lab = 0;
+    e = hipMemsetAsync(count, 0, 4, s);
+    if (e == hipSuccess && n_rays > 0)
+        e = rsi::proposal_labels(mesh->dev, pr, tri, n_rays, seg, lab, count, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&n_lab, count, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        bail(RSI_OK);
+        return fail_hip(e, "proposal labels");
+    }
+    if (n_labelled)
+        *n_labelled = n_lab;
+    if (epoch_loss)
+        e = hipMemsetAsync(epoch_loss, 0, 4 * (size_t)epochs, s);
+    for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+        const int64_t nbatches = (n_lab + batch - 1) / batch;
+        for (int64_t b = 0; b < nbatches && e == hipSuccess; ++b) {
+            const int64_t r0 = b * batch;
+            const int rows = (int)(n_lab - r0 < batch ? n_lab - r0 : batch);
+            // each batch adds (its mean loss) * rows / n_lab: the epoch's mean loss
+            e = rsi::proposal_batch_grad(mesh->dev, pr, rays_from, rays_to, seg, lab, r0, rows, pr.n_buckets,
+                                         epoch_loss ? epoch_loss + ep : loss_sink, 1.0f / (float)n_lab, ws, s,
+                                         nullptr);
+            if (e == hipSuccess)
+                e = rsi::proposal_adam(pr, lr, (int)(++pr.step), s);
+        }
+    }
+    if (e != hipSuccess) {
+        bail(RSI_OK);
+        return fail_hip(e, "proposal training");
+    }
+    (void)hipFreeAsync(tmp, s);
+    return RSI_OK;
+}
+
+rsi_status rsi_proposal_predict(rsi_mesh mesh, const float *rays_from, const float *rays_to, int64_t n_rays,
+                                uint8_t *bucket, void *stream) {
+    g_error.clear();
+    rsi_status st = prop_args(mesh, rays_from, rays_to, n_rays);
+    if (st != RSI_OK)
+        return st;
+    if (!mesh->dev.prop.ready)
+        return fail(RSI_E_STATE, "no trained or loaded proposal");
+    if (n_rays > 0 && (!bucket || (st = check_dev_ptr(bucket, "bucket")) != RSI_OK))
+        return bucket ? st : fail(RSI_E_ARG, "bucket must not be NULL");
+    hipError_t e = rsi::proposal_predict(mesh->dev, mesh->dev.prop, rays_from, rays_to, n_rays,
+                                         mesh->dev.prop.n_buckets, bucket, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_proposal_predict");
+}
+
+rsi_status rsi_proposal_params(rsi_mesh mesh, int32_t what, float *buf, void *stream) {
+    g_error.clear();
+    rsi_status st = prop_args(mesh, nullptr, nullptr, 0);
+    if (st != RSI_OK)
+        return st;
+    if (what != 0 && what != 1)
+        return fail(RSI_E_ARG, "what must be 0 (get) or 1 (set)");
+    if (!buf || (st = check_dev_ptr(buf, "buf")) != RSI_OK)
+        return buf ? st : fail(RSI_E_ARG, "buf must not be NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (what == 0 && !mesh->dev.prop.ready)
+        return fail(RSI_E_STATE, "no trained or loaded proposal");
+    if ((st = ensure_proposal(mesh, s, 1, false)) != RSI_OK)
+        return st;
+    rsi::Proposal &pr = mesh->dev.prop;
+    const size_t bytes = 4 * (size_t)rsi::kMlpParams;
+    hipError_t e;
+    if (what == 0) {
+        e = hipMemcpyAsync(buf, pr.P, bytes, hipMemcpyDeviceToDevice, s);
+    } else {
+        e = hipMemcpyAsync(pr.P, buf, bytes, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(pr.m1, 0, bytes, s);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(pr.m2, 0, bytes, s);
+        if (e == hipSuccess)
+            e = rsi::proposal_set_params(pr, s);
+        pr.step = 0;
+        pr.ready = true;
+    }
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_proposal_params");
+}
+
+rsi_status rsi_proposal_gradient(rsi_mesh mesh, const float *rays_from, const float *rays_to, const int32_t *labels,
+                                 int64_t n_rays, float *grad, float *logits, float *loss, void *stream) {
+    g_error.clear();
+    rsi_status st = prop_args(mesh, rays_from, rays_to, n_rays);
+    if (st != RSI_OK)
+        return st;
+    if (n_rays < 1 || n_rays > 65536)
+        return fail(RSI_E_ARG, "n_rays must be in 1..65536");
+    if (!mesh->dev.prop.ready)
+        return fail(RSI_E_STATE, "no trained or loaded proposal");
+    if (!labels || !grad || !logits || !loss)
+        return fail(RSI_E_ARG, "labels, grad, logits and loss must not be NULL");
+    if ((st = check_dev_ptr(labels, "labels")) != RSI_OK || (st = check_dev_ptr(grad, "grad")) != RSI_OK ||
+        (st = check_dev_ptr(logits, "logits")) != RSI_OK || (st = check_dev_ptr(loss, "loss")) != RSI_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rsi::Proposal &pr = mesh->dev.prop;
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, rsi::proposal_batch_scratch((int)n_rays), s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RSI_E_NOMEM, "gradient scratch");
+    }
+    e = hipMemsetAsync(loss, 0, 4, s);
+    if (e == hipSuccess)
+        e = rsi::proposal_batch_grad(mesh->dev, pr, rays_from, rays_to, nullptr, labels, 0, (int)n_rays,
+                                     pr.n_buckets, loss, 0.0f, static_cast<char *>(ws), s, logits);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(grad, pr.G, 4 * (size_t)rsi::kMlpParams, hipMemcpyDeviceToDevice, s);
+    (void)hipFreeAsync(ws, s);
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_proposal_gradient");
+}
+
+rsi_status rsi_proposal_features(rsi_mesh mesh, const float *rays_from, const float *rays_to, int64_t n_rays,
+                                 uint16_t *features, void *stream) {
+    g_error.clear();
+    rsi_status st = prop_args(mesh, rays_from, rays_to, n_rays);
+    if (st != RSI_OK)
+        return st;
+    if (n_rays > 0 && (!features || (st = check_dev_ptr(features, "features")) != RSI_OK))
+        return features ? st : fail(RSI_E_ARG, "features must not be NULL");
+    hipError_t e = rsi::proposal_features(mesh->dev, rays_from, rays_to, n_rays, reinterpret_cast<__bf16 *>(features),
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_proposal_features");
+}
+
+rsi_status rsi_proposal_frontier(rsi_mesh mesh, int32_t *bucket_ref, int32_t *bucket_first, int32_t *n_buckets,
+                                 void *stream) {
+    g_error.clear();
+    rsi_status st = prop_args(mesh, nullptr, nullptr, 0);
+    if (st != RSI_OK)
+        return st;
+    if (!bucket_ref || !bucket_first || !n_buckets)
+        return fail(RSI_E_ARG, "outputs must not be NULL");
+    if ((st = check_dev_ptr(bucket_ref, "bucket_ref")) != RSI_OK ||
+        (st = check_dev_ptr(bucket_first, "bucket_first")) != RSI_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rsi::Proposal &pr = mesh->dev.prop;
+    const bool had = pr.ready;
+    if ((st = ensure_proposal(mesh, s, 1, false)) != RSI_OK)
+        return st;
+    pr.ready = had || pr.ready;
+    hipError_t e = hipMemcpyAsync(bucket_ref, pr.bucket_ref, 4 * 256, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bucket_first, pr.bucket_first, 4 * 256, hipMemcpyDeviceToDevice, s);
+    *n_buckets = pr.n_buckets;
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_proposal_frontier");
+}
+
+namespace {
+struct PropHeader {
+    char magic[8];
+    int32_t inputs, hidden, outputs, layers;
+    int64_t params, step, n_triangles;
+    int32_t n_buckets, reserved;
+};
+}  // namespace
+
+rsi_status rsi_proposal_save(rsi_mesh mesh, const char *path) {
+    g_error.clear();
+    rsi_status st = prop_args(mesh, nullptr, nullptr, 0);
+    if (st != RSI_OK)
+        return st;
+    if (!path)
+        return fail(RSI_E_ARG, "path must not be NULL");
+    rsi::Proposal &pr = mesh->dev.prop;
+    if (!pr.ready)
+        return fail(RSI_E_STATE, "no trained or loaded proposal");
+    const size_t np = (size_t)rsi::kMlpParams;
+    std::string buf(3 * 4 * np, '\0');
+    hipError_t e = hipStreamSynchronize(mesh->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(&buf[0], pr.P, 4 * np, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(&buf[4 * np], pr.m1, 4 * np, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(&buf[8 * np], pr.m2, 4 * np, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return fail_hip(e, "rsi_proposal_save");
+    PropHeader h{{'R', 'S', 'I', 'M', 'L', 'P', '0', '1'}, rsi::kMlpIn, rsi::kMlpHidden, rsi::kMlpOut, 4,
+                 rsi::kMlpParams, pr.step, mesh->dev.nt, pr.n_buckets, 0};
+    FILE *f = std::fopen(path, "wb");
+    if (!f)
+        return fail(RSI_E_ARG, std::string("cannot open ") + path);
+    const bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 && std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+    std::fclose(f);
+    return ok ? RSI_OK : fail(RSI_E_ARG, std::string("short write to ") + path);
+}
+
+rsi_status rsi_proposal_load(rsi_mesh mesh, const char *path) {
+    g_error.clear();
+    rsi_status st = prop_args(mesh, nullptr, nullptr, 0);
+    if (st != RSI_OK)
+        return st;
+    if (!path)
+        return fail(RSI_E_ARG, "path must not be NULL");
+    FILE *f = std::fopen(path, "rb");
+    if (!f)
+        return fail(RSI_E_ARG, std::string("cannot open ") + path);
+    PropHeader h;
+    const size_t np = (size_t)rsi::kMlpParams;
+    std::string buf(3 * 4 * np, '\0');
+    const bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::fread(&buf[0], 1, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok || std::memcmp(h.magic, "RSIMLP01", 8) != 0 || h.inputs != rsi::kMlpIn || h.hidden != rsi::kMlpHidden ||
+        h.outputs != rsi::kMlpOut || h.params != rsi::kMlpParams)
+        return fail(RSI_E_ARG, std::string(path) + " is not a proposal file of this network");
+    hipStream_t s = mesh->stream;
+    if ((st = ensure_proposal(mesh, s, 1, false)) != RSI_OK)
+        return st;
+    rsi::Proposal &pr = mesh->dev.prop;
+    if (h.n_triangles != mesh->dev.nt || h.n_buckets != pr.n_buckets)
+        return fail(RSI_E_ARG, "proposal file was trained on a different mesh");
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        e = hipMemcpy(pr.P, &buf[0], 4 * np, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(pr.m1, &buf[4 * np], 4 * np, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(pr.m2, &buf[8 * np], 4 * np, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = rsi::proposal_set_params(pr, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail_hip(e, "rsi_proposal_load");
+    pr.step = h.step;
+    pr.ready = true;
     return RSI_OK;
 }
 

@@ -1,0 +1,651 @@
+// mlp.hip -- the learned subtree proposal: a small MLP that predicts, per
+// segment, which depth-8 subtree of the BVH holds its first hit, so the
+// traversal can visit that subtree first and stop early on a sure hit.  The
+// exact traversal still decides every result; the proposal only changes the
+// order of work.
+//
+// Network: 6 endpoint coordinates normalised to [-1, 1] over the mesh box,
+// plus sin / cos (pi f_k x) for 16 bands f_k = 2^(k/2) per coordinate
+// (198 features, padded to 224), three hidden layers of 256 with ReLU, 256
+// logits (one per frontier bucket; unused buckets masked).  bf16 weights and
+// activations, fp32 accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16);
+// fp32 master weights and Adam for training.
+//
+// MFMA 16x16x32 bf16 operand layout on a wave of 64 lanes (lane l):
+//   A (16 x 32): row l % 16, k = 8 (l / 16) + j, j = 0..7
+//   B (32 x 16): col l % 16, k = 8 (l / 16) + j
+//   D (16 x 16): row 4 (l / 16) + i, col l % 16, i = 0..3
+#include "rsi_internal.h"
+
+namespace rsi {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// -------------------------------------------------------------- features
+// Feature j of one segment (j < kMlpIn; zero past kMlpFeat).  Coordinates are
+// normalised as n = (p - lo) / (hi - lo) (0 on a flat axis), x = 2 n - 1; the
+// band frequencies are the float32 values 2^(k/2).
+__device__ __forceinline__ float band_freq(int k) {
+    return ldexpf((k & 1) ? 1.41421354f : 1.0f, k >> 1);
+}
+
+__device__ __forceinline__ float norm_coord(float p, float lo, float hi) {
+#pragma clang fp contract(off)
+    const float ext = hi - lo;
+    const float n = ext > 0.0f ? (p - lo) / ext : 0.0f;
+    return n * 2.0f - 1.0f;
+}
+
+// sin(pi a) and cos(pi a): the hardware sine / cosine take their argument in
+// turns, so a / 2 is reduced exactly to [-1/2, 1/2] first.  The features are
+// rounded to bf16 (8 bits), far coarser than the instruction's error.
+__device__ __forceinline__ void sincospi_fast(float a, float &sn, float &cs) {
+    float t = 0.5f * a;
+    t = t - rintf(t);
+    sn = __builtin_amdgcn_sinf(t);
+    cs = __builtin_amdgcn_cosf(t);
+}
+
+// Writes the 33 features that depend on coordinate c (its value, then
+// sin / cos of the 16 bands) into row[].
+__device__ __forceinline__ void coord_features(float x, int c, __bf16 *row) {
+#pragma clang fp contract(off)
+    row[c] = (__bf16)x;
+    for (int k = 0; k < kMlpBands; ++k) {
+        const float a = band_freq(k) * x;
+        float sn, cs;
+        sincospi_fast(a, sn, cs);
+        row[6 + c * 2 * kMlpBands + 2 * k] = (__bf16)sn;
+        row[6 + c * 2 * kMlpBands + 2 * k + 1] = (__bf16)cs;
+    }
+}
+
+__device__ __forceinline__ float seg_coord(const float *__restrict__ from, const float *__restrict__ to, int64_t i,
+                                           int c) {
+    return c < 3 ? from[3 * i + c] : to[3 * i + c - 3];
+}
+
+// X[r][0..kMlpIn) for rows [0, rows): segment index = ids ? ids[r0 + r] : r0 + r.
+__global__ __launch_bounds__(256) void k_features(const float *__restrict__ from, const float *__restrict__ to,
+                                                  const int32_t *__restrict__ ids, int64_t r0, int64_t rows,
+                                                  const float *__restrict__ bounds, __bf16 *__restrict__ X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = t / 7;
+    const int part = (int)(t % 7);
+    if (r >= rows)
+        return;
+    __bf16 *row = X + r * kMlpIn;
+    if (part == 6) {
+        for (int j = kMlpFeat; j < kMlpIn; ++j)
+            row[j] = (__bf16)0.0f;
+        return;
+    }
+    const int64_t seg = ids ? ids[r0 + r] : r0 + r;
+    const int c = part;
+    const float x = norm_coord(seg_coord(from, to, seg, c), bounds[c % 3], bounds[3 + c % 3]);
+    coord_features(x, c, row);
+}
+
+// ------------------------------------------------------------ tiled GEMM
+// C[m][n] = sum_k A(m, k) B(k, n) with arbitrary element strides, bf16 in,
+// fp32 accumulation; 64 x 64 tile per workgroup, 32 x 32 per wave, k steps of
+// 32 staged through LDS.  Epilogue: + bias[n], ReLU, times (mask(m, n) > 0),
+// stored as fp32 and / or bf16 with arbitrary strides.
+struct GemmArgs {
+    const __bf16 *A;
+    int64_t a_m, a_k;
+    const __bf16 *B;
+    int64_t b_k, b_n;
+    int M, N, K;
+    const float *bias;
+    int relu;
+    const __bf16 *mask;
+    int64_t mask_m, mask_n;
+    float *Cf;
+    __bf16 *Cb;
+    int64_t c_m, c_n;
+};
+
+constexpr int kGT = 64, kGK = 32, kGPad = 8;
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+    __shared__ __bf16 As[kGT][kGK + kGPad];
+    __shared__ __bf16 Bs[kGT][kGK + kGPad];  // stored [n][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const bool a_kfast = g.a_k == 1, b_kfast = g.b_k == 1;
+    for (int k0 = 0; k0 < g.K; k0 += kGK) {
+        for (int r = 0; r < (kGT * kGK) / 256; ++r) {
+            const int idx = tid + 256 * r;
+            int mm, kk;
+            if (a_kfast) { mm = idx / kGK; kk = idx % kGK; } else { mm = idx % kGT; kk = idx / kGT; }
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[mm][kk] = (gm < g.M && gk < g.K) ? g.A[gm * g.a_m + gk * g.a_k] : (__bf16)0.0f;
+            int nn;
+            if (b_kfast) { nn = idx / kGK; kk = idx % kGK; } else { nn = idx % kGT; kk = idx / kGT; }
+            const int gn = n0 + nn, gk2 = k0 + kk;
+            Bs[nn][kk] = (gn < g.N && gk2 < g.K) ? g.B[gk2 * g.b_k + gn * g.b_n] : (__bf16)0.0f;
+        }
+        __syncthreads();
+        const int kq = 8 * (lane >> 4);
+        for (int a = 0; a < 2; ++a) {
+            const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * a + (lane & 15)][kq]);
+            for (int b = 0; b < 2; ++b) {
+                const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * b + (lane & 15)][kq]);
+                acc[a][b] = mfma16(fa, fb, acc[a][b]);
+            }
+        }
+        __syncthreads();
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int i = 0; i < 4; ++i) {
+                const int m = m0 + wm + 16 * a + 4 * (lane >> 4) + i;
+                const int n = n0 + wn + 16 * b + (lane & 15);
+                if (m >= g.M || n >= g.N)
+                    continue;
+                float v = acc[a][b][i];
+                if (g.bias)
+                    v += g.bias[n];
+                if (g.relu)
+                    v = fmaxf(v, 0.0f);
+                if (g.mask && !((float)g.mask[m * g.mask_m + n * g.mask_n] > 0.0f))
+                    v = 0.0f;
+                if (g.Cf)
+                    g.Cf[m * g.c_m + n * g.c_n] = v;
+                if (g.Cb)
+                    g.Cb[m * g.c_m + n * g.c_n] = (__bf16)v;
+            }
+}
+
+// ------------------------------------------------- softmax cross-entropy
+// One row per wave: p = softmax(z over the first nb logits); the gradient of
+// the mean loss is (p - onehot(y)) / rows (0 for masked columns).  Adds the
+// row's loss times loss_scale to *loss.
+__global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z, const int32_t *__restrict__ y,
+                                                    int rows, int nb, float inv_rows, float loss_scale,
+                                                    __bf16 *__restrict__ dZ, float *__restrict__ loss) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= rows)
+        return;
+    const float *z = Z + (int64_t)row * kMlpOut;
+    float v[4];
+    float mx = -INFINITY;
+    for (int j = 0; j < 4; ++j) {
+        const int c = lane + 64 * j;
+        v[j] = c < nb ? z[c] : -INFINITY;
+        mx = fmaxf(mx, v[j]);
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+    float s = 0.0f;
+    for (int j = 0; j < 4; ++j)
+        s += (lane + 64 * j) < nb ? expf(v[j] - mx) : 0.0f;
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_xor(s, off);
+    const int label = y[row];
+    for (int j = 0; j < 4; ++j) {
+        const int c = lane + 64 * j;
+        float g = 0.0f;
+        if (c < nb)
+            g = (expf(v[j] - mx) / s - (c == label ? 1.0f : 0.0f)) * inv_rows;
+        dZ[(int64_t)row * kMlpOut + c] = (__bf16)g;
+    }
+    if (lane == 0 && label >= 0 && label < nb)
+        atomicAdd(loss, (logf(s) + mx - z[label]) * loss_scale);
+}
+
+// db[n] = sum over rows of dZ[row][n] (fp32 from bf16).
+__global__ __launch_bounds__(256) void k_col_sum(const __bf16 *__restrict__ dZ, int rows, float *__restrict__ db) {
+    const int n = threadIdx.x;
+    float s = 0.0f;
+    for (int r = 0; r < rows; ++r)
+        s += (float)dZ[(int64_t)r * kMlpOut + n];
+    db[n] = s;
+}
+
+// Adam on the fp32 master parameters; refreshes the bf16 copy of the weights.
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ P, const float *__restrict__ G,
+                                              float *__restrict__ m1, float *__restrict__ m2,
+                                              __bf16 *__restrict__ Wb, int64_t n_params, int64_t n_weights,
+                                              float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_params)
+        return;
+    const float g = G[i];
+    const float a = b1 * m1[i] + (1.0f - b1) * g;
+    const float b = b2 * m2[i] + (1.0f - b2) * g * g;
+    m1[i] = a;
+    m2[i] = b;
+    const float w = P[i] - lr * (a * c1) / (sqrtf(b * c2) + eps);
+    P[i] = w;
+    if (i < n_weights)
+        Wb[i] = (__bf16)w;
+}
+
+// Uniform(-a, a) initial weights from a counter-based hash (seed, index).
+__device__ __forceinline__ uint32_t mix32(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return (uint32_t)x;
+}
+
+__global__ __launch_bounds__(256) void k_init_params(float *__restrict__ P, __bf16 *__restrict__ Wb,
+                                                     float *__restrict__ m1, float *__restrict__ m2, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kMlpParams)
+        return;
+    float w = 0.0f;
+    if (i < kMlpWeights) {
+        const int fan_in = i < (int64_t)kMlpOut * kMlpIn ? kMlpFeat : kMlpHidden;
+        const float a = sqrtf(6.0f / (float)fan_in);
+        const float u = (mix32(seed * 0x9e3779b97f4a7c15ull + (uint64_t)i) >> 8) * 0x1p-24f;
+        w = (2.0f * u - 1.0f) * a;
+        if (i < (int64_t)kMlpOut * kMlpIn && (i % kMlpIn) >= kMlpFeat)
+            w = 0.0f;  // padding features carry no weight
+        Wb[i] = (__bf16)w;
+    }
+    P[i] = w;
+    m1[i] = 0.0f;
+    m2[i] = 0.0f;
+}
+
+// ------------------------------------------------ fused inference kernel
+// 64 segments per tile; four waves, wave w producing output columns
+// [64 w, 64 w + 64) of every layer for all 64 rows (16 MFMA per k step, so
+// each weight fragment fetched from L2 feeds 4 row tiles).  Activations stay
+// in LDS (two bf16 buffers, 66 KB: two workgroups per CU); the next k step's weight fragments are
+// loaded while the current step multiplies.  The accumulation order over k is
+// the one k_gemm uses, so the logits are bit-identical to the training
+// forward pass.
+constexpr int kPRows = 64;
+constexpr int kPPitch = kMlpHidden + 8;
+constexpr int kPRowTiles = kPRows / 16;
+
+__device__ __forceinline__ void layer_tile(const __bf16 *__restrict__ Xin, int K, const __bf16 *__restrict__ Wt,
+                                           int wave, int lane, f32x4 (&acc)[kPRowTiles][4]) {
+#pragma unroll
+    for (int a = 0; a < kPRowTiles; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int kq = 8 * (lane >> 4);
+    const __bf16 *wrow = Wt + (int64_t)(64 * wave + (lane & 15)) * K + kq;
+    const __bf16 *xrow = Xin + (lane & 15) * kPPitch + kq;
+    bf16x8 fb[4], nb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        fb[b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K);
+#pragma unroll 1
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const int kn = k0 + 32 < K ? k0 + 32 : k0;  // last step re-reads (harmless)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            nb[b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K + kn);
+#pragma unroll
+        for (int a = 0; a < kPRowTiles; ++a) {
+            const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(xrow + 16 * a * kPPitch + k0);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = mfma16(fa, fb[b], acc[a][b]);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            fb[b] = nb[b];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_propose(const float *__restrict__ from, const float *__restrict__ to,
+                                                     int64_t n, const float *__restrict__ bounds,
+                                                     const __bf16 *__restrict__ Wb, const float *__restrict__ P,
+                                                     int nb, uint8_t *__restrict__ bucket) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __bf16 *X0 = reinterpret_cast<__bf16 *>(lds_raw);
+    __bf16 *X1 = X0 + kPRows * kPPitch;
+    float *best_v = reinterpret_cast<float *>(X1 + kPRows * kPPitch);  // [4][kPRows]
+    int *best_i = reinterpret_cast<int *>(best_v + 4 * kPRows);        // [4][kPRows]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float *bias = P + kMlpWeights;
+    const int64_t tiles = (n + kPRows - 1) / kPRows;
+#pragma unroll 1
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t r0 = tile * kPRows;
+        // features -> X0 (pitch kPPitch)
+#pragma unroll 1
+        for (int q = tid; q < kPRows * 7; q += 256) {
+            const int r = q / 7, part = q % 7;
+            __bf16 *row = X0 + r * kPPitch;
+            if (part == 6) {
+                for (int j = kMlpFeat; j < kMlpIn; ++j)
+                    row[j] = (__bf16)0.0f;
+                continue;
+            }
+            const int64_t seg = r0 + r < n ? r0 + r : n - 1;
+            const float x = norm_coord(seg_coord(from, to, seg, part), bounds[part % 3], bounds[3 + part % 3]);
+            coord_features(x, part, row);
+        }
+        __syncthreads();
+        f32x4 acc[kPRowTiles][4];
+#pragma unroll 1
+        for (int l = 0; l < 3; ++l) {
+            const __bf16 *in = (l & 1) ? X1 : X0;
+            __bf16 *out = (l & 1) ? X0 : X1;
+            const int64_t woff = l == 0 ? 0 : (int64_t)kMlpOut * kMlpIn + (int64_t)(l - 1) * kMlpHidden * kMlpHidden;
+            layer_tile(in, l == 0 ? kMlpIn : kMlpHidden, Wb + woff, wave, lane, acc);
+            const float *bl = bias + l * kMlpHidden;
+            __syncthreads();  // every wave has read `in`; layer 2 writes over X0
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int col = 64 * wave + 16 * b + (lane & 15);
+                const float bv = bl[col];
+#pragma unroll
+                for (int a = 0; a < kPRowTiles; ++a)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = 16 * a + 4 * (lane >> 4) + i;
+                        out[row * kPPitch + col] = (__bf16)fmaxf(acc[a][b][i] + bv, 0.0f);
+                    }
+            }
+            __syncthreads();
+        }
+        // the third hidden layer wrote X1
+        layer_tile(X1, kMlpHidden, Wb + (int64_t)kMlpOut * kMlpIn + 2LL * kMlpHidden * kMlpHidden, wave, lane, acc);
+        const float *b4 = bias + 3 * kMlpHidden;
+        float b4v[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            b4v[b] = b4[64 * wave + 16 * b + (lane & 15)];
+        // argmax over valid buckets (smallest index on ties)
+#pragma unroll
+        for (int a = 0; a < kPRowTiles; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float bv = -INFINITY;
+                int bi = INT32_MAX;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int col = 64 * wave + 16 * b + (lane & 15);
+                    const float v = acc[a][b][i] + b4v[b];
+                    if (col < nb && (v > bv || (v == bv && col < bi))) {
+                        bv = v;
+                        bi = col;
+                    }
+                }
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) {
+                    const float ov = __shfl_xor(bv, off);
+                    const int oi = __shfl_xor(bi, off);
+                    if (ov > bv || (ov == bv && oi < bi)) {
+                        bv = ov;
+                        bi = oi;
+                    }
+                }
+                if ((lane & 15) == 0) {
+                    const int row = 16 * a + 4 * (lane >> 4) + i;
+                    best_v[wave * kPRows + row] = bv;
+                    best_i[wave * kPRows + row] = bi;
+                }
+            }
+        __syncthreads();
+        if (tid < kPRows && r0 + tid < n) {
+            float bv = best_v[tid];
+            int bi = best_i[tid];
+            for (int w = 1; w < 4; ++w) {
+                const float v = best_v[w * kPRows + tid];
+                const int i2 = best_i[w * kPRows + tid];
+                if (v > bv || (v == bv && i2 < bi)) {
+                    bv = v;
+                    bi = i2;
+                }
+            }
+            bucket[r0 + tid] = (uint8_t)(bi >= 0 && bi < nb ? bi : 0);
+        }
+        __syncthreads();
+    }
+}
+
+constexpr size_t kProposeLds = 2 * (size_t)kPRows * kPPitch * sizeof(__bf16) + 8 * (size_t)kPRows * 4;
+
+// ------------------------------------------------ frontier and labels
+// Left-to-right frontier of the tree at depth 8: internal nodes at depth 8
+// and leaves shallower than that.  One lane walks it level by level (at most
+// 511 nodes); then each bucket's first sorted leaf is found by descending left.
+__global__ void k_frontier(const Node *__restrict__ nodes, int root, int nt, int32_t *__restrict__ bucket_ref,
+                           int32_t *__restrict__ bucket_first, int32_t *__restrict__ n_buckets) {
+    __shared__ int cur[kMlpOut], nxt[kMlpOut];
+    __shared__ int count;
+    if (threadIdx.x == 0) {
+        int nc = 1;
+        cur[0] = root;
+        for (int d = 0; d < kFrontierDepth; ++d) {
+            int nn = 0;
+            for (int j = 0; j < nc; ++j) {
+                const int r = cur[j];
+                if (r >= 0) {
+                    nxt[nn++] = nodes[r].refs.x;
+                    nxt[nn++] = nodes[r].refs.y;
+                } else {
+                    nxt[nn++] = r;
+                }
+            }
+            for (int j = 0; j < nn; ++j)
+                cur[j] = nxt[j];
+            nc = nn;
+        }
+        count = nc;
+        *n_buckets = nc;
+    }
+    __syncthreads();
+    const int b = threadIdx.x;
+    if (b < count) {
+        int r = cur[b];
+        bucket_ref[b] = r;
+        for (int guard = 0; r >= 0 && guard < kDeepStack; ++guard)
+            r = nodes[r].refs.x;
+        bucket_first[b] = ~r;
+    }
+    (void)nt;
+}
+
+// rank[ids[k]] = k: sorted position of each input triangle.
+__global__ void k_rank(const int32_t *__restrict__ ids, int nt, int32_t *__restrict__ rank) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nt)
+        rank[ids[k]] = k;
+}
+
+// For every segment with a first hit: its bucket (the frontier subtree whose
+// leaf range holds the hit leaf), appended with the segment index to the
+// training list.
+__global__ void k_labels(const int32_t *__restrict__ tri_id, int64_t n, const int32_t *__restrict__ rank,
+                         const int32_t *__restrict__ bucket_first, const int32_t *__restrict__ n_buckets,
+                         int32_t *__restrict__ seg_out, int32_t *__restrict__ label_out,
+                         uint32_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int t = tri_id[i];
+    if (t < 0)
+        return;
+    const int leaf = rank[t];
+    int lo = 0, hi = *n_buckets - 1;  // last bucket whose first leaf <= leaf
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bucket_first[mid] <= leaf)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const uint32_t slot = atomicAdd(count, 1u);
+    seg_out[slot] = (int32_t)i;
+    label_out[slot] = lo;
+}
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+void gemm(const GemmArgs &g, hipStream_t s) {
+    dim3 grid(cdiv(g.N, kGT), cdiv(g.M, kGT));
+    k_gemm<<<grid, 256, 0, s>>>(g);
+}
+
+}  // namespace
+
+// ===================================================================== host
+hipError_t proposal_frontier(const MeshDev &m, Proposal &pr, hipStream_t s) {
+    if (m.nt < 1)
+        return hipErrorInvalidValue;
+    k_frontier<<<1, kMlpOut, 0, s>>>(m.nodes, m.root, (int)m.nt, pr.bucket_ref, pr.bucket_first, pr.dev_n_buckets);
+    k_rank<<<cdiv(m.nt, 256), 256, 0, s>>>(m.ids, (int)m.nt, pr.rank);
+    return hipGetLastError();
+}
+
+hipError_t proposal_init(Proposal &pr, uint64_t seed, hipStream_t s) {
+    k_init_params<<<cdiv(kMlpParams, 256), 256, 0, s>>>(pr.P, pr.Wb, pr.m1, pr.m2, seed);
+    return hipGetLastError();
+}
+
+hipError_t proposal_labels(const MeshDev &m, Proposal &pr, const int32_t *tri_id, int64_t n, int32_t *seg,
+                           int32_t *label, uint32_t *count, hipStream_t s) {
+    k_labels<<<cdiv(n, 256), 256, 0, s>>>(tri_id, n, pr.rank, pr.bucket_first, pr.dev_n_buckets, seg, label, count);
+    return hipGetLastError();
+}
+
+hipError_t proposal_predict(const MeshDev &m, const Proposal &pr, const float *from, const float *to, int64_t n,
+                            int nb, uint8_t *bucket, hipStream_t s) {
+    if (n == 0)
+        return hipSuccess;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t tiles = (n + kPRows - 1) / kPRows;
+    const int grid = (int)(tiles < 2 * cus ? tiles : 2 * cus);
+    static bool lds_set = false;
+    if (!lds_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mlp_propose),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kProposeLds);
+        lds_set = true;
+    }
+    k_mlp_propose<<<grid, 256, kProposeLds, s>>>(from, to, n, m.bounds, pr.Wb, pr.P, nb, bucket);
+    return hipGetLastError();
+}
+
+// Forward + backward of one batch (rows segments listed in seg[r0..r0+rows),
+// labels lab[r0..]); writes the parameter gradient into pr.G and adds the
+// mean loss to *loss.  ws must hold kMlpBatchScratch(rows) bytes.
+hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from, const float *to,
+                               const int32_t *seg, const int32_t *lab, int64_t r0, int rows, int nb, float *loss,
+                               float loss_scale, char *ws, hipStream_t s, float *logits_out) {
+    __bf16 *X0 = reinterpret_cast<__bf16 *>(ws);
+    __bf16 *H1 = X0 + (int64_t)rows * kMlpIn;
+    __bf16 *H2 = H1 + (int64_t)rows * kMlpHidden;
+    __bf16 *H3 = H2 + (int64_t)rows * kMlpHidden;
+    __bf16 *dZa = H3 + (int64_t)rows * kMlpHidden;
+    __bf16 *dZb = dZa + (int64_t)rows * kMlpOut;
+    float *Z4 = reinterpret_cast<float *>(dZb + (int64_t)rows * kMlpOut);
+    const __bf16 *W1 = pr.Wb, *W2 = W1 + kMlpOut * kMlpIn, *W3 = W2 + kMlpHidden * kMlpHidden,
+                 *W4 = W3 + kMlpHidden * kMlpHidden;
+    const float *bias = pr.P + kMlpWeights;
+    float *G = pr.G;
+    float *gW1 = G, *gW2 = gW1 + kMlpOut * kMlpIn, *gW3 = gW2 + kMlpHidden * kMlpHidden,
+          *gW4 = gW3 + kMlpHidden * kMlpHidden, *gb = G + kMlpWeights;
+
+    k_features<<<cdiv((int64_t)rows * 7, 256), 256, 0, s>>>(from, to, seg, r0, rows, m.bounds, X0);
+    // forward: Z = H W (W stored [out][in]), ReLU on hidden layers
+    const __bf16 *ins[4] = {X0, H1, H2, H3};
+    __bf16 *outs[3] = {H1, H2, H3};
+    const __bf16 *Ws[4] = {W1, W2, W3, W4};
+    for (int l = 0; l < 4; ++l) {
+        const int K = l == 0 ? kMlpIn : kMlpHidden;
+        GemmArgs g{};
+        g.A = ins[l]; g.a_m = K; g.a_k = 1;
+        g.B = Ws[l]; g.b_k = 1; g.b_n = K;
+        g.M = rows; g.N = kMlpOut; g.K = K;
+        g.bias = bias + l * kMlpHidden;
+        g.relu = l < 3;
+        g.c_m = kMlpOut; g.c_n = 1;
+        if (l < 3) g.Cb = outs[l]; else g.Cf = logits_out ? logits_out : Z4;
+        gemm(g, s);
+    }
+    k_softmax_ce<<<cdiv(rows, 4), 256, 0, s>>>(logits_out ? logits_out : Z4, lab + r0, rows, nb, 1.0f / rows,
+                                              loss_scale > 0.0f ? loss_scale : 1.0f / rows, dZa, loss);
+    // backward
+    __bf16 *dZ = dZa, *dZn = dZb;
+    float *gWs[4] = {gW1, gW2, gW3, gW4};
+    for (int l = 3; l >= 0; --l) {
+        const int K = l == 0 ? kMlpIn : kMlpHidden;
+        // dW^T[n][k] = sum_r H[r][k] dZ[r][n]  -> M = 256 (n), N = K (k), contraction over rows
+        GemmArgs g{};
+        g.A = dZ; g.a_m = 1; g.a_k = kMlpOut;
+        g.B = ins[l]; g.b_k = K; g.b_n = 1;
+        g.M = kMlpOut; g.N = K; g.K = rows;
+        g.Cf = gWs[l]; g.c_m = K; g.c_n = 1;
+        gemm(g, s);
+        k_col_sum<<<1, kMlpOut, 0, s>>>(dZ, rows, gb + l * kMlpHidden);
+        if (l > 0) {
+            // dH[r][k] = sum_n dZ[r][n] W[n][k], masked by H > 0
+            GemmArgs h{};
+            h.A = dZ; h.a_m = kMlpOut; h.a_k = 1;
+            h.B = Ws[l]; h.b_k = K; h.b_n = 1;
+            h.M = rows; h.N = K; h.K = kMlpOut;
+            h.mask = ins[l]; h.mask_m = K; h.mask_n = 1;
+            h.Cb = dZn; h.c_m = K; h.c_n = 1;
+            gemm(h, s);
+            __bf16 *t = dZ;
+            dZ = dZn;
+            dZn = t;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t proposal_adam(Proposal &pr, float lr, int step, hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f / (1.0f - powf(b1, (float)step));
+    const float c2 = 1.0f / (1.0f - powf(b2, (float)step));
+    k_adam<<<cdiv(kMlpParams, 256), 256, 0, s>>>(pr.P, pr.G, pr.m1, pr.m2, pr.Wb, kMlpParams, kMlpWeights, lr, b1,
+                                                 b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void k_params_to_bf16(const float *__restrict__ P, __bf16 *__restrict__ Wb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kMlpWeights)
+        Wb[i] = (__bf16)P[i];
+}
+}  // namespace
+
+hipError_t proposal_set_params(Proposal &pr, hipStream_t s) {
+    k_params_to_bf16<<<cdiv(kMlpWeights, 256), 256, 0, s>>>(pr.P, pr.Wb);
+    return hipGetLastError();
+}
+
+size_t proposal_batch_scratch(int rows) {
+    return (size_t)rows * (kMlpIn + 3 * kMlpHidden + 2 * kMlpOut) * 2 + (size_t)rows * kMlpOut * 4 + 256;
+}
+
+hipError_t proposal_features(const MeshDev &m, const float *from, const float *to, int64_t n, __bf16 *X,
+                             hipStream_t s) {
+    if (n == 0)
+        return hipSuccess;
+    k_features<<<cdiv(n * 7, 256), 256, 0, s>>>(from, to, nullptr, 0, n, m.bounds, X);
+    return hipGetLastError();
+}
+
+}  // namespace rsi

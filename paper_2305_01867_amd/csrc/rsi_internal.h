@@ -30,6 +30,33 @@ static_assert(sizeof(Tri) == 48, "leaf triangle must be 48 bytes");
 
 constexpr int kDeepStack = 128;  // exceeds the radix tree's largest possible depth (97)
 
+// Learned proposal (mlp.hip): sizes of the network and its parameter vector
+// [W1 (256 x 224), W2, W3, W4 (256 x 256), b1..b4 (256 each)], weights stored
+// [out][in].
+constexpr int kMlpBands = 16;
+constexpr int kMlpFeat = 6 + 6 * 2 * kMlpBands;  // 198
+constexpr int kMlpIn = 224;
+constexpr int kMlpHidden = 256;
+constexpr int kMlpOut = 256;
+constexpr int kFrontierDepth = 8;
+constexpr int64_t kMlpWeights = (int64_t)kMlpOut * kMlpIn + 3LL * kMlpHidden * kMlpHidden;
+constexpr int64_t kMlpParams = kMlpWeights + 4LL * kMlpHidden;
+
+struct Proposal {
+    bool ready = false;      // parameters initialised or loaded
+    int n_buckets = 0;       // host copy
+    int64_t step = 0;        // Adam steps taken
+    float *P = nullptr;      // fp32 master parameters [kMlpParams]
+    float *G = nullptr;      // gradient [kMlpParams]
+    float *m1 = nullptr, *m2 = nullptr;  // Adam moments
+    __bf16 *Wb = nullptr;    // bf16 weights [kMlpWeights]
+    int32_t *bucket_ref = nullptr;    // [256] frontier node reference per bucket
+    int32_t *bucket_first = nullptr;  // [256] first sorted leaf of each bucket
+    int32_t *dev_n_buckets = nullptr; // [1]
+    int32_t *rank = nullptr;          // [nt] sorted position of each triangle
+    void *block = nullptr;
+};
+
 // Device state of one built mesh.
 struct MeshDev {
     int64_t nv = 0, nt = 0;
@@ -47,6 +74,7 @@ struct MeshDev {
     int32_t *flags = nullptr;  // [4]: [0] bad-index flag
     void *sort_tmp = nullptr;  // key/id ping-pong + histograms
     int64_t bytes = 0;
+    Proposal prop;
 };
 
 // Build steps (build.hip).  All asynchronous on `s`.
@@ -69,8 +97,26 @@ struct TraverseArgs {
     uint32_t *queue_len = nullptr; // [1] device (inside counters workspace)
     uint32_t *visits = nullptr;    // stats only
     uint32_t *tests = nullptr;     // stats only
+    const uint8_t *bucket = nullptr;      // proposal per segment (NULL: none)
+    const int32_t *bucket_ref = nullptr;  // frontier node per bucket
 };
 hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
 hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
+
+// Learned proposal (mlp.hip).
+hipError_t proposal_frontier(const MeshDev &m, Proposal &pr, hipStream_t s);
+hipError_t proposal_init(Proposal &pr, uint64_t seed, hipStream_t s);
+hipError_t proposal_labels(const MeshDev &m, Proposal &pr, const int32_t *tri_id, int64_t n, int32_t *seg,
+                           int32_t *label, uint32_t *count, hipStream_t s);
+hipError_t proposal_predict(const MeshDev &m, const Proposal &pr, const float *from, const float *to, int64_t n,
+                            int nb, uint8_t *bucket, hipStream_t s);
+hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from, const float *to,
+                               const int32_t *seg, const int32_t *lab, int64_t r0, int rows, int nb, float *loss,
+                               float loss_scale, char *ws, hipStream_t s, float *logits_out);
+hipError_t proposal_adam(Proposal &pr, float lr, int step, hipStream_t s);
+size_t proposal_batch_scratch(int rows);
+hipError_t proposal_features(const MeshDev &m, const float *from, const float *to, int64_t n, __bf16 *X,
+                             hipStream_t s);
+hipError_t proposal_set_params(Proposal &pr, hipStream_t s);
 
 }  // namespace rsi

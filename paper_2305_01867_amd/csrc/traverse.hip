@@ -237,6 +237,8 @@ struct TravParams {
     unsigned long long *counters;
     uint32_t *visits;
     uint32_t *tests;
+    const uint8_t *bucket;
+    const int32_t *bucket_ref;
 };
 
 __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why) {
@@ -256,7 +258,10 @@ __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why)
 constexpr int kRefillMin = 8;     // refill when at least this many lanes idle
 constexpr int kDone = INT32_MIN;  // nothing left for the lane's segment
 
-template <int MODE, bool CERT, bool STATS>
+// PROP: proposal-first order.  Phase 0 traverses the predicted frontier
+// subtree; phase 1 the whole tree with that subtree left out.  Together they
+// visit exactly what the plain order visits, so results do not change.
+template <int MODE, bool CERT, bool STATS, bool PROP>
 __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
     extern __shared__ int lds_stack[];
     int *stk = lds_stack + threadIdx.x;
@@ -282,6 +287,9 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
     bool found = false, unsure = false, flagged = false, overflow = false;
     uint32_t n_nodes = 0, n_tests = 0;
     int64_t steps = 0;
+    int phase = 1, skip = kDone;  // kDone never equals a child reference
+    bool best_late = false;       // best hit found in phase 1 (a proposal miss)
+    uint32_t n_late = 0;          // this lane's proposal misses, summed per wave at exit
 
     auto pop = [&]() -> int { return sp > 0 ? stk[--sp * stride] : kDone; };
 
@@ -306,6 +314,12 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                     found = unsure = flagged = overflow = false;
                     n_nodes = n_tests = 0;
                     steps = 0;
+                    best_late = false;
+                    if (PROP) {
+                        skip = p.bucket_ref[p.bucket[ray]];
+                        ref = skip;
+                        phase = 0;
+                    }
                     if (!setup_ray(p.from, p.to, ray, scale, r)) {
                         if (STATS) {
                             p.visits[ray] = 0;
@@ -352,8 +366,12 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                     if (STATS)
                         ++n_nodes;
                     float tl, tr;
-                    const bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, r, tlimit, tl);
-                    const bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, r, tlimit, tr);
+                    bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, r, tlimit, tl);
+                    bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, r, tlimit, tr);
+                    if (PROP) {  // in phase 1 the proposed subtree is done already
+                        hl = hl && refs.x != skip;
+                        hr = hr && refs.y != skip;
+                    }
                     if (hl && hr) {
                         if (sp >= p.stack_depth) {
                             overflow = true;
@@ -391,12 +409,14 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                     if (decide32(m)) {
                         if (MODE == MODE_BOOL) {
                             found = true;
+                            best_late = phase == 1;
                             ref = kDone;
                         } else {
                             const float t = m.T / m.det;
                             if (t < best_t || (t == best_t && id < best_id)) {
                                 best_t = t;
                                 best_id = id;
+                                best_late = phase == 1;
                                 if (MODE == MODE_BARY) {
                                     best_u = m.U / m.det;
                                     best_v = m.W / m.det;
@@ -411,6 +431,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                     if (MODE == MODE_BOOL) {
                         if (c == kHit) {
                             found = true;
+                            best_late = phase == 1;
                             ref = kDone;
                         } else if (c == kUnsure) {
                             unsure = true;
@@ -423,6 +444,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                             best_lo = lo;
                             best_hi = hi;
                             best_id = id;
+                            best_late = phase == 1;
                             tlimit = fminf(tlimit, hi * (1.0f + 0x1p-20f));
                         } else if (!(lo > best_hi)) {
                             flagged = true;  // intervals overlap: order not certain
@@ -433,8 +455,16 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
             }
         }
 
+        // ---- proposal: the predicted subtree is exhausted, go on with the rest
+        if (PROP && ray >= 0 && ref == kDone && pend < 0 && phase == 0 && !found && !flagged && !overflow) {
+            phase = 1;
+            ref = p.root == skip ? kDone : p.root;
+        }
+
         // ---- finish lanes whose segment is decided
         if (ray >= 0 && ref == kDone && pend < 0) {
+            if (PROP && !STATS && best_late && (found || (MODE != MODE_BOOL && best_id >= 0 && !flagged && !overflow)))
+                ++n_late;  // the proposal did not hold the answer
             if (STATS) {
                 p.visits[ray] = n_nodes;
                 p.tests[ray] = n_tests;
@@ -460,6 +490,14 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
             }
             ray = -1;
         }
+    }
+    if (PROP && !STATS) {
+        // one atomic per wave: a shared counter across eight XCDs is costly
+        uint32_t w = n_late;
+        for (int off = 32; off > 0; off >>= 1)
+            w += __shfl_xor(w, off);
+        if (lane == 0 && w)
+            atomicAdd(p.counters + 2, (unsigned long long)w);
     }
 }
 
@@ -591,30 +629,39 @@ __global__ void k_fill_miss(Outs out, int64_t n, int mode) {
         write_out(out, i, mode, -1, 0.0f, 0.0f, 0.0f);
 }
 
-template <int MODE, bool CERT, bool STATS>
+template <int MODE, bool CERT, bool STATS, bool PROP>
 void launch_pass1(const TravParams &p, int block, hipStream_t s) {
     const size_t lds = (size_t)p.stack_depth * block * sizeof(int);
     int dev = 0, cus = 256, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_traverse<MODE, CERT, STATS>),
-                                                       block, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&k_traverse<MODE, CERT, STATS, PROP>), block, lds);
     if (per_cu < 1)
         per_cu = 1;
     const int64_t want = (p.n + block - 1) / block;
     const int64_t resident = (int64_t)cus * per_cu;
     const int grid = (int)(want < resident ? want : resident);
-    k_traverse<MODE, CERT, STATS><<<grid, block, lds, s>>>(p);
+    k_traverse<MODE, CERT, STATS, PROP><<<grid, block, lds, s>>>(p);
+}
+
+template <int MODE, bool STATS>
+void dispatch_mode(const TravParams &p, bool cert, bool prop, int block, hipStream_t s) {
+    if (cert)
+        prop ? launch_pass1<MODE, true, STATS, true>(p, block, s) : launch_pass1<MODE, true, STATS, false>(p, block, s);
+    else
+        prop ? launch_pass1<MODE, false, STATS, true>(p, block, s) : launch_pass1<MODE, false, STATS, false>(p, block, s);
 }
 
 template <bool STATS>
 void dispatch_pass1(const TravParams &p, int mode, bool cert, int block, hipStream_t s) {
+    const bool prop = p.bucket != nullptr;
     if (mode == MODE_BOOL)
-        cert ? launch_pass1<MODE_BOOL, true, STATS>(p, block, s) : launch_pass1<MODE_BOOL, false, STATS>(p, block, s);
+        dispatch_mode<MODE_BOOL, STATS>(p, cert, prop, block, s);
     else if (mode == MODE_FIRST)
-        cert ? launch_pass1<MODE_FIRST, true, STATS>(p, block, s) : launch_pass1<MODE_FIRST, false, STATS>(p, block, s);
+        dispatch_mode<MODE_FIRST, STATS>(p, cert, prop, block, s);
     else
-        cert ? launch_pass1<MODE_BARY, true, STATS>(p, block, s) : launch_pass1<MODE_BARY, false, STATS>(p, block, s);
+        dispatch_mode<MODE_BARY, STATS>(p, cert, prop, block, s);
 }
 
 TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
@@ -638,6 +685,8 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.counters = reinterpret_cast<unsigned long long *>(a.counters);
     p.visits = a.visits;
     p.tests = a.tests;
+    p.bucket = a.bucket;
+    p.bucket_ref = a.bucket_ref;
     return p;
 }
 
