@@ -179,7 +179,8 @@ typedef enum rsi_export_what {
                                    words 4-7  right box x lo, x hi, y lo, y hi
                                    words 8-11 left z lo, z hi, right z lo, z hi
                                    word 12, 13 left / right child: >= 0 internal node,
-                                   < 0 leaf at sorted position ~ref; words 14-15 zero   */
+                                   < 0 leaf at sorted position ~ref; words 14, 15 the
+                                   first and last sorted leaf the node covers            */
     RSI_EXPORT_PARENTS = 3,     /* int32 [2 N_t - 1]: parent of internal node i at [i]
                                    (-1 for the root), of leaf k at [N_t - 1 + k]        */
     RSI_EXPORT_COUNTERS = 4,    /* int32 [N_t - 1]: arrivals counted at each internal
@@ -275,6 +276,41 @@ rsi_status rsi_proposal_frontier(rsi_mesh mesh, int32_t *bucket_ref, int32_t *bu
  * count).  Loading checks the header against this mesh.  Both wait. */
 rsi_status rsi_proposal_save(rsi_mesh mesh, const char *path);
 rsi_status rsi_proposal_load(rsi_mesh mesh, const char *path);
+
+/* ------------------------------------------------------------------------
+ * Batched form: up to 64 meshes of uneven size and their segment batches in
+ * one BVH build and one persistent traversal launch.  Mesh m owns vertices
+ * [vertex_offsets[m], vertex_offsets[m+1]) of the concatenated vertex array,
+ * triangles [triangle_offsets[m], ...+1) whose indices are relative to its
+ * own first vertex, and segments [ray_offsets[m], ...+1).  Keys are the mesh
+ * id (6 bits) above a 57-bit Morton code (19 bits per axis of the mesh's own
+ * box), so one sort, one radix tree and one bottom-up pass cover all meshes
+ * and each mesh is one subtree.  The traversal takes (mesh, segment range)
+ * items of up to 2048 segments from a queue.  Reported triangle indices are
+ * relative to the segment's mesh.  rsi_batch_create allocates everything;
+ * rsi_batch_build and rsi_batch_intersect allocate nothing and never wait, so
+ * both may be captured in a HIP graph and replayed (inputs at the same
+ * addresses).  Triangles with an index outside their mesh are never hit.
+ * ---------------------------------------------------------------------- */
+typedef struct rsi_batch_s *rsi_batch;
+
+#define RSI_BATCH_MAX_MESHES 64
+
+/* Offsets: host int64 arrays of n_meshes + 1 entries, starting at 0 and
+ * non-decreasing.  Totals: triangles < 2^30, vertices and segments < 2^31. */
+rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, const int64_t *triangle_offsets,
+                            const int64_t *ray_offsets, void *stream, rsi_batch *out);
+/* vertices: device float [total][3]; triangles: device int32 [total][3]. */
+rsi_status rsi_batch_build(rsi_batch batch, const float *vertices, const int32_t *triangles, void *stream);
+/* Segments: device float [total][3] each; outputs as rsi_intersect, over all
+ * segments.  opts->proposal must be 0. */
+rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const float *rays_to, int32_t mode,
+                               const rsi_intersect_opts *opts, const rsi_outputs *out, void *stream);
+/* The combined BVH's arrays as rsi_mesh_export, plus RSI_EXPORT_MESH_ROOTS:
+ * int32 [n_meshes], each mesh's subtree root (INT32_MIN for an empty mesh). */
+#define RSI_EXPORT_MESH_ROOTS 7
+rsi_status rsi_batch_export(rsi_batch batch, int32_t what, void *dst, int64_t dst_bytes, void *stream);
+rsi_status rsi_batch_destroy(rsi_batch batch);
 
 const char *rsi_status_string(rsi_status status);
 const char *rsi_last_error(void);   /* message of this thread's last failure, "" if none */

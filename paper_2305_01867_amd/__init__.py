@@ -24,6 +24,7 @@ __all__ = [
     "rsi_proposal_train", "rsi_proposal_predict", "rsi_proposal_params", "rsi_proposal_gradient",
     "rsi_proposal_features", "rsi_proposal_frontier", "rsi_proposal_save", "rsi_proposal_load",
     "MLP_PARAMS", "MLP_INPUTS", "MLP_BUCKETS",
+    "Batch", "rsi_batch_create", "rsi_batch_build", "rsi_batch_intersect", "rsi_batch_export", "rsi_batch_destroy",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -98,6 +99,13 @@ def lib():
     L.rsi_proposal_frontier.argtypes = [P, P, P, ctypes.POINTER(I32), P]
     L.rsi_proposal_save.argtypes = [P, ctypes.c_char_p]
     L.rsi_proposal_load.argtypes = [P, ctypes.c_char_p]
+    L.rsi_batch_create.argtypes = [I32, P, P, P, P, ctypes.POINTER(P)]
+    L.rsi_batch_build.argtypes = [P, P, P, P]
+    L.rsi_batch_intersect.argtypes = [P, P, P, I32, ctypes.POINTER(_IntersectOpts), ctypes.POINTER(_Outputs), P]
+    L.rsi_batch_export.argtypes = [P, I32, P, I64, P]
+    L.rsi_batch_destroy.argtypes = [P]
+    for f in ("rsi_batch_create", "rsi_batch_build", "rsi_batch_intersect", "rsi_batch_export", "rsi_batch_destroy"):
+        getattr(L, f).restype = ctypes.c_int
     for f in ("rsi_build", "rsi_intersect", "rsi_destroy", "rsi_mesh_info_get", "rsi_mesh_export",
               "rsi_traversal_stats", "rsi_proposal_train", "rsi_proposal_predict", "rsi_proposal_params",
               "rsi_proposal_gradient", "rsi_proposal_features", "rsi_proposal_frontier", "rsi_proposal_save",
@@ -372,3 +380,121 @@ def rsi_proposal_save(mesh: Mesh, path: str):
 
 def rsi_proposal_load(mesh: Mesh, path: str):
     _check(lib().rsi_proposal_load(mesh.handle, os.fsencode(path)))
+
+
+# --------------------------------------------------------------- batched form
+class Batch:
+    """Many meshes and their segment batches (owns the library handle)."""
+
+    def __init__(self, handle, v_off, t_off, r_off):
+        self._h = handle
+        self.vertex_offsets = list(v_off)
+        self.triangle_offsets = list(t_off)
+        self.ray_offsets = list(r_off)
+        self.n_meshes = len(v_off) - 1
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RSIError(5, "batch destroyed")
+        return self._h
+
+    @property
+    def n_rays(self):
+        return self.ray_offsets[-1]
+
+    def close(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            _check(lib().rsi_batch_destroy(h))
+
+    def __del__(self):
+        try:
+            if self._h is not None and _lib is not None:
+                _lib.rsi_batch_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def rsi_batch_create(vertex_offsets, triangle_offsets, ray_offsets, stream=None) -> Batch:
+    """Offsets: sequences of n_meshes + 1 nondecreasing ints starting at 0."""
+    import numpy as np
+
+    offs = [np.ascontiguousarray(np.asarray(o, dtype=np.int64)) for o in (vertex_offsets, triangle_offsets, ray_offsets)]
+    if not (len(offs[0]) == len(offs[1]) == len(offs[2]) >= 2):
+        raise ValueError("three offset arrays of the same length n_meshes + 1 >= 2")
+    h = ctypes.c_void_p()
+    _check(lib().rsi_batch_create(len(offs[0]) - 1, *(o.ctypes.data_as(ctypes.c_void_p) for o in offs),
+                                  _stream_handle(stream), ctypes.byref(h)))
+    return Batch(h, *(o.tolist() for o in offs))
+
+
+def rsi_batch_build(batch: Batch, vertices: torch.Tensor, triangles: torch.Tensor, stream=None):
+    for t, name, dt in ((vertices, "vertices", torch.float32), (triangles, "triangles", torch.int32)):
+        if isinstance(t, torch.Tensor) and t.dtype != dt:
+            raise TypeError(f"{name} must be {dt}, got {t.dtype}")
+    _need(vertices, "vertices", torch.float32, 3)
+    _need(triangles, "triangles", torch.int32, 3)
+    if vertices.shape[0] != batch.vertex_offsets[-1] or triangles.shape[0] != batch.triangle_offsets[-1]:
+        raise ValueError("array sizes differ from the batch's offsets")
+    _check(lib().rsi_batch_build(batch.handle, _p(vertices), _p(triangles), _stream_handle(stream)))
+
+
+def rsi_batch_intersect(batch: Batch, rays_from, rays_to, mode: str = "boolean", precision: str = "plain",
+                        block: int = 0, stack_depth: int = 0, out: dict | None = None, stream=None) -> dict:
+    """Outputs over all segments (triangle indices relative to each mesh)."""
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {list(MODES)}")
+    n = _rays(rays_from, rays_to)
+    if n != batch.n_rays:
+        raise ValueError("segment count differs from the batch's ray offsets")
+    dev = rays_from.device
+    out = dict(out or {})
+    if mode == "boolean":
+        out.setdefault("hit", torch.empty(n, dtype=torch.uint8, device=dev))
+    else:
+        out.setdefault("tri_id", torch.empty(n, dtype=torch.int32, device=dev))
+    if mode == "barycentric":
+        out.setdefault("uvt", torch.empty((n, 3), dtype=torch.float32, device=dev))
+    out.setdefault("counters", torch.zeros(4, dtype=torch.int64, device=dev))
+
+    def ptr(k):
+        return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()
+
+    o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"))
+    opts = _iopts(precision, block, stack_depth, False)
+    _check(lib().rsi_batch_intersect(batch.handle, _p(rays_from), _p(rays_to), MODES[mode], ctypes.byref(opts),
+                                     ctypes.byref(o), _stream_handle(stream)))
+    return out
+
+
+def rsi_batch_export(batch: Batch, what: str, stream=None) -> torch.Tensor:
+    """Arrays of the combined BVH (as rsi_mesh_export) or "mesh_roots"."""
+    if what == "mesh_roots":
+        dst = torch.empty(batch.n_meshes, dtype=torch.int32, device="cuda")
+        _check(lib().rsi_batch_export(batch.handle, 7, _p(dst), dst.numel() * 4, _stream_handle(stream)))
+        return dst
+    view = Mesh(None, batch.vertex_offsets[-1], batch.triangle_offsets[-1], 63, stream)
+    nt = view.n_triangles
+    shapes = {
+        "sorted_keys": ((nt,), torch.int64), "sorted_ids": ((nt,), torch.int32),
+        "nodes": ((max(nt - 1, 0), 16), torch.int32), "parents": ((max(2 * nt - 1, 0),), torch.int32),
+        "counters": ((max(nt - 1, 0),), torch.int32), "leaves": ((nt, 12), torch.int32),
+        "bounds": ((8 if nt > 0 else 0,), torch.float32),
+    }
+    shape, dtype = shapes[what]
+    dst = torch.empty(shape, dtype=dtype, device="cuda")
+    _check(lib().rsi_batch_export(batch.handle, EXPORTS[what], _p(dst), dst.numel() * dst.element_size(),
+                                  _stream_handle(stream)))
+    return dst
+
+
+def rsi_batch_destroy(batch: Batch):
+    batch.close()

@@ -6,6 +6,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "rsi.h"
 #include "rsi_internal.h"
@@ -15,6 +17,15 @@ struct rsi_mesh_s {
     rsi::MeshDev dev;
     hipStream_t stream;  // the stream the mesh was built on (used to free it)
     void *block;         // the one device allocation holding every array
+};
+
+struct rsi_batch_s {
+    uint32_t magic;
+    rsi::MeshDev dev;   // the combined BVH
+    rsi::BatchDev b;
+    hipStream_t stream;
+    void *block;
+    bool built;
 };
 
 namespace {
@@ -66,7 +77,19 @@ rsi_status check_device() {
     return RSI_OK;
 }
 
+// Inside stream capture only stream work may be queued; pointer queries are
+// skipped there (the capture's first eager run has checked the same pointers).
+thread_local bool g_capturing = false;
+
+void note_capture(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    g_capturing = hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
+    (void)hipGetLastError();
+}
+
 bool is_device_ptr(const void *p) {
+    if (g_capturing)
+        return true;
     hipPointerAttribute_t attr;
     hipError_t e = hipPointerGetAttributes(&attr, p);
     if (e != hipSuccess) {
@@ -470,6 +493,255 @@ rsi_status rsi_mesh_export(rsi_mesh mesh, int32_t what, void *dst, int64_t dst_b
     if (e != hipSuccess)
         return fail_hip(e, "rsi_mesh_export");
     return RSI_OK;
+}
+
+// ------------------------------------------------------------------ batch
+constexpr uint32_t kBatchMagic = 0x52534942u;  // "RSIB"
+constexpr int64_t kBatchChunk = 2048;
+
+static bool valid_batch(rsi_batch b) { return b != nullptr && b->magic == kBatchMagic; }
+
+static bool offsets_ok(const int64_t *off, int M, int64_t limit) {
+    if (!off || off[0] != 0)
+        return false;
+    for (int m = 0; m < M; ++m)
+        if (off[m + 1] < off[m])
+            return false;
+    return off[M] < limit;
+}
+
+rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, const int64_t *triangle_offsets,
+                            const int64_t *ray_offsets, void *stream, rsi_batch *out) {
+    g_error.clear();
+    if (!out)
+        return fail(RSI_E_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (n_meshes < 1 || n_meshes > RSI_BATCH_MAX_MESHES)
+        return fail(RSI_E_ARG, "n_meshes must be in 1..64");
+    const int M = n_meshes;
+    if (!offsets_ok(vertex_offsets, M, int64_t(1) << 31) || !offsets_ok(triangle_offsets, M, int64_t(1) << 30) ||
+        !offsets_ok(ray_offsets, M, int64_t(1) << 31))
+        return fail(RSI_E_ARG, "offsets must start at 0, not decrease, and stay below the size limits");
+    rsi_status st = check_device();
+    if (st != RSI_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rsi_batch bt = new (std::nothrow) rsi_batch_s();
+    if (!bt)
+        return fail(RSI_E_NOMEM, "host allocation failed");
+    bt->magic = kBatchMagic;
+    bt->stream = s;
+    bt->block = nullptr;
+    bt->built = false;
+    rsi::MeshDev &d = bt->dev;
+    rsi::BatchDev &b = bt->b;
+    d.nv = vertex_offsets[M];
+    d.nt = triangle_offsets[M];
+    d.morton_bits = 63;
+    d.root = d.nt >= 2 ? 0 : (d.nt == 1 ? ~0 : INT32_MIN);
+    b.M = M;
+    b.n_rays = ray_offsets[M];
+    std::vector<int4> items;
+    for (int m = 0; m < M; ++m)
+        for (int64_t a = ray_offsets[m]; a < ray_offsets[m + 1]; a += kBatchChunk)
+            items.push_back(make_int4(m, (int)a, (int)std::min(a + kBatchChunk, ray_offsets[m + 1]), 0));
+    b.n_items = (int)items.size();
+    const int64_t nt = d.nt, nv = d.nv;
+    const size_t sz_V = round_up(12 * (size_t)nv + 4), sz_F = round_up(12 * (size_t)nt + 4);
+    const size_t sz_keys = round_up(8 * (size_t)nt + 8), sz_ids = round_up(4 * (size_t)nt + 4);
+    const size_t sz_nodes = round_up(64 * (size_t)(nt > 1 ? nt - 1 : 1));
+    const size_t sz_par = round_up(4 * (size_t)(nt > 0 ? 2 * nt - 1 : 1)), sz_cnt = round_up(4 * (size_t)(nt > 1 ? nt - 1 : 1));
+    const size_t sz_tris = round_up(48 * (size_t)nt + 48), sz_small = 256;
+    const size_t sz_tmp = round_up(rsi::sort_tmp_bytes(nt, 63));
+    const size_t sz_off = round_up(8 * (size_t)(M + 1)) * 2 + round_up(4 * (size_t)(M + 1)) + round_up(4 * (size_t)M) * 2;
+    const size_t sz_tm = round_up(4 * (size_t)nt + 4), sz_mb = round_up(32 * (size_t)M);
+    const size_t sz_items = round_up(16 * (size_t)(b.n_items + 1));
+    const size_t sz_q = round_up(4 * (size_t)b.n_rays + 4) + 256;
+    const size_t total = sz_V + sz_F + sz_keys + sz_ids + sz_nodes + sz_par + sz_cnt + sz_tris + sz_small + sz_tmp +
+                         sz_off + sz_tm + sz_mb + sz_items + sz_q;
+    hipError_t e = hipMallocAsync(&bt->block, total, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        bt->magic = kDead;
+        delete bt;
+        return fail(RSI_E_NOMEM, std::string("hipMallocAsync failed: ") + hipGetErrorString(e));
+    }
+    char *p = static_cast<char *>(bt->block);
+    auto take = [&](size_t bytes) {
+        char *q = p;
+        p += bytes;
+        return q;
+    };
+    d.V = reinterpret_cast<float *>(take(sz_V));
+    d.F = reinterpret_cast<int32_t *>(take(sz_F));
+    d.keys = take(sz_keys);
+    d.ids = reinterpret_cast<int32_t *>(take(sz_ids));
+    d.nodes = reinterpret_cast<rsi::Node *>(take(sz_nodes));
+    d.parent = reinterpret_cast<int32_t *>(take(sz_par));
+    d.counters = reinterpret_cast<int32_t *>(take(sz_cnt));
+    d.tris = reinterpret_cast<rsi::Tri *>(take(sz_tris));
+    char *small = take(sz_small);
+    d.bounds = reinterpret_cast<float *>(small);
+    d.flags = reinterpret_cast<int32_t *>(small + 64);
+    d.sort_tmp = take(sz_tmp);
+    b.v_off = reinterpret_cast<int64_t *>(take(round_up(8 * (size_t)(M + 1))));
+    b.t_off = reinterpret_cast<int64_t *>(take(round_up(8 * (size_t)(M + 1))));
+    b.r_off = reinterpret_cast<int32_t *>(take(round_up(4 * (size_t)(M + 1))));
+    b.mesh_toff = reinterpret_cast<int32_t *>(take(round_up(4 * (size_t)M)));
+    b.roots = reinterpret_cast<int32_t *>(take(round_up(4 * (size_t)M)));
+    b.tri_mesh = reinterpret_cast<int32_t *>(take(sz_tm));
+    b.mesh_bounds = reinterpret_cast<float *>(take(sz_mb));
+    b.items = reinterpret_cast<int4 *>(take(sz_items));
+    char *q = take(sz_q);
+    b.counters = reinterpret_cast<uint64_t *>(q);
+    b.queue_len = reinterpret_cast<uint32_t *>(q + 32);
+    b.queue = reinterpret_cast<int32_t *>(q + 256);
+    d.bytes = (int64_t)total;
+    std::vector<int32_t> r32(M + 1), toff(M);
+    for (int m = 0; m <= M; ++m)
+        r32[m] = (int32_t)ray_offsets[m];
+    for (int m = 0; m < M; ++m)
+        toff[m] = (int32_t)triangle_offsets[m];
+    e = hipMemcpyAsync(b.v_off, vertex_offsets, 8 * (size_t)(M + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b.t_off, triangle_offsets, 8 * (size_t)(M + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b.r_off, r32.data(), 4 * (size_t)(M + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b.mesh_toff, toff.data(), 4 * (size_t)M, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && b.n_items > 0)
+        e = hipMemcpyAsync(b.items, items.data(), 16 * (size_t)b.n_items, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);  // the host vectors go out of scope
+    if (e != hipSuccess) {
+        rsi_batch_destroy(bt);
+        return fail_hip(e, "rsi_batch_create");
+    }
+    *out = bt;
+    return RSI_OK;
+}
+
+rsi_status rsi_batch_build(rsi_batch batch, const float *vertices, const int32_t *triangles, void *stream) {
+    g_error.clear();
+    if (!valid_batch(batch))
+        return fail(RSI_E_STATE, "invalid or destroyed batch handle");
+    rsi::MeshDev &d = batch->dev;
+    if ((d.nv > 0 && (!vertices || !aligned4(vertices))) || (d.nt > 0 && (!triangles || !aligned4(triangles))))
+        return fail(RSI_E_ARG, "vertices / triangles must be non-NULL and 4-byte aligned");
+    rsi_status st = check_device();
+    if (st != RSI_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    note_capture(s);
+    if ((d.nv > 0 && (st = check_dev_ptr(vertices, "vertices")) != RSI_OK) ||
+        (d.nt > 0 && (st = check_dev_ptr(triangles, "triangles")) != RSI_OK))
+        return st;
+    if ((st = pending_error("before rsi_batch_build")) != RSI_OK)
+        return st;
+    hipError_t e = rsi::launch_batch_build(d, batch->b, vertices, triangles, s);
+    if (e != hipSuccess)
+        return fail_hip(e, "rsi_batch_build");
+    batch->built = true;
+    return RSI_OK;
+}
+
+rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const float *rays_to, int32_t mode,
+                               const rsi_intersect_opts *opts, const rsi_outputs *out, void *stream) {
+    g_error.clear();
+    if (!valid_batch(batch))
+        return fail(RSI_E_STATE, "invalid or destroyed batch handle");
+    if (!batch->built)
+        return fail(RSI_E_STATE, "rsi_batch_build has not been called");
+    rsi::BatchDev &b = batch->b;
+    const int64_t n = b.n_rays;
+    if (mode != RSI_MODE_BOOLEAN && mode != RSI_MODE_FIRST_HIT && mode != RSI_MODE_BARYCENTRIC)
+        return fail(RSI_E_ARG, "unknown mode");
+    int precision, block, stack;
+    rsi_status st = parse_intersect_opts(opts, precision, block, stack);
+    if (st != RSI_OK)
+        return st;
+    if (opts && opts->proposal)
+        return fail(RSI_E_ARG, "the batched form has no learned proposal");
+    if (!out)
+        return fail(RSI_E_ARG, "out must not be NULL");
+    if (n > 0 && (!rays_from || !rays_to || !aligned4(rays_from) || !aligned4(rays_to)))
+        return fail(RSI_E_ARG, "rays_from / rays_to must be non-NULL and 4-byte aligned");
+    if (n > 0 && ((mode == RSI_MODE_BOOLEAN && !out->hit) || (mode != RSI_MODE_BOOLEAN && !out->tri_id) ||
+                  (mode == RSI_MODE_BARYCENTRIC && !out->uvt)))
+        return fail(RSI_E_ARG, "missing output buffer for this mode");
+    if ((st = check_device()) != RSI_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    note_capture(s);
+    if (n > 0 && ((st = check_dev_ptr(rays_from, "rays_from")) != RSI_OK ||
+                  (st = check_dev_ptr(rays_to, "rays_to")) != RSI_OK))
+        return st;
+    if ((st = pending_error("before rsi_batch_intersect")) != RSI_OK)
+        return st;
+    rsi::TraverseArgs a;
+    a.from = rays_from;
+    a.to = rays_to;
+    a.n = n;
+    a.mode = mode;
+    a.certified = precision == RSI_PRECISION_CERTIFIED;
+    a.block = block;
+    a.stack = stack;
+    a.hit = out->hit;
+    a.tri_id = out->tri_id;
+    a.uvt = out->uvt;
+    a.counters = out->counters ? out->counters : b.counters;
+    a.queue = b.queue;
+    a.queue_len = b.queue_len;
+    a.items = b.items;
+    a.n_items = b.n_items;
+    a.n_meshes = b.M;
+    a.mesh_root = b.roots;
+    a.mesh_toff = b.mesh_toff;
+    a.ray_off = b.r_off;
+    hipError_t e = rsi::launch_intersect(batch->dev, a, s);
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_batch_intersect");
+}
+
+rsi_status rsi_batch_export(rsi_batch batch, int32_t what, void *dst, int64_t dst_bytes, void *stream) {
+    g_error.clear();
+    if (!valid_batch(batch))
+        return fail(RSI_E_STATE, "invalid or destroyed batch handle");
+    if (what == RSI_EXPORT_MESH_ROOTS) {
+        const int64_t bytes = 4 * (int64_t)batch->b.M;
+        if (!dst || dst_bytes < bytes)
+            return fail(RSI_E_ARG, "dst too small");
+        rsi_status st = check_device();
+        if (st != RSI_OK)
+            return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const bool host_dst = !is_device_ptr(dst);
+        hipError_t e = hipMemcpyAsync(dst, batch->b.roots, (size_t)bytes, hipMemcpyDefault, s);
+        if (e == hipSuccess && host_dst)
+            e = hipStreamSynchronize(s);
+        return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_batch_export");
+    }
+    // the other items come from the combined BVH, exported like a mesh
+    rsi_mesh_s view;
+    view.magic = kMagic;
+    view.dev = batch->dev;
+    view.stream = batch->stream;
+    view.block = nullptr;
+    rsi_status st = rsi_mesh_export(&view, what, dst, dst_bytes, stream);
+    view.magic = kDead;
+    return st;
+}
+
+rsi_status rsi_batch_destroy(rsi_batch batch) {
+    if (!batch)
+        return RSI_OK;
+    if (batch->magic != kBatchMagic)
+        return fail(RSI_E_STATE, "invalid or destroyed batch handle");
+    batch->magic = kDead;
+    hipError_t e = hipSuccess;
+    if (batch->block)
+        e = hipFreeAsync(batch->block, batch->stream);
+    delete batch;
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_batch_destroy");
 }
 
 // ------------------------------------------------------------------ proposal

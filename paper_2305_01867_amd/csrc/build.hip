@@ -56,7 +56,8 @@ __global__ __launch_bounds__(1024) void k_mesh_bounds(const float *__restrict__ 
         for (int a = 0; a < 3; ++a) {
             bounds[a] = lo[a];
             bounds[3 + a] = hi[a];
-            scale = fmaxf(scale, fmaxf(fabsf(lo[a]), fabsf(hi[a])));
+            if (lo[a] <= hi[a])  // no vertices: no scale
+                scale = fmaxf(scale, fmaxf(fabsf(lo[a]), fabsf(hi[a])));
         }
         bounds[6] = scale;
         bounds[7] = 0.0f;
@@ -120,6 +121,34 @@ __global__ __launch_bounds__(256) void k_morton(const float *__restrict__ V, int
         key = (K)(key << 1) | spread3((K)quantise(c[a], lo, ext, two_b, top));
     }
     keys[t] = key;
+}
+
+// Batched form: the key of a triangle of mesh m is m (6 bits) above a 57-bit
+// Morton code (19 bits per axis) of its centroid normalised to mesh m's box,
+// so each mesh's triangles are contiguous after the sort and form one subtree.
+__global__ __launch_bounds__(256) void k_morton_batch(const float *__restrict__ V, const int32_t *__restrict__ F,
+                                                      const int32_t *__restrict__ tri_mesh, int64_t nt,
+                                                      const float *__restrict__ mesh_bounds,
+                                                      uint64_t *__restrict__ keys, int32_t *__restrict__ ids) {
+#pragma clang fp contract(off)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt)
+        return;
+    ids[t] = (int32_t)t;
+    const int m = tri_mesh[t];
+    const int32_t i0 = F[3 * t], i1 = F[3 * t + 1], i2 = F[3 * t + 2];
+    if (i0 < 0 || i1 < 0 || i2 < 0) {  // marked invalid while copying
+        keys[t] = (uint64_t)m << 57;
+        return;
+    }
+    const float *bb = mesh_bounds + 8 * m;
+    const float two_b = (float)(1u << 19), top = (float)((1u << 19) - 1u);
+    uint64_t key = 0;
+    for (int a = 2; a >= 0; --a) {
+        const float c = ((V[3 * (int64_t)i0 + a] + V[3 * (int64_t)i1 + a]) + V[3 * (int64_t)i2 + a]) / 3.0f;
+        key = (key << 1) | spread3((uint64_t)quantise(c, bb[a], bb[3 + a] - bb[a], two_b, top));
+    }
+    keys[t] = ((uint64_t)m << 57) | key;
 }
 
 // ---------------------------------------------------------- 3. radix sort
@@ -273,7 +302,7 @@ __global__ __launch_bounds__(256) void k_radix_tree(const K *__restrict__ keys, 
     const int lo = min(i, j), hi = max(i, j);
     const int left = (lo == split) ? ~split : split;
     const int right = (hi == split + 1) ? ~(split + 1) : split + 1;
-    nodes[i].refs = make_int4(left, right, 0, 0);
+    nodes[i].refs = make_int4(left, right, lo, hi);
     parent[left >= 0 ? left : (n - 1) + ~left] = i;
     parent[right >= 0 ? right : (n - 1) + ~right] = i;
     counters[i] = 0;
@@ -370,8 +399,10 @@ __global__ void k_zero_i32(int32_t *p, int n) {
 
 inline int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
 
+// Sort (key, id), build the radix tree and fill the boxes bottom-up, for keys
+// already in m.keys and ids in m.ids.
 template <typename K>
-hipError_t build_typed(MeshDev &m, hipStream_t s) {
+hipError_t build_from_keys(MeshDev &m, int key_bits, hipStream_t s) {
     const int64_t nt = m.nt;
     K *keys = static_cast<K *>(m.keys);
     K *keys_tmp = static_cast<K *>(m.sort_tmp);
@@ -379,9 +410,6 @@ hipError_t build_typed(MeshDev &m, hipStream_t s) {
     const int ntiles = blocks_for(nt, kSortTile);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ids_tmp + nt);
 
-    k_morton<K><<<blocks_for(nt, 256), 256, 0, s>>>(m.V, m.nv, m.F, nt, m.bounds, keys, m.ids, m.flags);
-
-    const int key_bits = m.morton_bits;
     K *src_k = keys, *dst_k = keys_tmp;
     int32_t *src_i = m.ids, *dst_i = ids_tmp;
     for (int shift = 0; shift < key_bits; shift += 8) {
@@ -399,13 +427,30 @@ hipError_t build_typed(MeshDev &m, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename K>
+hipError_t build_typed(MeshDev &m, hipStream_t s) {
+    const int64_t nt = m.nt;
+    k_morton<K><<<blocks_for(nt, 256), 256, 0, s>>>(m.V, m.nv, m.F, nt, m.bounds, static_cast<K *>(m.keys), m.ids,
+                                                    m.flags);
+    return build_from_keys<K>(m, m.morton_bits, s);
+}
+
 }  // namespace
+
+hipError_t launch_morton_batch(MeshDev &m, const int32_t *tri_mesh, const float *mesh_bounds, hipStream_t s) {
+    if (m.nt > 0)
+        k_morton_batch<<<blocks_for(m.nt, 256), 256, 0, s>>>(m.V, m.F, tri_mesh, m.nt, mesh_bounds,
+                                                            static_cast<uint64_t *>(m.keys), m.ids);
+    return hipGetLastError();
+}
 
 size_t sort_tmp_bytes(int64_t nt, int morton_bits) {
     const size_t kb = morton_bits > 32 ? 8 : 4;
     const int64_t ntiles = (nt + kSortTile - 1) / kSortTile;
     return kb * nt + 4 * nt + 4 * (size_t)kRadix * ntiles + 256;
 }
+
+hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s) { return build_from_keys<uint64_t>(m, key_bits, s); }
 
 hipError_t launch_build(MeshDev &m, const float *, const int32_t *, hipStream_t s, size_t) {
     k_zero_i32<<<1, 64, 0, s>>>(m.flags, 4);

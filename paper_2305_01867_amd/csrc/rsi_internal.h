@@ -14,7 +14,7 @@ struct alignas(16) Node {
     float4 xy_left;   // left  x lo, x hi, y lo, y hi
     float4 xy_right;  // right x lo, x hi, y lo, y hi
     float4 z_both;    // left z lo, z hi, right z lo, z hi
-    int4 refs;        // left ref, right ref, 0, 0
+    int4 refs;        // left ref, right ref, first and last sorted leaf of the node
 };
 static_assert(sizeof(Node) == 64, "node must be 64 bytes");
 
@@ -77,9 +77,29 @@ struct MeshDev {
     Proposal prop;
 };
 
+// Batched form (batch.hip): many meshes in one BVH.
+struct BatchDev {
+    int M = 0;
+    int64_t *v_off = nullptr, *t_off = nullptr;  // device [M + 1]
+    int32_t *r_off = nullptr;                    // device [M + 1] first segment of each mesh
+    int32_t *mesh_toff = nullptr;                // device [M] first triangle of each mesh
+    int32_t *roots = nullptr;                    // device [M] subtree root (INT32_MIN: empty)
+    int32_t *tri_mesh = nullptr;                 // device [nt]
+    float *mesh_bounds = nullptr;                // device [M][8]
+    int4 *items = nullptr;                       // device [n_items] (mesh, first, end, 0)
+    int n_items = 0;
+    int32_t *queue = nullptr;                    // device [n_rays]
+    uint32_t *queue_len = nullptr;               // device [2]
+    uint64_t *counters = nullptr;                // device [4]
+    int64_t n_rays = 0;
+};
+hipError_t launch_batch_build(MeshDev &m, BatchDev &b, const float *V, const int32_t *F, hipStream_t s);
+
 // Build steps (build.hip).  All asynchronous on `s`.
 hipError_t launch_build(MeshDev &m, const float *V, const int32_t *F, hipStream_t s, size_t sort_tmp_bytes);
 size_t sort_tmp_bytes(int64_t nt, int morton_bits);
+hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s);
+hipError_t launch_morton_batch(MeshDev &m, const int32_t *tri_mesh, const float *mesh_bounds, hipStream_t s);
 
 // Intersection (traverse.hip).
 struct TraverseArgs {
@@ -99,6 +119,13 @@ struct TraverseArgs {
     uint32_t *tests = nullptr;     // stats only
     const uint8_t *bucket = nullptr;      // proposal per segment (NULL: none)
     const int32_t *bucket_ref = nullptr;  // frontier node per bucket
+    // batched form (NULL items: one mesh)
+    const int4 *items = nullptr;          // (mesh, first segment, end segment, 0)
+    int n_items = 0;
+    int n_meshes = 0;
+    const int32_t *mesh_root = nullptr;   // subtree root per mesh (INT32_MIN: empty)
+    const int32_t *mesh_toff = nullptr;   // first triangle of each mesh
+    const int32_t *ray_off = nullptr;     // [n_meshes + 1] first segment of each mesh
 };
 hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
 hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s);

@@ -239,6 +239,12 @@ struct TravParams {
     uint32_t *tests;
     const uint8_t *bucket;
     const int32_t *bucket_ref;
+    const int4 *items;
+    int n_items;
+    int n_meshes;
+    const int32_t *mesh_root;
+    const int32_t *mesh_toff;
+    const int32_t *ray_off;
 };
 
 __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why) {
@@ -272,11 +278,17 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
     const int n_internal = (int)p.nt - 1;
     const int64_t max_steps = 2 * p.nt + 8;
 
-    // each wave owns a contiguous range of segments; its lanes draw from it
+    // One mesh: each wave owns a contiguous range of segments and its lanes
+    // draw from it.  Batched form: waves take (mesh, segment range) items from
+    // a shared queue, one atomic per item.  Wave-uniform state.
+    const bool batch = p.items != nullptr;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    int64_t cursor = p.n * wave_id / waves;        // the same in every lane of the wave
-    const int64_t range_end = p.n * (wave_id + 1) / waves;
+    int64_t cursor = batch ? 0 : p.n * wave_id / waves;
+    int64_t range_end = batch ? 0 : p.n * (wave_id + 1) / waves;
+    bool items_left = batch;
+    int cur_root = p.root, cur_toff = 0;
+    int lane_root = p.root, lane_toff = 0;  // of the lane's current segment
 
     int64_t ray = -1;
     Ray r;
@@ -296,6 +308,21 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
     for (;;) {
         // ---- refill idle lanes
         const uint64_t idle = __ballot(ray < 0);
+        if (items_left && cursor >= range_end && idle) {
+            uint32_t k = 0;
+            if (lane == 0)
+                k = atomicAdd(p.next_ray, 1u);
+            k = __shfl(k, 0);
+            if (k < (uint32_t)p.n_items) {
+                const int4 it = p.items[k];
+                cursor = it.y;
+                range_end = it.z;
+                cur_root = p.mesh_root[it.x];
+                cur_toff = p.mesh_toff[it.x];
+            } else {
+                items_left = false;
+            }
+        }
         if (cursor < range_end && idle && (__popcll(idle) >= kRefillMin || idle == ~0ull)) {
             const int cnt = __popcll(idle);
             const int64_t base = cursor;
@@ -304,7 +331,9 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                 const int64_t idx = base + __popcll(idle & lt_mask);
                 if (idx < range_end) {
                     ray = idx;
-                    ref = p.root;
+                    lane_root = cur_root;
+                    lane_toff = cur_toff;
+                    ref = lane_root;
                     pend = -1;
                     sp = 0;
                     tlimit = 1.0f;
@@ -336,7 +365,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
         }
         const uint64_t active = __ballot(ray >= 0);
         if (!active) {
-            if (cursor >= range_end)
+            if (cursor >= range_end && !items_left)
                 break;
             continue;
         }
@@ -458,7 +487,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
         // ---- proposal: the predicted subtree is exhausted, go on with the rest
         if (PROP && ray >= 0 && ref == kDone && pend < 0 && phase == 0 && !found && !flagged && !overflow) {
             phase = 1;
-            ref = p.root == skip ? kDone : p.root;
+            ref = lane_root == skip ? kDone : lane_root;
         }
 
         // ---- finish lanes whose segment is decided
@@ -484,9 +513,9 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
             } else if (CERT && MODE == MODE_BARY && best_id >= 0) {
                 const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
                 const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, best_id);
-                write_out(p.out, ray, MODE, best_id, (float)h.u, (float)h.v, (float)h.t);
+                write_out(p.out, ray, MODE, best_id - lane_toff, (float)h.u, (float)h.v, (float)h.t);
             } else {
-                write_out(p.out, ray, MODE, best_id, best_u, best_v, best_t);
+                write_out(p.out, ray, MODE, best_id >= 0 ? best_id - lane_toff : -1, best_u, best_v, best_t);
             }
             ray = -1;
         }
@@ -516,6 +545,19 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
     const uint32_t count = *p.queue_len;
     for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < count; qi += gridDim.x * blockDim.x) {
         const int64_t i = p.queue[qi];
+        int root = p.root, toff = 0;
+        if (p.items) {  // batched form: the mesh of segment i
+            int lo = 0, hi = p.n_meshes - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (p.ray_off[mid] <= i)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            root = p.mesh_root[lo];
+            toff = p.mesh_toff[lo];
+        }
         Ray r;
         const bool ok = setup_ray(p.from, p.to, i, p.bounds[6], r);
         const float *o = p.from + 3 * i, *e = p.to + 3 * i;
@@ -569,15 +611,19 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
             }
         };
 
-        if (!ok) {
+        if (root == kDone) {
+            // empty mesh: nothing to test
+        } else if (!ok) {
             if (CERT) {
-                // brute force over every leaf: the box test is not reliable here
-                for (int64_t leaf = 0; leaf < p.nt && !done; ++leaf)
-                    test_leaf((int)leaf);
+                // brute force over every leaf under the root: the box test is not reliable here
+                const int first = root < 0 ? ~root : p.nodes[root].refs.z;
+                const int last = root < 0 ? ~root : p.nodes[root].refs.w;
+                for (int leaf = first; leaf <= last && !done; ++leaf)
+                    test_leaf(leaf);
             }
         } else {
             int sp = 0;
-            int ref = p.root;
+            int ref = root;
             const int64_t max_steps = 2 * p.nt + 8;
             const int n_internal = (int)p.nt - 1;
             for (int64_t steps = 0; steps <= max_steps && ref < n_internal && ~ref < p.nt; ++steps) {
@@ -609,10 +655,11 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
                 ref = stk[(--sp) * kFinishThreads];
             }
         }
+        const int local = best_id >= 0 ? best_id - toff : -1;
         if (CERT)
-            write_out(p.out, i, MODE, best_id, (float)bu, (float)bv, (float)bt);
+            write_out(p.out, i, MODE, local, (float)bu, (float)bv, (float)bt);
         else
-            write_out(p.out, i, MODE, best_id, bu32, bv32, best_t32);
+            write_out(p.out, i, MODE, local, bu32, bv32, best_t32);
     }
 }
 
@@ -687,6 +734,12 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.tests = a.tests;
     p.bucket = a.bucket;
     p.bucket_ref = a.bucket_ref;
+    p.items = a.items;
+    p.n_items = a.n_items;
+    p.n_meshes = a.n_meshes;
+    p.mesh_root = a.mesh_root;
+    p.mesh_toff = a.mesh_toff;
+    p.ray_off = a.ray_off;
     return p;
 }
 

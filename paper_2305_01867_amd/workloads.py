@@ -28,6 +28,7 @@ __all__ = [
     "appendix_scene",
     "tiny_config",
     "paper_scale_config",
+    "batched_config",
     "HEADLINE_SEEDS",
 ]
 
@@ -134,3 +135,25 @@ def paper_scale_config(n_rays: int = 10_000_000):
     V, F = heightfield(128, HEADLINE_SEEDS[0])
     O, E = rays_in_box(n_rays, HEADLINE_SEEDS[1], V.min(axis=0), V.max(axis=0))
     return V, F, O, E
+
+
+def batched_config(n_meshes: int = 64, tri_range=(2e3, 2e5), ray_range=(1e4, 1e6), size_seed: int = 40):
+    """Independent heightfields of log-uniform size and their own segment
+    batches: N_t* = exp U(ln lo, ln hi), grid n = max(2, round(sqrt(N_t*/2)) + 1),
+    mesh m = H(n, 1000 + m); N_r = round(exp U(...)) segments drawn as in the
+    paper-scale case (end points uniform in the mesh box inflated 10%), seed
+    2000 + m.  Returns (V, F, O, E, v_off, t_off, r_off) with triangle indices
+    relative to each mesh's first vertex."""
+    rng = np.random.default_rng(size_seed)
+    nt_star = np.exp(rng.uniform(np.log(tri_range[0]), np.log(tri_range[1]), n_meshes))
+    nr = np.round(np.exp(rng.uniform(np.log(ray_range[0]), np.log(ray_range[1]), n_meshes))).astype(np.int64)
+    Vs, Fs, Os, Es = [], [], [], []
+    for m in range(n_meshes):
+        n = max(2, int(round(np.sqrt(nt_star[m] / 2.0))) + 1)
+        V, F = heightfield(n, 1000 + m)
+        O, E = rays_in_box(int(nr[m]), 2000 + m, V.min(axis=0), V.max(axis=0))
+        Vs.append(V); Fs.append(F); Os.append(O); Es.append(E)
+    v_off = np.concatenate([[0], np.cumsum([len(v) for v in Vs])]).astype(np.int64)
+    t_off = np.concatenate([[0], np.cumsum([len(f) for f in Fs])]).astype(np.int64)
+    r_off = np.concatenate([[0], np.cumsum([len(o) for o in Os])]).astype(np.int64)
+    return (np.concatenate(Vs), np.concatenate(Fs), np.concatenate(Os), np.concatenate(Es), v_off, t_off, r_off)

@@ -60,6 +60,7 @@ def check_structure(V, F, bits):
         want_r = np.where(t["right_leaf"] == 1, ~t["right"], t["right"])
         assert np.array_equal(lref, want_l), "left children differ"
         assert np.array_equal(rref, want_r), "right children differ"
+        assert np.array_equal(words[:, 14], t["first"]) and np.array_equal(words[:, 15], t["last"])
 
         def child_boxes(idx, is_leaf):
             return np.where(is_leaf[:, None] == 1, want["leaf_boxes"][idx], want["node_boxes"][np.minimum(idx, nt - 2)])
