@@ -29,6 +29,10 @@ __all__ = [
     "tiny_config",
     "paper_scale_config",
     "batched_config",
+    "fold",
+    "precision_config",
+    "learned_mesh",
+    "learned_rays",
     "HEADLINE_SEEDS",
 ]
 
@@ -157,3 +161,122 @@ def batched_config(n_meshes: int = 64, tri_range=(2e3, 2e5), ray_range=(1e4, 1e6
     t_off = np.concatenate([[0], np.cumsum([len(f) for f in Fs])]).astype(np.int64)
     r_off = np.concatenate([[0], np.cumsum([len(o) for o in Os])]).astype(np.int64)
     return (np.concatenate(Vs), np.concatenate(Fs), np.concatenate(Os), np.concatenate(Es), v_off, t_off, r_off)
+
+
+def fold(V, seed: int, width: float = 0.05):
+    """Fold a band of a heightfield into an overhang: centre c ~ U(0.3, 0.7);
+    for |x - c| < w, x' = x - a sin(pi (x - c) / w) with a = 1.5 w / pi (x'
+    runs backwards in the middle of the band), and z' = z + 0.2 s((x - c + w)
+    / (2 w)) with the smoothstep s, lifting the folded part so the sheet does
+    not cut itself.  Topology is unchanged."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.3, 0.7)
+    V = np.asarray(V, np.float64).copy()
+    x = V[:, 0]
+    band = np.abs(x - c) < width
+    a = 1.5 * width / np.pi
+    u = np.clip((x - c + width) / (2 * width), 0.0, 1.0)
+    step = u * u * (3 - 2 * u)
+    V[:, 2] = V[:, 2] + 0.2 * step
+    V[band, 0] = x[band] - a * np.sin(np.pi * (x[band] - c) / width)
+    return V.astype(np.float32)
+
+
+def _interior_edges(n):
+    """Vertex pairs of the heightfield's edges shared by two triangles."""
+    i, j = np.meshgrid(np.arange(n - 1), np.arange(n - 1), indexing="xy")
+    i, j = i.ravel(), j.ravel()
+    diag = np.stack([j * n + i, (j + 1) * n + i + 1], 1)              # every diagonal is shared
+    k = np.arange(1, n - 1)
+    ii, kk = np.meshgrid(np.arange(n - 1), k, indexing="xy")
+    horiz = np.stack([kk.ravel() * n + ii.ravel(), kk.ravel() * n + ii.ravel() + 1], 1)   # rows 1..n-2
+    vert = np.stack([ii.ravel() * n + kk.ravel(), (ii.ravel() + 1) * n + kk.ravel()], 1)  # columns 1..n-2
+    return np.concatenate([diag, horiz, vert])
+
+
+def precision_config(n_rays: int = 10_000_000, n: int = 256, seeds=(31, 32)):
+    """The precision form: H(n, 31) folded, and n_rays segments -- 75% drawn as
+    in the paper-scale case; 20% aimed within ~1e-7 (relative) of a shared
+    interior edge (or, with p = 0.25, an interior vertex): p = A + l (B - A),
+    l ~ U(0.05, 0.95), moved by d |p|_inf in a random direction, d ~
+    U(-1e-7, 1e-7), direction random with |d_z| >= 0.3, half-length
+    U(0.05, 0.5); 5% near-parallel: through a random triangle's interior point
+    offset along its normal by U(-1e-7, 1e-7), direction in its plane tilted
+    out of it by U(0, 1e-6) rad, half-length U(0.01, 0.1).  Returns
+    (V, F, O, E, kind) with kind 0 / 1 / 2 for the three groups."""
+    V, F = heightfield(n, seeds[0])
+    V = fold(V, seeds[0] + 100)
+    rng = np.random.default_rng(seeds[1])
+    kind = rng.choice(3, size=n_rays, p=[0.75, 0.20, 0.05]).astype(np.int8)
+    O, E = rays_in_box(n_rays, seeds[1] + 1, V.min(axis=0), V.max(axis=0))
+    Vd = V.astype(np.float64)
+    # aimed at edges / vertices
+    idx = np.nonzero(kind == 1)[0]
+    m = len(idx)
+    edges = _interior_edges(n)
+    e = edges[rng.integers(0, len(edges), m)]
+    lam = rng.uniform(0.05, 0.95, m)
+    P = Vd[e[:, 0]] + lam[:, None] * (Vd[e[:, 1]] - Vd[e[:, 0]])
+    on_vertex = rng.uniform(size=m) < 0.25
+    inner = np.array([j * n + i for j in range(1, n - 1) for i in range(1, n - 1)])
+    P[on_vertex] = Vd[inner[rng.integers(0, len(inner), on_vertex.sum())]]
+    g = rng.normal(size=(m, 3))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    P += g * (rng.uniform(-1e-7, 1e-7, m) * np.abs(P).max(axis=1))[:, None]
+    d = rng.normal(size=(m, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    small = np.abs(d[:, 2]) < 0.3
+    d[small, 2] = np.where(d[small, 2] >= 0, 0.3, -0.3)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    h = rng.uniform(0.05, 0.5, m)[:, None]
+    O[idx] = (P - h * d).astype(np.float32)
+    E[idx] = (P + h * d).astype(np.float32)
+    # near-parallel
+    idx = np.nonzero(kind == 2)[0]
+    m = len(idx)
+    t = rng.integers(0, F.shape[0], m)
+    A, B, C = Vd[F[t, 0]], Vd[F[t, 1]], Vd[F[t, 2]]
+    nrm = np.cross(B - A, C - A)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    u = rng.normal(size=(m, 3))
+    u -= nrm * np.sum(u * nrm, axis=1, keepdims=True)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    th = rng.uniform(0.0, 1e-6, m)[:, None]
+    d = np.cos(th) * u + np.sin(th) * nrm
+    w = rng.dirichlet([1.0, 1.0, 1.0], m)
+    P = w[:, :1] * A + w[:, 1:2] * B + w[:, 2:] * C + nrm * rng.uniform(-1e-7, 1e-7, m)[:, None]
+    h = rng.uniform(0.01, 0.1, m)[:, None]
+    O[idx] = (P - h * d).astype(np.float32)
+    E[idx] = (P + h * d).astype(np.float32)
+    return V, F, O, E, kind
+
+
+# crossing probability of the learned form's segments, set once so that about
+# 60% of the segments hit (binary64 oracle on 20,000 segments drawn with seed
+# 4242: 0.6047 at 0.24; 0.6138 at 0.26; 0.68 at 0.41)
+LEARNED_P_CROSS = 0.24
+
+
+def learned_mesh(seeds=(51, 52)):
+    """H(512, 51) plus two folded 32 x 32 sheets, one at z + 0.25 over
+    [0.15, 0.45]^2 and one at z - 0.25 over [0.55, 0.85]^2 (about 5.26e5
+    triangles)."""
+    V, F = heightfield(512, seeds[0])
+    parts_V, parts_F, off = [V], [F], V.shape[0]
+    for k, (x0, z0) in enumerate([(0.15, 0.25), (0.55, -0.25)]):
+        Vs, Fs = heightfield(32, seeds[1] + k)
+        Vs = fold(Vs, seeds[1] + 10 + k)
+        Vs = Vs.astype(np.float64)
+        Vs[:, 0] = x0 + 0.3 * Vs[:, 0]
+        Vs[:, 1] = x0 + 0.3 * Vs[:, 1]
+        Vs[:, 2] = Vs[:, 2] + z0
+        parts_V.append(Vs.astype(np.float32))
+        parts_F.append(Fs + off)
+        off += Vs.shape[0]
+    return np.concatenate(parts_V), np.concatenate(parts_F).astype(np.int32)
+
+
+def learned_rays(n_rays: int, seed: int):
+    """Crossing-mix segments (as in the tiny case) with the frozen crossing
+    probability; training uses seed 5001, evaluation chunks 5100 + k."""
+    return rays_crossing_mix(n_rays, seed, p_cross=LEARNED_P_CROSS)
