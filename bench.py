@@ -17,6 +17,9 @@ Printed: one JSON line (rank 0).  Besides the contract fields it carries
   cpu_baseline  the binary64 brute-force oracle timed on the host cores on a
                 bounded sample of the same segments
   variants      Mrays/s of intersect alone per mode and precision
+  learned_vs_plain  the learned subtree proposal (trained on 2e6 other
+                segments the method labels) against the plain order:
+                intersect Mrays/s, node visits, proposal miss rate, MLP cost
 """
 import argparse
 import json
@@ -41,6 +44,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-rays", type=int, default=2_000_000)
+    ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -204,6 +210,53 @@ def main():
             torch.cuda.synchronize()
             variants["build_ms"] = round(b0.elapsed_time(b1) / 5, 4)
 
+    # ---------------- learned proposal vs plain order (BVH resident, untimed region)
+    learned = None
+    if not args.no_learned:
+        lo, hi = V.min(axis=0), V.max(axis=0)
+        Ot, Et = workloads.rays_in_box(args.train_rays, 23, lo, hi)  # training segments, own seed
+        dOt, dEt = torch.from_numpy(Ot).to(dev), torch.from_numpy(Et).to(dev)
+        with rsi.rsi_build(dV, dF) as mesh:
+            torch.cuda.synchronize()
+            t_tr = time.perf_counter()
+            loss, n_lab = rsi.rsi_proposal_train(mesh, dOt, dEt, epochs=args.train_epochs, batch=4096, lr=2e-3,
+                                                 seed=1)
+            t_tr = time.perf_counter() - t_tr
+            del dOt, dEt
+
+            def timed(fn, reps=3):
+                fn()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(reps):
+                    fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                return a.elapsed_time(b) / reps
+
+            o = outs[args.mode]
+            ms_plain = timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision, out=o))
+            ms_learned = timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision,
+                                                         out=o, proposal=True))
+            late = int(o["counters"][2].item())
+            n_hit = int(o["hit"].sum().item()) if args.mode == "boolean" else int((o["tri_id"] >= 0).sum().item())
+            ms_mlp = timed(lambda: rsi.rsi_proposal_predict(mesh, dO, dE))
+            v_p, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision)
+            v_l, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision, proposal=True)
+            learned = {
+                "train_segments": args.train_rays, "labelled": n_lab, "epochs": args.train_epochs,
+                "train_s": round(t_tr, 2), "epoch_loss": [round(x, 4) for x in loss.tolist()],
+                "proposal_miss_rate": round(late / max(n_hit, 1), 4),
+                "intersect_mrays_s_plain_order": round(n / (ms_plain * 1e-3) / 1e6, 1),
+                "intersect_mrays_s_learned": round(n / (ms_learned * 1e-3) / 1e6, 1),
+                "mlp_inference_ms": round(ms_mlp, 3),
+                "mlp_tflops": round(n * 2 * 253952 / (ms_mlp * 1e-3) / 1e12, 1),
+                "mean_node_visits_plain_order": round(float(v_p.double().mean().item()), 2),
+                "mean_node_visits_learned": round(float(v_l.double().mean().item()), 2),
+                "mode": args.mode, "precision": args.precision,
+            }
+        print(f"[bench] learned: {learned}", file=sys.stderr, flush=True)
+
     # ---------------- CPU baseline: the oracle on a bounded sample
     cpu = None
     if not args.no_cpu_baseline:
@@ -239,6 +292,7 @@ def main():
         "counters": {"redecided_fp64": counters[0], "stack_overflow": counters[1]},
         "hit_fraction": hit_frac,
         "variants": variants,
+        "learned_vs_plain": learned,
     }
     print(json.dumps(line), flush=True)
 

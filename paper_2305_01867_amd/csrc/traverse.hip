@@ -371,6 +371,10 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
         }
 
         // ---- node phase
+        // Push and pop are branch-free: every lane has one spare LDS slot past
+        // its stack_depth entries, so the push slot is written unconditionally
+        // (a slot at or above sp holds nothing live), and the top of stack is
+        // read ahead of the node fetch and used only if the node yields nothing.
         for (;;) {
             if (ray >= 0 && pend < 0 && ref < 0 && ref != kDone) {
                 pend = ~ref;
@@ -389,6 +393,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                     ref = kDone;
                     pend = -1;
                 } else {
+                    const int top = stk[(sp > 0 ? sp - 1 : 0) * stride];
                     const Node *nd = p.nodes + ref;
                     const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
                     const int4 refs = nd->refs;
@@ -401,21 +406,16 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                         hl = hl && refs.x != skip;
                         hr = hr && refs.y != skip;
                     }
-                    if (hl && hr) {
-                        if (sp >= p.stack_depth) {
-                            overflow = true;
-                            ref = kDone;
-                            pend = -1;
-                        } else {
-                            const bool left_first = tl <= tr;
-                            stk[sp * stride] = left_first ? refs.y : refs.x;
-                            ++sp;
-                            ref = left_first ? refs.x : refs.y;
-                        }
-                    } else if (hl || hr) {
-                        ref = hl ? refs.x : refs.y;
-                    } else {
-                        ref = pop();
+                    const bool both = hl && hr, any = hl || hr;
+                    const bool left_first = both ? tl <= tr : hl;
+                    stk[sp * stride] = left_first ? refs.y : refs.x;
+                    const int next = left_first ? refs.x : refs.y;
+                    overflow = overflow || (both && sp >= p.stack_depth);
+                    ref = any ? next : (sp > 0 ? top : kDone);
+                    sp += both ? 1 : (!any && sp > 0 ? -1 : 0);
+                    if (both && sp > p.stack_depth) {
+                        ref = kDone;  // overflow: the segment goes to the deep-stack pass
+                        pend = -1;
                     }
                 }
             }
@@ -678,7 +678,7 @@ __global__ void k_fill_miss(Outs out, int64_t n, int mode) {
 
 template <int MODE, bool CERT, bool STATS, bool PROP>
 void launch_pass1(const TravParams &p, int block, hipStream_t s) {
-    const size_t lds = (size_t)p.stack_depth * block * sizeof(int);
+    const size_t lds = (size_t)(p.stack_depth + 1) * block * sizeof(int);  // + one spare slot per lane
     int dev = 0, cus = 256, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
