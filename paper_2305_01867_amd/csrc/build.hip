@@ -311,83 +311,141 @@ __global__ __launch_bounds__(256) void k_radix_tree(const K *__restrict__ keys, 
 }
 
 // ------------------------------------------------- 5. leaves and bottom-up
-// One lane per sorted leaf: write its triangle, then climb.  At each internal
-// node the lane stores its subtree's box in its slot and increments the node's
-// counter (acquire-release at agent scope, so boxes written on another XCD are
-// visible); the first arrival stops, the second merges both boxes and goes on.
-__global__ __launch_bounds__(256) void k_leaves_bottom_up(const float *__restrict__ V, int64_t nv,
-                                                          const int32_t *__restrict__ F,
-                                                          const int32_t *__restrict__ ids, int n,
-                                                          Tri *__restrict__ tris, Node *nodes,
-                                                          const int32_t *__restrict__ parent, int32_t *counters) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n)
-        return;
-    int t = ids[k];
-    const bool t_ok = t >= 0 && t < n;  // always true for a correct sort; guards the loads below
-    if (!t_ok)
-        t = 0;
-    const int32_t i0 = F[3 * (int64_t)t], i1 = F[3 * (int64_t)t + 1], i2 = F[3 * (int64_t)t + 2];
-    float lo[3], hi[3];
-    Tri tri;
-    if (!t_ok || i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
-        // an invalid triangle is never hit and does not widen any box
-        tri.a = make_float4(NAN, NAN, NAN, __int_as_float(t));
-        tri.e1 = make_float4(NAN, NAN, NAN, 0.0f);
-        tri.e2 = make_float4(NAN, NAN, NAN, 0.0f);
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = INFINITY;
-            hi[a] = -INFINITY;
-        }
+// Boxes are merged bottom-up, each internal node by the second of its two
+// children to finish.  Two kernels keep the cross-workgroup protocol short:
+//   k_leaves_tile  one workgroup per tile of kBoxTile consecutive leaves.  A
+//                  lane writes its leaf's triangle and climbs while the node's
+//                  leaf range lies inside the tile, with arrival counters and
+//                  child boxes in LDS.  A lane that reaches a node spanning
+//                  tiles leaves its box in the node and lists the node.
+//   k_boxes_span   one workgroup finishes the spanning nodes (a small top
+//                  tree) from those lists, with workgroup-scope atomics.
+// Every child box also lands in its parent node in HBM; a finished internal
+// node's counter reads 2.
+constexpr int kBoxTile = 1024;
+
+__device__ __forceinline__ void store_child_box(Node *node, bool is_left, const float *lo, const float *hi) {
+    if (is_left) {
+        node->xy_left = make_float4(lo[0], hi[0], lo[1], hi[1]);
+        *reinterpret_cast<float2 *>(&node->z_both.x) = make_float2(lo[2], hi[2]);
     } else {
-        float A[3], B[3], C[3];
-        for (int a = 0; a < 3; ++a) {
-            A[a] = V[3 * (int64_t)i0 + a];
-            B[a] = V[3 * (int64_t)i1 + a];
-            C[a] = V[3 * (int64_t)i2 + a];
-            lo[a] = fminf(A[a], fminf(B[a], C[a]));
-            hi[a] = fmaxf(A[a], fmaxf(B[a], C[a]));
-        }
-        tri.a = make_float4(A[0], A[1], A[2], __int_as_float(t));
-        tri.e1 = make_float4(B[0] - A[0], B[1] - A[1], B[2] - A[2], 0.0f);
-        tri.e2 = make_float4(C[0] - A[0], C[1] - A[1], C[2] - A[2], 0.0f);
+        node->xy_right = make_float4(lo[0], hi[0], lo[1], hi[1]);
+        *reinterpret_cast<float2 *>(&node->z_both.z) = make_float2(lo[2], hi[2]);
     }
-    tris[k] = tri;
-    if (n < 2)
-        return;
-    int self = ~k;
-    int p = parent[(n - 1) + k];
-    // a radix tree is at most 97 levels deep; the bound only guards the loop
-    for (int level = 0; p >= 0 && p < n - 1 && level < kDeepStack; ++level) {
-        Node *node = nodes + p;
-        const bool is_left = node->refs.x == self;
-        if (is_left) {
-            node->xy_left = make_float4(lo[0], hi[0], lo[1], hi[1]);
-            *reinterpret_cast<float2 *>(&node->z_both.x) = make_float2(lo[2], hi[2]);
+}
+
+__global__ __launch_bounds__(kBoxTile) void k_leaves_tile(const float *__restrict__ V, int64_t nv,
+                                                         const int32_t *__restrict__ F,
+                                                         const int32_t *__restrict__ ids, int n,
+                                                         Tri *__restrict__ tris, Node *nodes,
+                                                         const int32_t *__restrict__ parent, int32_t *counters,
+                                                         int32_t *__restrict__ span_list,
+                                                         int32_t *__restrict__ span_len) {
+    __shared__ int arrived[kBoxTile];
+    __shared__ float box[kBoxTile][2][6];
+    __shared__ int n_span;
+    const int base = blockIdx.x * kBoxTile;
+    const int last = min(base + kBoxTile, n) - 1;  // last leaf of the tile
+    arrived[threadIdx.x] = 0;
+    if (threadIdx.x == 0)
+        n_span = 0;
+    __syncthreads();
+    const int k = base + (int)threadIdx.x;
+    if (k < n) {
+        int t = ids[k];
+        const bool t_ok = t >= 0 && t < n;  // always true for a correct sort; guards the loads below
+        if (!t_ok)
+            t = 0;
+        const int32_t i0 = F[3 * (int64_t)t], i1 = F[3 * (int64_t)t + 1], i2 = F[3 * (int64_t)t + 2];
+        float lo[3], hi[3];
+        Tri tri;
+        if (!t_ok || i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
+            // an invalid triangle is never hit and does not widen any box
+            tri.a = make_float4(NAN, NAN, NAN, __int_as_float(t));
+            tri.e1 = make_float4(NAN, NAN, NAN, 0.0f);
+            tri.e2 = make_float4(NAN, NAN, NAN, 0.0f);
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = INFINITY;
+                hi[a] = -INFINITY;
+            }
         } else {
-            node->xy_right = make_float4(lo[0], hi[0], lo[1], hi[1]);
-            *reinterpret_cast<float2 *>(&node->z_both.z) = make_float2(lo[2], hi[2]);
+            float A[3], B[3], C[3];
+            for (int a = 0; a < 3; ++a) {
+                A[a] = V[3 * (int64_t)i0 + a];
+                B[a] = V[3 * (int64_t)i1 + a];
+                C[a] = V[3 * (int64_t)i2 + a];
+                lo[a] = fminf(A[a], fminf(B[a], C[a]));
+                hi[a] = fmaxf(A[a], fmaxf(B[a], C[a]));
+            }
+            tri.a = make_float4(A[0], A[1], A[2], __int_as_float(t));
+            tri.e1 = make_float4(B[0] - A[0], B[1] - A[1], B[2] - A[2], 0.0f);
+            tri.e2 = make_float4(C[0] - A[0], C[1] - A[1], C[2] - A[2], 0.0f);
         }
-        const int before = __hip_atomic_fetch_add(counters + p, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (before == 0)
-            return;  // the sibling subtree is not finished; its last lane continues
-        float4 xy;
-        float2 z;
-        if (is_left) {
-            xy = node->xy_right;
-            z = *reinterpret_cast<const float2 *>(&node->z_both.z);
-        } else {
-            xy = node->xy_left;
-            z = *reinterpret_cast<const float2 *>(&node->z_both.x);
+        tris[k] = tri;
+        int self = ~k;
+        int p = n >= 2 ? parent[(n - 1) + k] : -1;
+        // a radix tree is at most 97 levels deep; the bound only guards the loop
+        for (int level = 0; p >= 0 && p < n - 1 && level < kDeepStack; ++level) {
+            Node *node = nodes + p;
+            const int4 refs = node->refs;
+            const bool is_left = refs.x == self;
+            store_child_box(node, is_left, lo, hi);
+            if (refs.z < base || refs.w > last) {
+                // spans tiles: at most one entry per leaf of the tile
+                const int slot = atomicAdd(&n_span, 1);
+                span_list[base + slot] = p;
+                break;
+            }
+            // p lies in its own leaf range, so p - base indexes the tile
+            float *mine = box[p - base][is_left ? 0 : 1];
+            for (int a = 0; a < 3; ++a) {
+                mine[a] = lo[a];
+                mine[3 + a] = hi[a];
+            }
+            __threadfence_block();
+            if (atomicAdd(&arrived[p - base], 1) == 0)
+                break;  // the sibling subtree is not finished; its last lane continues
+            __threadfence_block();
+            const float *other = box[p - base][is_left ? 1 : 0];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fminf(lo[a], other[a]);
+                hi[a] = fmaxf(hi[a], other[3 + a]);
+            }
+            counters[p] = 2;
+            self = p;
+            p = parent[p];
         }
-        lo[0] = fminf(lo[0], xy.x);
-        hi[0] = fmaxf(hi[0], xy.y);
-        lo[1] = fminf(lo[1], xy.z);
-        hi[1] = fmaxf(hi[1], xy.w);
-        lo[2] = fminf(lo[2], z.x);
-        hi[2] = fmaxf(hi[2], z.y);
-        self = p;
-        p = parent[p];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        span_len[blockIdx.x] = n_span;
+}
+
+// One workgroup: lane b takes the listed nodes of tiles b, b + 1024, ...  The
+// second arrival at a node merges the two child boxes (each written by the
+// first kernel, or by this workgroup before its release) and climbs on.
+__global__ __launch_bounds__(1024) void k_boxes_span(Node *nodes, const int32_t *__restrict__ parent,
+                                                     int32_t *counters, const int32_t *__restrict__ span_list,
+                                                     const int32_t *__restrict__ span_len, int ntiles, int n) {
+    for (int b = threadIdx.x; b < ntiles; b += blockDim.x) {
+        const int len = span_len[b];
+        for (int e = 0; e < len && e < kBoxTile; ++e) {
+            int p = span_list[b * kBoxTile + e];
+            for (int level = 0; p >= 0 && p < n - 1 && level < kDeepStack; ++level) {
+                if (__hip_atomic_fetch_add(counters + p, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+                    break;
+                const Node *node = nodes + p;
+                const float4 L = node->xy_left, R = node->xy_right, Z = node->z_both;
+                const float lo[3] = {fminf(L.x, R.x), fminf(L.z, R.z), fminf(Z.x, Z.z)};
+                const float hi[3] = {fmaxf(L.y, R.y), fmaxf(L.w, R.w), fmaxf(Z.y, Z.w)};
+                const int pp = parent[p];
+                if (pp < 0 || pp >= n - 1)
+                    break;  // p is the root
+                Node *up = nodes + pp;
+                store_child_box(up, up->refs.x == p, lo, hi);
+                p = pp;
+            }
+        }
     }
 }
 
@@ -422,8 +480,14 @@ hipError_t build_from_keys(MeshDev &m, int key_bits, hipStream_t s) {
     // 4 or 8 passes: the sorted data is back in (keys, ids)
     if (nt >= 2)
         k_radix_tree<K><<<blocks_for(nt - 1, 256), 256, 0, s>>>(keys, (int)nt, m.nodes, m.parent, m.counters);
-    k_leaves_bottom_up<<<blocks_for(nt, 256), 256, 0, s>>>(m.V, m.nv, m.F, m.ids, (int)nt, m.tris, m.nodes,
-                                                           m.parent, m.counters);
+    // the sort's scratch is free again: per-tile lists of spanning nodes
+    const int box_tiles = blocks_for(nt, kBoxTile);
+    int32_t *span_list = static_cast<int32_t *>(m.sort_tmp);
+    int32_t *span_len = span_list + (int64_t)box_tiles * kBoxTile;
+    k_leaves_tile<<<box_tiles, kBoxTile, 0, s>>>(m.V, m.nv, m.F, m.ids, (int)nt, m.tris, m.nodes, m.parent,
+                                                 m.counters, span_list, span_len);
+    if (box_tiles > 1)
+        k_boxes_span<<<1, 1024, 0, s>>>(m.nodes, m.parent, m.counters, span_list, span_len, box_tiles, (int)nt);
     return hipGetLastError();
 }
 
@@ -447,7 +511,10 @@ hipError_t launch_morton_batch(MeshDev &m, const int32_t *tri_mesh, const float 
 size_t sort_tmp_bytes(int64_t nt, int morton_bits) {
     const size_t kb = morton_bits > 32 ? 8 : 4;
     const int64_t ntiles = (nt + kSortTile - 1) / kSortTile;
-    return kb * nt + 4 * nt + 4 * (size_t)kRadix * ntiles + 256;
+    const size_t sort = kb * nt + 4 * nt + 4 * (size_t)kRadix * ntiles + 256;
+    const int64_t box_tiles = (nt + kBoxTile - 1) / kBoxTile;
+    const size_t lists = 4 * (size_t)box_tiles * (kBoxTile + 1) + 256;  // span lists after the sort
+    return sort > lists ? sort : lists;
 }
 
 hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s) { return build_from_keys<uint64_t>(m, key_bits, s); }

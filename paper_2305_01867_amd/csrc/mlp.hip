@@ -208,12 +208,27 @@ __global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z,
         atomicAdd(loss, (logf(s) + mx - z[label]) * loss_scale);
 }
 
-// db[n] = sum over rows of dZ[row][n] (fp32 from bf16).
-__global__ __launch_bounds__(256) void k_col_sum(const __bf16 *__restrict__ dZ, int rows, float *__restrict__ db) {
+// db[n] = sum over rows of dZ[row][n] (fp32 from bf16), in two fixed-order
+// stages: partial[b][n] over rows [64 b, 64 b + 64), then the partials in
+// order -- deterministic, and 64x more parallel than one pass.
+constexpr int kColRows = 64;
+
+__global__ __launch_bounds__(256) void k_col_partial(const __bf16 *__restrict__ dZ, int rows,
+                                                     float *__restrict__ partial) {
+    const int n = threadIdx.x, b = blockIdx.x;
+    const int r1 = min(rows, (b + 1) * kColRows);
+    float s = 0.0f;
+    for (int r = b * kColRows; r < r1; ++r)
+        s += (float)dZ[(int64_t)r * kMlpOut + n];
+    partial[(int64_t)b * kMlpOut + n] = s;
+}
+
+__global__ __launch_bounds__(256) void k_col_final(const float *__restrict__ partial, int nblk,
+                                                   float *__restrict__ db) {
     const int n = threadIdx.x;
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r)
-        s += (float)dZ[(int64_t)r * kMlpOut + n];
+    for (int b = 0; b < nblk; ++b)
+        s += partial[(int64_t)b * kMlpOut + n];
     db[n] = s;
 }
 
@@ -596,7 +611,9 @@ hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from
         g.M = kMlpOut; g.N = K; g.K = rows;
         g.Cf = gWs[l]; g.c_m = K; g.c_n = 1;
         gemm(g, s);
-        k_col_sum<<<1, kMlpOut, 0, s>>>(dZ, rows, gb + l * kMlpHidden);
+        const int nblk = cdiv(rows, kColRows);
+        k_col_partial<<<nblk, kMlpOut, 0, s>>>(dZ, rows, Z4);  // the logits in Z4 are spent by now
+        k_col_final<<<1, kMlpOut, 0, s>>>(Z4, nblk, gb + l * kMlpHidden);
         if (l > 0) {
             // dH[r][k] = sum_n dZ[r][n] W[n][k], masked by H > 0
             GemmArgs h{};

@@ -531,135 +531,291 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
 }
 
 // ------------------------------------------------------------------ pass 2
-// Segments from the queue, one per lane, with an LDS stack deep enough for any
-// radix tree (128 entries).  CERTIFIED: a candidate the binary32 bound already
-// proves a miss is skipped; every other candidate is decided in binary64 in
-// the oracle's operation order.  A segment whose binary32 setup is not finite
-// is tested against every triangle.
+// Queued segments are finished exactly: a stack deep enough for any radix
+// tree, and in CERTIFIED precision every candidate not already a proven
+// binary32 miss decided in binary64 with the oracle's operation order.  A
+// segment whose binary32 setup is not finite is tested against every
+// triangle under its root.
+//
+// Two shapes, chosen per launch from the queue length (uniform per block):
+//   short queue: one wave per segment.  The wave shares an LDS stack and pops
+//     up to 64 subtrees per step, one per lane, so a segment takes about
+//     (tree depth + candidates / 64) steps instead of one dependent load per
+//     visited node.
+//   long queue: one lane per segment with a private deep stack (throughput).
 constexpr int kFinishThreads = 64;
+constexpr int kWaveFinishMax = 8192;                      // queue length up to which a wave takes a segment
+constexpr int kWaveStack = kDeepStack * kFinishThreads;  // shared entries (same LDS as the private stacks)
+// Steps that pop k entries push at most 2k; popping at most (kWaveSoft - size)
+// keeps the stack at or below kWaveSoft, and above it single pops (a plain
+// depth-first walk) add at most one entry per tree level.
+constexpr int kWaveSoft = kWaveStack - kDeepStack;
 
 template <int MODE, bool CERT>
-__global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
-    __shared__ int deep[kDeepStack * kFinishThreads];
-    int *stk = deep + threadIdx.x;
-    const uint32_t count = *p.queue_len;
-    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < count; qi += gridDim.x * blockDim.x) {
-        const int64_t i = p.queue[qi];
-        int root = p.root, toff = 0;
-        if (p.items) {  // batched form: the mesh of segment i
-            int lo = 0, hi = p.n_meshes - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (p.ray_off[mid] <= i)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            root = p.mesh_root[lo];
-            toff = p.mesh_toff[lo];
-        }
-        Ray r;
-        const bool ok = setup_ray(p.from, p.to, i, p.bounds[6], r);
+struct Finish {
+    Ray r;
+    double ox, oy, oz, ex, ey, ez;
+    int best_id;
+    double bu, bv, bt;
+    float t32, u32, v32;
+    float tlimit;
+    bool done;
+
+    __device__ bool init(const TravParams &p, int64_t i) {
+        best_id = -1;
+        bu = bv = bt = 0.0;
+        t32 = INFINITY;
+        u32 = v32 = 0.0f;
+        tlimit = 1.0f;
+        done = false;
         const float *o = p.from + 3 * i, *e = p.to + 3 * i;
-        const double ox = o[0], oy = o[1], oz = o[2], ex = e[0], ey = e[1], ez = e[2];
-        int best_id = -1;
-        double bu = 0.0, bv = 0.0, bt = 0.0;
-        float best_t32 = INFINITY, bu32 = 0.0f, bv32 = 0.0f;
-        float tlimit = 1.0f;
-        bool done = false;
+        ox = o[0]; oy = o[1]; oz = o[2];
+        ex = e[0]; ey = e[1]; ez = e[2];
+        return setup_ray(p.from, p.to, i, p.bounds[6], r);
+    }
 
-        auto test_leaf = [&](int leaf) {
-            const Tri tri = p.tris[leaf];
-            const int id = __float_as_int(tri.a.w);
-            const MT32 m = mt32(tri, r);
-            if (CERT) {
-                float lo, hi;
-                if (classify(m, tri, r, lo, hi) == kMiss)
-                    return;  // the bound proves the binary64 test misses too
-                MT64 h{false, 0.0, 0.0, 0.0};
-                if (valid_tri(p.F, p.nv, id))
-                    h = mt64(ox, oy, oz, ex, ey, ez, p.V, p.F, id);
-                if (h.hit) {
-                    if (MODE == MODE_BOOL) {
-                        best_id = id;
-                        done = true;
-                        return;
-                    }
-                    if (best_id < 0 || h.t < bt || (h.t == bt && id < best_id)) {
-                        best_id = id;
-                        bu = h.u;
-                        bv = h.v;
-                        bt = h.t;
-                        // round up, then widen: no box holding a hit at t <= bt is culled
-                        tlimit = fminf(tlimit, __double2float_ru(h.t) * (1.0f + 0x1p-20f));
-                    }
-                }
-            } else if (decide32(m)) {
-                if (MODE == MODE_BOOL) {
-                    best_id = id;
-                    done = true;
-                    return;
-                }
-                const float t = m.T / m.det;
-                if (t < best_t32 || (t == best_t32 && id < best_id)) {
-                    best_t32 = t;
-                    best_id = id;
-                    bu32 = m.U / m.det;
-                    bv32 = m.W / m.det;
-                    tlimit = t;
-                }
+    __device__ void test_leaf(const TravParams &p, int leaf) {
+        const Tri tri = p.tris[leaf];
+        const int id = __float_as_int(tri.a.w);
+        const MT32 m = mt32(tri, r);
+        if (CERT) {
+            float lo, hi;
+            if (classify(m, tri, r, lo, hi) == kMiss)
+                return;  // the bound proves the binary64 test misses too
+            MT64 h{false, 0.0, 0.0, 0.0};
+            if (valid_tri(p.F, p.nv, id))
+                h = mt64(ox, oy, oz, ex, ey, ez, p.V, p.F, id);
+            if (!h.hit)
+                return;
+            if (MODE == MODE_BOOL) {
+                best_id = id;
+                done = true;
+                return;
             }
-        };
-
-        if (root == kDone) {
-            // empty mesh: nothing to test
-        } else if (!ok) {
-            if (CERT) {
-                // brute force over every leaf under the root: the box test is not reliable here
-                const int first = root < 0 ? ~root : p.nodes[root].refs.z;
-                const int last = root < 0 ? ~root : p.nodes[root].refs.w;
-                for (int leaf = first; leaf <= last && !done; ++leaf)
-                    test_leaf(leaf);
+            if (best_id < 0 || h.t < bt || (h.t == bt && id < best_id)) {
+                best_id = id;
+                bu = h.u;
+                bv = h.v;
+                bt = h.t;
+                // round up, then widen: no box holding a hit at t <= bt is culled
+                tlimit = fminf(tlimit, __double2float_ru(h.t) * (1.0f + 0x1p-20f));
             }
-        } else {
-            int sp = 0;
-            int ref = root;
-            const int64_t max_steps = 2 * p.nt + 8;
-            const int n_internal = (int)p.nt - 1;
-            for (int64_t steps = 0; steps <= max_steps && ref < n_internal && ~ref < p.nt; ++steps) {
-                if (ref >= 0) {
-                    const Node *nd = p.nodes + ref;
-                    const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
-                    const int4 refs = nd->refs;
-                    float tl, tr;
-                    const bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, r, tlimit, tl);
-                    const bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, r, tlimit, tr);
-                    if (hl && hr) {
-                        const bool left_first = tl <= tr;
-                        if (sp < kDeepStack)
-                            stk[(sp++) * kFinishThreads] = left_first ? refs.y : refs.x;
-                        ref = left_first ? refs.x : refs.y;
-                        continue;
-                    }
-                    if (hl || hr) {
-                        ref = hl ? refs.x : refs.y;
-                        continue;
-                    }
-                } else {
-                    test_leaf(~ref);
-                    if (done)
-                        break;
-                }
-                if (sp == 0)
-                    break;
-                ref = stk[(--sp) * kFinishThreads];
+        } else if (decide32(m)) {
+            if (MODE == MODE_BOOL) {
+                best_id = id;
+                done = true;
+                return;
+            }
+            const float t = m.T / m.det;
+            if (t < t32 || (t == t32 && id < best_id)) {
+                t32 = t;
+                best_id = id;
+                u32 = m.U / m.det;
+                v32 = m.W / m.det;
+                tlimit = t;
             }
         }
+    }
+
+    __device__ void write(const TravParams &p, int64_t i, int toff) const {
         const int local = best_id >= 0 ? best_id - toff : -1;
         if (CERT)
             write_out(p.out, i, MODE, local, (float)bu, (float)bv, (float)bt);
         else
-            write_out(p.out, i, MODE, local, bu32, bv32, best_t32);
+            write_out(p.out, i, MODE, local, u32, v32, t32);
+    }
+
+    // Wave-wide result: the smallest (t, triangle id) of all lanes' hits.
+    __device__ void reduce_wave() {
+        for (int off = 32; off > 0; off >>= 1) {
+            const int oid = __shfl_xor(best_id, off);
+            if (CERT) {
+                const double ot = __shfl_xor(bt, off), ou = __shfl_xor(bu, off), ov = __shfl_xor(bv, off);
+                if (oid >= 0 && (best_id < 0 || ot < bt || (ot == bt && oid < best_id))) {
+                    best_id = oid;
+                    bt = ot;
+                    bu = ou;
+                    bv = ov;
+                }
+            } else {
+                const float ot = __shfl_xor(t32, off), ou = __shfl_xor(u32, off), ov = __shfl_xor(v32, off);
+                if (oid >= 0 && (best_id < 0 || ot < t32 || (ot == t32 && oid < best_id))) {
+                    best_id = oid;
+                    t32 = ot;
+                    u32 = ou;
+                    v32 = ov;
+                }
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ void segment_root(const TravParams &p, int64_t i, int &root, int &toff) {
+    root = p.root;
+    toff = 0;
+    if (p.items) {  // batched form: the mesh of segment i
+        int lo = 0, hi = p.n_meshes - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (p.ray_off[mid] <= i)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        root = p.mesh_root[lo];
+        toff = p.mesh_toff[lo];
+    }
+}
+
+// One wave (the whole 64-thread block) finishes segment i.
+template <int MODE, bool CERT>
+__device__ void finish_wave(const TravParams &p, int64_t i, int *stk) {
+    const int lane = threadIdx.x;
+    const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int n_internal = (int)p.nt - 1;
+    int root, toff;
+    segment_root(p, i, root, toff);
+    Finish<MODE, CERT> f;
+    const bool ok = f.init(p, i);
+    if (root == kDone) {
+        // empty mesh: nothing to test
+    } else if (!ok) {
+        if (CERT) {
+            const int64_t first = root < 0 ? ~root : p.nodes[root].refs.z;
+            const int64_t last = root < 0 ? ~root : p.nodes[root].refs.w;
+            for (int64_t base = first; base <= last; base += 64) {
+                if (base + lane <= last)
+                    f.test_leaf(p, (int)(base + lane));
+                if (MODE == MODE_BOOL && __ballot(f.done))
+                    break;
+            }
+        }
+    } else {
+        int size = 1;
+        if (lane == 0)
+            stk[0] = root;
+        __syncthreads();
+        const int64_t max_steps = 2 * p.nt + 8;  // every step pops at least one of < 2 nt subtrees
+        for (int64_t step = 0; step < max_steps && size > 0; ++step) {
+            const int room = kWaveSoft - size;
+            int k = room < 1 ? 1 : (room < 64 ? room : 64);
+            k = k < size ? k : size;
+            const int ref = lane < k ? stk[size - 1 - lane] : kDone;
+            __syncthreads();
+            size -= k;
+            int c0 = kDone, c1 = kDone;  // subtrees to push, nearer one on top
+            if (ref >= 0 && ref < n_internal) {
+                const Node *nd = p.nodes + ref;
+                const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
+                const int4 refs = nd->refs;
+                float tl, tr;
+                const bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, f.r, f.tlimit, tl);
+                const bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, f.r, f.tlimit, tr);
+                if (hl && hr) {
+                    const bool left_first = tl <= tr;
+                    c0 = left_first ? refs.y : refs.x;
+                    c1 = left_first ? refs.x : refs.y;
+                } else if (hl || hr) {
+                    c0 = hl ? refs.x : refs.y;
+                }
+            } else if (ref != kDone && ref < 0 && ~ref < p.nt) {
+                f.test_leaf(p, ~ref);
+            }
+            const uint64_t m0 = __ballot(c0 != kDone), m1 = __ballot(c1 != kDone);
+            const int o = size + __popcll(m0 & lt_mask) + __popcll(m1 & lt_mask);
+            if (c0 != kDone && o < kWaveStack)
+                stk[o] = c0;
+            if (c1 != kDone && o + 1 < kWaveStack)
+                stk[o + 1] = c1;
+            size += __popcll(m0) + __popcll(m1);
+            size = size < kWaveStack ? size : kWaveStack;
+            __syncthreads();
+            if (MODE == MODE_BOOL) {
+                if (__ballot(f.done))
+                    break;
+            } else {
+                float tl = f.tlimit;  // any lane's hit bounds the nearest one
+                for (int off = 32; off > 0; off >>= 1)
+                    tl = fminf(tl, __shfl_xor(tl, off));
+                f.tlimit = tl;
+            }
+        }
+    }
+    if (MODE == MODE_BOOL) {
+        f.best_id = __ballot(f.best_id >= 0) ? 0 : -1;
+        toff = 0;
+    } else {
+        f.reduce_wave();
+    }
+    if (lane == 0)
+        f.write(p, i, toff);
+    __syncthreads();  // the stack is reused by the block's next segment
+}
+
+// One lane finishes segment i with its private stack (stride kFinishThreads).
+template <int MODE, bool CERT>
+__device__ void finish_lane(const TravParams &p, int64_t i, int *stk) {
+    int root, toff;
+    segment_root(p, i, root, toff);
+    Finish<MODE, CERT> f;
+    const bool ok = f.init(p, i);
+    if (root == kDone) {
+        // empty mesh: nothing to test
+    } else if (!ok) {
+        if (CERT) {
+            // brute force over every leaf under the root: the box test is not reliable here
+            const int first = root < 0 ? ~root : p.nodes[root].refs.z;
+            const int last = root < 0 ? ~root : p.nodes[root].refs.w;
+            for (int leaf = first; leaf <= last && !f.done; ++leaf)
+                f.test_leaf(p, leaf);
+        }
+    } else {
+        int sp = 0;
+        int ref = root;
+        const int64_t max_steps = 2 * p.nt + 8;
+        const int n_internal = (int)p.nt - 1;
+        for (int64_t steps = 0; steps <= max_steps && ref < n_internal && ~ref < p.nt; ++steps) {
+            if (ref >= 0) {
+                const Node *nd = p.nodes + ref;
+                const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
+                const int4 refs = nd->refs;
+                float tl, tr;
+                const bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, f.r, f.tlimit, tl);
+                const bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, f.r, f.tlimit, tr);
+                if (hl && hr) {
+                    const bool left_first = tl <= tr;
+                    if (sp < kDeepStack)
+                        stk[(sp++) * kFinishThreads] = left_first ? refs.y : refs.x;
+                    ref = left_first ? refs.x : refs.y;
+                    continue;
+                }
+                if (hl || hr) {
+                    ref = hl ? refs.x : refs.y;
+                    continue;
+                }
+            } else {
+                f.test_leaf(p, ~ref);
+                if (f.done)
+                    break;
+            }
+            if (sp == 0)
+                break;
+            ref = stk[(--sp) * kFinishThreads];
+        }
+    }
+    f.write(p, i, toff);
+}
+
+template <int MODE, bool CERT>
+__global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
+    __shared__ int deep[kWaveStack];
+    const uint32_t count = *p.queue_len;
+    if (count <= (uint32_t)kWaveFinishMax) {
+        for (uint32_t qi = blockIdx.x; qi < count; qi += gridDim.x)
+            finish_wave<MODE, CERT>(p, p.queue[qi], deep);
+    } else {
+        for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < count; qi += gridDim.x * blockDim.x)
+            finish_lane<MODE, CERT>(p, p.queue[qi], deep + threadIdx.x);
     }
 }
 
@@ -755,8 +911,9 @@ hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t
         return hipGetLastError();
     }
     dispatch_pass1<false>(p, a.mode, a.certified != 0, a.block, s);
-    const int64_t want = (a.n + kFinishThreads - 1) / kFinishThreads;
-    const int grid2 = (int)(want < 1024 ? want : 1024);
+    // enough blocks for one per segment of a short queue; a long queue is
+    // taken 64 segments per block
+    const int grid2 = (int)(a.n < 2048 ? a.n : 2048);
     if (a.mode == MODE_BOOL)
         a.certified ? k_finish<MODE_BOOL, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_BOOL, false><<<grid2, kFinishThreads, 0, s>>>(p);
     else if (a.mode == MODE_FIRST)
