@@ -38,6 +38,8 @@ def _load():
     I64 = ctypes.c_int64
     lib.rsi_oracle_intersect.argtypes = [P, I64, P, I64, P, P, I64, P, P, P, P, ctypes.c_int]
     lib.rsi_oracle_intersect.restype = ctypes.c_int
+    lib.rsi_oracle_intercept_count.argtypes = [P, I64, P, I64, P, P, I64, P, ctypes.c_int]
+    lib.rsi_oracle_intercept_count.restype = ctypes.c_int
     lib.rsi_oracle_all_hits.argtypes = [P, I64, P, I64, P, P, P, P, ctypes.c_int]
     lib.rsi_oracle_all_hits.restype = ctypes.c_int
     lib.rsi_oracle_radix_tree.argtypes = [P, I64, ctypes.c_int, P, P, P, P, P, P]
@@ -86,6 +88,21 @@ def intersect(V, F, O, E, n_threads: int = 0):
     if rc != 0:
         raise ValueError("triangle index out of range" if rc == -1 else "oracle allocation failed")
     return hit, ids, uvt, nh
+
+
+def intercept_count(V, F, O, E, n_threads: int = 0):
+    """Distinct intersections per segment (paper: Background -- the
+    intercept-count mode): the number of distinct binary64 t among the hits
+    of the exhaustive test.  int32 [N]."""
+    V, O, E = _f32(V), _f32(O), _f32(E)
+    F = _i32(F)
+    n = O.shape[0]
+    count = np.zeros(n, np.int32)
+    rc = _load().rsi_oracle_intercept_count(_ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(O), _ptr(E), n,
+                                            _ptr(count), int(n_threads))
+    if rc != 0:
+        raise ValueError("triangle index out of range" if rc == -1 else "oracle allocation failed")
+    return count
 
 
 def all_hits(V, F, o, e, cap: int = 4096):

@@ -197,6 +197,91 @@ int rsi_oracle_all_hits(const float *V, int64_t n_vert, const int32_t *F, int64_
     return n;
 }
 
+/*
+ * Number of distinct intersections of each segment with the surface (paper:
+ * Background -- the experimental intercept-count mode, the number of unique
+ * intersections per ray).  Reading: the number of distinct binary64 t values
+ * among the segment's hits, each decided exactly as above, so several
+ * triangles hit at the same t (a shared edge or vertex) count once.
+ *   count   int32 [n_rays]   output
+ * Returns 0, -1 on a bad index, -2 if memory runs out.
+ */
+static int cmp_double(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+int rsi_oracle_intercept_count(const float *V, int64_t n_vert,
+                               const int32_t *F, int64_t n_tri,
+                               const float *from, const float *to, int64_t n_rays,
+                               int32_t *count, int n_threads)
+{
+    int64_t j, i;
+    for (j = 0; j < 3 * n_tri; ++j)
+        if (F[j] < 0 || (int64_t)F[j] >= n_vert)
+            return -1;
+    double *tri = (double *)malloc(sizeof(double) * 9 * (size_t)(n_tri > 0 ? n_tri : 1));
+    if (!tri)
+        return -2;
+    for (j = 0; j < n_tri; ++j)
+        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 3; ++k)
+                tri[9 * j + 3 * c + k] = (double)V[3 * (int64_t)F[3 * j + c] + k];
+    int failed = 0;
+#ifdef _OPENMP
+    if (n_threads > 0)
+        omp_set_num_threads(n_threads);
+#pragma omp parallel reduction(| : failed)
+#endif
+    {
+        size_t cap = 64;
+        double *ts = (double *)malloc(sizeof(double) * cap);
+        if (!ts)
+            failed = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+        for (i = 0; i < n_rays; ++i) {
+            if (!ts) {
+                count[i] = -1;
+                continue;
+            }
+            double O[3], E[3];
+            for (int k = 0; k < 3; ++k) {
+                O[k] = (double)from[3 * i + k];
+                E[k] = (double)to[3 * i + k];
+            }
+            size_t n = 0;
+            for (int64_t jj = 0; jj < n_tri; ++jj) {
+                double u, v, t;
+                const double *T = tri + 9 * jj;
+                if (!oracle_pair(O, E, T, T + 3, T + 6, &u, &v, &t))
+                    continue;
+                if (n == cap) {
+                    double *grown = (double *)realloc(ts, sizeof(double) * 2 * cap);
+                    if (!grown) {
+                        failed = 1;
+                        break;
+                    }
+                    ts = grown;
+                    cap *= 2;
+                }
+                ts[n++] = t;
+            }
+            qsort(ts, n, sizeof(double), cmp_double);
+            int32_t distinct = 0;
+            for (size_t k = 0; k < n; ++k)
+                if (k == 0 || ts[k] != ts[k - 1])
+                    ++distinct;
+            count[i] = distinct;
+        }
+        free(ts);
+    }
+    free(tri);
+    return failed ? -2 : 0;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Binary radix tree over sorted keys (Karras 2012, section 3).            */
 /* ---------------------------------------------------------------------- */
