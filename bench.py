@@ -39,12 +39,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rays", type=int, default=10_000_000)
-    ap.add_argument("--mode", default="boolean", choices=["boolean", "first_hit", "barycentric"])
+    ap.add_argument("--mode", default="boolean", choices=["boolean", "first_hit", "barycentric", "intercept_count"])
     ap.add_argument("--precision", default="certified", choices=["plain", "certified"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--train-rays", type=int, default=2_000_000)
     ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -86,6 +87,20 @@ def measured_traffic(mode, precision):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -116,7 +131,8 @@ def main():
     n = O.shape[0]
     stream = torch.cuda.current_stream()
 
-    out_keys = {"boolean": ("hit",), "first_hit": ("tri_id",), "barycentric": ("tri_id", "uvt")}
+    out_keys = {"boolean": ("hit",), "first_hit": ("tri_id",), "barycentric": ("tri_id", "uvt"),
+                "intercept_count": ("count",)}
     outs = {}
     for m, ks in out_keys.items():
         o = {"counters": torch.zeros(4, dtype=torch.int64, device=dev)}
@@ -126,6 +142,8 @@ def main():
             o["tri_id"] = torch.empty(n, dtype=torch.int32, device=dev)
         if "uvt" in ks:
             o["uvt"] = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        if "count" in ks:
+            o["count"] = torch.empty(n, dtype=torch.int32, device=dev)
         outs[m] = o
 
     def step(mode=args.mode, precision=args.precision, ev=None):
@@ -160,6 +178,10 @@ def main():
         hit_frac = float(outs["boolean"]["hit"].float().mean().item())
     print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, intersect {intersect_avg:.3f} ms "
           f"-> {value:.1f} Mrays/s", file=sys.stderr, flush=True)
+    # results of each path on the leading segments, for the oracle comparison below
+    key = {"boolean": "hit", "intercept_count": "count"}.get(args.mode, "tri_id")
+    keep = min(n, 1 << 22)
+    results = {f"{args.precision} (timed path)": outs[args.mode][key][:keep].cpu().numpy().copy()}
 
     # ---------------- algorithmic bytes of the traversal (instrumented, untimed)
     with rsi.rsi_build(dV, dF) as mesh:
@@ -169,7 +191,7 @@ def main():
         mean_tests = float(tests.double().mean().item())
         p50_visits = float(visits.double().median().item())
         p99_visits = float(torch.quantile(visits[: min(n, 1 << 24)].double(), 0.99).item())
-    out_bytes = {"boolean": 1, "first_hit": 4, "barycentric": 16}[args.mode]
+    out_bytes = {"boolean": 1, "first_hit": 4, "barycentric": 16, "intercept_count": 4}[args.mode]
     bytes_per_ray = 24 + out_bytes + 64 * mean_visits + 48 * mean_tests
     achieved_gbs = n * bytes_per_ray / (intersect_avg * 1e-3) / 1e9
     roofline = {
@@ -187,7 +209,7 @@ def main():
     variants = {}
     if not args.no_variants:
         with rsi.rsi_build(dV, dF) as mesh:
-            for mode in ("boolean", "first_hit", "barycentric"):
+            for mode in ("boolean", "first_hit", "barycentric", "intercept_count"):
                 for prec in ("plain", "certified"):
                     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision=prec, out=outs[mode])
@@ -202,6 +224,22 @@ def main():
                     variants[f"{mode}/{prec}"] = {"mrays_s": round(n / (ms * 1e-3) / 1e6, 1),
                                                   "ms": round(ms, 3), "redecided_fp64": c[0],
                                                   "stack_overflow": c[1]}
+                    if mode == args.mode and prec != args.precision:
+                        results[prec] = outs[mode][key][:keep].cpu().numpy().copy()
+            for order in ("midpoint", "origin_octant"):  # segment processing orders (same results)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                run = lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision,
+                                                out=outs[args.mode], ray_sort=order)
+                run()
+                a.record(stream)
+                for _ in range(3):
+                    run()
+                b.record(stream)
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b) / 3
+                variants[f"{args.mode}/{args.precision}/order={order}"] = {
+                    "mrays_s": round(n / (ms * 1e-3) / 1e6, 1), "ms": round(ms, 3)}
+                results[f"{args.precision}, order={order}"] = outs[args.mode][key][:keep].cpu().numpy().copy()
             b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             b0.record(stream)
             for _ in range(5):
@@ -212,7 +250,7 @@ def main():
 
     # ---------------- learned proposal vs plain order (BVH resident, untimed region)
     learned = None
-    if not args.no_learned:
+    if not args.no_learned and args.mode != "intercept_count":
         lo, hi = V.min(axis=0), V.max(axis=0)
         Ot, Et = workloads.rays_in_box(args.train_rays, 23, lo, hi)  # training segments, own seed
         dOt, dEt = torch.from_numpy(Ot).to(dev), torch.from_numpy(Et).to(dev)
@@ -239,6 +277,7 @@ def main():
             ms_learned = timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision,
                                                          out=o, proposal=True))
             late = int(o["counters"][2].item())
+            results[f"{args.precision} + learned proposal"] = o[key][:keep].cpu().numpy().copy()
             n_hit = int(o["hit"].sum().item()) if args.mode == "boolean" else int((o["tri_id"] >= 0).sum().item())
             ms_mlp = timed(lambda: rsi.rsi_proposal_predict(mesh, dO, dE))
             v_p, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision)
@@ -257,6 +296,50 @@ def main():
             }
         print(f"[bench] learned: {learned}", file=sys.stderr, flush=True)
 
+    # ---------------- batched form: 64 meshes, build + intersect replayed from a graph
+    batched = None
+    if not args.no_batched:
+        del outs
+        torch.cuda.empty_cache()
+        Vb, Fb, Ob, Eb, vo, to, ro = workloads.batched_config()
+        dVb, dFb = torch.from_numpy(Vb).to(dev), torch.from_numpy(Fb).to(dev)
+        dOb, dEb = torch.from_numpy(Ob).to(dev), torch.from_numpy(Eb).to(dev)
+        nb = Ob.shape[0]
+        bkey = "hit" if args.mode == "boolean" else ("count" if args.mode == "intercept_count" else "tri_id")
+        bout = {bkey: torch.empty(nb, dtype=torch.uint8 if bkey == "hit" else torch.int32, device=dev),
+                "counters": torch.zeros(4, dtype=torch.int64, device=dev)}
+        if args.mode == "barycentric":
+            bout["uvt"] = torch.empty((nb, 3), dtype=torch.float32, device=dev)
+        with rsi.rsi_batch_create(vo, to, ro) as b:
+            def bstep():
+                rsi.rsi_batch_build(b, dVb, dFb)
+                rsi.rsi_batch_intersect(b, dOb, dEb, mode=args.mode, precision=args.precision, out=bout)
+            bstep()
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
+                    bstep()
+            torch.cuda.current_stream().wait_stream(side)
+            g.replay()
+            torch.cuda.synchronize()
+            reps = 5
+            a, bb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                g.replay()
+            bb.record(stream)
+            torch.cuda.synchronize()
+            ms_b = a.elapsed_time(bb) / reps
+            batched = {"workload": f"64 heightfields, {Fb.shape[0]} triangles, {nb} segments",
+                       "graph_replay_ms": round(ms_b, 3), "mrays_s": round(nb / (ms_b * 1e-3) / 1e6, 1),
+                       "redecided_fp64": int(bout["counters"][0].item()), "mode": args.mode,
+                       "precision": args.precision}
+        print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
+        del dVb, dFb, dOb, dEb, bout
+
     # ---------------- CPU baseline: the oracle on a bounded sample
     cpu = None
     if not args.no_cpu_baseline:
@@ -266,14 +349,20 @@ def main():
         s0 = time.perf_counter()
         oracle.intersect(V, F, O[:probe], E[:probe])
         dt = time.perf_counter() - s0
-        m = int(min(n, max(probe, probe * args.cpu_seconds / max(dt, 1e-6))))
+        m = int(min(n, keep, max(probe, probe * args.cpu_seconds / max(dt, 1e-6))))
         s0 = time.perf_counter()
-        oracle.intersect(V, F, O[:m], E[:m])
+        o_hit, o_id, _, _ = oracle.intersect(V, F, O[:m], E[:m])
         dt = time.perf_counter() - s0
+        want = o_hit if args.mode == "boolean" else o_id
+        if args.mode == "intercept_count":
+            want = oracle.intercept_count(V, F, O[:m], E[:m])
+        mismatches = {name: int(np.sum(r[:m] != want)) for name, r in results.items()}
+        print(f"[bench] mismatches vs the oracle on {m} segments: {mismatches}", file=sys.stderr, flush=True)
         cpu = {"value": round(m / dt / 1e6, 6), "unit": "Mrays/s", "cores": oracle.max_threads(),
                "kind": "oracle",
                "sample": f"first {m} of the {n} segments x all {F.shape[0]} triangles "
-                         f"(binary64 brute force, all three modes in one pass), {dt:.1f} s"}
+                         f"(binary64 brute force, all three modes in one pass), {dt:.1f} s",
+               "host": host_cpu(), "mismatches_vs_oracle": mismatches}
         print(f"[bench] cpu oracle: {cpu['value']} Mrays/s on {cpu['cores']} threads", file=sys.stderr,
               flush=True)
 
@@ -293,6 +382,7 @@ def main():
         "hit_fraction": hit_frac,
         "variants": variants,
         "learned_vs_plain": learned,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

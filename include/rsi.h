@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define RSI_ABI_VERSION 1
+#define RSI_ABI_VERSION 2  /* 2: intercept-count mode, rsi_outputs.count */
 
 typedef struct rsi_mesh_s *rsi_mesh; /* opaque; owned by the library until rsi_destroy */
 
@@ -64,7 +64,15 @@ typedef enum rsi_status {
 typedef enum rsi_mode {
     RSI_MODE_BOOLEAN = 0,     /* paper's mode=boolean: one flag per segment */
     RSI_MODE_FIRST_HIT = 1,   /* index of the nearest hit triangle */
-    RSI_MODE_BARYCENTRIC = 2  /* paper's mode=barycentric: nearest hit + (u, v, t) */
+    RSI_MODE_BARYCENTRIC = 2, /* paper's mode=barycentric: nearest hit + (u, v, t) */
+    RSI_MODE_INTERCEPT_COUNT = 3 /* paper's mode=intercept_count (Background section:
+                                    the number of unique intersections per ray): the
+                                    number of distinct t among the segment's hits, so
+                                    triangles met at one point (a shared edge or
+                                    vertex) count once.  CERTIFIED: distinct binary64 t
+                                    of the binary64 decisions, as the oracle; PLAIN:
+                                    distinct binary32 t of the binary32 decisions.
+                                    No proposal order. */
 } rsi_mode;
 
 typedef enum rsi_precision {
@@ -74,6 +82,18 @@ typedef enum rsi_precision {
                                     orderings inside the bound are re-decided in binary64
                                     on the GPU, so results equal the binary64 decisions */
 } rsi_precision;
+
+/* Processing order of segments (rsi_intersect_opts.ray_sort).  Neighbouring
+ * lanes of a wave follow similar tree paths when their segments are close in
+ * space, which the Morton order of segments provides (the spatial sort of the
+ * paper's Background section, applied to segments instead of triangles).
+ * Codes are 30-bit, over the mesh box; the batched form keeps the mesh id
+ * above them, so each mesh's segments stay within their own range. */
+typedef enum rsi_ray_order {
+    RSI_RAY_ORDER_INPUT = 0,         /* input order */
+    RSI_RAY_ORDER_MIDPOINT = 1,      /* Morton code of the segment midpoint */
+    RSI_RAY_ORDER_ORIGIN_OCTANT = 2  /* direction octant, then Morton code of the start point */
+} rsi_ray_order;
 
 /* Build options; pass NULL for defaults. */
 typedef struct rsi_build_opts {
@@ -90,7 +110,10 @@ typedef struct rsi_intersect_opts {
     int32_t block;        /* threads per workgroup: 64, 128 or 256; 0 = 256 */
     int32_t stack_depth;  /* traversal stack entries per lane in LDS, 1..64; 0 = 20.
                              Deeper paths are finished exactly by a second pass. */
-    int32_t ray_sort;     /* 0 = rays processed in input order (the only value so far) */
+    int32_t ray_sort;     /* rsi_ray_order: order in which segments are processed.
+                             Results are written at input indices in every order;
+                             a value other than 0 adds a key pass and a sort of the
+                             segment indices (16 B of scratch per segment). */
     int32_t proposal;     /* 1 = visit the learned proposal's bucket first (needs a
                              trained or loaded proposal); 0 = plain order */
 } rsi_intersect_opts;
@@ -99,6 +122,7 @@ typedef struct rsi_intersect_opts {
  *   BOOLEAN:     hit
  *   FIRST_HIT:   tri_id            (hit filled too when not NULL)
  *   BARYCENTRIC: tri_id and uvt    (hit filled too when not NULL)
+ *   INTERCEPT_COUNT: count         (hit filled too when not NULL)
  * Results are written at the segment's input index. */
 typedef struct rsi_outputs {
     uint8_t *hit;       /* [N_r] 1 if the segment meets the surface, else 0 */
@@ -108,8 +132,10 @@ typedef struct rsi_outputs {
                            precision; NaN on a miss */
     uint64_t *counters; /* optional [4]: [0] segments re-decided in binary64, [1] segments
                            that outgrew the LDS stack, [2] hitting segments whose answer
-                           was not in the proposed bucket (proposal misses), [3] reserved
-                           (0).  Zeroed by the call before it counts. */
+                           was not in the proposed bucket (proposal misses), [3] count-mode
+                           segments with more distinct hits than a lane keeps (8), finished
+                           by the second pass.  Zeroed by the call before it counts. */
+    int32_t *count;     /* [N_r] intercept-count mode: distinct intersections, 0 on a miss */
 } rsi_outputs;
 
 /*
@@ -207,6 +233,25 @@ rsi_status rsi_traversal_stats(rsi_mesh mesh, const float *rays_from, const floa
                                int64_t n_rays, int32_t mode, const rsi_intersect_opts *opts,
                                uint32_t *node_visits, uint32_t *leaf_tests, void *stream);
 
+/*
+ * rsi_debug_certify -- the CERTIFIED precision's binary32 test on n given
+ * (segment, triangle) pairs, for checking its error bounds (the paper's
+ * Epilogue: binary32 Moller-Trumbore can misjudge near-parallel segments, and
+ * binary64 intermediates fix that; the bound decides which pairs binary32 may
+ * settle).  Pair i is segment rays_from[i] -> rays_to[i] and the triangle with
+ * corners corners[i][0..2] (xyz each), set up as the traversal does (direction
+ * and edges rounded to binary32).  Device arrays:
+ *   values  float [n][10]: det, U, W, T (binary32), their bounds B(det), B(U),
+ *           B(W), B(T), and for a sure hit the interval [tlo, thi] around t
+ *           (NaN otherwise).  The bounds claim |X32 - X| <= B(X) and
+ *           |X32 - X64| <= B(X) for the exact value X and the binary64 value X64
+ *           computed in the oracle's operation order.
+ *   classes int32 [n]: 0 sure miss, 1 sure hit, 2 unsure (decided in binary64).
+ * Queued on `stream`; RSI_E_ARG for NULL or misaligned pointers or n < 0.
+ */
+rsi_status rsi_debug_certify(const float *rays_from, const float *rays_to, const float *corners, int64_t n,
+                             float *values, int32_t *classes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned subtree proposal.  A small MLP predicts, per segment, the depth-8
  * subtree ("bucket") of the tree that holds its first hit; rsi_intersect with
@@ -287,7 +332,8 @@ rsi_status rsi_proposal_load(rsi_mesh mesh, const char *path);
  * box), so one sort, one radix tree and one bottom-up pass cover all meshes
  * and each mesh is one subtree.  The traversal takes (mesh, segment range)
  * items of up to 2048 segments from a queue.  Reported triangle indices are
- * relative to the segment's mesh.  rsi_batch_create allocates everything;
+ * relative to the segment's mesh.  rsi_batch_create allocates everything
+ * (including ~16 B per segment for the optional segment ordering);
  * rsi_batch_build and rsi_batch_intersect allocate nothing and never wait, so
  * both may be captured in a HIP graph and replayed (inputs at the same
  * addresses).  Triangles with an index outside their mesh are never hit.

@@ -30,7 +30,8 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "librsi.so")
 
-MODES = {"boolean": 0, "first_hit": 1, "barycentric": 2}
+ABI_VERSION = 2
+MODES = {"boolean": 0, "first_hit": 1, "barycentric": 2, "intercept_count": 3}
 PRECISIONS = {"plain": 0, "certified": 1}
 EXPORTS = {"sorted_keys": 0, "sorted_ids": 1, "nodes": 2, "parents": 3, "counters": 4, "leaves": 5, "bounds": 6}
 STATUS = {0: "RSI_OK", 1: "RSI_E_ARG", 2: "RSI_E_RANGE", 3: "RSI_E_NOMEM", 4: "RSI_E_HIP",
@@ -54,7 +55,7 @@ class _IntersectOpts(ctypes.Structure):
 
 class _Outputs(ctypes.Structure):
     _fields_ = [("hit", ctypes.c_void_p), ("tri_id", ctypes.c_void_p), ("uvt", ctypes.c_void_p),
-                ("counters", ctypes.c_void_p)]
+                ("counters", ctypes.c_void_p), ("count", ctypes.c_void_p)]
 
 
 class _TrainOpts(ctypes.Structure):
@@ -91,6 +92,7 @@ def lib():
     L.rsi_mesh_info_get.argtypes = [P, ctypes.POINTER(_MeshInfo)]
     L.rsi_mesh_export.argtypes = [P, I32, P, I64, P]
     L.rsi_traversal_stats.argtypes = [P, P, P, I64, I32, ctypes.POINTER(_IntersectOpts), P, P, P]
+    L.rsi_debug_certify.argtypes = [P, P, P, I64, P, P, P]
     L.rsi_proposal_train.argtypes = [P, P, P, I64, ctypes.POINTER(_TrainOpts), P, ctypes.POINTER(I64), P]
     L.rsi_proposal_predict.argtypes = [P, P, P, I64, P, P]
     L.rsi_proposal_params.argtypes = [P, I32, P, P]
@@ -109,7 +111,7 @@ def lib():
     for f in ("rsi_build", "rsi_intersect", "rsi_destroy", "rsi_mesh_info_get", "rsi_mesh_export",
               "rsi_traversal_stats", "rsi_proposal_train", "rsi_proposal_predict", "rsi_proposal_params",
               "rsi_proposal_gradient", "rsi_proposal_features", "rsi_proposal_frontier", "rsi_proposal_save",
-              "rsi_proposal_load"):
+              "rsi_proposal_load", "rsi_debug_certify"):
         getattr(L, f).restype = ctypes.c_int
     L.rsi_status_string.argtypes = [ctypes.c_int]
     L.rsi_status_string.restype = ctypes.c_char_p
@@ -117,6 +119,9 @@ def lib():
     L.rsi_last_error.restype = ctypes.c_char_p
     L.rsi_abi_version.argtypes = []
     L.rsi_abi_version.restype = ctypes.c_int32
+    if L.rsi_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{library_path} has ABI {L.rsi_abi_version()}, this binding expects {ABI_VERSION}: "
+                           "rebuild it with paper_2305_01867_amd/build_lib.py")
     _lib = L
     return L
 
@@ -203,19 +208,29 @@ def rsi_destroy(mesh: Mesh):
     mesh.close()
 
 
-def _iopts(precision, block, stack_depth, proposal=False):
+RAY_ORDERS = {"input": 0, "midpoint": 1, "origin_octant": 2}
+
+
+def _iopts(precision, block, stack_depth, proposal=False, ray_sort=0):
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")
-    return _IntersectOpts(PRECISIONS[precision], int(block), int(stack_depth), 0, int(bool(proposal)))
+    if isinstance(ray_sort, str):
+        if ray_sort not in RAY_ORDERS:
+            raise ValueError(f"ray_sort must be one of {list(RAY_ORDERS)}")
+        ray_sort = RAY_ORDERS[ray_sort]
+    return _IntersectOpts(PRECISIONS[precision], int(block), int(stack_depth), int(ray_sort), int(bool(proposal)))
 
 
 def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
                   precision: str = "plain", block: int = 0, stack_depth: int = 0, out: dict | None = None,
-                  stream=None, proposal: bool = False) -> dict:
+                  stream=None, proposal: bool = False, ray_sort=0) -> dict:
     """Test segments [N, 3] float32 against the mesh.  Returns a dict with the
-    outputs of the mode ("hit" uint8, "tri_id" int32, "uvt" float32 [N, 3]) and
-    "counters" uint64 [4] (re-decided in binary64, past the LDS stack, 0, 0).
-    `out` may supply preallocated tensors under the same keys."""
+    outputs of the mode ("hit" uint8, "tri_id" int32, "uvt" float32 [N, 3],
+    "count" int32) and "counters" uint64 [4] (re-decided in binary64, past the
+    LDS stack, proposal misses, count-mode list overflows).
+    `out` may supply preallocated tensors under the same keys.  ray_sort:
+    processing order ("input", "midpoint", "origin_octant" or 0 / 1 / 2);
+    results are at input indices in every order."""
     if mode not in MODES:
         raise ValueError(f"mode must be one of {list(MODES)}")
     _need(rays_from, "rays_from", torch.float32, 3)
@@ -227,13 +242,15 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
     out = dict(out or {})
     if mode == "boolean":
         out.setdefault("hit", torch.empty(n, dtype=torch.uint8, device=dev))
+    elif mode == "intercept_count":
+        out.setdefault("count", torch.empty(n, dtype=torch.int32, device=dev))
     else:
         out.setdefault("tri_id", torch.empty(n, dtype=torch.int32, device=dev))
     if mode == "barycentric":
         out.setdefault("uvt", torch.empty((n, 3), dtype=torch.float32, device=dev))
     out.setdefault("counters", torch.zeros(4, dtype=torch.int64, device=dev))
     spec = {"hit": (torch.uint8, None), "tri_id": (torch.int32, None), "uvt": (torch.float32, 3),
-            "counters": (torch.int64, None)}
+            "count": (torch.int32, None), "counters": (torch.int64, None)}
     for k, t in out.items():
         if k not in spec:
             raise ValueError(f"unknown output {k}")
@@ -246,8 +263,8 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
     def ptr(k):
         return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()
 
-    o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"))
-    opts = _iopts(precision, block, stack_depth, proposal)
+    o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"), ptr("count"))
+    opts = _iopts(precision, block, stack_depth, proposal, ray_sort)
     _check(lib().rsi_intersect(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
                                ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
                                ctypes.byref(o), _stream_handle(stream)))
@@ -256,19 +273,34 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
 
 def rsi_traversal_stats(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
                         precision: str = "plain", block: int = 0, stack_depth: int = 0, stream=None,
-                        proposal: bool = False):
+                        proposal: bool = False, ray_sort=0):
     """Per-segment (node visits, leaf tests) of the traversal, uint32 -> int64 tensors."""
     _need(rays_from, "rays_from", torch.float32, 3)
     _need(rays_to, "rays_to", torch.float32, 3)
     n = rays_from.shape[0]
     visits = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
     tests = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
-    opts = _iopts(precision, block, stack_depth, proposal)
+    opts = _iopts(precision, block, stack_depth, proposal, ray_sort)
     _check(lib().rsi_traversal_stats(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
                                      ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
                                      ctypes.c_void_p(visits.data_ptr()), ctypes.c_void_p(tests.data_ptr()),
                                      _stream_handle(stream)))
     return visits, tests
+
+
+def rsi_debug_certify(rays_from: torch.Tensor, rays_to: torch.Tensor, corners: torch.Tensor, stream=None):
+    """Binary32 predicates, their bounds and the certified classification for
+    pairs (segment i, triangle with corners[i] [n, 3, 3]).  Returns (values
+    float32 [n, 10], classes int32 [n]); see include/rsi.h."""
+    n = _rays(rays_from, rays_to)
+    _need(corners, "corners", torch.float32)
+    if corners.shape != (n, 3, 3) or not corners.is_contiguous():
+        raise ValueError("corners must be a contiguous [n, 3, 3] tensor")
+    values = torch.empty((n, 10), dtype=torch.float32, device=rays_from.device)
+    classes = torch.empty(n, dtype=torch.int32, device=rays_from.device)
+    _check(lib().rsi_debug_certify(_p(rays_from), _p(rays_to), _p(corners), n, _p(values), _p(classes),
+                                   _stream_handle(stream)))
+    return values, classes
 
 
 def rsi_mesh_info_get(mesh: Mesh) -> dict:
@@ -448,7 +480,8 @@ def rsi_batch_build(batch: Batch, vertices: torch.Tensor, triangles: torch.Tenso
 
 
 def rsi_batch_intersect(batch: Batch, rays_from, rays_to, mode: str = "boolean", precision: str = "plain",
-                        block: int = 0, stack_depth: int = 0, out: dict | None = None, stream=None) -> dict:
+                        block: int = 0, stack_depth: int = 0, out: dict | None = None, stream=None,
+                        ray_sort=0) -> dict:
     """Outputs over all segments (triangle indices relative to each mesh)."""
     if mode not in MODES:
         raise ValueError(f"mode must be one of {list(MODES)}")
@@ -459,6 +492,8 @@ def rsi_batch_intersect(batch: Batch, rays_from, rays_to, mode: str = "boolean",
     out = dict(out or {})
     if mode == "boolean":
         out.setdefault("hit", torch.empty(n, dtype=torch.uint8, device=dev))
+    elif mode == "intercept_count":
+        out.setdefault("count", torch.empty(n, dtype=torch.int32, device=dev))
     else:
         out.setdefault("tri_id", torch.empty(n, dtype=torch.int32, device=dev))
     if mode == "barycentric":
@@ -468,8 +503,8 @@ def rsi_batch_intersect(batch: Batch, rays_from, rays_to, mode: str = "boolean",
     def ptr(k):
         return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()
 
-    o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"))
-    opts = _iopts(precision, block, stack_depth, False)
+    o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"), ptr("count"))
+    opts = _iopts(precision, block, stack_depth, False, ray_sort)
     _check(lib().rsi_batch_intersect(batch.handle, _p(rays_from), _p(rays_to), MODES[mode], ctypes.byref(opts),
                                      ctypes.byref(o), _stream_handle(stream)))
     return out

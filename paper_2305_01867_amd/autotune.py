@@ -1,16 +1,17 @@
 """Launch-parameter autotuner for the intersection kernels.
 
-For a given workload it times every candidate (threads per workgroup x LDS
-stack depth) with HIP events on the caller's stream, keeps the fastest, and
-caches the choice in a JSON file keyed by a size class (mode, precision,
-number of meshes, log2 of triangles and of segments), so later runs of the
-same class reuse it without timing.  The stack depth trades LDS per workgroup
-(occupancy) against how often a segment overflows to the deep-stack pass.
-Segment order is always the input order (ray_sort 0 is the only value the
-library offers).
+For a given workload it times every point of a grid of launch choices with
+HIP events on the caller's stream, keeps the fastest, and caches the choice
+in a JSON file keyed by a size class (mode, precision, number of meshes,
+log2 of triangles and of segments), so later runs of the same class reuse it
+without timing.  The default grid covers threads per workgroup, the LDS
+stack depth (occupancy against how often a segment overflows to the
+deep-stack pass) and the segment processing order; MORTON_BITS can be added
+for a `run` that rebuilds the tree (30-bit against 63-bit keys).
 """
 from __future__ import annotations
 
+import itertools
 import json
 import math
 import os
@@ -19,6 +20,9 @@ import torch
 
 BLOCKS = (64, 128, 256)
 STACKS = (8, 12, 16, 20, 24, 32)
+RAY_SORTS = (0, 1, 2)  # input order, midpoint Morton, octant + start Morton
+MORTON_BITS = (30, 63)
+SPACE = {"block": BLOCKS, "stack_depth": STACKS, "ray_sort": RAY_SORTS}
 
 
 def size_class(mode: str, precision: str, n_meshes: int, n_triangles: int, n_rays: int) -> str:
@@ -26,9 +30,11 @@ def size_class(mode: str, precision: str, n_meshes: int, n_triangles: int, n_ray
             f"/r{int(math.log2(max(n_rays, 1)))}")
 
 
-def tune(run, key: str, cache_path: str | None = None, blocks=BLOCKS, stacks=STACKS, reps: int = 2):
-    """run(block, stack_depth) must queue one intersection on the current
-    stream.  Returns (best {"block", "stack_depth", "ms"}, all timings)."""
+def tune(run, key: str, cache_path: str | None = None, space: dict | None = None, reps: int = 2):
+    """run(**choice) must queue one intersection (and, if the grid holds
+    morton_bits, the build it needs) on the current stream.  Returns (best
+    choice with its "ms", all timings), or (cached choice, None)."""
+    space = dict(SPACE if space is None else space)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
@@ -36,17 +42,18 @@ def tune(run, key: str, cache_path: str | None = None, blocks=BLOCKS, stacks=STA
         if key in cache:
             return cache[key], None
     stream = torch.cuda.current_stream()
+    names = list(space)
     timings = []
-    for block in blocks:
-        for stack in stacks:
-            run(block, stack)  # warm-up (also first-use costs)
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(reps):
-                run(block, stack)
-            b.record(stream)
-            b.synchronize()
-            timings.append({"block": block, "stack_depth": stack, "ms": a.elapsed_time(b) / reps})
+    for values in itertools.product(*(space[k] for k in names)):
+        choice = dict(zip(names, values))
+        run(**choice)  # warm-up (also first-use costs)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            run(**choice)
+        b.record(stream)
+        b.synchronize()
+        timings.append({**choice, "ms": a.elapsed_time(b) / reps})
     best = min(timings, key=lambda t: t["ms"])
     if cache_path:
         cache[key] = best

@@ -117,10 +117,12 @@ size_t round_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool valid_mesh(rsi_mesh m) { return m != nullptr && m->magic == kMagic; }
 
-rsi_status parse_intersect_opts(const rsi_intersect_opts *opts, int &precision, int &block, int &stack) {
+rsi_status parse_intersect_opts(const rsi_intersect_opts *opts, int &precision, int &block, int &stack,
+                                int &ray_sort) {
     precision = RSI_PRECISION_PLAIN;
     block = 256;
     stack = 20;
+    ray_sort = RSI_RAY_ORDER_INPUT;
     if (!opts)
         return RSI_OK;
     if (opts->precision != RSI_PRECISION_PLAIN && opts->precision != RSI_PRECISION_CERTIFIED)
@@ -136,8 +138,10 @@ rsi_status parse_intersect_opts(const rsi_intersect_opts *opts, int &precision, 
             return fail(RSI_E_ARG, "stack_depth must be in 1..64");
         stack = opts->stack_depth;
     }
-    if (opts->ray_sort != 0)
-        return fail(RSI_E_ARG, "ray_sort: only 0 (input order) is available");
+    if (opts->ray_sort != RSI_RAY_ORDER_INPUT && opts->ray_sort != RSI_RAY_ORDER_MIDPOINT &&
+        opts->ray_sort != RSI_RAY_ORDER_ORIGIN_OCTANT)
+        return fail(RSI_E_ARG, "ray_sort must be 0 (input order), 1 (midpoint Morton) or 2 (octant + start Morton)");
+    ray_sort = opts->ray_sort;
     if (opts->proposal != 0 && opts->proposal != 1)
         return fail(RSI_E_ARG, "proposal must be 0 or 1");
     return RSI_OK;
@@ -151,7 +155,8 @@ rsi_status check_ray_args(rsi_mesh mesh, const float *from, const float *to, int
         return fail(RSI_E_ARG, "n_rays must be >= 0");
     if (n >= (int64_t(1) << 31))
         return fail(RSI_E_CAPACITY, "n_rays must be < 2^31");
-    if (mode != RSI_MODE_BOOLEAN && mode != RSI_MODE_FIRST_HIT && mode != RSI_MODE_BARYCENTRIC)
+    if (mode != RSI_MODE_BOOLEAN && mode != RSI_MODE_FIRST_HIT && mode != RSI_MODE_BARYCENTRIC &&
+        mode != RSI_MODE_INTERCEPT_COUNT)
         return fail(RSI_E_ARG, "unknown mode");
     if (n > 0 && (!from || !to))
         return fail(RSI_E_ARG, "rays_from / rays_to must not be NULL");
@@ -316,10 +321,12 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     rsi_status st = check_ray_args(mesh, from, to, n, mode);
     if (st != RSI_OK)
         return st;
-    int precision, block, stack;
-    if ((st = parse_intersect_opts(opts, precision, block, stack)) != RSI_OK)
+    int precision, block, stack, ray_sort;
+    if ((st = parse_intersect_opts(opts, precision, block, stack, ray_sort)) != RSI_OK)
         return st;
     const bool use_prop = opts && opts->proposal == 1 && n > 0 && mesh->dev.nt > 0;
+    if (use_prop && mode == RSI_MODE_INTERCEPT_COUNT)
+        return fail(RSI_E_ARG, "intercept-count mode has no proposal order");
     if (use_prop && !mesh->dev.prop.ready)
         return fail(RSI_E_STATE, "proposal = 1 needs a trained or loaded proposal (rsi_proposal_train / _load)");
     if (!stats) {
@@ -328,12 +335,15 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
         if (n > 0) {
             if (mode == RSI_MODE_BOOLEAN && !out->hit)
                 return fail(RSI_E_ARG, "boolean mode needs out->hit");
-            if (mode != RSI_MODE_BOOLEAN && !out->tri_id)
+            if ((mode == RSI_MODE_FIRST_HIT || mode == RSI_MODE_BARYCENTRIC) && !out->tri_id)
                 return fail(RSI_E_ARG, "this mode needs out->tri_id");
+            if (mode == RSI_MODE_INTERCEPT_COUNT && !out->count)
+                return fail(RSI_E_ARG, "intercept-count mode needs out->count");
             if (mode == RSI_MODE_BARYCENTRIC && !out->uvt)
                 return fail(RSI_E_ARG, "barycentric mode needs out->uvt");
         }
         if ((out->tri_id && !aligned4(out->tri_id)) || (out->uvt && !aligned4(out->uvt)) ||
+            (out->count && !aligned4(out->count)) ||
             (out->counters && (reinterpret_cast<uintptr_t>(out->counters) & 7u)))
             return fail(RSI_E_ARG, "output buffers must be aligned to their element size");
     } else if (n > 0 && (!visits || !tests || !aligned4(visits) || !aligned4(tests))) {
@@ -353,6 +363,8 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
                 return st;
             if (out->uvt && (st = check_dev_ptr(out->uvt, "out->uvt")) != RSI_OK)
                 return st;
+            if (out->count && (st = check_dev_ptr(out->count, "out->count")) != RSI_OK)
+                return st;
         } else if ((st = check_dev_ptr(visits, "node_visits")) != RSI_OK ||
                    (st = check_dev_ptr(tests, "leaf_tests")) != RSI_OK) {
             return st;
@@ -365,7 +377,10 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *ws = nullptr;
-    const size_t ws_bytes = 4 * (size_t)n + 64 + (use_prop ? (size_t)n + 256 : 0);
+    const size_t q_bytes = (4 * (size_t)n + 64 + 255) & ~size_t(255);
+    const size_t b_bytes = use_prop ? ((size_t)n + 511) & ~size_t(255) : 0;
+    const bool sorted = ray_sort != RSI_RAY_ORDER_INPUT && n > 1 && mesh->dev.nt > 0;
+    const size_t ws_bytes = q_bytes + b_bytes + (sorted ? rsi::ray_sort_ws_bytes(n) : 0);
     hipError_t e = hipMallocAsync(&ws, ws_bytes, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -383,8 +398,13 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     uint64_t *ws_counters = reinterpret_cast<uint64_t *>(static_cast<char *>(ws));
     a.queue_len = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + 32);
     a.queue = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + 64);
+    if (sorted) {
+        a.ray_sort = ray_sort;
+        a.key_bounds = mesh->dev.bounds;
+        a.sort_ws = static_cast<char *>(ws) + q_bytes + b_bytes;
+    }
     if (use_prop) {
-        uint8_t *bucket = static_cast<uint8_t *>(ws) + 64 + 4 * (size_t)n;
+        uint8_t *bucket = static_cast<uint8_t *>(ws) + q_bytes;
         e = rsi::proposal_predict(mesh->dev, mesh->dev.prop, from, to, n, mesh->dev.prop.n_buckets, bucket, s);
         if (e != hipSuccess) {
             (void)hipFreeAsync(ws, s);
@@ -402,6 +422,7 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
         a.hit = out->hit;
         a.tri_id = out->tri_id;
         a.uvt = out->uvt;
+        a.count = out->count;
         a.counters = out->counters ? out->counters : ws_counters;
         e = rsi::launch_intersect(mesh->dev, a, s);
     }
@@ -422,6 +443,30 @@ rsi_status rsi_traversal_stats(rsi_mesh mesh, const float *rays_from, const floa
                                int32_t mode, const rsi_intersect_opts *opts, uint32_t *node_visits,
                                uint32_t *leaf_tests, void *stream) {
     return run_rays(mesh, rays_from, rays_to, n_rays, mode, opts, nullptr, node_visits, leaf_tests, stream, true);
+}
+
+rsi_status rsi_debug_certify(const float *rays_from, const float *rays_to, const float *corners, int64_t n,
+                             float *values, int32_t *classes, void *stream) {
+    g_error.clear();
+    if (n < 0)
+        return fail(RSI_E_ARG, "n must be >= 0");
+    if (n == 0)
+        return RSI_OK;
+    if (!rays_from || !rays_to || !corners || !values || !classes || !aligned4(rays_from) || !aligned4(rays_to) ||
+        !aligned4(corners) || !aligned4(values) || !aligned4(classes))
+        return fail(RSI_E_ARG, "all arrays must be non-NULL and 4-byte aligned");
+    rsi_status st = check_device();
+    if (st != RSI_OK)
+        return st;
+    if ((st = check_dev_ptr(rays_from, "rays_from")) != RSI_OK || (st = check_dev_ptr(rays_to, "rays_to")) != RSI_OK ||
+        (st = check_dev_ptr(corners, "corners")) != RSI_OK || (st = check_dev_ptr(values, "values")) != RSI_OK ||
+        (st = check_dev_ptr(classes, "classes")) != RSI_OK)
+        return st;
+    if ((st = pending_error("before rsi_debug_certify")) != RSI_OK)
+        return st;
+    const hipError_t e = rsi::launch_debug_certify(rays_from, rays_to, corners, n, values, classes,
+                                                   static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_debug_certify");
 }
 
 rsi_status rsi_mesh_info_get(rsi_mesh mesh, rsi_mesh_info *info) {
@@ -557,8 +602,9 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     const size_t sz_tm = round_up(4 * (size_t)nt + 4), sz_mb = round_up(32 * (size_t)M);
     const size_t sz_items = round_up(16 * (size_t)(b.n_items + 1));
     const size_t sz_q = round_up(4 * (size_t)b.n_rays + 4) + 256;
+    const size_t sz_order = round_up(rsi::ray_sort_ws_bytes(b.n_rays));
     const size_t total = sz_V + sz_F + sz_keys + sz_ids + sz_nodes + sz_par + sz_cnt + sz_tris + sz_small + sz_tmp +
-                         sz_off + sz_tm + sz_mb + sz_items + sz_q;
+                         sz_off + sz_tm + sz_mb + sz_items + sz_q + sz_order;
     hipError_t e = hipMallocAsync(&bt->block, total, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -596,6 +642,7 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     b.counters = reinterpret_cast<uint64_t *>(q);
     b.queue_len = reinterpret_cast<uint32_t *>(q + 32);
     b.queue = reinterpret_cast<int32_t *>(q + 256);
+    b.sort_ws = take(sz_order);
     d.bytes = (int64_t)total;
     std::vector<int32_t> r32(M + 1), toff(M);
     for (int m = 0; m <= M; ++m)
@@ -654,10 +701,11 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
         return fail(RSI_E_STATE, "rsi_batch_build has not been called");
     rsi::BatchDev &b = batch->b;
     const int64_t n = b.n_rays;
-    if (mode != RSI_MODE_BOOLEAN && mode != RSI_MODE_FIRST_HIT && mode != RSI_MODE_BARYCENTRIC)
+    if (mode != RSI_MODE_BOOLEAN && mode != RSI_MODE_FIRST_HIT && mode != RSI_MODE_BARYCENTRIC &&
+        mode != RSI_MODE_INTERCEPT_COUNT)
         return fail(RSI_E_ARG, "unknown mode");
-    int precision, block, stack;
-    rsi_status st = parse_intersect_opts(opts, precision, block, stack);
+    int precision, block, stack, ray_sort;
+    rsi_status st = parse_intersect_opts(opts, precision, block, stack, ray_sort);
     if (st != RSI_OK)
         return st;
     if (opts && opts->proposal)
@@ -666,8 +714,9 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
         return fail(RSI_E_ARG, "out must not be NULL");
     if (n > 0 && (!rays_from || !rays_to || !aligned4(rays_from) || !aligned4(rays_to)))
         return fail(RSI_E_ARG, "rays_from / rays_to must be non-NULL and 4-byte aligned");
-    if (n > 0 && ((mode == RSI_MODE_BOOLEAN && !out->hit) || (mode != RSI_MODE_BOOLEAN && !out->tri_id) ||
-                  (mode == RSI_MODE_BARYCENTRIC && !out->uvt)))
+    if (n > 0 && ((mode == RSI_MODE_BOOLEAN && !out->hit) ||
+                  ((mode == RSI_MODE_FIRST_HIT || mode == RSI_MODE_BARYCENTRIC) && !out->tri_id) ||
+                  (mode == RSI_MODE_BARYCENTRIC && !out->uvt) || (mode == RSI_MODE_INTERCEPT_COUNT && !out->count)))
         return fail(RSI_E_ARG, "missing output buffer for this mode");
     if ((st = check_device()) != RSI_OK)
         return st;
@@ -689,6 +738,7 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
     a.hit = out->hit;
     a.tri_id = out->tri_id;
     a.uvt = out->uvt;
+    a.count = out->count;
     a.counters = out->counters ? out->counters : b.counters;
     a.queue = b.queue;
     a.queue_len = b.queue_len;
@@ -698,6 +748,11 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
     a.mesh_root = b.roots;
     a.mesh_toff = b.mesh_toff;
     a.ray_off = b.r_off;
+    if (ray_sort != RSI_RAY_ORDER_INPUT) {
+        a.ray_sort = ray_sort;
+        a.key_bounds = b.mesh_bounds;
+        a.sort_ws = b.sort_ws;
+    }
     hipError_t e = rsi::launch_intersect(batch->dev, a, s);
     return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_batch_intersect");
 }

@@ -9,7 +9,9 @@
 //   3. LDS radix sort         stable LSD, 8-bit digits: tile histograms,
 //                             one device-wide scan, stable tile scatter
 //   4. radix tree             one lane per internal node (Karras section 3)
-//   5. leaves + bottom-up     one lane per leaf; counters at agent scope
+//   5. leaves + bottom-up     one lane per leaf, arrival counters in LDS
+//                             inside a leaf tile; one workgroup finishes the
+//                             nodes that span tiles
 #include "rsi_internal.h"
 
 namespace rsi {
@@ -193,6 +195,74 @@ __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ hist,
         hist[i] = run;
         run += v;
     }
+}
+
+// Large histograms: per-block sums, a scan of those (k_sort_scan), then each
+// block scans its own segment from its offset.  Reads are coalesced rounds of
+// 1024 entries; seg is a multiple of 1024.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, uint32_t &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off)
+            x += y;
+    }
+    if (lane == 63)
+        wsum[w] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int k = 0; k < nw; ++k) {
+        const uint32_t t = wsum[k];
+        before += k < w ? t : 0u;
+        all += t;
+    }
+    __syncthreads();  // wsum is reused by the next round
+    total = all;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_partials(const uint32_t *__restrict__ hist, int64_t len, int64_t seg,
+                                                        uint32_t *__restrict__ partial) {
+    __shared__ uint32_t wsum[16];
+    const int64_t beg = (int64_t)blockIdx.x * seg, end = beg + seg < len ? beg + seg : len;
+    uint32_t s = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x)
+        s += hist[i];
+    uint32_t total;
+    (void)block_excl_scan(s, wsum, total);
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(uint32_t *__restrict__ hist, int64_t len, int64_t seg,
+                                                     const uint32_t *__restrict__ partial) {
+    __shared__ uint32_t wsum[16];
+    const int64_t beg = (int64_t)blockIdx.x * seg, end = beg + seg < len ? beg + seg : len;
+    uint32_t run = partial[blockIdx.x];
+    for (int64_t r = beg; r < end; r += blockDim.x) {
+        const int64_t i = r + threadIdx.x;
+        const uint32_t v = i < end ? hist[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan(v, wsum, total);
+        if (i < end)
+            hist[i] = run + ex;
+        run += total;
+    }
+}
+
+// Exclusive scan of hist[0..len); partial holds 1024 entries.
+void scan_hist(uint32_t *hist, int64_t len, uint32_t *partial, hipStream_t s) {
+    if (len <= 32768) {
+        k_sort_scan<<<1, 1024, 0, s>>>(hist, len);
+        return;
+    }
+    const int64_t per = (len + 1023) / 1024;
+    const int64_t seg = (per + 1023) / 1024 * 1024;
+    const int g = (int)((len + seg - 1) / seg);
+    k_scan_partials<<<g, 1024, 0, s>>>(hist, len, seg, partial);
+    k_sort_scan<<<1, 1024, 0, s>>>(partial, g);
+    k_scan_apply<<<g, 1024, 0, s>>>(hist, len, seg, partial);
 }
 
 // Stable scatter of one tile.  Rounds of 256 consecutive keys are ranked in
@@ -457,27 +527,40 @@ __global__ void k_zero_i32(int32_t *p, int n) {
 
 inline int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
 
+// Stable LSD passes over (keys, ids) with 8-bit digits; tmp holds the
+// ping-pong copies, the tile histograms and the scan partials.  An even
+// number of passes (key_bits 30 or 63 rounded up to 32 or 64) leaves the
+// result in (keys, ids).
+template <typename K>
+void sort_passes(K *keys, int32_t *ids, void *tmp, int64_t n, int key_bits, hipStream_t s) {
+    K *keys_tmp = static_cast<K *>(tmp);
+    int32_t *ids_tmp = reinterpret_cast<int32_t *>(keys_tmp + n);
+    const int ntiles = blocks_for(n, kSortTile);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ids_tmp + n);
+    uint32_t *partial = hist + (int64_t)kRadix * ntiles;
+    K *src_k = keys, *dst_k = keys_tmp;
+    int32_t *src_i = ids, *dst_i = ids_tmp;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        k_sort_hist<K><<<ntiles, kSortThreads, 0, s>>>(src_k, n, shift, ntiles, hist);
+        scan_hist(hist, (int64_t)kRadix * ntiles, partial, s);
+        k_sort_scatter<K><<<ntiles, kSortThreads, 0, s>>>(src_k, src_i, dst_k, dst_i, n, shift, ntiles, hist);
+        K *tk = src_k; src_k = dst_k; dst_k = tk;
+        int32_t *ti = src_i; src_i = dst_i; dst_i = ti;
+    }
+}
+
+size_t pass_tmp_bytes(int64_t n, size_t key_bytes) {
+    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    return key_bytes * n + 4 * n + 4 * (size_t)kRadix * ntiles + 4 * 1024 + 256;
+}
+
 // Sort (key, id), build the radix tree and fill the boxes bottom-up, for keys
 // already in m.keys and ids in m.ids.
 template <typename K>
 hipError_t build_from_keys(MeshDev &m, int key_bits, hipStream_t s) {
     const int64_t nt = m.nt;
     K *keys = static_cast<K *>(m.keys);
-    K *keys_tmp = static_cast<K *>(m.sort_tmp);
-    int32_t *ids_tmp = reinterpret_cast<int32_t *>(keys_tmp + nt);
-    const int ntiles = blocks_for(nt, kSortTile);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(ids_tmp + nt);
-
-    K *src_k = keys, *dst_k = keys_tmp;
-    int32_t *src_i = m.ids, *dst_i = ids_tmp;
-    for (int shift = 0; shift < key_bits; shift += 8) {
-        k_sort_hist<K><<<ntiles, kSortThreads, 0, s>>>(src_k, nt, shift, ntiles, hist);
-        k_sort_scan<<<1, 1024, 0, s>>>(hist, (int64_t)kRadix * ntiles);
-        k_sort_scatter<K><<<ntiles, kSortThreads, 0, s>>>(src_k, src_i, dst_k, dst_i, nt, shift, ntiles, hist);
-        K *tk = src_k; src_k = dst_k; dst_k = tk;
-        int32_t *ti = src_i; src_i = dst_i; dst_i = ti;
-    }
-    // 4 or 8 passes: the sorted data is back in (keys, ids)
+    sort_passes<K>(keys, m.ids, m.sort_tmp, nt, key_bits, s);  // 4 or 8 passes: back in (keys, ids)
     if (nt >= 2)
         k_radix_tree<K><<<blocks_for(nt - 1, 256), 256, 0, s>>>(keys, (int)nt, m.nodes, m.parent, m.counters);
     // the sort's scratch is free again: per-tile lists of spanning nodes
@@ -510,11 +593,18 @@ hipError_t launch_morton_batch(MeshDev &m, const int32_t *tri_mesh, const float 
 
 size_t sort_tmp_bytes(int64_t nt, int morton_bits) {
     const size_t kb = morton_bits > 32 ? 8 : 4;
-    const int64_t ntiles = (nt + kSortTile - 1) / kSortTile;
-    const size_t sort = kb * nt + 4 * nt + 4 * (size_t)kRadix * ntiles + 256;
+    const size_t sort = pass_tmp_bytes(nt, kb);
     const int64_t box_tiles = (nt + kBoxTile - 1) / kBoxTile;
     const size_t lists = 4 * (size_t)box_tiles * (kBoxTile + 1) + 256;  // span lists after the sort
     return sort > lists ? sort : lists;
+}
+
+size_t sort_u32_tmp_bytes(int64_t n) { return pass_tmp_bytes(n, 4); }
+
+hipError_t sort_u32_pairs(uint32_t *keys, int32_t *ids, void *tmp, int64_t n, hipStream_t s) {
+    if (n > 1)
+        sort_passes<uint32_t>(keys, ids, tmp, n, 32, s);  // four passes
+    return hipGetLastError();
 }
 
 hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s) { return build_from_keys<uint64_t>(m, key_bits, s); }

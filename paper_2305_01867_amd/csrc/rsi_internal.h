@@ -89,6 +89,7 @@ struct BatchDev {
     int4 *items = nullptr;                       // device [n_items] (mesh, first, end, 0)
     int n_items = 0;
     int32_t *queue = nullptr;                    // device [n_rays]
+    void *sort_ws = nullptr;                     // device ray_sort_ws_bytes(n_rays): segment order
     uint32_t *queue_len = nullptr;               // device [2]
     uint64_t *counters = nullptr;                // device [4]
     int64_t n_rays = 0;
@@ -99,6 +100,9 @@ hipError_t launch_batch_build(MeshDev &m, BatchDev &b, const float *V, const int
 hipError_t launch_build(MeshDev &m, const float *V, const int32_t *F, hipStream_t s, size_t sort_tmp_bytes);
 size_t sort_tmp_bytes(int64_t nt, int morton_bits);
 hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s);
+// Stable sort of (32-bit key, id) pairs in place; tmp holds sort_u32_tmp_bytes(n).
+size_t sort_u32_tmp_bytes(int64_t n);
+hipError_t sort_u32_pairs(uint32_t *keys, int32_t *ids, void *tmp, int64_t n, hipStream_t s);
 hipError_t launch_morton_batch(MeshDev &m, const int32_t *tri_mesh, const float *mesh_bounds, hipStream_t s);
 
 // Intersection (traverse.hip).
@@ -112,6 +116,7 @@ struct TraverseArgs {
     uint8_t *hit = nullptr;
     int32_t *tri_id = nullptr;
     float *uvt = nullptr;
+    int32_t *count = nullptr;      // intercept-count mode
     uint64_t *counters = nullptr;  // [4] device
     int32_t *queue = nullptr;      // [n] device
     uint32_t *queue_len = nullptr; // [1] device (inside counters workspace)
@@ -126,7 +131,15 @@ struct TraverseArgs {
     const int32_t *mesh_root = nullptr;   // subtree root per mesh (INT32_MIN: empty)
     const int32_t *mesh_toff = nullptr;   // first triangle of each mesh
     const int32_t *ray_off = nullptr;     // [n_meshes + 1] first segment of each mesh
+    // segment order: 0 input order, 1 Morton code of the midpoint, 2 direction
+    // octant above the Morton code of the start point (codes over the mesh box)
+    int ray_sort = 0;
+    const float *key_bounds = nullptr;    // [n_meshes or 1][8] lo.xyz, hi.xyz, scale, 0
+    void *sort_ws = nullptr;              // ray_sort != 0: ray_sort_ws_bytes(n) bytes
 };
+size_t ray_sort_ws_bytes(int64_t n);
+hipError_t launch_debug_certify(const float *from, const float *to, const float *corners, int64_t n, float *vals,
+                                int32_t *cls, hipStream_t s);
 hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
 hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
 

@@ -24,6 +24,8 @@
 // particular any binary64 hit of a non-grazing segment.
 #include "rsi_internal.h"
 
+#include <type_traits>
+
 namespace rsi {
 namespace {
 
@@ -31,7 +33,8 @@ constexpr float kEtaRel = 0x1p-20f;
 constexpr float kBoundK = 12.0f * 0x1p-24f;  // >= 8 u32 (binary32) + 8 u64 (binary64) with slack
 constexpr float kBoundTiny = 0x1p-140f;      // absorbs underflow in the products
 constexpr int kMiss = 0, kHit = 1, kUnsure = 2;
-enum { MODE_BOOL = 0, MODE_FIRST = 1, MODE_BARY = 2 };
+enum { MODE_BOOL = 0, MODE_FIRST = 1, MODE_BARY = 2, MODE_COUNT = 3 };
+constexpr int kCountSlots = 8;  // distinct t a lane keeps in registers in count mode
 
 struct Ray {
     float3 o, d;   // start point, direction E - O (rounded)
@@ -121,17 +124,28 @@ __device__ __forceinline__ bool decide32(const MT32 &m) {
 // unit roundoff 2^-53.  B(X) = 12 * 2^-24 * M(X) covers both with room for the
 // roundings of M itself.  For a hit the interval [tlo, thi] holds the exact t
 // and the binary64 t.
-__device__ __forceinline__ int classify(const MT32 &m, const Tri &tri, const Ray &r, float &tlo, float &thi) {
+struct Bounds {
+    float d, U, W, T;
+};
+
+__device__ __forceinline__ Bounds mt_bounds(const MT32 &m, const Tri &tri, const Ray &r) {
     const float adx = fabsf(r.d.x), ady = fabsf(r.d.y), adz = fabsf(r.d.z);
     const float asx = fabsf(m.s.x), asy = fabsf(m.s.y), asz = fabsf(m.s.z);
     const float a1x = fabsf(tri.e1.x), a1y = fabsf(tri.e1.y), a1z = fabsf(tri.e1.z);
     const float a2x = fabsf(tri.e2.x), a2y = fabsf(tri.e2.y), a2z = fabsf(tri.e2.z);
     const float Pmx = ady * a2z + adz * a2y, Pmy = adz * a2x + adx * a2z, Pmz = adx * a2y + ady * a2x;
     const float Qmx = asy * a1z + asz * a1y, Qmy = asz * a1x + asx * a1z, Qmz = asx * a1y + asy * a1x;
-    const float Bd = fmaf(kBoundK, a1x * Pmx + a1y * Pmy + a1z * Pmz, kBoundTiny);
-    const float BU = fmaf(kBoundK, asx * Pmx + asy * Pmy + asz * Pmz, kBoundTiny);
-    const float BW = fmaf(kBoundK, adx * Qmx + ady * Qmy + adz * Qmz, kBoundTiny);
-    const float BT = fmaf(kBoundK, a2x * Qmx + a2y * Qmy + a2z * Qmz, kBoundTiny);
+    Bounds b;
+    b.d = fmaf(kBoundK, a1x * Pmx + a1y * Pmy + a1z * Pmz, kBoundTiny);
+    b.U = fmaf(kBoundK, asx * Pmx + asy * Pmy + asz * Pmz, kBoundTiny);
+    b.W = fmaf(kBoundK, adx * Qmx + ady * Qmy + adz * Qmz, kBoundTiny);
+    b.T = fmaf(kBoundK, a2x * Qmx + a2y * Qmy + a2z * Qmz, kBoundTiny);
+    return b;
+}
+
+__device__ __forceinline__ int classify(const MT32 &m, const Tri &tri, const Ray &r, float &tlo, float &thi) {
+    const Bounds bb = mt_bounds(m, tri, r);
+    const float Bd = bb.d, BU = bb.U, BW = bb.W, BT = bb.T;
     const float aD = fabsf(m.det);
     // a hit needs |U|, |W|, |T| <= |det| in binary64; a sure excess is a sure miss
     const float cap = aD + Bd;
@@ -203,9 +217,20 @@ struct Outs {
     uint8_t *hit;
     int32_t *id;
     float *uvt;
+    int32_t *count;
 };
 
+__device__ __forceinline__ void write_count(const Outs &o, int64_t i, int32_t c) {
+    if (o.hit)
+        o.hit[i] = c > 0 ? 1 : 0;
+    o.count[i] = c;
+}
+
 __device__ __forceinline__ void write_out(const Outs &o, int64_t i, int mode, int id, float u, float v, float t) {
+    if (mode == MODE_COUNT) {
+        write_count(o, i, id >= 0 ? 1 : 0);
+        return;
+    }
     if (o.hit)
         o.hit[i] = id >= 0 ? 1 : 0;
     if (mode != MODE_BOOL)
@@ -245,6 +270,7 @@ struct TravParams {
     const int32_t *mesh_root;
     const int32_t *mesh_toff;
     const int32_t *ray_off;
+    const int32_t *order;  // segment at each processing position (NULL: input order)
 };
 
 __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why) {
@@ -302,6 +328,11 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
     int phase = 1, skip = kDone;  // kDone never equals a child reference
     bool best_late = false;       // best hit found in phase 1 (a proposal miss)
     uint32_t n_late = 0;          // this lane's proposal misses, summed per wave at exit
+    // count mode: the distinct t found so far (binary64 when certified)
+    using TCount = typename std::conditional<CERT, double, float>::type;
+    TCount tk[kCountSlots];
+    int nk = 0;
+    bool list_full = false;
 
     auto pop = [&]() -> int { return sp > 0 ? stk[--sp * stride] : kDone; };
 
@@ -330,7 +361,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
             if (ray < 0) {
                 const int64_t idx = base + __popcll(idle & lt_mask);
                 if (idx < range_end) {
-                    ray = idx;
+                    ray = p.order ? p.order[idx] : idx;
                     lane_root = cur_root;
                     lane_toff = cur_toff;
                     ref = lane_root;
@@ -342,6 +373,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                     best_u = best_v = 0.0f;
                     found = unsure = flagged = overflow = false;
                     n_nodes = n_tests = 0;
+                    nk = 0;
+                    list_full = false;
                     steps = 0;
                     best_late = false;
                     if (PROP) {
@@ -434,7 +467,41 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                     ++n_tests;
                 const MT32 m = mt32(tri, r);
                 const int id = __float_as_int(tri.a.w);
-                if (!CERT) {
+                if (MODE == MODE_COUNT) {
+                    // every hit counts once per distinct t; no early exit, no pruning
+                    bool hit = false;
+                    TCount t = 0;
+                    if (!CERT) {
+                        hit = decide32(m);
+                        t = (TCount)(m.T / m.det);
+                    } else {
+                        float lo, hi;
+                        if (classify(m, tri, r, lo, hi) != kMiss && valid_tri(p.F, p.nv, id)) {
+                            const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
+                            const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, id);
+                            hit = h.hit;
+                            t = (TCount)h.t;
+                        }
+                    }
+                    if (hit) {
+                        bool dup = false;
+#pragma unroll
+                        for (int k = 0; k < kCountSlots; ++k)
+                            dup = dup || (k < nk && tk[k] == t);
+                        if (!dup) {
+                            if (nk == kCountSlots) {
+                                list_full = true;  // finished by the second pass
+                                ref = kDone;
+                            } else {
+#pragma unroll
+                                for (int k = 0; k < kCountSlots; ++k)
+                                    if (k == nk)
+                                        tk[k] = t;
+                                ++nk;
+                            }
+                        }
+                    }
+                } else if (!CERT) {
                     if (decide32(m)) {
                         if (MODE == MODE_BOOL) {
                             found = true;
@@ -497,6 +564,13 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
             if (STATS) {
                 p.visits[ray] = n_nodes;
                 p.tests[ray] = n_tests;
+            } else if (MODE == MODE_COUNT) {
+                if (overflow)
+                    enqueue(p, ray, 1);
+                else if (list_full)
+                    enqueue(p, ray, 3);
+                else
+                    write_count(p.out, ray, nk);
             } else if (MODE == MODE_BOOL) {
                 if (found)
                     p.out.hit[ray] = 1;
@@ -560,14 +634,23 @@ struct Finish {
     float t32, u32, v32;
     float tlimit;
     bool done;
+    // count mode: only hits beyond the last counted t take part
+    double floor64;
+    float floor32;
 
-    __device__ bool init(const TravParams &p, int64_t i) {
+    __device__ void reset_best() {
         best_id = -1;
         bu = bv = bt = 0.0;
         t32 = INFINITY;
         u32 = v32 = 0.0f;
         tlimit = 1.0f;
         done = false;
+    }
+
+    __device__ bool init(const TravParams &p, int64_t i) {
+        reset_best();
+        floor64 = -INFINITY;
+        floor32 = -INFINITY;
         const float *o = p.from + 3 * i, *e = p.to + 3 * i;
         ox = o[0]; oy = o[1]; oz = o[2];
         ex = e[0]; ey = e[1]; ez = e[2];
@@ -585,7 +668,7 @@ struct Finish {
             MT64 h{false, 0.0, 0.0, 0.0};
             if (valid_tri(p.F, p.nv, id))
                 h = mt64(ox, oy, oz, ex, ey, ez, p.V, p.F, id);
-            if (!h.hit)
+            if (!h.hit || !(h.t > floor64))
                 return;
             if (MODE == MODE_BOOL) {
                 best_id = id;
@@ -607,6 +690,8 @@ struct Finish {
                 return;
             }
             const float t = m.T / m.det;
+            if (!(t > floor32))
+                return;
             if (t < t32 || (t == t32 && id < best_id)) {
                 t32 = t;
                 best_id = id;
@@ -667,16 +752,13 @@ __device__ __forceinline__ void segment_root(const TravParams &p, int64_t i, int
     }
 }
 
-// One wave (the whole 64-thread block) finishes segment i.
+// The wave's search for one segment from `root`: every lane's share of the
+// candidates goes through f.test_leaf; the caller reduces across the wave.
 template <int MODE, bool CERT>
-__device__ void finish_wave(const TravParams &p, int64_t i, int *stk) {
+__device__ void wave_search(const TravParams &p, Finish<MODE, CERT> &f, bool ok, int root, int *stk) {
     const int lane = threadIdx.x;
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int n_internal = (int)p.nt - 1;
-    int root, toff;
-    segment_root(p, i, root, toff);
-    Finish<MODE, CERT> f;
-    const bool ok = f.init(p, i);
     if (root == kDone) {
         // empty mesh: nothing to test
     } else if (!ok) {
@@ -741,15 +823,45 @@ __device__ void finish_wave(const TravParams &p, int64_t i, int *stk) {
             }
         }
     }
+    __syncthreads();  // the stack is reused by the next search
+}
+
+// One wave (the whole 64-thread block) finishes segment i.  Count mode asks
+// for the nearest hit beyond the last counted t until there is none, so
+// every distinct t is counted once with no list to outgrow.
+template <int MODE, bool CERT>
+__device__ void finish_wave(const TravParams &p, int64_t i, int *stk) {
+    int root, toff;
+    segment_root(p, i, root, toff);
+    Finish<MODE, CERT> f;
+    const bool ok = f.init(p, i);
+    if (MODE == MODE_COUNT) {
+        int32_t cnt = 0;
+        for (int64_t q = 0; q <= p.nt; ++q) {  // at most one round per triangle
+            f.reset_best();
+            wave_search<MODE, CERT>(p, f, ok, root, stk);
+            f.reduce_wave();
+            if (f.best_id < 0)
+                break;
+            ++cnt;
+            if (CERT)
+                f.floor64 = f.bt;
+            else
+                f.floor32 = f.t32;
+        }
+        if (threadIdx.x == 0)
+            write_count(p.out, i, cnt);
+        return;
+    }
+    wave_search<MODE, CERT>(p, f, ok, root, stk);
     if (MODE == MODE_BOOL) {
         f.best_id = __ballot(f.best_id >= 0) ? 0 : -1;
         toff = 0;
     } else {
         f.reduce_wave();
     }
-    if (lane == 0)
+    if (threadIdx.x == 0)
         f.write(p, i, toff);
-    __syncthreads();  // the stack is reused by the block's next segment
 }
 
 // One lane finishes segment i with its private stack (stride kFinishThreads).
@@ -810,13 +922,78 @@ template <int MODE, bool CERT>
 __global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
     __shared__ int deep[kWaveStack];
     const uint32_t count = *p.queue_len;
-    if (count <= (uint32_t)kWaveFinishMax) {
+    if (MODE == MODE_COUNT || count <= (uint32_t)kWaveFinishMax) {
         for (uint32_t qi = blockIdx.x; qi < count; qi += gridDim.x)
             finish_wave<MODE, CERT>(p, p.queue[qi], deep);
     } else {
-        for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < count; qi += gridDim.x * blockDim.x)
-            finish_lane<MODE, CERT>(p, p.queue[qi], deep + threadIdx.x);
+        if constexpr (MODE != MODE_COUNT)
+            for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < count; qi += gridDim.x * blockDim.x)
+                finish_lane<MODE, CERT>(p, p.queue[qi], deep + threadIdx.x);
     }
+}
+
+// ------------------------------------------------------------ segment order
+// Spatially coherent processing order: neighbouring lanes then take segments
+// that start (or lie) close together and head the same way, so they share
+// tree paths and cached nodes.  30-bit keys; in the batched form the top six
+// bits are the mesh, so each mesh's segments stay in its own position range
+// and the work items stay valid.
+__device__ __forceinline__ uint32_t spread_bits(uint32_t v) {  // bit k -> bit 3k, 10 bits
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t cell(float x, float lo, float hi, int bits) {
+    const float f = hi > lo ? (x - lo) / (hi - lo) : 0.0f;
+    const float c = fminf(fmaxf(f, 0.0f), 1.0f) * (float)(1u << bits);  // NaN -> 0
+    const uint32_t q = (uint32_t)c;
+    return q < (1u << bits) ? q : (1u << bits) - 1u;
+}
+
+__global__ void k_ray_keys(const float *__restrict__ from, const float *__restrict__ to, int64_t n, int kind,
+                           const float *__restrict__ bounds, const int32_t *__restrict__ ray_off, int n_meshes,
+                           uint32_t *__restrict__ keys, int32_t *__restrict__ ids) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    int m = 0;
+    if (ray_off) {
+        int lo = 0, hi = n_meshes - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ray_off[mid] <= i)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        m = lo;
+    }
+    const float *b = bounds + 8 * m;
+    const float ox = from[3 * i], oy = from[3 * i + 1], oz = from[3 * i + 2];
+    const float ex = to[3 * i], ey = to[3 * i + 1], ez = to[3 * i + 2];
+    const int mesh_bits = ray_off ? 6 : 0;
+    const int oct_bits = kind == 2 ? 3 : 0;
+    const int bits = (30 - mesh_bits - oct_bits) / 3;
+    float px = ox, py = oy, pz = oz;
+    if (kind == 1) {
+        px = 0.5f * (ox + ex);
+        py = 0.5f * (oy + ey);
+        pz = 0.5f * (oz + ez);
+    }
+    const uint32_t code = (spread_bits(cell(pz, b[2], b[5], bits)) << 2) |
+                          (spread_bits(cell(py, b[1], b[4], bits)) << 1) | spread_bits(cell(px, b[0], b[3], bits));
+    uint32_t key = code;
+    if (kind == 2) {
+        const uint32_t oct = (ex < ox ? 1u : 0u) | (ey < oy ? 2u : 0u) | (ez < oz ? 4u : 0u);
+        key |= oct << (3 * bits);
+    }
+    key |= (uint32_t)m << (30 - mesh_bits);
+    keys[i] = key;
+    ids[i] = (int32_t)i;
 }
 
 __global__ void k_reset(uint32_t *queue_len, unsigned long long *counters) {
@@ -863,8 +1040,12 @@ void dispatch_pass1(const TravParams &p, int mode, bool cert, int block, hipStre
         dispatch_mode<MODE_BOOL, STATS>(p, cert, prop, block, s);
     else if (mode == MODE_FIRST)
         dispatch_mode<MODE_FIRST, STATS>(p, cert, prop, block, s);
-    else
+    else if (mode == MODE_BARY)
         dispatch_mode<MODE_BARY, STATS>(p, cert, prop, block, s);
+    else if (cert)  // count mode has no proposal order
+        launch_pass1<MODE_COUNT, true, STATS, false>(p, block, s);
+    else
+        launch_pass1<MODE_COUNT, false, STATS, false>(p, block, s);
 }
 
 TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
@@ -880,7 +1061,7 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.from = a.from;
     p.to = a.to;
     p.n = a.n;
-    p.out = Outs{a.hit, a.tri_id, a.uvt};
+    p.out = Outs{a.hit, a.tri_id, a.uvt, a.count};
     p.stack_depth = a.stack;
     p.queue = a.queue;
     p.queue_len = a.queue_len;
@@ -896,10 +1077,30 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.mesh_root = a.mesh_root;
     p.mesh_toff = a.mesh_toff;
     p.ray_off = a.ray_off;
+    p.order = nullptr;
     return p;
 }
 
+// Keys and a stable sort of the segment indices; p.order then lists them.
+hipError_t order_segments(const TraverseArgs &a, TravParams &p, hipStream_t s) {
+    if (a.ray_sort == 0 || a.n < 2)
+        return hipSuccess;
+    uint32_t *keys = static_cast<uint32_t *>(a.sort_ws);
+    int32_t *ids = reinterpret_cast<int32_t *>(keys + ((a.n + 63) & ~int64_t(63)));
+    void *tmp = ids + ((a.n + 63) & ~int64_t(63));
+    k_ray_keys<<<(int)((a.n + 255) / 256), 256, 0, s>>>(a.from, a.to, a.n, a.ray_sort, a.key_bounds, a.ray_off,
+                                                       a.n_meshes, keys, ids);
+    const hipError_t e = sort_u32_pairs(keys, ids, tmp, a.n, s);
+    p.order = ids;
+    return e;
+}
+
 }  // namespace
+
+size_t ray_sort_ws_bytes(int64_t n) {
+    const int64_t padded = (n + 63) & ~int64_t(63);
+    return 8 * (size_t)padded + sort_u32_tmp_bytes(n) + 256;
+}
 
 hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t s) {
     TravParams p = make_params(m, a);
@@ -910,6 +1111,9 @@ hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t
         k_fill_miss<<<(int)((a.n + 255) / 256), 256, 0, s>>>(p.out, a.n, a.mode);
         return hipGetLastError();
     }
+    const hipError_t e = order_segments(a, p, s);
+    if (e != hipSuccess)
+        return e;
     dispatch_pass1<false>(p, a.mode, a.certified != 0, a.block, s);
     // enough blocks for one per segment of a short queue; a long queue is
     // taken 64 segments per block
@@ -918,8 +1122,46 @@ hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t
         a.certified ? k_finish<MODE_BOOL, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_BOOL, false><<<grid2, kFinishThreads, 0, s>>>(p);
     else if (a.mode == MODE_FIRST)
         a.certified ? k_finish<MODE_FIRST, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_FIRST, false><<<grid2, kFinishThreads, 0, s>>>(p);
-    else
+    else if (a.mode == MODE_BARY)
         a.certified ? k_finish<MODE_BARY, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_BARY, false><<<grid2, kFinishThreads, 0, s>>>(p);
+    else
+        a.certified ? k_finish<MODE_COUNT, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_COUNT, false><<<grid2, kFinishThreads, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+namespace {
+// Diagnostics of the certified test on given pairs: the same ray and triangle
+// set-up as the traversal, then the binary32 quantities, their bounds and the
+// classification.  vals[i] = det, U, W, T, B(det), B(U), B(W), B(T), tlo, thi.
+__global__ void k_debug_certify(const float *__restrict__ from, const float *__restrict__ to,
+                                const float *__restrict__ corners, int64_t n, float *__restrict__ vals,
+                                int32_t *__restrict__ cls) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    Ray r;
+    r.o = make_float3(from[3 * i], from[3 * i + 1], from[3 * i + 2]);
+    r.d = make_float3(to[3 * i] - r.o.x, to[3 * i + 1] - r.o.y, to[3 * i + 2] - r.o.z);
+    const float *c = corners + 9 * i;
+    Tri tri;
+    tri.a = make_float4(c[0], c[1], c[2], 0.0f);
+    tri.e1 = make_float4(c[3] - c[0], c[4] - c[1], c[5] - c[2], 0.0f);
+    tri.e2 = make_float4(c[6] - c[0], c[7] - c[1], c[8] - c[2], 0.0f);
+    const MT32 m = mt32(tri, r);
+    const Bounds b = mt_bounds(m, tri, r);
+    float tlo = NAN, thi = NAN;
+    cls[i] = classify(m, tri, r, tlo, thi);
+    float *v = vals + 10 * i;
+    v[0] = m.det; v[1] = m.U; v[2] = m.W; v[3] = m.T;
+    v[4] = b.d; v[5] = b.U; v[6] = b.W; v[7] = b.T;
+    v[8] = tlo; v[9] = thi;
+}
+}  // namespace
+
+hipError_t launch_debug_certify(const float *from, const float *to, const float *corners, int64_t n, float *vals,
+                                int32_t *cls, hipStream_t s) {
+    if (n > 0)
+        k_debug_certify<<<(int)((n + 255) / 256), 256, 0, s>>>(from, to, corners, n, vals, cls);
     return hipGetLastError();
 }
 
@@ -928,6 +1170,9 @@ hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s) 
     k_reset<<<1, 64, 0, s>>>(a.queue_len, p.counters);
     if (m.nt == 0 || a.n == 0)
         return hipGetLastError();
+    const hipError_t e = order_segments(a, p, s);
+    if (e != hipSuccess)
+        return e;
     dispatch_pass1<true>(p, a.mode, a.certified != 0, a.block, s);
     return hipGetLastError();
 }

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = rsi.lib()
-    assert L.rsi_abi_version() == 1
+    assert L.rsi_abi_version() == 2
     for code in range(7):
         assert L.rsi_status_string(code).decode().startswith("RSI_")
     assert b"unknown" in L.rsi_status_string(99)
@@ -66,6 +66,14 @@ def test_intersect_argument_errors_need_no_gpu():
     assert L.rsi_destroy(None) == 0
     assert L.rsi_mesh_info_get(None, None) == 5
     assert L.rsi_mesh_export(None, 0, None, 0, None) == 5
+
+
+def test_debug_certify_argument_errors_need_no_gpu():
+    L = rsi.lib()
+    assert L.rsi_debug_certify(None, None, None, -1, None, None, None) == 1  # negative count
+    assert L.rsi_debug_certify(None, None, None, 0, None, None, None) == 0   # nothing to do
+    assert L.rsi_debug_certify(None, None, None, 5, None, None, None) == 1   # NULL arrays
+    assert b"non-NULL" in L.rsi_last_error()
 
 
 def test_valid_arguments_without_a_gpu_report_state_error():

@@ -95,6 +95,35 @@ def test_combined_tree_keeps_each_mesh_in_one_subtree():
         assert np.array_equal(np.sort(ids[lo:hi + 1]), np.arange(to[m], to[m + 1]))
 
 
+def test_batch_segment_orders_agree():
+    """Each mesh's segments stay in their own position range under the
+    mesh-prefixed segment keys, so every order gives the input-order results."""
+    parts, V, F, O, E, vo, to, ro = small_batch()
+    with rsi.rsi_batch_create(vo, to, ro) as b:
+        rsi.rsi_batch_build(b, dev(V), dev(F))
+        dO, dE = dev(O), dev(E)
+        for mode in MODES:
+            ref = {k: host(v) for k, v in rsi.rsi_batch_intersect(b, dO, dE, mode=mode, precision="certified").items()}
+            for order in ("midpoint", "origin_octant"):
+                got = rsi.rsi_batch_intersect(b, dO, dE, mode=mode, precision="certified", ray_sort=order)
+                for k in ref:
+                    if k != "counters":
+                        assert np.array_equal(host(got[k]), ref[k], equal_nan=True), (mode, order, k)
+
+
+def test_batch_intercept_count_equals_oracle():
+    parts, V, F, O, E, vo, to, ro = small_batch()
+    with rsi.rsi_batch_create(vo, to, ro) as b:
+        rsi.rsi_batch_build(b, dev(V), dev(F))
+        got = host(rsi.rsi_batch_intersect(b, dev(O), dev(E), mode="intercept_count",
+                                           precision="certified")["count"])
+        for m, (Vm, Fm, Om, Em) in enumerate(parts):
+            if len(Om) == 0:
+                continue
+            want = oracle.intercept_count(Vm, Fm, Om, Em) if len(Fm) else np.zeros(len(Om), np.int32)
+            assert np.array_equal(got[ro[m]:ro[m + 1]], want), m
+
+
 def test_graph_capture_replays_build_and_intersect():
     parts, V, F, O, E, vo, to, ro = small_batch()
     dV, dF, dO, dE = dev(V), dev(F), dev(O), dev(E)
@@ -133,11 +162,17 @@ def test_autotuner_picks_and_caches():
         rsi.rsi_batch_build(b, dev(V), dev(F))
         path = os.path.join(d, "tune.json")
         key = autotune.size_class("boolean", "certified", len(parts), F.shape[0], O.shape[0])
-        run = lambda block, stack: rsi.rsi_batch_intersect(b, dO, dE, mode="boolean", precision="certified",
-                                                           block=block, stack_depth=stack)
+        want = host(rsi.rsi_batch_intersect(b, dO, dE, mode="boolean", precision="certified")["hit"])
+
+        def run(block, stack_depth, ray_sort):
+            got = rsi.rsi_batch_intersect(b, dO, dE, mode="boolean", precision="certified", block=block,
+                                          stack_depth=stack_depth, ray_sort=ray_sort)
+            assert np.array_equal(host(got["hit"]), want), (block, stack_depth, ray_sort)
+
         best, timings = autotune.tune(run, key, path, reps=1)
         assert best["block"] in autotune.BLOCKS and best["stack_depth"] in autotune.STACKS
-        assert len(timings) == len(autotune.BLOCKS) * len(autotune.STACKS)
+        assert best["ray_sort"] in autotune.RAY_SORTS
+        assert len(timings) == len(autotune.BLOCKS) * len(autotune.STACKS) * len(autotune.RAY_SORTS)
         assert json.load(open(path))[key] == best
         again, t2 = autotune.tune(run, key, path)
         assert again == best and t2 is None

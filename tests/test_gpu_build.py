@@ -93,7 +93,7 @@ def test_soup_sizes(n_tri):
     check_structure(V, F, 63)
 
 
-@pytest.mark.parametrize("n_side", [2, 3, 33, 64, 128, 256])
+@pytest.mark.parametrize("n_side", [2, 3, 33, 64, 128, 256, 400, 401])  # 400+: multi-block histogram scan
 def test_heightfields(n_side):
     V, F = workloads.heightfield(n_side, 100 + n_side)
     check_structure(V, F, 30 if n_side % 2 == 0 else 63)

@@ -206,6 +206,36 @@ def test_stack_depth_one_and_block_sizes_stay_exact():
                         assert got["counters"][1] > 0
 
 
+def test_segment_orders_exact_and_every_segment_once():
+    """Sorted processing orders write every result at its input index: outputs
+    prefilled with sentinels are all overwritten with the oracle's values, and
+    every segment is traversed (its root fetched) exactly as in input order.
+    (Per-segment node counts may differ between orders: a postponed leaf test
+    tightens the nearest-hit limit at a moment that depends on the wave.)"""
+    V, F = workloads.heightfield(32, 21)
+    for n in (1, 65, 2049, 5000):
+        O, E = workloads.rays_in_box(n, 30 + n, V.min(0), V.max(0))
+        hit, ids, uvt, _ = oracle.intersect(V, F, O, E)
+        with rsi.rsi_build(dev(V), dev(F)) as mesh:
+            for order in ("midpoint", "origin_octant"):
+                say(f"  n={n} order={order}")
+                for mode in MODES:
+                    out = {"hit": torch.full((n,), 7, dtype=torch.uint8, device="cuda"),
+                           "tri_id": torch.full((n,), -7, dtype=torch.int32, device="cuda")}
+                    if mode == "barycentric":
+                        out["uvt"] = torch.full((n, 3), 5.0, dtype=torch.float32, device="cuda")
+                    r = rsi.rsi_intersect(mesh, dev(O), dev(E), mode=mode, precision="certified", ray_sort=order,
+                                          out=out)
+                    got = {k: host(v) for k, v in r.items()}
+                    assert np.array_equal(got["hit"], hit), (order, mode)
+                    expect_exact(got, hit, ids, uvt, mode)
+                plain_in = intersect(mesh, O, E, "first_hit", "plain")
+                plain_sorted = intersect(mesh, O, E, "first_hit", "plain", ray_sort=order)
+                assert np.array_equal(plain_in["tri_id"], plain_sorted["tri_id"])
+                visits, _ = rsi.rsi_traversal_stats(mesh, dev(O), dev(E), mode="first_hit", ray_sort=order)
+                assert host(visits).min() >= 1
+
+
 def test_ragged_and_edge_sizes():
     V, F = workloads.heightfield(20, 3)
     with rsi.rsi_build(dev(V), dev(F)) as mesh:
@@ -290,5 +320,9 @@ def test_paper_scale_sampled():
             if mode == "boolean":
                 frac = float(c.mean())
                 say(f"  hit fraction {frac:.4f}")
+                for order in ("midpoint", "origin_octant"):  # the multi-block scan path of the sort
+                    srt = host(rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision="certified",
+                                                 ray_sort=order)["hit"])
+                    assert np.array_equal(srt, c), order
             del cert, plain
             torch.cuda.empty_cache()
