@@ -10,8 +10,8 @@
 //                             one device-wide scan, stable tile scatter
 //   4. radix tree             one lane per internal node (Karras section 3)
 //   5. leaves + bottom-up     one lane per leaf, arrival counters in LDS
-//                             inside a leaf tile; one workgroup finishes the
-//                             nodes that span tiles
+//                             inside subtrees of <= 1024 leaves; one
+//                             workgroup finishes the nodes above them
 #include "rsi_internal.h"
 
 namespace rsi {
@@ -21,6 +21,8 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 2048 keys per tile
 constexpr int kRadix = 256;
+constexpr int kBoxTile = 1024;  // leaves per bottom-up workgroup (one per lane)
+constexpr int kNoTile = INT32_MIN;  // never a child reference (leaves are ~k with k < 2^30)
 
 // ---------------------------------------------------------------- 1. extent
 __global__ __launch_bounds__(1024) void k_mesh_bounds(const float *__restrict__ V, int64_t nv,
@@ -342,9 +344,13 @@ __device__ __forceinline__ int prefix(const K *__restrict__ k, int n, int i, K k
     return (int)(8 * sizeof(K)) + __builtin_clz((unsigned)(i ^ j));
 }
 
+// Also lists the bottom-up tiles: the largest subtrees with at most kBoxTile
+// leaves (children of larger nodes, or the root itself), wave-aggregated into
+// tiles[0 .. *n_tiles).
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_tree(const K *__restrict__ keys, int n, Node *__restrict__ nodes,
-                                                    int32_t *__restrict__ parent, int32_t *__restrict__ counters) {
+                                                    int32_t *__restrict__ parent, int32_t *__restrict__ counters,
+                                                    int32_t *__restrict__ tiles, int32_t *__restrict__ n_tiles) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1)
         return;
@@ -378,22 +384,51 @@ __global__ __launch_bounds__(256) void k_radix_tree(const K *__restrict__ keys, 
     counters[i] = 0;
     if (i == 0)
         parent[0] = -1;
+
+    int emit0 = kNoTile, emit1 = kNoTile;
+    if (hi - lo + 1 > kBoxTile) {
+        if (split - lo + 1 <= kBoxTile)
+            emit0 = left;
+        if (hi - split <= kBoxTile)
+            emit1 = right;
+    } else if (i == 0) {
+        emit0 = 0;  // the whole tree is one tile
+    }
+    const uint64_t m1 = __ballot(emit0 != kNoTile || emit1 != kNoTile);
+    const uint64_t m2 = __ballot(emit0 != kNoTile && emit1 != kNoTile);
+    if (m1) {
+        const int lane = threadIdx.x & 63;
+        const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+        const int leader = __ffsll((unsigned long long)m1) - 1;
+        int base = 0;
+        if (lane == leader)
+            base = atomicAdd(n_tiles, __popcll(m1) + __popcll(m2));
+        base = __shfl(base, leader);
+        int o = base + __popcll(m1 & lt) + __popcll(m2 & lt);
+        if (emit0 != kNoTile)
+            tiles[o++] = emit0;
+        if (emit1 != kNoTile)
+            tiles[o] = emit1;
+    }
+}
+
+__global__ void k_single_tile(int32_t *tiles, int32_t *n_tiles) {
+    tiles[0] = ~0;  // one triangle: the leaf is the whole tree
+    *n_tiles = 1;
 }
 
 // ------------------------------------------------- 5. leaves and bottom-up
 // Boxes are merged bottom-up, each internal node by the second of its two
-// children to finish.  Two kernels keep the cross-workgroup protocol short:
-//   k_leaves_tile  one workgroup per tile of kBoxTile consecutive leaves.  A
-//                  lane writes its leaf's triangle and climbs while the node's
-//                  leaf range lies inside the tile, with arrival counters and
-//                  child boxes in LDS.  A lane that reaches a node spanning
-//                  tiles leaves its box in the node and lists the node.
-//   k_boxes_span   one workgroup finishes the spanning nodes (a small top
-//                  tree) from those lists, with workgroup-scope atomics.
-// Every child box also lands in its parent node in HBM; a finished internal
-// node's counter reads 2.
-constexpr int kBoxTile = 1024;
-
+// children to finish (the paper's Case Study 2: one arrival counter per
+// internal node).  The tree is cut into tiles, the largest subtrees with at
+// most kBoxTile leaves (listed by k_radix_tree), and nodes above them:
+//   k_leaves_subtree  one workgroup per tile: counters and child boxes in LDS,
+//                     no cross-workgroup synchronisation at all;
+//   k_boxes_top       one workgroup climbs the nodes above the tiles (about
+//                     log2(N_t / kBoxTile) levels) with workgroup-scope atomics.
+// Cross-XCD agent-scope atomics, which cost an L2 write-back each on gfx950,
+// are not needed.  Every child box lands in its parent node in HBM; a
+// finished internal node's counter reads 2.
 __device__ __forceinline__ void store_child_box(Node *node, bool is_left, const float *lo, const float *hi) {
     if (is_left) {
         node->xy_left = make_float4(lo[0], hi[0], lo[1], hi[1]);
@@ -404,117 +439,130 @@ __device__ __forceinline__ void store_child_box(Node *node, bool is_left, const 
     }
 }
 
-__global__ __launch_bounds__(kBoxTile) void k_leaves_tile(const float *__restrict__ V, int64_t nv,
-                                                         const int32_t *__restrict__ F,
-                                                         const int32_t *__restrict__ ids, int n,
-                                                         Tri *__restrict__ tris, Node *nodes,
-                                                         const int32_t *__restrict__ parent, int32_t *counters,
-                                                         int32_t *__restrict__ span_list,
-                                                         int32_t *__restrict__ span_len) {
+// Phase 1: one workgroup per listed tile (a subtree of at most kBoxTile
+// leaves, sorted positions [a, b]).  Lane j takes leaf a + j, writes its
+// triangle and climbs; every internal node of the tile lies in [a, b], so
+// arrival counters and child boxes live in LDS at p - a.  The lane completing
+// the tile root hands its box to the root's parent.
+__global__ __launch_bounds__(kBoxTile) void k_leaves_subtree(const float *__restrict__ V, int64_t nv,
+                                                            const int32_t *__restrict__ F,
+                                                            const int32_t *__restrict__ ids, int n,
+                                                            Tri *__restrict__ tris, Node *nodes,
+                                                            const int32_t *__restrict__ parent, int32_t *counters,
+                                                            const int32_t *__restrict__ tiles,
+                                                            const int32_t *__restrict__ n_tiles) {
     __shared__ int arrived[kBoxTile];
     __shared__ float box[kBoxTile][2][6];
-    __shared__ int n_span;
-    const int base = blockIdx.x * kBoxTile;
-    const int last = min(base + kBoxTile, n) - 1;  // last leaf of the tile
-    arrived[threadIdx.x] = 0;
-    if (threadIdx.x == 0)
-        n_span = 0;
-    __syncthreads();
-    const int k = base + (int)threadIdx.x;
-    if (k < n) {
-        int t = ids[k];
-        const bool t_ok = t >= 0 && t < n;  // always true for a correct sort; guards the loads below
-        if (!t_ok)
-            t = 0;
-        const int32_t i0 = F[3 * (int64_t)t], i1 = F[3 * (int64_t)t + 1], i2 = F[3 * (int64_t)t + 2];
-        float lo[3], hi[3];
-        Tri tri;
-        if (!t_ok || i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
-            // an invalid triangle is never hit and does not widen any box
-            tri.a = make_float4(NAN, NAN, NAN, __int_as_float(t));
-            tri.e1 = make_float4(NAN, NAN, NAN, 0.0f);
-            tri.e2 = make_float4(NAN, NAN, NAN, 0.0f);
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = INFINITY;
-                hi[a] = -INFINITY;
-            }
+    const int total = *n_tiles;
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        const int c = tiles[e];
+        int a, b;
+        if (c < 0) {
+            a = b = ~c;
         } else {
-            float A[3], B[3], C[3];
-            for (int a = 0; a < 3; ++a) {
-                A[a] = V[3 * (int64_t)i0 + a];
-                B[a] = V[3 * (int64_t)i1 + a];
-                C[a] = V[3 * (int64_t)i2 + a];
-                lo[a] = fminf(A[a], fminf(B[a], C[a]));
-                hi[a] = fmaxf(A[a], fmaxf(B[a], C[a]));
-            }
-            tri.a = make_float4(A[0], A[1], A[2], __int_as_float(t));
-            tri.e1 = make_float4(B[0] - A[0], B[1] - A[1], B[2] - A[2], 0.0f);
-            tri.e2 = make_float4(C[0] - A[0], C[1] - A[1], C[2] - A[2], 0.0f);
+            const int4 r = nodes[c].refs;
+            a = r.z;
+            b = r.w;
         }
-        tris[k] = tri;
-        int self = ~k;
-        int p = n >= 2 ? parent[(n - 1) + k] : -1;
-        // a radix tree is at most 97 levels deep; the bound only guards the loop
-        for (int level = 0; p >= 0 && p < n - 1 && level < kDeepStack; ++level) {
-            Node *node = nodes + p;
-            const int4 refs = node->refs;
-            const bool is_left = refs.x == self;
-            store_child_box(node, is_left, lo, hi);
-            if (refs.z < base || refs.w > last) {
-                // spans tiles: at most one entry per leaf of the tile
-                const int slot = atomicAdd(&n_span, 1);
-                span_list[base + slot] = p;
-                break;
+        arrived[threadIdx.x] = 0;
+        __syncthreads();
+        const int k = a + (int)threadIdx.x;
+        if (a >= 0 && k <= b && b < n && b - a < kBoxTile) {
+            int t = ids[k];
+            const bool t_ok = t >= 0 && t < n;  // always true for a correct sort; guards the loads below
+            if (!t_ok)
+                t = 0;
+            const int32_t i0 = F[3 * (int64_t)t], i1 = F[3 * (int64_t)t + 1], i2 = F[3 * (int64_t)t + 2];
+            float lo[3], hi[3];
+            Tri tri;
+            if (!t_ok || i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
+                // an invalid triangle is never hit and does not widen any box
+                tri.a = make_float4(NAN, NAN, NAN, __int_as_float(t));
+                tri.e1 = make_float4(NAN, NAN, NAN, 0.0f);
+                tri.e2 = make_float4(NAN, NAN, NAN, 0.0f);
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = INFINITY;
+                    hi[d] = -INFINITY;
+                }
+            } else {
+                float A[3], B[3], C[3];
+                for (int d = 0; d < 3; ++d) {
+                    A[d] = V[3 * (int64_t)i0 + d];
+                    B[d] = V[3 * (int64_t)i1 + d];
+                    C[d] = V[3 * (int64_t)i2 + d];
+                    lo[d] = fminf(A[d], fminf(B[d], C[d]));
+                    hi[d] = fmaxf(A[d], fmaxf(B[d], C[d]));
+                }
+                tri.a = make_float4(A[0], A[1], A[2], __int_as_float(t));
+                tri.e1 = make_float4(B[0] - A[0], B[1] - A[1], B[2] - A[2], 0.0f);
+                tri.e2 = make_float4(C[0] - A[0], C[1] - A[1], C[2] - A[2], 0.0f);
             }
-            // p lies in its own leaf range, so p - base indexes the tile
-            float *mine = box[p - base][is_left ? 0 : 1];
-            for (int a = 0; a < 3; ++a) {
-                mine[a] = lo[a];
-                mine[3 + a] = hi[a];
+            tris[k] = tri;
+            int self = ~k;
+            int p = n >= 2 ? parent[(n - 1) + k] : -1;
+            if (self == c) {
+                // a one-leaf tile: its box goes straight to the parent
+                if (p >= 0 && p < n - 1)
+                    store_child_box(nodes + p, nodes[p].refs.x == self, lo, hi);
+            } else {
+                // a radix tree is at most 97 levels deep; the bound only guards the loop
+                for (int level = 0; p >= a && p <= b && p < n - 1 && level < kDeepStack; ++level) {
+                    Node *node = nodes + p;
+                    const bool is_left = node->refs.x == self;
+                    store_child_box(node, is_left, lo, hi);
+                    float *mine = box[p - a][is_left ? 0 : 1];
+                    for (int d = 0; d < 3; ++d) {
+                        mine[d] = lo[d];
+                        mine[3 + d] = hi[d];
+                    }
+                    __threadfence_block();
+                    if (atomicAdd(&arrived[p - a], 1) == 0)
+                        break;  // the sibling subtree is not finished; its last lane continues
+                    __threadfence_block();
+                    const float *other = box[p - a][is_left ? 1 : 0];
+                    for (int d = 0; d < 3; ++d) {
+                        lo[d] = fminf(lo[d], other[d]);
+                        hi[d] = fmaxf(hi[d], other[3 + d]);
+                    }
+                    counters[p] = 2;
+                    if (p == c) {
+                        const int q = parent[p];
+                        if (q >= 0 && q < n - 1)
+                            store_child_box(nodes + q, nodes[q].refs.x == p, lo, hi);
+                        break;
+                    }
+                    self = p;
+                    p = parent[p];
+                }
             }
-            __threadfence_block();
-            if (atomicAdd(&arrived[p - base], 1) == 0)
-                break;  // the sibling subtree is not finished; its last lane continues
-            __threadfence_block();
-            const float *other = box[p - base][is_left ? 1 : 0];
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = fminf(lo[a], other[a]);
-                hi[a] = fmaxf(hi[a], other[3 + a]);
-            }
-            counters[p] = 2;
-            self = p;
-            p = parent[p];
         }
+        __syncthreads();  // LDS is reused by the next tile
     }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        span_len[blockIdx.x] = n_span;
 }
 
-// One workgroup: lane b takes the listed nodes of tiles b, b + 1024, ...  The
-// second arrival at a node merges the two child boxes (each written by the
-// first kernel, or by this workgroup before its release) and climbs on.
-__global__ __launch_bounds__(1024) void k_boxes_span(Node *nodes, const int32_t *__restrict__ parent,
-                                                     int32_t *counters, const int32_t *__restrict__ span_list,
-                                                     const int32_t *__restrict__ span_len, int ntiles, int n) {
-    for (int b = threadIdx.x; b < ntiles; b += blockDim.x) {
-        const int len = span_len[b];
-        for (int e = 0; e < len && e < kBoxTile; ++e) {
-            int p = span_list[b * kBoxTile + e];
-            for (int level = 0; p >= 0 && p < n - 1 && level < kDeepStack; ++level) {
-                if (__hip_atomic_fetch_add(counters + p, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
-                    break;
-                const Node *node = nodes + p;
-                const float4 L = node->xy_left, R = node->xy_right, Z = node->z_both;
-                const float lo[3] = {fminf(L.x, R.x), fminf(L.z, R.z), fminf(Z.x, Z.z)};
-                const float hi[3] = {fmaxf(L.y, R.y), fmaxf(L.w, R.w), fmaxf(Z.y, Z.w)};
-                const int pp = parent[p];
-                if (pp < 0 || pp >= n - 1)
-                    break;  // p is the root
-                Node *up = nodes + pp;
-                store_child_box(up, up->refs.x == p, lo, hi);
-                p = pp;
-            }
+// Phase 2: one workgroup finishes the nodes above the tiles (every node with
+// more than kBoxTile leaves).  Each listed tile is an arrival at its parent;
+// the second arrival merges the two child boxes (written by phase 1, or by
+// this workgroup before its release) and climbs on.
+__global__ __launch_bounds__(1024) void k_boxes_top(Node *nodes, const int32_t *__restrict__ parent,
+                                                    int32_t *counters, const int32_t *__restrict__ tiles,
+                                                    const int32_t *__restrict__ n_tiles, int n) {
+    const int total = *n_tiles;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        const int c = tiles[e];
+        int p = c < 0 ? parent[(n - 1) + ~c] : parent[c];
+        for (int level = 0; p >= 0 && p < n - 1 && level < kDeepStack; ++level) {
+            if (__hip_atomic_fetch_add(counters + p, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+                break;
+            const Node *node = nodes + p;
+            const float4 L = node->xy_left, R = node->xy_right, Z = node->z_both;
+            const float lo[3] = {fminf(L.x, R.x), fminf(L.z, R.z), fminf(Z.x, Z.z)};
+            const float hi[3] = {fmaxf(L.y, R.y), fmaxf(L.w, R.w), fmaxf(Z.y, Z.w)};
+            const int q = parent[p];
+            if (q < 0 || q >= n - 1)
+                break;  // p is the root
+            store_child_box(nodes + q, nodes[q].refs.x == p, lo, hi);
+            p = q;
         }
     }
 }
@@ -561,16 +609,24 @@ hipError_t build_from_keys(MeshDev &m, int key_bits, hipStream_t s) {
     const int64_t nt = m.nt;
     K *keys = static_cast<K *>(m.keys);
     sort_passes<K>(keys, m.ids, m.sort_tmp, nt, key_bits, s);  // 4 or 8 passes: back in (keys, ids)
-    if (nt >= 2)
-        k_radix_tree<K><<<blocks_for(nt - 1, 256), 256, 0, s>>>(keys, (int)nt, m.nodes, m.parent, m.counters);
-    // the sort's scratch is free again: per-tile lists of spanning nodes
-    const int box_tiles = blocks_for(nt, kBoxTile);
-    int32_t *span_list = static_cast<int32_t *>(m.sort_tmp);
-    int32_t *span_len = span_list + (int64_t)box_tiles * kBoxTile;
-    k_leaves_tile<<<box_tiles, kBoxTile, 0, s>>>(m.V, m.nv, m.F, m.ids, (int)nt, m.tris, m.nodes, m.parent,
-                                                 m.counters, span_list, span_len);
-    if (box_tiles > 1)
-        k_boxes_span<<<1, 1024, 0, s>>>(m.nodes, m.parent, m.counters, span_list, span_len, box_tiles, (int)nt);
+    // the sort's scratch is free again: the list of bottom-up tiles
+    int32_t *n_tiles = static_cast<int32_t *>(m.sort_tmp);
+    int32_t *tiles = n_tiles + 64;
+    if (nt >= 2) {
+        k_zero_i32<<<1, 64, 0, s>>>(n_tiles, 1);
+        k_radix_tree<K><<<blocks_for(nt - 1, 256), 256, 0, s>>>(keys, (int)nt, m.nodes, m.parent, m.counters, tiles,
+                                                                n_tiles);
+    } else {
+        k_single_tile<<<1, 1, 0, s>>>(tiles, n_tiles);
+    }
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t grid = nt < 2 * (int64_t)cus ? nt : 2 * (int64_t)cus;  // tiles are taken in a loop
+    k_leaves_subtree<<<(int)grid, kBoxTile, 0, s>>>(m.V, m.nv, m.F, m.ids, (int)nt, m.tris, m.nodes, m.parent,
+                                                    m.counters, tiles, n_tiles);
+    if (nt > kBoxTile)
+        k_boxes_top<<<1, 1024, 0, s>>>(m.nodes, m.parent, m.counters, tiles, n_tiles, (int)nt);
     return hipGetLastError();
 }
 
@@ -594,8 +650,7 @@ hipError_t launch_morton_batch(MeshDev &m, const int32_t *tri_mesh, const float 
 size_t sort_tmp_bytes(int64_t nt, int morton_bits) {
     const size_t kb = morton_bits > 32 ? 8 : 4;
     const size_t sort = pass_tmp_bytes(nt, kb);
-    const int64_t box_tiles = (nt + kBoxTile - 1) / kBoxTile;
-    const size_t lists = 4 * (size_t)box_tiles * (kBoxTile + 1) + 256;  // span lists after the sort
+    const size_t lists = 4 * (size_t)nt + 4 * 64 + 256;  // tile list after the sort (at most one per leaf)
     return sort > lists ? sort : lists;
 }
 

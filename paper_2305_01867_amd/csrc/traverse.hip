@@ -618,6 +618,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
 //     visited node.
 //   long queue: one lane per segment with a private deep stack (throughput).
 constexpr int kFinishThreads = 64;
+constexpr int kCountList = 2048;  // hits a wave collects per segment in count mode
 constexpr int kWaveFinishMax = 8192;                      // queue length up to which a wave takes a segment
 constexpr int kWaveStack = kDeepStack * kFinishThreads;  // shared entries (same LDS as the private stacks)
 // Steps that pop k entries push at most 2k; popping at most (kWaveSoft - size)
@@ -634,9 +635,12 @@ struct Finish {
     float t32, u32, v32;
     float tlimit;
     bool done;
-    // count mode: only hits beyond the last counted t take part
+    // count mode: only hits beyond the last counted t take part; with
+    // `list` set, every such hit's t is appended there instead
     double floor64;
     float floor32;
+    double *list;
+    int *list_len;
 
     __device__ void reset_best() {
         best_id = -1;
@@ -651,6 +655,8 @@ struct Finish {
         reset_best();
         floor64 = -INFINITY;
         floor32 = -INFINITY;
+        list = nullptr;
+        list_len = nullptr;
         const float *o = p.from + 3 * i, *e = p.to + 3 * i;
         ox = o[0]; oy = o[1]; oz = o[2];
         ex = e[0]; ey = e[1]; ez = e[2];
@@ -670,6 +676,10 @@ struct Finish {
                 h = mt64(ox, oy, oz, ex, ey, ez, p.V, p.F, id);
             if (!h.hit || !(h.t > floor64))
                 return;
+            if (MODE == MODE_COUNT && list) {
+                append(h.t);
+                return;
+            }
             if (MODE == MODE_BOOL) {
                 best_id = id;
                 done = true;
@@ -692,6 +702,10 @@ struct Finish {
             const float t = m.T / m.det;
             if (!(t > floor32))
                 return;
+            if (MODE == MODE_COUNT && list) {
+                append((double)t);
+                return;
+            }
             if (t < t32 || (t == t32 && id < best_id)) {
                 t32 = t;
                 best_id = id;
@@ -700,6 +714,12 @@ struct Finish {
                 tlimit = t;
             }
         }
+    }
+
+    __device__ void append(double t) {
+        const int k = atomicAdd(list_len, 1);
+        if (k < kCountList)
+            list[k] = t;
     }
 
     __device__ void write(const TravParams &p, int64_t i, int toff) const {
@@ -826,16 +846,45 @@ __device__ void wave_search(const TravParams &p, Finish<MODE, CERT> &f, bool ok,
     __syncthreads();  // the stack is reused by the next search
 }
 
-// One wave (the whole 64-thread block) finishes segment i.  Count mode asks
-// for the nearest hit beyond the last counted t until there is none, so
-// every distinct t is counted once with no list to outgrow.
+// One wave (the whole 64-thread block) finishes segment i.  Count mode
+// collects the t of every hit in LDS and counts the distinct values; a
+// segment with more hits than the list holds asks instead, round by round,
+// for the nearest hit beyond the last counted t until there is none.
 template <int MODE, bool CERT>
 __device__ void finish_wave(const TravParams &p, int64_t i, int *stk) {
     int root, toff;
     segment_root(p, i, root, toff);
     Finish<MODE, CERT> f;
     const bool ok = f.init(p, i);
-    if (MODE == MODE_COUNT) {
+    if constexpr (MODE == MODE_COUNT) {
+        // one search collecting every hit's t; the distinct values are then
+        // counted in LDS.  Only a list that overflows falls back to rounds.
+        __shared__ double list[kCountList];
+        __shared__ int list_len;
+        if (threadIdx.x == 0)
+            list_len = 0;
+        __syncthreads();
+        f.list = list;
+        f.list_len = &list_len;
+        wave_search<MODE, CERT>(p, f, ok, root, stk);
+        const int m = list_len;
+        f.list = nullptr;
+        if (m <= kCountList) {
+            int distinct = 0;
+            for (int j = threadIdx.x; j < m; j += blockDim.x) {
+                const double v = list[j];
+                bool first = true;
+                for (int k = 0; k < j && first; ++k)
+                    first = list[k] != v;
+                distinct += first ? 1 : 0;
+            }
+            for (int off = 32; off > 0; off >>= 1)
+                distinct += __shfl_xor(distinct, off);
+            if (threadIdx.x == 0)
+                write_count(p.out, i, distinct);
+            __syncthreads();  // the list is reused by the block's next segment
+            return;
+        }
         int32_t cnt = 0;
         for (int64_t q = 0; q <= p.nt; ++q) {  // at most one round per triangle
             f.reset_best();
@@ -851,17 +900,19 @@ __device__ void finish_wave(const TravParams &p, int64_t i, int *stk) {
         }
         if (threadIdx.x == 0)
             write_count(p.out, i, cnt);
+        __syncthreads();
         return;
-    }
-    wave_search<MODE, CERT>(p, f, ok, root, stk);
-    if (MODE == MODE_BOOL) {
-        f.best_id = __ballot(f.best_id >= 0) ? 0 : -1;
-        toff = 0;
     } else {
-        f.reduce_wave();
+        wave_search<MODE, CERT>(p, f, ok, root, stk);
+        if (MODE == MODE_BOOL) {
+            f.best_id = __ballot(f.best_id >= 0) ? 0 : -1;
+            toff = 0;
+        } else {
+            f.reduce_wave();
+        }
+        if (threadIdx.x == 0)
+            f.write(p, i, toff);
     }
-    if (threadIdx.x == 0)
-        f.write(p, i, toff);
 }
 
 // One lane finishes segment i with its private stack (stride kFinishThreads).

@@ -48,6 +48,23 @@ def test_closed_form_scenes():
             assert hit.tolist() == [1, 1, 1, 0]
 
 
+def test_more_hits_than_the_wave_list():
+    """1100 stacked split layers: a vertical segment through the diagonals
+    meets 2200 triangles at 1100 points (more hits than the pass-2 list holds:
+    the round-by-round count); one inside the triangles meets 1100."""
+    k = 1100
+    V, F = stacked(k)
+    O = np.array([[0.5, 0.5, k + 0.5], [0.75, 0.25, k + 0.5]], np.float32)
+    E = np.array([[0.5, 0.5, -0.5], [0.75, 0.25, -0.5]], np.float32)
+    want = oracle.intercept_count(V, F, O, E)
+    assert want.tolist() == [k, k]
+    with rsi.rsi_build(dev(V), dev(F)) as mesh:
+        for prec in ("certified", "plain"):
+            got, cnt = gpu_count(mesh, O, E, prec)
+            assert got.tolist() == [k, k], prec
+            assert cnt[3] == 2
+
+
 def test_heightfield_counts_exact():
     V, F, O, E = workloads.tiny_config()
     want = oracle.intercept_count(V, F, O, E)
