@@ -105,6 +105,23 @@ def intercept_count(V, F, O, E, n_threads: int = 0):
     return count
 
 
+def derived(O, E, ids, uvt):
+    """The barycentric mode's result tuple (paper: Background -- the intersecting
+    rays with the intersecting triangle, the distance to and the location of the
+    nearest intersecting point; Performance section, steps 3a-3d): for every
+    hitting segment, in ascending index, (index, distance, triangle, point)
+    with distance = t ||E - O|| and point = O + t (E - O), in binary64 from the
+    float32 end points and the binary64 t."""
+    O = np.asarray(O, np.float32).astype(np.float64)
+    E = np.asarray(E, np.float32).astype(np.float64)
+    ids = np.asarray(ids)
+    idx = np.nonzero(ids >= 0)[0]
+    d = E[idx] - O[idx]
+    t = np.asarray(uvt, np.float64)[idx, 2]
+    length = np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2])
+    return idx.astype(np.int64), t * length, ids[idx].astype(np.int32), O[idx] + t[:, None] * d
+
+
 def all_hits(V, F, o, e, cap: int = 4096):
     """Every triangle one segment hits, ascending index: (ids, uvt)."""
     V = _f32(V)
