@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define RSI_ABI_VERSION 2  /* 2: intercept-count mode, rsi_outputs.count */
+#define RSI_ABI_VERSION 3  /* 2: intercept-count mode, rsi_outputs.count; 3: waves_per_cu */
 
 typedef struct rsi_mesh_s *rsi_mesh; /* opaque; owned by the library until rsi_destroy */
 
@@ -116,6 +116,10 @@ typedef struct rsi_intersect_opts {
                              segment indices (16 B of scratch per segment). */
     int32_t proposal;     /* 1 = visit the learned proposal's bucket first (needs a
                              trained or loaded proposal); 0 = plain order */
+    int32_t waves_per_cu; /* resident waves per compute unit of the persistent
+                             traversal, 1..32 (capped by what registers and LDS
+                             allow); 0 = the library default.  Fewer waves share a
+                             CU's L1 cache among fewer tree paths. */
 } rsi_intersect_opts;
 
 /* Output buffers (device pointers, caller-owned).  Required per mode:
@@ -232,6 +236,31 @@ rsi_status rsi_mesh_export(rsi_mesh mesh, int32_t what, void *dst, int64_t dst_b
 rsi_status rsi_traversal_stats(rsi_mesh mesh, const float *rays_from, const float *rays_to,
                                int64_t n_rays, int32_t mode, const rsi_intersect_opts *opts,
                                uint32_t *node_visits, uint32_t *leaf_tests, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Derived outputs of the barycentric mode (paper: Background -- the
+ * intersecting rays with the intersecting triangle, the distance to and the
+ * location of the nearest intersecting point; Performance section, steps
+ * 3a-3d, which the paper moved from host numpy to GPU kernels).  Inputs are
+ * the segments and the tri_id / uvt arrays an rsi_intersect call in
+ * BARYCENTRIC mode wrote (device memory, N_r entries); a segment hits iff
+ * tri_id >= 0.  Distances are t |to - from| and points from + t (to - from),
+ * evaluated in binary64 from the float32 end points and t, rounded once.
+ * ---------------------------------------------------------------------- */
+
+/* Per segment: distance float [N_r] and point float [N_r][3] (either may be
+ * NULL), NaN for a segment that misses.  Queued on `stream`. */
+rsi_status rsi_derive(const float *rays_from, const float *rays_to, int64_t n_rays, const int32_t *tri_id,
+                      const float *uvt, float *distance, float *point, void *stream);
+
+/* The paper's result tuple, compacted: for each hitting segment in ascending
+ * index, hit_index int64 (its index), distance float, hit_tri int32 (its
+ * triangle) and point float [3], written to slots 0 .. *n_hits - 1 (arrays of
+ * N_r entries; any may be NULL).  n_hits: device int64, required.  Queued on
+ * `stream` (the call allocates 4 B per 4096 segments of scratch, stream-ordered). */
+rsi_status rsi_compact_hits(const float *rays_from, const float *rays_to, int64_t n_rays, const int32_t *tri_id,
+                            const float *uvt, int64_t *hit_index, float *distance, int32_t *hit_tri, float *point,
+                            int64_t *n_hits, void *stream);
 
 /*
  * rsi_debug_certify -- the CERTIFIED precision's binary32 test on n given

@@ -30,7 +30,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "librsi.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MODES = {"boolean": 0, "first_hit": 1, "barycentric": 2, "intercept_count": 3}
 PRECISIONS = {"plain": 0, "certified": 1}
 EXPORTS = {"sorted_keys": 0, "sorted_ids": 1, "nodes": 2, "parents": 3, "counters": 4, "leaves": 5, "bounds": 6}
@@ -50,7 +50,7 @@ class _BuildOpts(ctypes.Structure):
 
 class _IntersectOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("block", ctypes.c_int32), ("stack_depth", ctypes.c_int32),
-                ("ray_sort", ctypes.c_int32), ("proposal", ctypes.c_int32)]
+                ("ray_sort", ctypes.c_int32), ("proposal", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
 
 
 class _Outputs(ctypes.Structure):
@@ -93,6 +93,8 @@ def lib():
     L.rsi_mesh_export.argtypes = [P, I32, P, I64, P]
     L.rsi_traversal_stats.argtypes = [P, P, P, I64, I32, ctypes.POINTER(_IntersectOpts), P, P, P]
     L.rsi_debug_certify.argtypes = [P, P, P, I64, P, P, P]
+    L.rsi_derive.argtypes = [P, P, I64, P, P, P, P, P]
+    L.rsi_compact_hits.argtypes = [P, P, I64, P, P, P, P, P, P, P, P]
     L.rsi_proposal_train.argtypes = [P, P, P, I64, ctypes.POINTER(_TrainOpts), P, ctypes.POINTER(I64), P]
     L.rsi_proposal_predict.argtypes = [P, P, P, I64, P, P]
     L.rsi_proposal_params.argtypes = [P, I32, P, P]
@@ -111,7 +113,7 @@ def lib():
     for f in ("rsi_build", "rsi_intersect", "rsi_destroy", "rsi_mesh_info_get", "rsi_mesh_export",
               "rsi_traversal_stats", "rsi_proposal_train", "rsi_proposal_predict", "rsi_proposal_params",
               "rsi_proposal_gradient", "rsi_proposal_features", "rsi_proposal_frontier", "rsi_proposal_save",
-              "rsi_proposal_load", "rsi_debug_certify"):
+              "rsi_proposal_load", "rsi_debug_certify", "rsi_derive", "rsi_compact_hits"):
         getattr(L, f).restype = ctypes.c_int
     L.rsi_status_string.argtypes = [ctypes.c_int]
     L.rsi_status_string.restype = ctypes.c_char_p
@@ -211,19 +213,20 @@ def rsi_destroy(mesh: Mesh):
 RAY_ORDERS = {"input": 0, "midpoint": 1, "origin_octant": 2}
 
 
-def _iopts(precision, block, stack_depth, proposal=False, ray_sort=0):
+def _iopts(precision, block, stack_depth, proposal=False, ray_sort=0, waves_per_cu=0):
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")
     if isinstance(ray_sort, str):
         if ray_sort not in RAY_ORDERS:
             raise ValueError(f"ray_sort must be one of {list(RAY_ORDERS)}")
         ray_sort = RAY_ORDERS[ray_sort]
-    return _IntersectOpts(PRECISIONS[precision], int(block), int(stack_depth), int(ray_sort), int(bool(proposal)))
+    return _IntersectOpts(PRECISIONS[precision], int(block), int(stack_depth), int(ray_sort), int(bool(proposal)),
+                          int(waves_per_cu))
 
 
 def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
                   precision: str = "plain", block: int = 0, stack_depth: int = 0, out: dict | None = None,
-                  stream=None, proposal: bool = False, ray_sort=0) -> dict:
+                  stream=None, proposal: bool = False, ray_sort=0, waves_per_cu: int = 0) -> dict:
     """Test segments [N, 3] float32 against the mesh.  Returns a dict with the
     outputs of the mode ("hit" uint8, "tri_id" int32, "uvt" float32 [N, 3],
     "count" int32) and "counters" uint64 [4] (re-decided in binary64, past the
@@ -264,7 +267,7 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
         return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()
 
     o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"), ptr("count"))
-    opts = _iopts(precision, block, stack_depth, proposal, ray_sort)
+    opts = _iopts(precision, block, stack_depth, proposal, ray_sort, waves_per_cu)
     _check(lib().rsi_intersect(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
                                ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
                                ctypes.byref(o), _stream_handle(stream)))
@@ -273,14 +276,14 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
 
 def rsi_traversal_stats(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
                         precision: str = "plain", block: int = 0, stack_depth: int = 0, stream=None,
-                        proposal: bool = False, ray_sort=0):
+                        proposal: bool = False, ray_sort=0, waves_per_cu: int = 0):
     """Per-segment (node visits, leaf tests) of the traversal, uint32 -> int64 tensors."""
     _need(rays_from, "rays_from", torch.float32, 3)
     _need(rays_to, "rays_to", torch.float32, 3)
     n = rays_from.shape[0]
     visits = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
     tests = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
-    opts = _iopts(precision, block, stack_depth, proposal, ray_sort)
+    opts = _iopts(precision, block, stack_depth, proposal, ray_sort, waves_per_cu)
     _check(lib().rsi_traversal_stats(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
                                      ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
                                      ctypes.c_void_p(visits.data_ptr()), ctypes.c_void_p(tests.data_ptr()),
@@ -301,6 +304,71 @@ def rsi_debug_certify(rays_from: torch.Tensor, rays_to: torch.Tensor, corners: t
     _check(lib().rsi_debug_certify(_p(rays_from), _p(rays_to), _p(corners), n, _p(values), _p(classes),
                                    _stream_handle(stream)))
     return values, classes
+
+
+def _bary(rays_from, rays_to, result):
+    n = _rays(rays_from, rays_to)
+    if "tri_id" not in result or "uvt" not in result:
+        raise ValueError("result must hold the barycentric outputs 'tri_id' and 'uvt'")
+    _need(result["tri_id"], "result['tri_id']", torch.int32)
+    _need(result["uvt"], "result['uvt']", torch.float32, 3)
+    if result["tri_id"].shape[0] < n or result["uvt"].shape[0] < n:
+        raise ValueError("result arrays are shorter than the segment arrays")
+    return n
+
+
+def rsi_derive(rays_from, rays_to, result: dict, stream=None) -> dict:
+    """Distance t |E - O| and point O + t (E - O) of every segment from a
+    barycentric result (NaN on a miss): {"distance": [N], "point": [N, 3]}."""
+    n = _bary(rays_from, rays_to, result)
+    dist = torch.empty(n, dtype=torch.float32, device=rays_from.device)
+    point = torch.empty((n, 3), dtype=torch.float32, device=rays_from.device)
+    _check(lib().rsi_derive(_p(rays_from), _p(rays_to), n, _p(result["tri_id"]), _p(result["uvt"]), _p(dist),
+                            _p(point), _stream_handle(stream)))
+    return {"distance": dist, "point": point}
+
+
+def rsi_compact_hits(rays_from, rays_to, result: dict, stream=None):
+    """The paper's barycentric tuple (intersecting_rays, distances,
+    hit_triangles, hit_points) from a barycentric result, hitting segments in
+    ascending index.  Waits for the stream once to learn the number of hits."""
+    n = _bary(rays_from, rays_to, result)
+    dev = rays_from.device
+    idx = torch.empty(n, dtype=torch.int64, device=dev)
+    dist = torch.empty(n, dtype=torch.float32, device=dev)
+    tri = torch.empty(n, dtype=torch.int32, device=dev)
+    point = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib().rsi_compact_hits(_p(rays_from), _p(rays_to), n, _p(result["tri_id"]), _p(result["uvt"]), _p(idx),
+                                  _p(dist), _p(tri), _p(point), _p(count), _stream_handle(stream)))
+    k = int(count.item())
+    return idx[:k], dist[:k], tri[:k], point[:k]
+
+
+def rsi_test(vertices, triangles, rays_from, rays_to, mode: str = "boolean", precision: str = "certified", **opts):
+    """The paper's one-call usage (Usage section: test(vertices, triangles,
+    raysFrom, raysTo, cfg)): builds the mesh, intersects and returns, by mode,
+    the hit flags (boolean), the compacted (intersecting_rays, distances,
+    hit_triangles, hit_points) (barycentric), the number of distinct
+    intersections (intercept_count) or the nearest triangle (first_hit).
+    Arrays may be numpy or torch; numpy inputs are copied to the GPU and the
+    results come back as numpy."""
+    import numpy as _np
+    as_numpy = isinstance(rays_from, _np.ndarray)
+    dev = torch.device("cuda")
+    t = lambda x, dt: (torch.from_numpy(_np.ascontiguousarray(x, dt)).to(dev) if isinstance(x, _np.ndarray)
+                       else x)
+    V, F = t(vertices, _np.float32), t(triangles, _np.int32)
+    O, E = t(rays_from, _np.float32), t(rays_to, _np.float32)
+    with rsi_build(V, F) as mesh:
+        r = rsi_intersect(mesh, O, E, mode=mode, precision=precision, **opts)
+        if mode == "barycentric":
+            out = rsi_compact_hits(O, E, r)
+        else:
+            out = {"boolean": r.get("hit"), "first_hit": r.get("tri_id"), "intercept_count": r.get("count")}[mode]
+    if as_numpy:
+        out = tuple(x.cpu().numpy() for x in out) if isinstance(out, tuple) else out.cpu().numpy()
+    return out
 
 
 def rsi_mesh_info_get(mesh: Mesh) -> dict:
@@ -481,7 +549,7 @@ def rsi_batch_build(batch: Batch, vertices: torch.Tensor, triangles: torch.Tenso
 
 def rsi_batch_intersect(batch: Batch, rays_from, rays_to, mode: str = "boolean", precision: str = "plain",
                         block: int = 0, stack_depth: int = 0, out: dict | None = None, stream=None,
-                        ray_sort=0) -> dict:
+                        ray_sort=0, waves_per_cu: int = 0) -> dict:
     """Outputs over all segments (triangle indices relative to each mesh)."""
     if mode not in MODES:
         raise ValueError(f"mode must be one of {list(MODES)}")
@@ -504,7 +572,7 @@ def rsi_batch_intersect(batch: Batch, rays_from, rays_to, mode: str = "boolean",
         return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()
 
     o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"), ptr("count"))
-    opts = _iopts(precision, block, stack_depth, False, ray_sort)
+    opts = _iopts(precision, block, stack_depth, False, ray_sort, waves_per_cu)
     _check(lib().rsi_batch_intersect(batch.handle, _p(rays_from), _p(rays_to), MODES[mode], ctypes.byref(opts),
                                      ctypes.byref(o), _stream_handle(stream)))
     return out

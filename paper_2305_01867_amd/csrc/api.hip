@@ -118,11 +118,12 @@ size_t round_up(size_t x) { return (x + 255) & ~size_t(255); }
 bool valid_mesh(rsi_mesh m) { return m != nullptr && m->magic == kMagic; }
 
 rsi_status parse_intersect_opts(const rsi_intersect_opts *opts, int &precision, int &block, int &stack,
-                                int &ray_sort) {
+                                int &ray_sort, int &waves) {
     precision = RSI_PRECISION_PLAIN;
     block = 256;
     stack = 20;
     ray_sort = RSI_RAY_ORDER_INPUT;
+    waves = 0;
     if (!opts)
         return RSI_OK;
     if (opts->precision != RSI_PRECISION_PLAIN && opts->precision != RSI_PRECISION_CERTIFIED)
@@ -144,6 +145,9 @@ rsi_status parse_intersect_opts(const rsi_intersect_opts *opts, int &precision, 
     ray_sort = opts->ray_sort;
     if (opts->proposal != 0 && opts->proposal != 1)
         return fail(RSI_E_ARG, "proposal must be 0 or 1");
+    if (opts->waves_per_cu < 0 || opts->waves_per_cu > 32)
+        return fail(RSI_E_ARG, "waves_per_cu must be in 0..32");
+    waves = opts->waves_per_cu;
     return RSI_OK;
 }
 
@@ -321,8 +325,8 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     rsi_status st = check_ray_args(mesh, from, to, n, mode);
     if (st != RSI_OK)
         return st;
-    int precision, block, stack, ray_sort;
-    if ((st = parse_intersect_opts(opts, precision, block, stack, ray_sort)) != RSI_OK)
+    int precision, block, stack, ray_sort, waves;
+    if ((st = parse_intersect_opts(opts, precision, block, stack, ray_sort, waves)) != RSI_OK)
         return st;
     const bool use_prop = opts && opts->proposal == 1 && n > 0 && mesh->dev.nt > 0;
     if (use_prop && mode == RSI_MODE_INTERCEPT_COUNT)
@@ -395,6 +399,7 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     a.certified = precision == RSI_PRECISION_CERTIFIED;
     a.block = block;
     a.stack = stack;
+    a.waves_per_cu = waves;
     uint64_t *ws_counters = reinterpret_cast<uint64_t *>(static_cast<char *>(ws));
     a.queue_len = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + 32);
     a.queue = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + 64);
@@ -443,6 +448,76 @@ rsi_status rsi_traversal_stats(rsi_mesh mesh, const float *rays_from, const floa
                                int32_t mode, const rsi_intersect_opts *opts, uint32_t *node_visits,
                                uint32_t *leaf_tests, void *stream) {
     return run_rays(mesh, rays_from, rays_to, n_rays, mode, opts, nullptr, node_visits, leaf_tests, stream, true);
+}
+
+// Checks shared by the derived-output entries: segments and barycentric results.
+static rsi_status check_derive_args(const float *from, const float *to, int64_t n, const int32_t *tri_id,
+                                    const float *uvt) {
+    if (n < 0)
+        return fail(RSI_E_ARG, "n_rays must be >= 0");
+    if (n > 0 && (!from || !to || !tri_id || !uvt || !aligned4(from) || !aligned4(to) || !aligned4(tri_id) ||
+                  !aligned4(uvt)))
+        return fail(RSI_E_ARG, "rays_from, rays_to, tri_id and uvt must be non-NULL and 4-byte aligned");
+    if (n > ((int64_t)1 << 31) - 1)
+        return fail(RSI_E_CAPACITY, "at most 2^31 - 1 segments");
+    rsi_status st = check_device();
+    if (st != RSI_OK)
+        return st;
+    if (n > 0 && ((st = check_dev_ptr(from, "rays_from")) != RSI_OK || (st = check_dev_ptr(to, "rays_to")) != RSI_OK ||
+                  (st = check_dev_ptr(tri_id, "tri_id")) != RSI_OK || (st = check_dev_ptr(uvt, "uvt")) != RSI_OK))
+        return st;
+    return pending_error("before a derived-output call");
+}
+
+rsi_status rsi_derive(const float *rays_from, const float *rays_to, int64_t n_rays, const int32_t *tri_id,
+                      const float *uvt, float *distance, float *point, void *stream) {
+    g_error.clear();
+    rsi_status st = check_derive_args(rays_from, rays_to, n_rays, tri_id, uvt);
+    if (st != RSI_OK)
+        return st;
+    if ((distance && !aligned4(distance)) || (point && !aligned4(point)))
+        return fail(RSI_E_ARG, "distance / point must be 4-byte aligned");
+    if (n_rays == 0 || (!distance && !point))
+        return RSI_OK;
+    if ((distance && (st = check_dev_ptr(distance, "distance")) != RSI_OK) ||
+        (point && (st = check_dev_ptr(point, "point")) != RSI_OK))
+        return st;
+    const hipError_t e = rsi::launch_derive(rays_from, rays_to, n_rays, tri_id, uvt, distance, point,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_derive");
+}
+
+rsi_status rsi_compact_hits(const float *rays_from, const float *rays_to, int64_t n_rays, const int32_t *tri_id,
+                            const float *uvt, int64_t *hit_index, float *distance, int32_t *hit_tri, float *point,
+                            int64_t *n_hits, void *stream) {
+    g_error.clear();
+    rsi_status st = check_derive_args(rays_from, rays_to, n_rays, tri_id, uvt);
+    if (st != RSI_OK)
+        return st;
+    if (!n_hits || (reinterpret_cast<uintptr_t>(n_hits) & 7u) ||
+        (hit_index && (reinterpret_cast<uintptr_t>(hit_index) & 7u)) || (distance && !aligned4(distance)) ||
+        (hit_tri && !aligned4(hit_tri)) || (point && !aligned4(point)))
+        return fail(RSI_E_ARG, "n_hits must be non-NULL; outputs must be aligned to their element size");
+    if ((st = check_dev_ptr(n_hits, "n_hits")) != RSI_OK ||
+        (hit_index && (st = check_dev_ptr(hit_index, "hit_index")) != RSI_OK) ||
+        (distance && (st = check_dev_ptr(distance, "distance")) != RSI_OK) ||
+        (hit_tri && (st = check_dev_ptr(hit_tri, "hit_tri")) != RSI_OK) ||
+        (point && (st = check_dev_ptr(point, "point")) != RSI_OK))
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, rsi::compact_ws_bytes(n_rays), s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? RSI_E_NOMEM : RSI_E_HIP,
+                    std::string("hipMallocAsync failed: ") + hipGetErrorString(e));
+    }
+    e = rsi::launch_compact(rays_from, rays_to, n_rays, tri_id, uvt, hit_index, distance, hit_tri, point, n_hits, ws,
+                            s);
+    const hipError_t e2 = hipFreeAsync(ws, s);
+    if (e != hipSuccess)
+        return fail_hip(e, "rsi_compact_hits");
+    return e2 == hipSuccess ? RSI_OK : fail_hip(e2, "hipFreeAsync");
 }
 
 rsi_status rsi_debug_certify(const float *rays_from, const float *rays_to, const float *corners, int64_t n,
@@ -704,8 +779,8 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
     if (mode != RSI_MODE_BOOLEAN && mode != RSI_MODE_FIRST_HIT && mode != RSI_MODE_BARYCENTRIC &&
         mode != RSI_MODE_INTERCEPT_COUNT)
         return fail(RSI_E_ARG, "unknown mode");
-    int precision, block, stack, ray_sort;
-    rsi_status st = parse_intersect_opts(opts, precision, block, stack, ray_sort);
+    int precision, block, stack, ray_sort, waves;
+    rsi_status st = parse_intersect_opts(opts, precision, block, stack, ray_sort, waves);
     if (st != RSI_OK)
         return st;
     if (opts && opts->proposal)
@@ -735,6 +810,7 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
     a.certified = precision == RSI_PRECISION_CERTIFIED;
     a.block = block;
     a.stack = stack;
+    a.waves_per_cu = waves;
     a.hit = out->hit;
     a.tri_id = out->tri_id;
     a.uvt = out->uvt;

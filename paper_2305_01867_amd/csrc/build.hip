@@ -656,6 +656,12 @@ size_t sort_tmp_bytes(int64_t nt, int morton_bits) {
 
 size_t sort_u32_tmp_bytes(int64_t n) { return pass_tmp_bytes(n, 4); }
 
+hipError_t scan_u32_exclusive(uint32_t *a, int64_t len, uint32_t *partial, hipStream_t s) {
+    if (len > 0)
+        scan_hist(a, len, partial, s);
+    return hipGetLastError();
+}
+
 hipError_t sort_u32_pairs(uint32_t *keys, int32_t *ids, void *tmp, int64_t n, hipStream_t s) {
     if (n > 1)
         sort_passes<uint32_t>(keys, ids, tmp, n, 32, s);  // four passes

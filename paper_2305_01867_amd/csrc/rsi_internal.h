@@ -103,6 +103,16 @@ hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s);
 // Stable sort of (32-bit key, id) pairs in place; tmp holds sort_u32_tmp_bytes(n).
 size_t sort_u32_tmp_bytes(int64_t n);
 hipError_t sort_u32_pairs(uint32_t *keys, int32_t *ids, void *tmp, int64_t n, hipStream_t s);
+// Exclusive prefix sum of a[0..len) in place; partial holds 1024 entries.
+hipError_t scan_u32_exclusive(uint32_t *a, int64_t len, uint32_t *partial, hipStream_t s);
+
+// Derived outputs of the barycentric mode (derive.hip).
+hipError_t launch_derive(const float *from, const float *to, int64_t n, const int32_t *tri_id, const float *uvt,
+                         float *dist, float *point, hipStream_t s);
+size_t compact_ws_bytes(int64_t n);
+hipError_t launch_compact(const float *from, const float *to, int64_t n, const int32_t *tri_id, const float *uvt,
+                          int64_t *hit_index, float *dist, int32_t *hit_tri, float *point, int64_t *n_hits,
+                          void *ws, hipStream_t s);
 hipError_t launch_morton_batch(MeshDev &m, const int32_t *tri_mesh, const float *mesh_bounds, hipStream_t s);
 
 // Intersection (traverse.hip).
@@ -113,6 +123,7 @@ struct TraverseArgs {
     int certified = 0;
     int block = 256;
     int stack = 24;
+    int waves_per_cu = 0;          // 0: library default
     uint8_t *hit = nullptr;
     int32_t *tri_id = nullptr;
     float *uvt = nullptr;

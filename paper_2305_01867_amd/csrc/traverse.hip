@@ -256,6 +256,7 @@ struct TravParams {
     int64_t n;
     Outs out;
     int stack_depth;
+    int waves_per_cu;
     int32_t *queue;
     uint32_t *queue_len;
     uint32_t *next_ray;
@@ -288,6 +289,9 @@ __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why)
 // aside and continues with internal nodes; the leaf phase runs when half the
 // wave is waiting on a leaf, so the leaf code runs for many lanes at once.
 constexpr int kRefillMin = 8;     // refill when at least this many lanes idle
+// Resident waves per CU of the persistent traversal unless asked otherwise:
+// fewer waves than registers allow share the CU's L1 among fewer tree paths.
+constexpr int kDefaultWavesPerCU = 32;
 constexpr int kDone = INT32_MIN;  // nothing left for the lane's segment
 
 // PROP: proposal-first order.  Phase 0 traverses the predicted frontier
@@ -302,7 +306,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
     const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const float scale = p.bounds[6];
     const int n_internal = (int)p.nt - 1;
-    const int64_t max_steps = 2 * p.nt + 8;
+    const int max_steps = 2 * (int)p.nt + 8;  // N_t < 2^30
+    const int depth_lim = p.stack_depth * stride;  // stack offsets are kept in units of lanes
 
     // One mesh: each wave owns a contiguous range of segments and its lanes
     // draw from it.  Batched form: waves take (mesh, segment range) items from
@@ -318,13 +323,13 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
 
     int64_t ray = -1;
     Ray r;
-    int ref = kDone, pend = -1, sp = 0;
+    int ref = kDone, pend = -1, sp = 0;  // sp: offset of the next free slot (a multiple of stride)
     float tlimit = 1.0f;
     int best_id = -1;
     float best_t = INFINITY, best_lo = INFINITY, best_hi = INFINITY, best_u = 0.0f, best_v = 0.0f;
     bool found = false, unsure = false, flagged = false, overflow = false;
     uint32_t n_nodes = 0, n_tests = 0;
-    int64_t steps = 0;
+    int steps = 0;
     int phase = 1, skip = kDone;  // kDone never equals a child reference
     bool best_late = false;       // best hit found in phase 1 (a proposal miss)
     uint32_t n_late = 0;          // this lane's proposal misses, summed per wave at exit
@@ -334,7 +339,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
     int nk = 0;
     bool list_full = false;
 
-    auto pop = [&]() -> int { return sp > 0 ? stk[--sp * stride] : kDone; };
+    auto pop = [&]() -> int { return sp > 0 ? stk[sp -= stride] : kDone; };
 
     for (;;) {
         // ---- refill idle lanes
@@ -426,7 +431,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                     ref = kDone;
                     pend = -1;
                 } else {
-                    const int top = stk[(sp > 0 ? sp - 1 : 0) * stride];
+                    const int top = stk[sp > 0 ? sp - stride : 0];
                     const Node *nd = p.nodes + ref;
                     const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
                     const int4 refs = nd->refs;
@@ -441,12 +446,12 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
                     }
                     const bool both = hl && hr, any = hl || hr;
                     const bool left_first = both ? tl <= tr : hl;
-                    stk[sp * stride] = left_first ? refs.y : refs.x;
+                    stk[sp] = left_first ? refs.y : refs.x;
                     const int next = left_first ? refs.x : refs.y;
-                    overflow = overflow || (both && sp >= p.stack_depth);
+                    overflow = overflow || (both && sp >= depth_lim);
                     ref = any ? next : (sp > 0 ? top : kDone);
-                    sp += both ? 1 : (!any && sp > 0 ? -1 : 0);
-                    if (both && sp > p.stack_depth) {
+                    sp += both ? stride : (!any && sp > 0 ? -stride : 0);
+                    if (both && sp > depth_lim) {
                         ref = kDone;  // overflow: the segment goes to the deep-stack pass
                         pend = -1;
                     }
@@ -1068,6 +1073,8 @@ void launch_pass1(const TravParams &p, int block, hipStream_t s) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, reinterpret_cast<const void *>(&k_traverse<MODE, CERT, STATS, PROP>), block, lds);
+    const int cap = p.waves_per_cu / (block / 64);  // resident blocks per CU asked for
+    per_cu = per_cu < cap ? per_cu : cap;
     if (per_cu < 1)
         per_cu = 1;
     const int64_t want = (p.n + block - 1) / block;
@@ -1114,6 +1121,7 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.n = a.n;
     p.out = Outs{a.hit, a.tri_id, a.uvt, a.count};
     p.stack_depth = a.stack;
+    p.waves_per_cu = a.waves_per_cu > 0 ? a.waves_per_cu : kDefaultWavesPerCU;
     p.queue = a.queue;
     p.queue_len = a.queue_len;
     p.next_ray = a.queue_len + 1;

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = rsi.lib()
-    assert L.rsi_abi_version() == 2
+    assert L.rsi_abi_version() == 3
     for code in range(7):
         assert L.rsi_status_string(code).decode().startswith("RSI_")
     assert b"unknown" in L.rsi_status_string(99)
@@ -74,6 +74,14 @@ def test_debug_certify_argument_errors_need_no_gpu():
     assert L.rsi_debug_certify(None, None, None, 0, None, None, None) == 0   # nothing to do
     assert L.rsi_debug_certify(None, None, None, 5, None, None, None) == 1   # NULL arrays
     assert b"non-NULL" in L.rsi_last_error()
+
+
+def test_derived_output_argument_errors_need_no_gpu():
+    L = rsi.lib()
+    assert L.rsi_derive(None, None, -1, None, None, None, None, None) == 1
+    assert L.rsi_derive(None, None, 4, None, None, None, None, None) == 1   # NULL inputs
+    assert L.rsi_compact_hits(None, None, -1, None, None, None, None, None, None, None, None) == 1
+    assert L.rsi_compact_hits(None, None, 4, None, None, None, None, None, None, None, None) == 1
 
 
 def test_valid_arguments_without_a_gpu_report_state_error():
