@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-host", action="store_true", help="skip the host-resident (PCIe-inclusive) runs")
     ap.add_argument("--train-rays", type=int, default=2_000_000)
     ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -296,6 +297,38 @@ def main():
             }
         print(f"[bench] learned: {learned}", file=sys.stderr, flush=True)
 
+    # ---------------- host-resident runs: host arrays in, host results out (PCIe included)
+    host = None
+    if not args.no_host:
+        pin = lambda a: torch.from_numpy(a).pin_memory()
+        hV, hF, hO, hE = pin(V), pin(F), pin(O), pin(E)
+        host = {"workload": "same mesh and segments, from pinned host memory to host results",
+                "paper_ms_same_shape_other_gpu": {"boolean": 355.094, "barycentric": 456.346,
+                                                  "intercept_count": 383.117}}
+        for hmode in ("boolean", "barycentric", "intercept_count"):
+            def job():
+                gV, gF = hV.to(dev, non_blocking=True), hF.to(dev, non_blocking=True)
+                gO, gE = hO.to(dev, non_blocking=True), hE.to(dev, non_blocking=True)
+                with rsi.rsi_build(gV, gF) as mesh:
+                    r = rsi.rsi_intersect(mesh, gO, gE, mode=hmode, precision=args.precision)
+                    if hmode == "barycentric":
+                        res = tuple(x.cpu() for x in rsi.rsi_compact_hits(gO, gE, r))
+                    else:
+                        res = r["hit" if hmode == "boolean" else "count"].cpu()
+                torch.cuda.synchronize()
+                return res
+            job()
+            t_h = []
+            for _ in range(3):
+                t0h = time.perf_counter()
+                res = job()
+                t_h.append((time.perf_counter() - t0h) * 1e3)
+            host[hmode + "_ms"] = round(min(t_h), 2)
+            if hmode == "barycentric":
+                host["barycentric_hits"] = int(res[0].shape[0])
+        print(f"[bench] host-resident: {host}", file=sys.stderr, flush=True)
+        del hV, hF, hO, hE
+
     # ---------------- batched form: 64 meshes, build + intersect replayed from a graph
     batched = None
     if not args.no_batched:
@@ -383,6 +416,7 @@ def main():
         "variants": variants,
         "learned_vs_plain": learned,
         "batched": batched,
+        "host_resident": host,
     }
     print(json.dumps(line), flush=True)
 

@@ -1,0 +1,158 @@
+"""BVH diagnostics: decode the exported tree and print it as a node listing or
+a Graphviz graph.
+
+Paper: Case Study 1 (the BVH debugging strategy: copy the node arrays from
+device memory, decode each node's fields, check connectivity) and its Test
+code and Graphviz subsection (a DOT description of the binary radix tree,
+internal nodes labelled with their leaf range [a,b], leaves drawn as boxes
+labelled "[c] d" with the sorted leaf position c and triangle id d).
+
+The exported layout differs from the paper's C struct: a node here holds both
+children's boxes and the leaf range it covers (include/rsi.h,
+RSI_EXPORT_NODES), numbered as in Karras 2012 (root = internal node 0).  The
+decoder works on host numpy arrays, so it also serves trees built elsewhere.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def decode(nodes, leaves, parents=None, counters=None):
+    """Decode exported arrays (int32 views, as copied from the device).
+
+    nodes: int32 [N_t - 1, 16]; leaves: int32 [N_t, 12]; parents: int32
+    [2 N_t - 1] or None; counters: int32 [N_t - 1] or None.  Returns a dict
+    of numpy arrays:
+      left, right      child reference (>= 0 internal node, < 0 leaf ~k)
+      left_box, right_box, box   float [N_t - 1, 6] (lo.xyz, hi.xyz); box is
+                       the union of the two children's boxes
+      first, last      leaf range of each internal node
+      leaf_box         float [N_t, 6]; leaf_tri int32 [N_t] (triangle index)
+      parent, counter  as exported (None if not given)
+    """
+    nodes = np.asarray(nodes, np.int32).reshape(-1, 16)
+    leaves = np.asarray(leaves, np.int32).reshape(-1, 12)
+    f = nodes.view(np.float32)
+    left_box = np.stack([f[:, 0], f[:, 2], f[:, 8], f[:, 1], f[:, 3], f[:, 9]], axis=1)
+    right_box = np.stack([f[:, 4], f[:, 6], f[:, 10], f[:, 5], f[:, 7], f[:, 11]], axis=1)
+    box = np.concatenate([np.minimum(left_box[:, :3], right_box[:, :3]),
+                          np.maximum(left_box[:, 3:], right_box[:, 3:])], axis=1)
+    # a leaf's box is the one its parent stores for it; a lone leaf (one
+    # triangle) has no parent, so its box is rebuilt from A and the edges
+    lf = leaves.view(np.float32)
+    A, e1, e2 = lf[:, 0:3], lf[:, 4:7], lf[:, 8:11]
+    corners = np.stack([A, A + e1, A + e2])
+    leaf_box = np.concatenate([corners.min(axis=0), corners.max(axis=0)], axis=1)
+    for side_ref, side_box in ((nodes[:, 12], left_box), (nodes[:, 13], right_box)):
+        is_leaf = side_ref < 0
+        leaf_box[~side_ref[is_leaf]] = side_box[is_leaf]
+    return {
+        "left": nodes[:, 12].copy(), "right": nodes[:, 13].copy(),
+        "left_box": left_box, "right_box": right_box, "box": box,
+        "first": nodes[:, 14].copy(), "last": nodes[:, 15].copy(),
+        "leaf_box": leaf_box, "leaf_tri": leaves[:, 3].copy(),
+        "parent": None if parents is None else np.asarray(parents, np.int32).copy(),
+        "counter": None if counters is None else np.asarray(counters, np.int32).copy(),
+    }
+
+
+def export(mesh) -> dict:
+    """Decode a built mesh (rsi_build) or batch (rsi_batch_*)."""
+    from . import Batch, rsi_batch_export, rsi_mesh_export
+
+    get = (lambda w: rsi_batch_export(mesh, w)) if isinstance(mesh, Batch) else (lambda w: rsi_mesh_export(mesh, w))
+    host = lambda w: get(w).cpu().numpy()
+    return decode(host("nodes"), host("leaves"), host("parents"), host("counters"))
+
+
+def _rng(b, k):
+    return f"[{b[k]:.6g},{b[k + 3]:.6g}]"
+
+
+def listing(tree: dict) -> str:
+    """Text listing of every internal and leaf node: box, parent, children
+    (leaf or internal), arrival counter and leaf range; leaves with their
+    triangle index (the fields the paper's Case Study 1 listing shows)."""
+    out = ["BVH tree structure", "---------------------------", "Internal nodes"]
+    n_int = tree["left"].shape[0]
+    par = tree["parent"]
+    for i in range(n_int):
+        b = tree["box"][i]
+        tag = "  ------ ROOT NODE" if i == 0 else ""
+        out.append(f"[{i}] x:{_rng(b, 0)}, y:{_rng(b, 1)}, z:{_rng(b, 2)}{tag}")
+        kind = lambda r: f"{~r}(leaf)" if r < 0 else f"{r}(internal)"
+        p = "" if par is None or i == 0 else f", parent: {par[i]}"
+        out.append(f"self: {i}{p}")
+        out.append(f"children: L {kind(tree['left'][i])}, R {kind(tree['right'][i])}")
+        cnt = "" if tree["counter"] is None else f"atomic: {tree['counter'][i]}, "
+        out.append(f"{cnt}range: {tree['first'][i]}..{tree['last'][i]}")
+        out.append("")
+    out += ["---------------------------", "Leaf nodes"]
+    n_leaf = tree["leaf_tri"].shape[0]
+    for k in range(n_leaf):
+        b = tree["leaf_box"][k]
+        out.append(f"[{k}] x:{_rng(b, 0)}, y:{_rng(b, 1)}, z:{_rng(b, 2)}")
+        if par is not None and n_leaf > 1:
+            out.append(f"parent: {par[n_int + k]}")
+        out.append(f"triangleID: {tree['leaf_tri'][k]}")
+        out.append("")
+    return "\n".join(out)
+
+
+def to_dot(tree: dict, name: str = "bvh") -> str:
+    """Graphviz DOT description of the binary radix tree: internal node i as
+    an ellipse labelled with its leaf range "[a,b]", leaf k as a box labelled
+    "[k] d" with d its triangle index, and an edge from every node to each
+    child."""
+    lines = [f"digraph {name} {{", "  node [fontname=\"Helvetica\"];"]
+    n_int = tree["left"].shape[0]
+    for i in range(n_int):
+        extra = ", style=bold" if i == 0 else ""
+        lines.append(f"  n{i} [label=\"[{tree['first'][i]},{tree['last'][i]}]\"{extra}];")
+    for k, d in enumerate(tree["leaf_tri"]):
+        lines.append(f"  l{k} [shape=box, label=\"[{k}] {d}\"];")
+    ref = lambda r: f"l{~r}" if r < 0 else f"n{r}"
+    for i in range(n_int):
+        lines.append(f"  n{i} -> {ref(tree['left'][i])};")
+        lines.append(f"  n{i} -> {ref(tree['right'][i])};")
+    lines.append("}")
+    return "\n".join(lines) + "\n"
+
+
+def check(tree: dict) -> list:
+    """Structural checks of a decoded tree (the connectivity the paper's
+    debugging looked for); returns a list of problems, empty when sound:
+    every leaf and non-root internal node has exactly one parent, child
+    ranges partition the parent's range, each box contains its children's
+    boxes, and counters (if present) read 2."""
+    problems = []
+    n_int = tree["left"].shape[0]
+    n_leaf = tree["leaf_tri"].shape[0]
+    if n_leaf <= 1:
+        return problems
+    seen = np.zeros(n_int + n_leaf, np.int32)
+    for i in range(n_int):
+        ranges = []
+        for side, r in (("left", tree["left"][i]), ("right", tree["right"][i])):
+            slot = n_int + ~r if r < 0 else r
+            if not (0 <= slot < n_int + n_leaf):
+                problems.append(f"node {i}: {side} child {r} out of range")
+                continue
+            seen[slot] += 1
+            lo, hi = (~r, ~r) if r < 0 else (tree["first"][r], tree["last"][r])
+            ranges.append((lo, hi))
+            cb = tree["leaf_box"][~r] if r < 0 else tree["box"][r]
+            pb = tree[side + "_box"][i]
+            if not (np.all(pb[:3] <= cb[:3]) and np.all(pb[3:] >= cb[3:])):
+                problems.append(f"node {i}: {side} box does not contain its child")
+        if len(ranges) == 2 and not (ranges[0][0] == tree["first"][i] and ranges[0][1] + 1 == ranges[1][0]
+                                     and ranges[1][1] == tree["last"][i]):
+            problems.append(f"node {i}: child ranges {ranges} do not split [{tree['first'][i]},{tree['last'][i]}]")
+    if seen[0] != 0:
+        problems.append("the root has a parent")
+    bad = np.nonzero(seen[1:] != 1)[0] + 1
+    if bad.size:
+        problems.append(f"{bad.size} nodes without exactly one parent")
+    if tree["counter"] is not None and np.any(tree["counter"] != 2):
+        problems.append(f"{int(np.sum(tree['counter'] != 2))} internal nodes not completed (counter != 2)")
+    return problems

@@ -141,3 +141,21 @@ def test_host_pointer_rejected():
     st = rsi.lib().rsi_build(V.ctypes.data_as(ctypes.c_void_p), 3, F.ctypes.data_as(ctypes.c_void_p), 1, None,
                              None, ctypes.byref(h))
     assert st == 1 and b"device pointer" in rsi.lib().rsi_last_error()
+
+
+def test_diagnostics_on_the_device_tree():
+    """The exported device tree decodes into the paper's Case Study 1 graph
+    (root [0,3]; [0,1] and [2,3]; leaves [0] 0, [1] 3, [2] 1, [3] 2) and a
+    large tree passes the structural checks."""
+    from paper_2305_01867_amd import diagnostics
+    V, F, _, _ = workloads.appendix_scene()
+    with rsi.rsi_build(dev(V), dev(F)) as mesh:
+        tree = diagnostics.export(mesh)
+    assert diagnostics.check(tree) == []
+    dot = diagnostics.to_dot(tree)
+    leaves = sorted(l.split('label="')[1].split('"')[0] for l in dot.splitlines() if "shape=box" in l)
+    assert leaves == ["[0] 0", "[1] 3", "[2] 1", "[3] 2"]
+    assert 'n0 [label="[0,3]", style=bold];' in dot
+    V, F = workloads.heightfield(128, 21)
+    with rsi.rsi_build(dev(V), dev(F)) as mesh:
+        assert diagnostics.check(diagnostics.export(mesh)) == []
