@@ -248,6 +248,13 @@ def main():
             b1.record(stream)
             torch.cuda.synchronize()
             variants["build_ms"] = round(b0.elapsed_time(b1) / 5, 4)
+            rsi.rsi_build(dV, dF, algorithm="agglomerative").close()
+            torch.cuda.synchronize()
+            t_a = time.perf_counter()
+            for _ in range(5):
+                rsi.rsi_build(dV, dF, algorithm="agglomerative").close()  # waits once per build for the root
+            torch.cuda.synchronize()
+            variants["build_ms_agglomerative"] = round((time.perf_counter() - t_a) * 1e3 / 5, 4)
 
     # ---------------- learned proposal vs plain order (BVH resident, untimed region)
     learned = None

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define RSI_ABI_VERSION 3  /* 2: intercept-count mode, rsi_outputs.count; 3: waves_per_cu */
+#define RSI_ABI_VERSION 4  /* 2: intercept-count mode, rsi_outputs.count; 3: waves_per_cu; 4: build algorithm */
 
 typedef struct rsi_mesh_s *rsi_mesh; /* opaque; owned by the library until rsi_destroy */
 
@@ -102,6 +102,13 @@ typedef struct rsi_build_opts {
     int32_t check_indices; /* nonzero: wait for the build and return RSI_E_RANGE if any
                               index is outside [0, N_v).  Without it such triangles are
                               never hit and the build does not wait. */
+    int32_t algorithm;     /* 0 (default): radix tree of Karras 2012 (internal node i at
+                              one end of its leaf range, root 0), then bottom-up boxes
+                              in LDS tiles.  1: agglomerative single pass (Apetrei 2014,
+                              as in the paper's Case Study 1 dump): the same tree with
+                              internal nodes numbered by their split position; the
+                              build waits once to learn the root's index.  Results of
+                              rsi_intersect do not depend on it. */
 } rsi_build_opts;
 
 /* Intersection options; pass NULL for defaults. */

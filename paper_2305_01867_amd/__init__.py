@@ -30,7 +30,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "librsi.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MODES = {"boolean": 0, "first_hit": 1, "barycentric": 2, "intercept_count": 3}
 PRECISIONS = {"plain": 0, "certified": 1}
 EXPORTS = {"sorted_keys": 0, "sorted_ids": 1, "nodes": 2, "parents": 3, "counters": 4, "leaves": 5, "bounds": 6}
@@ -45,7 +45,7 @@ class RSIError(RuntimeError):
 
 
 class _BuildOpts(ctypes.Structure):
-    _fields_ = [("morton_bits", ctypes.c_int32), ("check_indices", ctypes.c_int32)]
+    _fields_ = [("morton_bits", ctypes.c_int32), ("check_indices", ctypes.c_int32), ("algorithm", ctypes.c_int32)]
 
 
 class _IntersectOpts(ctypes.Structure):
@@ -189,15 +189,22 @@ class Mesh:
         self.close()
 
 
+BUILD_ALGORITHMS = {"radix_tree": 0, "agglomerative": 1}
+
+
 def rsi_build(vertices: torch.Tensor, triangles: torch.Tensor, morton_bits: int = 30,
-              check_indices: bool = False, stream=None) -> Mesh:
-    """Build the BVH of a mesh: vertices float32 [N_v, 3], triangles int32 [N_t, 3]."""
+              check_indices: bool = False, stream=None, algorithm: str = "radix_tree") -> Mesh:
+    """Build the BVH of a mesh: vertices float32 [N_v, 3], triangles int32 [N_t, 3].
+    algorithm: "radix_tree" (default) or "agglomerative" (single pass, nodes
+    numbered by split position; waits once for the root)."""
+    if algorithm not in BUILD_ALGORITHMS:
+        raise ValueError(f"algorithm must be one of {list(BUILD_ALGORITHMS)}")
     for t, name, dt in ((vertices, "vertices", torch.float32), (triangles, "triangles", torch.int32)):
         if isinstance(t, torch.Tensor) and t.dtype != dt:
             raise TypeError(f"{name} must be {dt}, got {t.dtype}")
     _need(vertices, "vertices", torch.float32, 3)
     _need(triangles, "triangles", torch.int32, 3)
-    opts = _BuildOpts(int(morton_bits), int(bool(check_indices)))
+    opts = _BuildOpts(int(morton_bits), int(bool(check_indices)), BUILD_ALGORITHMS[algorithm])
     h = ctypes.c_void_p()
     s = _stream_handle(stream)
     _check(lib().rsi_build(ctypes.c_void_p(vertices.data_ptr()), vertices.shape[0],

@@ -6,7 +6,8 @@ in a JSON file keyed by a size class (mode, precision, number of meshes,
 log2 of triangles and of segments), so later runs of the same class reuse it
 without timing.  The default grid covers threads per workgroup, the LDS
 stack depth (occupancy against how often a segment overflows to the
-deep-stack pass) and the segment processing order; MORTON_BITS can be added
+deep-stack pass), the resident waves per CU (fewer waves share a CU's L1
+among fewer tree paths) and the segment processing order; MORTON_BITS can be added
 for a `run` that rebuilds the tree (30-bit against 63-bit keys).
 """
 from __future__ import annotations
@@ -21,8 +22,9 @@ import torch
 BLOCKS = (64, 128, 256)
 STACKS = (8, 12, 16, 20, 24, 32)
 RAY_SORTS = (0, 1, 2)  # input order, midpoint Morton, octant + start Morton
+WAVES_PER_CU = (0, 8, 12, 16, 24)  # 0: as many as registers and LDS allow
 MORTON_BITS = (30, 63)
-SPACE = {"block": BLOCKS, "stack_depth": STACKS, "ray_sort": RAY_SORTS}
+SPACE = {"block": BLOCKS, "stack_depth": STACKS, "ray_sort": RAY_SORTS, "waves_per_cu": WAVES_PER_CU}
 
 
 def size_class(mode: str, precision: str, n_meshes: int, n_triangles: int, n_rays: int) -> str:

@@ -197,13 +197,16 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *t
         return fail(RSI_E_ARG, "vertices must not be NULL");
     if ((vertices && !aligned4(vertices)) || (triangles && !aligned4(triangles)))
         return fail(RSI_E_ARG, "vertices / triangles must be 4-byte aligned");
-    int bits = 30, check = 0;
+    int bits = 30, check = 0, algorithm = 0;
     if (opts) {
         if (opts->morton_bits != 0 && opts->morton_bits != 30 && opts->morton_bits != 63)
             return fail(RSI_E_ARG, "morton_bits must be 30 or 63");
         if (opts->morton_bits)
             bits = opts->morton_bits;
         check = opts->check_indices != 0;
+        if (opts->algorithm != 0 && opts->algorithm != 1)
+            return fail(RSI_E_ARG, "algorithm must be 0 (radix tree) or 1 (agglomerative)");
+        algorithm = opts->algorithm;
     }
     rsi_status st = check_device();
     if (st != RSI_OK)
@@ -226,6 +229,7 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *t
     d.nv = n_vertices;
     d.nt = n_triangles;
     d.morton_bits = bits;
+    d.algorithm = algorithm;
     const int64_t nt = n_triangles;
     if (nt == 0) {
         d.root = INT32_MIN;
@@ -279,6 +283,21 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *t
     if (e != hipSuccess) {
         rsi_destroy(m);
         return fail_hip(e, "rsi_build launch");
+    }
+    if (algorithm == 1 && nt >= 2) {
+        int32_t root = 0;
+        e = hipMemcpyAsync(&root, d.flags + 1, sizeof(root), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            rsi_destroy(m);
+            return fail_hip(e, "rsi_build (agglomerative root)");
+        }
+        if (root < 0 || root >= nt - 1) {
+            rsi_destroy(m);
+            return fail(RSI_E_HIP, "the agglomerative build did not reach a root");
+        }
+        d.root = root;
     }
     if (check) {
         int32_t flag = 0;

@@ -429,6 +429,41 @@ __global__ void k_single_tile(int32_t *tiles, int32_t *n_tiles) {
 // Cross-XCD agent-scope atomics, which cost an L2 write-back each on gfx950,
 // are not needed.  Every child box lands in its parent node in HBM; a
 // finished internal node's counter reads 2.
+// Leaf k (sorted position): write its triangle (A, B - A, C - A, input index)
+// and return its box.  An invalid triangle is never hit and widens no box.
+__device__ __forceinline__ void make_leaf(const float *__restrict__ V, int64_t nv, const int32_t *__restrict__ F,
+                                          const int32_t *__restrict__ ids, int n, int k, Tri *__restrict__ tris,
+                                          float *lo, float *hi) {
+    int t = ids[k];
+    const bool t_ok = t >= 0 && t < n;  // always true for a correct sort; guards the loads below
+    if (!t_ok)
+        t = 0;
+    const int32_t i0 = F[3 * (int64_t)t], i1 = F[3 * (int64_t)t + 1], i2 = F[3 * (int64_t)t + 2];
+    Tri tri;
+    if (!t_ok || i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
+        tri.a = make_float4(NAN, NAN, NAN, __int_as_float(t));
+        tri.e1 = make_float4(NAN, NAN, NAN, 0.0f);
+        tri.e2 = make_float4(NAN, NAN, NAN, 0.0f);
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = INFINITY;
+            hi[d] = -INFINITY;
+        }
+    } else {
+        float A[3], B[3], C[3];
+        for (int d = 0; d < 3; ++d) {
+            A[d] = V[3 * (int64_t)i0 + d];
+            B[d] = V[3 * (int64_t)i1 + d];
+            C[d] = V[3 * (int64_t)i2 + d];
+            lo[d] = fminf(A[d], fminf(B[d], C[d]));
+            hi[d] = fmaxf(A[d], fmaxf(B[d], C[d]));
+        }
+        tri.a = make_float4(A[0], A[1], A[2], __int_as_float(t));
+        tri.e1 = make_float4(B[0] - A[0], B[1] - A[1], B[2] - A[2], 0.0f);
+        tri.e2 = make_float4(C[0] - A[0], C[1] - A[1], C[2] - A[2], 0.0f);
+    }
+    tris[k] = tri;
+}
+
 __device__ __forceinline__ void store_child_box(Node *node, bool is_left, const float *lo, const float *hi) {
     if (is_left) {
         node->xy_left = make_float4(lo[0], hi[0], lo[1], hi[1]);
@@ -468,36 +503,8 @@ __global__ __launch_bounds__(kBoxTile) void k_leaves_subtree(const float *__rest
         __syncthreads();
         const int k = a + (int)threadIdx.x;
         if (a >= 0 && k <= b && b < n && b - a < kBoxTile) {
-            int t = ids[k];
-            const bool t_ok = t >= 0 && t < n;  // always true for a correct sort; guards the loads below
-            if (!t_ok)
-                t = 0;
-            const int32_t i0 = F[3 * (int64_t)t], i1 = F[3 * (int64_t)t + 1], i2 = F[3 * (int64_t)t + 2];
             float lo[3], hi[3];
-            Tri tri;
-            if (!t_ok || i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
-                // an invalid triangle is never hit and does not widen any box
-                tri.a = make_float4(NAN, NAN, NAN, __int_as_float(t));
-                tri.e1 = make_float4(NAN, NAN, NAN, 0.0f);
-                tri.e2 = make_float4(NAN, NAN, NAN, 0.0f);
-                for (int d = 0; d < 3; ++d) {
-                    lo[d] = INFINITY;
-                    hi[d] = -INFINITY;
-                }
-            } else {
-                float A[3], B[3], C[3];
-                for (int d = 0; d < 3; ++d) {
-                    A[d] = V[3 * (int64_t)i0 + d];
-                    B[d] = V[3 * (int64_t)i1 + d];
-                    C[d] = V[3 * (int64_t)i2 + d];
-                    lo[d] = fminf(A[d], fminf(B[d], C[d]));
-                    hi[d] = fmaxf(A[d], fmaxf(B[d], C[d]));
-                }
-                tri.a = make_float4(A[0], A[1], A[2], __int_as_float(t));
-                tri.e1 = make_float4(B[0] - A[0], B[1] - A[1], B[2] - A[2], 0.0f);
-                tri.e2 = make_float4(C[0] - A[0], C[1] - A[1], C[2] - A[2], 0.0f);
-            }
-            tris[k] = tri;
+            make_leaf(V, nv, F, ids, n, k, tris, lo, hi);
             int self = ~k;
             int p = n >= 2 ? parent[(n - 1) + k] : -1;
             if (self == c) {
@@ -567,6 +574,77 @@ __global__ __launch_bounds__(1024) void k_boxes_top(Node *nodes, const int32_t *
     }
 }
 
+// ------------------------------------------ 5'. agglomerative single pass
+// The same binary radix tree, built bottom-up in one pass (Apetrei 2014,
+// "Fast and simple agglomerative LBVH construction"; the numbering the paper's
+// Case Study 1 dump shows): a lane per leaf climbs; a node covering [l, r]
+// joins the neighbour across the boundary with the longer common prefix, so
+// its parent is internal node r (it is the left child) or l - 1 (the right
+// child) -- internal nodes are numbered by their split position.  The first
+// child to reach a parent leaves its far bound in other[p] and stops; the
+// second learns the parent's range from the exchange, merges the boxes and
+// climbs on.  Every step is a cross-workgroup exchange at agent scope.
+template <typename K>
+__global__ __launch_bounds__(256) void k_agglomerate(const K *__restrict__ keys, const float *__restrict__ V,
+                                                     int64_t nv, const int32_t *__restrict__ F,
+                                                     const int32_t *__restrict__ ids, int n, Tri *__restrict__ tris,
+                                                     Node *nodes, int32_t *__restrict__ parent, int32_t *counters,
+                                                     int32_t *other, int32_t *__restrict__ root_out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n)
+        return;
+    float lo[3], hi[3];
+    make_leaf(V, nv, F, ids, n, k, tris, lo, hi);
+    if (n < 2) {
+        *root_out = ~0;
+        return;
+    }
+    auto delta = [&](int i) { return prefix(keys, n, i, keys[i], i + 1); };  // boundary between i and i + 1
+    int l = k, r = k, self = ~k;
+    for (int level = 0; level < kDeepStack; ++level) {
+        const bool left_child = l == 0 || (r != n - 1 && delta(r) > delta(l - 1));
+        const int p = left_child ? r : l - 1;
+        Node *node = nodes + p;
+        store_child_box(node, left_child, lo, hi);
+        if (left_child)
+            node->refs.x = self;
+        else
+            node->refs.y = self;
+        parent[self >= 0 ? self : (n - 1) + ~self] = p;
+        const int prev = __hip_atomic_exchange(other + p, left_child ? l : r, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        if (prev < 0)
+            return;  // the sibling is not finished; its lane continues
+        const int pl = left_child ? l : prev, pr = left_child ? prev : r;
+        const float4 xy = left_child ? node->xy_right : node->xy_left;
+        const float2 z = left_child ? *reinterpret_cast<const float2 *>(&node->z_both.z)
+                                    : *reinterpret_cast<const float2 *>(&node->z_both.x);
+        lo[0] = fminf(lo[0], xy.x);
+        hi[0] = fmaxf(hi[0], xy.y);
+        lo[1] = fminf(lo[1], xy.z);
+        hi[1] = fmaxf(hi[1], xy.w);
+        lo[2] = fminf(lo[2], z.x);
+        hi[2] = fmaxf(hi[2], z.y);
+        node->refs.z = pl;
+        node->refs.w = pr;
+        counters[p] = 2;
+        l = pl;
+        r = pr;
+        self = p;
+        if (l == 0 && r == n - 1) {
+            parent[p] = -1;
+            *root_out = p;
+            return;
+        }
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
 __global__ void k_zero_i32(int32_t *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
@@ -609,6 +687,17 @@ hipError_t build_from_keys(MeshDev &m, int key_bits, hipStream_t s) {
     const int64_t nt = m.nt;
     K *keys = static_cast<K *>(m.keys);
     sort_passes<K>(keys, m.ids, m.sort_tmp, nt, key_bits, s);  // 4 or 8 passes: back in (keys, ids)
+    if (m.algorithm == 1) {
+        // the sort's scratch is free again: the exchange slots
+        int32_t *other = static_cast<int32_t *>(m.sort_tmp);
+        if (nt >= 2) {
+            k_fill_i32<<<blocks_for(nt - 1, 256), 256, 0, s>>>(other, nt - 1, -1);
+            k_zero_i32<<<blocks_for(nt - 1, 256), 256, 0, s>>>(m.counters, (int)(nt - 1));
+        }
+        k_agglomerate<K><<<blocks_for(nt, 256), 256, 0, s>>>(keys, m.V, m.nv, m.F, m.ids, (int)nt, m.tris, m.nodes,
+                                                            m.parent, m.counters, other, m.flags + 1);
+        return hipGetLastError();
+    }
     // the sort's scratch is free again: the list of bottom-up tiles
     int32_t *n_tiles = static_cast<int32_t *>(m.sort_tmp);
     int32_t *tiles = n_tiles + 64;

@@ -61,6 +61,7 @@ struct Proposal {
 struct MeshDev {
     int64_t nv = 0, nt = 0;
     int morton_bits = 30;
+    int algorithm = 0;         // 0 radix tree + tiled bottom-up, 1 agglomerative single pass
     int root = 0;
     float *V = nullptr;        // [nv][3] copy of the vertices
     int32_t *F = nullptr;      // [nt][3] copy of the triangles
@@ -71,7 +72,7 @@ struct MeshDev {
     int32_t *counters = nullptr; // [nt-1]
     Tri *tris = nullptr;       // [nt]
     float *bounds = nullptr;   // [8]
-    int32_t *flags = nullptr;  // [4]: [0] bad-index flag
+    int32_t *flags = nullptr;  // [4]: [0] bad-index flag, [1] root of the agglomerative build
     void *sort_tmp = nullptr;  // key/id ping-pong + histograms
     int64_t bytes = 0;
     Proposal prop;

@@ -291,7 +291,7 @@ __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why)
 constexpr int kRefillMin = 8;     // refill when at least this many lanes idle
 // Resident waves per CU of the persistent traversal unless asked otherwise:
 // fewer waves than registers allow share the CU's L1 among fewer tree paths.
-constexpr int kDefaultWavesPerCU = 32;
+constexpr int kDefaultWavesPerCU = 16;
 constexpr int kDone = INT32_MIN;  // nothing left for the lane's segment
 
 // PROP: proposal-first order.  Phase 0 traverses the predicted frontier

@@ -29,6 +29,9 @@ def decode(nodes, leaves, parents=None, counters=None):
       first, last      leaf range of each internal node
       leaf_box         float [N_t, 6]; leaf_tri int32 [N_t] (triangle index)
       parent, counter  as exported (None if not given)
+      root             index of the internal node no other node points to
+                       (0 in the radix-tree numbering, the split position of
+                       the whole range in the agglomerative one), -1 if none
     """
     nodes = np.asarray(nodes, np.int32).reshape(-1, 16)
     leaves = np.asarray(leaves, np.int32).reshape(-1, 12)
@@ -46,7 +49,13 @@ def decode(nodes, leaves, parents=None, counters=None):
     for side_ref, side_box in ((nodes[:, 12], left_box), (nodes[:, 13], right_box)):
         is_leaf = side_ref < 0
         leaf_box[~side_ref[is_leaf]] = side_box[is_leaf]
+    child = np.zeros(nodes.shape[0], bool)
+    for side_ref in (nodes[:, 12], nodes[:, 13]):
+        inner = side_ref[(side_ref >= 0) & (side_ref < nodes.shape[0])]
+        child[inner] = True
+    roots = np.nonzero(~child)[0]
     return {
+        "root": int(roots[0]) if roots.size == 1 else -1,
         "left": nodes[:, 12].copy(), "right": nodes[:, 13].copy(),
         "left_box": left_box, "right_box": right_box, "box": box,
         "first": nodes[:, 14].copy(), "last": nodes[:, 15].copy(),
@@ -78,10 +87,10 @@ def listing(tree: dict) -> str:
     par = tree["parent"]
     for i in range(n_int):
         b = tree["box"][i]
-        tag = "  ------ ROOT NODE" if i == 0 else ""
+        tag = "  ------ ROOT NODE" if i == tree["root"] else ""
         out.append(f"[{i}] x:{_rng(b, 0)}, y:{_rng(b, 1)}, z:{_rng(b, 2)}{tag}")
         kind = lambda r: f"{~r}(leaf)" if r < 0 else f"{r}(internal)"
-        p = "" if par is None or i == 0 else f", parent: {par[i]}"
+        p = "" if par is None or i == tree["root"] else f", parent: {par[i]}"
         out.append(f"self: {i}{p}")
         out.append(f"children: L {kind(tree['left'][i])}, R {kind(tree['right'][i])}")
         cnt = "" if tree["counter"] is None else f"atomic: {tree['counter'][i]}, "
@@ -107,7 +116,7 @@ def to_dot(tree: dict, name: str = "bvh") -> str:
     lines = [f"digraph {name} {{", "  node [fontname=\"Helvetica\"];"]
     n_int = tree["left"].shape[0]
     for i in range(n_int):
-        extra = ", style=bold" if i == 0 else ""
+        extra = ", style=bold" if i == tree["root"] else ""
         lines.append(f"  n{i} [label=\"[{tree['first'][i]},{tree['last'][i]}]\"{extra}];")
     for k, d in enumerate(tree["leaf_tri"]):
         lines.append(f"  l{k} [shape=box, label=\"[{k}] {d}\"];")
@@ -148,9 +157,12 @@ def check(tree: dict) -> list:
         if len(ranges) == 2 and not (ranges[0][0] == tree["first"][i] and ranges[0][1] + 1 == ranges[1][0]
                                      and ranges[1][1] == tree["last"][i]):
             problems.append(f"node {i}: child ranges {ranges} do not split [{tree['first'][i]},{tree['last'][i]}]")
-    if seen[0] != 0:
-        problems.append("the root has a parent")
-    bad = np.nonzero(seen[1:] != 1)[0] + 1
+    root = tree["root"]
+    if root < 0:
+        problems.append("no single root")
+    elif seen[root] != 0 or (tree["first"][root], tree["last"][root]) != (0, n_leaf - 1):
+        problems.append("the root has a parent or does not cover every leaf")
+    bad = np.array([j for j in np.nonzero(seen != 1)[0] if j != root])
     if bad.size:
         problems.append(f"{bad.size} nodes without exactly one parent")
     if tree["counter"] is not None and np.any(tree["counter"] != 2):

@@ -164,15 +164,15 @@ def test_autotuner_picks_and_caches():
         key = autotune.size_class("boolean", "certified", len(parts), F.shape[0], O.shape[0])
         want = host(rsi.rsi_batch_intersect(b, dO, dE, mode="boolean", precision="certified")["hit"])
 
-        def run(block, stack_depth, ray_sort):
-            got = rsi.rsi_batch_intersect(b, dO, dE, mode="boolean", precision="certified", block=block,
-                                          stack_depth=stack_depth, ray_sort=ray_sort)
-            assert np.array_equal(host(got["hit"]), want), (block, stack_depth, ray_sort)
+        def run(**choice):
+            got = rsi.rsi_batch_intersect(b, dO, dE, mode="boolean", precision="certified", **choice)
+            assert np.array_equal(host(got["hit"]), want), choice
 
         best, timings = autotune.tune(run, key, path, reps=1)
         assert best["block"] in autotune.BLOCKS and best["stack_depth"] in autotune.STACKS
-        assert best["ray_sort"] in autotune.RAY_SORTS
-        assert len(timings) == len(autotune.BLOCKS) * len(autotune.STACKS) * len(autotune.RAY_SORTS)
+        assert best["ray_sort"] in autotune.RAY_SORTS and best["waves_per_cu"] in autotune.WAVES_PER_CU
+        assert len(timings) == (len(autotune.BLOCKS) * len(autotune.STACKS) * len(autotune.RAY_SORTS)
+                                * len(autotune.WAVES_PER_CU))
         assert json.load(open(path))[key] == best
         again, t2 = autotune.tune(run, key, path)
         assert again == best and t2 is None

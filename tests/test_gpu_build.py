@@ -159,3 +159,37 @@ def test_diagnostics_on_the_device_tree():
     V, F = workloads.heightfield(128, 21)
     with rsi.rsi_build(dev(V), dev(F)) as mesh:
         assert diagnostics.check(diagnostics.export(mesh)) == []
+
+
+def canonical(words, n):
+    """{(first, last): (left range, right range)} of a tree in the export layout."""
+    rng = lambda r: (~r, ~r) if r < 0 else (int(words[r, 14]), int(words[r, 15]))
+    return {(int(w[14]), int(w[15])): (rng(int(w[12])), rng(int(w[13]))) for w in words}
+
+
+@pytest.mark.parametrize("case", ["scene", "heightfield", "duplicates"])
+def test_agglomerative_build_is_the_same_tree(case):
+    """The single-pass agglomerative build gives the radix tree's topology and
+    boxes, numbered by split position: the paper's Case Study 1 dump has its
+    root at internal index 1."""
+    from paper_2305_01867_amd import diagnostics
+    if case == "scene":
+        V, F, _, _ = workloads.appendix_scene()
+    elif case == "heightfield":
+        V, F = workloads.heightfield(100, 4)
+    else:
+        V, F = triangle_soup(5000, 3, n_vert=300, clustered=True)
+    for bits in (30, 63):
+        with rsi.rsi_build(dev(V), dev(F), morton_bits=bits) as a, \
+                rsi.rsi_build(dev(V), dev(F), morton_bits=bits, algorithm="agglomerative") as b:
+            wa, wb = export(a, "nodes"), export(b, "nodes")
+            assert canonical(wa, F.shape[0]) == canonical(wb, F.shape[0])
+            ta, tb = diagnostics.export(a), diagnostics.export(b)
+            assert diagnostics.check(tb) == []
+            ka = {(f, l): tuple(bx) for f, l, bx in zip(ta["first"], ta["last"], ta["box"])}
+            kb = {(f, l): tuple(bx) for f, l, bx in zip(tb["first"], tb["last"], tb["box"])}
+            assert ka == kb
+            assert np.array_equal(export(a, "leaves"), export(b, "leaves"))
+            assert rsi.rsi_mesh_info_get(b)["root"] == tb["root"]
+            if case == "scene":
+                assert tb["root"] == 1 and "[1] x:[12,13], y:[2,3], z:[1,1.3]  ------ ROOT NODE" in diagnostics.listing(tb)

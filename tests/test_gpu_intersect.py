@@ -38,8 +38,9 @@ def expect_exact(got, want_hit, want_id, want_uvt, mode):
 def check_all_modes(V, F, O, E, label, plain_budget=None, **kw):
     say(f"[intersect] {label}: {F.shape[0]} triangles, {O.shape[0]} segments")
     hit, ids, uvt, _ = oracle.intersect(V, F, O, E)
-    with rsi.rsi_build(dev(V), dev(F), **{k: v for k, v in kw.items() if k == "morton_bits"}) as mesh:
-        ikw = {k: v for k, v in kw.items() if k != "morton_bits"}
+    bkeys = ("morton_bits", "algorithm")
+    with rsi.rsi_build(dev(V), dev(F), **{k: v for k, v in kw.items() if k in bkeys}) as mesh:
+        ikw = {k: v for k, v in kw.items() if k not in bkeys}
         for mode in MODES:
             say(f"  mode={mode} certified")
             got = intersect(mesh, O, E, mode, "certified", **ikw)
@@ -74,6 +75,7 @@ def test_case_study_1_scene(golden_case_study_1):
 def test_tiny_heightfield_config():
     V, F, O, E = workloads.tiny_config()
     check_all_modes(V, F, O, E, "64x64 heightfield, 1e4 crossing-mix segments", plain_budget=20)
+    check_all_modes(V, F, O, E, "same, agglomerative build", algorithm="agglomerative")
     check_all_modes(V, F, O, E, "same, 63-bit keys, stack 8, block 64", morton_bits=63, stack_depth=8, block=64)
 
 
