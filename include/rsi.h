@@ -107,8 +107,14 @@ typedef struct rsi_build_opts {
                               in LDS tiles.  1: agglomerative single pass (Apetrei 2014,
                               as in the paper's Case Study 1 dump): the same tree with
                               internal nodes numbered by their split position; the
-                              build waits once to learn the root's index.  Results of
-                              rsi_intersect do not depend on it. */
+                              build waits once to learn the root's index.  2: the radix
+                              tree, then three passes of treelet restructuring (Karras
+                              & Aila 2013): internal nodes rewired to lower the tree's
+                              surface-area cost, so queries visit fewer nodes; a node's
+                              leaves are then no longer a contiguous range (words 14 /
+                              15 of RSI_EXPORT_NODES hold their smallest and largest
+                              sorted position).  Results of rsi_intersect do not
+                              depend on it. */
 } rsi_build_opts;
 
 /* Intersection options; pass NULL for defaults. */
@@ -217,7 +223,8 @@ typedef enum rsi_export_what {
                                    words 8-11 left z lo, z hi, right z lo, z hi
                                    word 12, 13 left / right child: >= 0 internal node,
                                    < 0 leaf at sorted position ~ref; words 14, 15 the
-                                   first and last sorted leaf the node covers            */
+                                   first and last sorted leaf the node covers (smallest
+                                   and largest, after treelet restructuring)              */
     RSI_EXPORT_PARENTS = 3,     /* int32 [2 N_t - 1]: parent of internal node i at [i]
                                    (-1 for the root), of leaf k at [N_t - 1 + k]        */
     RSI_EXPORT_COUNTERS = 4,    /* int32 [N_t - 1]: arrivals counted at each internal

@@ -189,14 +189,15 @@ class Mesh:
         self.close()
 
 
-BUILD_ALGORITHMS = {"radix_tree": 0, "agglomerative": 1}
+BUILD_ALGORITHMS = {"radix_tree": 0, "agglomerative": 1, "restructured": 2}
 
 
 def rsi_build(vertices: torch.Tensor, triangles: torch.Tensor, morton_bits: int = 30,
               check_indices: bool = False, stream=None, algorithm: str = "radix_tree") -> Mesh:
     """Build the BVH of a mesh: vertices float32 [N_v, 3], triangles int32 [N_t, 3].
-    algorithm: "radix_tree" (default) or "agglomerative" (single pass, nodes
-    numbered by split position; waits once for the root)."""
+    algorithm: "radix_tree" (default), "agglomerative" (single pass, nodes
+    numbered by split position; waits once for the root) or "restructured"
+    (radix tree + treelet restructuring: fewer node visits per query)."""
     if algorithm not in BUILD_ALGORITHMS:
         raise ValueError(f"algorithm must be one of {list(BUILD_ALGORITHMS)}")
     for t, name, dt in ((vertices, "vertices", torch.float32), (triangles, "triangles", torch.int32)):

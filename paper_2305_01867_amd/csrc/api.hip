@@ -204,8 +204,8 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *t
         if (opts->morton_bits)
             bits = opts->morton_bits;
         check = opts->check_indices != 0;
-        if (opts->algorithm != 0 && opts->algorithm != 1)
-            return fail(RSI_E_ARG, "algorithm must be 0 (radix tree) or 1 (agglomerative)");
+        if (opts->algorithm < 0 || opts->algorithm > 2)
+            return fail(RSI_E_ARG, "algorithm must be 0 (radix tree), 1 (agglomerative) or 2 (restructured)");
         algorithm = opts->algorithm;
     }
     rsi_status st = check_device();
@@ -904,8 +904,8 @@ static rsi_status ensure_proposal(rsi_mesh mesh, hipStream_t s, uint64_t seed, b
         const size_t f = round_up(4 * (size_t)rsi::kMlpParams);
         const size_t wb = round_up(2 * (size_t)rsi::kMlpWeights);
         const size_t small = round_up(4 * 256) * 2 + 256;
-        const size_t rk = round_up(4 * (size_t)d.nt);
-        hipError_t e = hipMallocAsync(&pr.block, 4 * f + wb + small + rk, s);
+        const size_t rk = round_up(4 * (size_t)d.nt), lbk = round_up((size_t)d.nt);
+        hipError_t e = hipMallocAsync(&pr.block, 4 * f + wb + small + rk + lbk, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             pr.block = nullptr;
@@ -920,7 +920,8 @@ static rsi_status ensure_proposal(rsi_mesh mesh, hipStream_t s, uint64_t seed, b
         pr.bucket_ref = reinterpret_cast<int32_t *>(p); p += round_up(4 * 256);
         pr.bucket_first = reinterpret_cast<int32_t *>(p); p += round_up(4 * 256);
         pr.dev_n_buckets = reinterpret_cast<int32_t *>(p); p += 256;
-        pr.rank = reinterpret_cast<int32_t *>(p);
+        pr.rank = reinterpret_cast<int32_t *>(p); p += rk;
+        pr.leaf_bucket = reinterpret_cast<uint8_t *>(p);
         e = rsi::proposal_frontier(d, pr, s);
         int32_t nb = 0;
         if (e == hipSuccess)

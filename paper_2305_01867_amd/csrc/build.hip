@@ -23,6 +23,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;  // 2048 keys per tile
 constexpr int kRadix = 256;
 constexpr int kBoxTile = 1024;  // leaves per bottom-up workgroup (one per lane)
 constexpr int kNoTile = INT32_MIN;  // never a child reference (leaves are ~k with k < 2^30)
+constexpr int kRestructureRounds = 3;  // treelet restructuring passes of algorithm 2
 
 // ---------------------------------------------------------------- 1. extent
 __global__ __launch_bounds__(1024) void k_mesh_bounds(const float *__restrict__ V, int64_t nv,
@@ -762,9 +763,10 @@ hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s) { return b
 hipError_t launch_build(MeshDev &m, const float *, const int32_t *, hipStream_t s, size_t) {
     k_zero_i32<<<1, 64, 0, s>>>(m.flags, 4);
     k_mesh_bounds<<<1, 1024, 0, s>>>(m.V, m.nv, m.bounds);
-    if (m.morton_bits > 32)
-        return build_typed<uint64_t>(m, s);
-    return build_typed<uint32_t>(m, s);
+    hipError_t e = m.morton_bits > 32 ? build_typed<uint64_t>(m, s) : build_typed<uint32_t>(m, s);
+    if (e == hipSuccess && m.algorithm == 2)
+        e = launch_restructure(m, kRestructureRounds, s);
+    return e;
 }
 
 }  // namespace rsi

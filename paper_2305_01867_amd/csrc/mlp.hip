@@ -441,8 +441,9 @@ constexpr size_t kProposeLds = 2 * (size_t)kPRows * kPPitch * sizeof(__bf16) + 8
 // Left-to-right frontier of the tree at depth 8: internal nodes at depth 8
 // and leaves shallower than that.  One lane walks it level by level (at most
 // 511 nodes); then each bucket's first sorted leaf is found by descending left.
-__global__ void k_frontier(const Node *__restrict__ nodes, int root, int nt, int32_t *__restrict__ bucket_ref,
-                           int32_t *__restrict__ bucket_first, int32_t *__restrict__ n_buckets) {
+__global__ void k_frontier(const Node *__restrict__ nodes, const int32_t *__restrict__ parent, int root, int nt,
+                           int32_t *__restrict__ bucket_ref, int32_t *__restrict__ bucket_first,
+                           int32_t *__restrict__ n_buckets, uint8_t *__restrict__ leaf_bucket) {
     __shared__ int cur[kMlpOut], nxt[kMlpOut];
     __shared__ int count;
     if (threadIdx.x == 0) {
@@ -471,11 +472,38 @@ __global__ void k_frontier(const Node *__restrict__ nodes, int root, int nt, int
     if (b < count) {
         int r = cur[b];
         bucket_ref[b] = r;
-        for (int guard = 0; r >= 0 && guard < kDeepStack; ++guard)
-            r = nodes[r].refs.x;
-        bucket_first[b] = ~r;
+        int x = r;
+        for (int guard = 0; x >= 0 && guard < kDeepStack; ++guard)
+            x = nodes[x].refs.x;
+        bucket_first[b] = ~x;
+        // mark every leaf of the bucket's subtree: a walk without a stack (down
+        // the left children, then up until a left child with an unvisited right
+        // sibling), bounded by the subtree's 2 N_t node steps
+        auto up = [&](int c) { return c >= 0 ? parent[c] : parent[(nt - 1) + ~c]; };
+        x = r;
+        for (int64_t step = 0; step < 4 * (int64_t)nt + 8; ++step) {
+            while (x >= 0 && step++ < 4 * (int64_t)nt + 8)
+                x = nodes[x].refs.x;
+            if (x < 0 && ~x < nt)
+                leaf_bucket[~x] = (uint8_t)b;
+            // climb until x is a left child whose parent's right child is unvisited
+            int c = x;
+            bool next = false;
+            while (c != r && step++ < 4 * (int64_t)nt + 8) {
+                const int q = up(c);
+                if (q < 0 || q >= nt - 1)
+                    break;
+                if (nodes[q].refs.x == c) {
+                    x = nodes[q].refs.y;
+                    next = true;
+                    break;
+                }
+                c = q;
+            }
+            if (!next)
+                break;
+        }
     }
-    (void)nt;
 }
 
 // rank[ids[k]] = k: sorted position of each input triangle.
@@ -485,31 +513,20 @@ __global__ void k_rank(const int32_t *__restrict__ ids, int nt, int32_t *__restr
         rank[ids[k]] = k;
 }
 
-// For every segment with a first hit: its bucket (the frontier subtree whose
-// leaf range holds the hit leaf), appended with the segment index to the
-// training list.
+// For every segment with a first hit: its bucket (the frontier subtree that
+// holds the hit leaf), appended with the segment index to the training list.
 __global__ void k_labels(const int32_t *__restrict__ tri_id, int64_t n, const int32_t *__restrict__ rank,
-                         const int32_t *__restrict__ bucket_first, const int32_t *__restrict__ n_buckets,
-                         int32_t *__restrict__ seg_out, int32_t *__restrict__ label_out,
-                         uint32_t *__restrict__ count) {
+                         const uint8_t *__restrict__ leaf_bucket, int32_t *__restrict__ seg_out,
+                         int32_t *__restrict__ label_out, uint32_t *__restrict__ count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
     const int t = tri_id[i];
     if (t < 0)
         return;
-    const int leaf = rank[t];
-    int lo = 0, hi = *n_buckets - 1;  // last bucket whose first leaf <= leaf
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (bucket_first[mid] <= leaf)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
     const uint32_t slot = atomicAdd(count, 1u);
     seg_out[slot] = (int32_t)i;
-    label_out[slot] = lo;
+    label_out[slot] = leaf_bucket[rank[t]];
 }
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -525,8 +542,9 @@ void gemm(const GemmArgs &g, hipStream_t s) {
 hipError_t proposal_frontier(const MeshDev &m, Proposal &pr, hipStream_t s) {
     if (m.nt < 1)
         return hipErrorInvalidValue;
-    k_frontier<<<1, kMlpOut, 0, s>>>(m.nodes, m.root, (int)m.nt, pr.bucket_ref, pr.bucket_first, pr.dev_n_buckets);
     k_rank<<<cdiv(m.nt, 256), 256, 0, s>>>(m.ids, (int)m.nt, pr.rank);
+    k_frontier<<<1, kMlpOut, 0, s>>>(m.nodes, m.parent, m.root, (int)m.nt, pr.bucket_ref, pr.bucket_first,
+                                     pr.dev_n_buckets, pr.leaf_bucket);
     return hipGetLastError();
 }
 
@@ -537,7 +555,7 @@ hipError_t proposal_init(Proposal &pr, uint64_t seed, hipStream_t s) {
 
 hipError_t proposal_labels(const MeshDev &m, Proposal &pr, const int32_t *tri_id, int64_t n, int32_t *seg,
                            int32_t *label, uint32_t *count, hipStream_t s) {
-    k_labels<<<cdiv(n, 256), 256, 0, s>>>(tri_id, n, pr.rank, pr.bucket_first, pr.dev_n_buckets, seg, label, count);
+    k_labels<<<cdiv(n, 256), 256, 0, s>>>(tri_id, n, pr.rank, pr.leaf_bucket, seg, label, count);
     return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ struct Proposal {
     int32_t *bucket_first = nullptr;  // [256] first sorted leaf of each bucket
     int32_t *dev_n_buckets = nullptr; // [1]
     int32_t *rank = nullptr;          // [nt] sorted position of each triangle
+    uint8_t *leaf_bucket = nullptr;   // [nt] bucket of each sorted leaf
     void *block = nullptr;
 };
 
@@ -61,7 +62,8 @@ struct Proposal {
 struct MeshDev {
     int64_t nv = 0, nt = 0;
     int morton_bits = 30;
-    int algorithm = 0;         // 0 radix tree + tiled bottom-up, 1 agglomerative single pass
+    int algorithm = 0;         // 0 radix tree + tiled bottom-up, 1 agglomerative single pass,
+                               // 2 radix tree + treelet restructuring
     int root = 0;
     float *V = nullptr;        // [nv][3] copy of the vertices
     int32_t *F = nullptr;      // [nt][3] copy of the triangles
@@ -101,6 +103,10 @@ hipError_t launch_batch_build(MeshDev &m, BatchDev &b, const float *V, const int
 hipError_t launch_build(MeshDev &m, const float *V, const int32_t *F, hipStream_t s, size_t sort_tmp_bytes);
 size_t sort_tmp_bytes(int64_t nt, int morton_bits);
 hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s);
+// Treelet restructuring of a built radix tree (restructure.hip); needs the
+// tile list the radix-tree kernel left in m.sort_tmp.
+hipError_t launch_restructure(MeshDev &m, int rounds, hipStream_t s);
+size_t restructure_lds_bytes();
 // Stable sort of (32-bit key, id) pairs in place; tmp holds sort_u32_tmp_bytes(n).
 size_t sort_u32_tmp_bytes(int64_t n);
 hipError_t sort_u32_pairs(uint32_t *keys, int32_t *ids, void *tmp, int64_t n, hipStream_t s);

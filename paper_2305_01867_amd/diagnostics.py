@@ -128,12 +128,13 @@ def to_dot(tree: dict, name: str = "bvh") -> str:
     return "\n".join(lines) + "\n"
 
 
-def check(tree: dict) -> list:
+def check(tree: dict, contiguous: bool = False) -> list:
     """Structural checks of a decoded tree (the connectivity the paper's
     debugging looked for); returns a list of problems, empty when sound:
-    every leaf and non-root internal node has exactly one parent, child
-    ranges partition the parent's range, each box contains its children's
-    boxes, and counters (if present) read 2."""
+    every leaf and non-root internal node has exactly one parent, the
+    children's leaf spans make up the parent's, each box contains its
+    children's boxes, and counters (if present) read 2.  With contiguous=True
+    (radix-tree numbering) the spans must also split the parent's range."""
     problems = []
     n_int = tree["left"].shape[0]
     n_leaf = tree["leaf_tri"].shape[0]
@@ -154,9 +155,16 @@ def check(tree: dict) -> list:
             pb = tree[side + "_box"][i]
             if not (np.all(pb[:3] <= cb[:3]) and np.all(pb[3:] >= cb[3:])):
                 problems.append(f"node {i}: {side} box does not contain its child")
-        if len(ranges) == 2 and not (ranges[0][0] == tree["first"][i] and ranges[0][1] + 1 == ranges[1][0]
-                                     and ranges[1][1] == tree["last"][i]):
+        # leaf spans: children's spans make up the parent's (a contiguous split
+        # in the radix-tree numbering; after treelet restructuring the spans
+        # are smallest / largest leaf and may interleave)
+        if contiguous and len(ranges) == 2 and not (ranges[0][0] == tree["first"][i]
+                                                    and ranges[0][1] + 1 == ranges[1][0]
+                                                    and ranges[1][1] == tree["last"][i]):
             problems.append(f"node {i}: child ranges {ranges} do not split [{tree['first'][i]},{tree['last'][i]}]")
+        if len(ranges) == 2 and (min(ranges[0][0], ranges[1][0]) != tree["first"][i]
+                                 or max(ranges[0][1], ranges[1][1]) != tree["last"][i]):
+            problems.append(f"node {i}: child spans {ranges} do not make up [{tree['first'][i]},{tree['last'][i]}]")
     root = tree["root"]
     if root < 0:
         problems.append("no single root")

@@ -42,7 +42,7 @@ def export_layout(V, F, bits=30):
 def test_case_study_1_graph_and_listing():
     V, F, _, _ = workloads.appendix_scene()
     tree = diagnostics.decode(*export_layout(V, F))
-    assert diagnostics.check(tree) == []
+    assert diagnostics.check(tree, contiguous=True) == []
     dot = diagnostics.to_dot(tree)
     assert 'n0 [label="[0,3]", style=bold];' in dot
     labels = sorted(l.split('label="')[1].split('"')[0] for l in dot.splitlines() if "label=" in l and "shape=box" in l)
@@ -59,7 +59,7 @@ def test_case_study_1_graph_and_listing():
 def test_check_finds_planted_faults():
     V, F = workloads.heightfield(9, 2)
     nodes, leaves, parents, counters = export_layout(V, F)
-    assert diagnostics.check(diagnostics.decode(nodes, leaves, parents, counters)) == []
+    assert diagnostics.check(diagnostics.decode(nodes, leaves, parents, counters), contiguous=True) == []
     bad = nodes.copy()
     bad[3, 13] = bad[3, 12]  # a child listed twice, another lost
     assert diagnostics.check(diagnostics.decode(bad, leaves, parents, counters))

@@ -151,7 +151,7 @@ def test_diagnostics_on_the_device_tree():
     V, F, _, _ = workloads.appendix_scene()
     with rsi.rsi_build(dev(V), dev(F)) as mesh:
         tree = diagnostics.export(mesh)
-    assert diagnostics.check(tree) == []
+    assert diagnostics.check(tree, contiguous=True) == []
     dot = diagnostics.to_dot(tree)
     leaves = sorted(l.split('label="')[1].split('"')[0] for l in dot.splitlines() if "shape=box" in l)
     assert leaves == ["[0] 0", "[1] 3", "[2] 1", "[3] 2"]
@@ -193,3 +193,43 @@ def test_agglomerative_build_is_the_same_tree(case):
             assert rsi.rsi_mesh_info_get(b)["root"] == tb["root"]
             if case == "scene":
                 assert tb["root"] == 1 and "[1] x:[12,13], y:[2,3], z:[1,1.3]  ------ ROOT NODE" in diagnostics.listing(tb)
+
+
+def sah_area(tree):
+    """Sum of the internal boxes' half surface areas over the root's (the
+    node-visit weight of random segments)."""
+    b = tree["box"].astype(np.float64)
+    d = b[:, 3:] - b[:, :3]
+    a = d[:, 0] * d[:, 1] + d[:, 1] * d[:, 2] + d[:, 2] * d[:, 0]
+    return float(a.sum() / a[tree["root"]])
+
+
+@pytest.mark.parametrize("case", ["scene", "small", "paper_scale", "large", "duplicates"])
+def test_restructured_build_is_a_valid_cheaper_tree(case):
+    """Treelet restructuring keeps the leaves, gives a valid tree (every leaf
+    once, boxes that contain their children, counters at 2), lowers the
+    surface-area sum, and is deterministic."""
+    from paper_2305_01867_amd import diagnostics
+    if case == "scene":
+        V, F, _, _ = workloads.appendix_scene()
+    elif case == "small":
+        V, F = workloads.heightfield(9, 5)
+    elif case == "paper_scale":
+        V, F = workloads.heightfield(128, 21)
+    elif case == "large":
+        V, F = workloads.heightfield(401, 8)  # 3.2e5 triangles: tiles and a top tree
+    else:
+        V, F = triangle_soup(5000, 3, n_vert=300, clustered=True)
+    with rsi.rsi_build(dev(V), dev(F)) as a, rsi.rsi_build(dev(V), dev(F), algorithm="restructured") as b, \
+            rsi.rsi_build(dev(V), dev(F), algorithm="restructured") as c:
+        assert np.array_equal(export(a, "leaves"), export(b, "leaves"))
+        ta, tb = diagnostics.export(a), diagnostics.export(b)
+        assert diagnostics.check(tb) == [], diagnostics.check(tb)[:5]
+        assert tb["root"] == 0 and tb["first"][0] == 0 and tb["last"][0] == F.shape[0] - 1
+        assert np.array_equal(ta["box"][0], tb["box"][0])
+        sa, sb = sah_area(ta), sah_area(tb)
+        say(f"[restructure] {case}: {F.shape[0]} triangles, surface-area sum {sa:.2f} -> {sb:.2f}")
+        if F.shape[0] >= 64:
+            assert sb < 0.95 * sa
+        for w in ("nodes", "parents", "counters"):
+            assert np.array_equal(export(b, w), export(c, w)), w

@@ -76,6 +76,7 @@ def test_tiny_heightfield_config():
     V, F, O, E = workloads.tiny_config()
     check_all_modes(V, F, O, E, "64x64 heightfield, 1e4 crossing-mix segments", plain_budget=20)
     check_all_modes(V, F, O, E, "same, agglomerative build", algorithm="agglomerative")
+    check_all_modes(V, F, O, E, "same, restructured tree", algorithm="restructured")
     check_all_modes(V, F, O, E, "same, 63-bit keys, stack 8, block 64", morton_bits=63, stack_depth=8, block=64)
 
 
@@ -322,6 +323,14 @@ def test_paper_scale_sampled():
             if mode == "boolean":
                 frac = float(c.mean())
                 say(f"  hit fraction {frac:.4f}")
+                with rsi.rsi_build(dev(V), dev(F), algorithm="restructured") as rmesh:
+                    r = host(rsi.rsi_intersect(rmesh, dO, dE, mode=mode, precision="certified")["hit"])
+                    assert np.array_equal(r, c), "restructured tree"
+                    v0, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=mode, precision="certified")
+                    v1, _ = rsi.rsi_traversal_stats(rmesh, dO, dE, mode=mode, precision="certified")
+                    m0, m1 = float(v0.double().mean()), float(v1.double().mean())
+                    say(f"  mean node visits: radix tree {m0:.2f}, restructured {m1:.2f}")
+                    assert m1 < m0
                 for order in ("midpoint", "origin_octant"):  # the multi-block scan path of the sort
                     srt = host(rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision="certified",
                                                  ray_sort=order)["hit"])

@@ -144,3 +144,21 @@ def test_training_lowers_loss_and_keeps_results_exact():
             f"proposal miss rate {miss_rate:.3f}")
         assert m[2] < m[1]
         assert miss_rate < 0.95  # chance level is 1 - 1/(number of buckets) ~ 0.996
+
+
+def test_proposal_on_a_restructured_tree():
+    """Buckets are subtrees, not leaf ranges, once treelets are rewired: the
+    labels come from each leaf's bucket, and proposal-first results stay the
+    oracle's."""
+    V, F = workloads.heightfield(48, 12)
+    O, E = workloads.rays_in_box(40000, 35, V.min(0), V.max(0))
+    Ot, Et = workloads.rays_in_box(2000, 36, V.min(0), V.max(0))
+    hit, ids, _, _ = oracle.intersect(V, F, Ot, Et)
+    with rsi.rsi_build(dev(V), dev(F), algorithm="restructured") as mesh:
+        loss, n_lab = rsi.rsi_proposal_train(mesh, dev(O), dev(E), epochs=3, batch=2048, lr=2e-3, seed=8)
+        say(f"  restructured tree: labelled {n_lab}, epoch loss {loss.tolist()}")
+        assert n_lab > 20000 and loss[-1] < 0.8 * loss[0]
+        for mode, key, want in (("boolean", "hit", hit), ("first_hit", "tri_id", ids)):
+            got = host(rsi.rsi_intersect(mesh, dev(Ot), dev(Et), mode=mode, precision="certified",
+                                         proposal=True)[key])
+            assert np.array_equal(got, want), mode
