@@ -23,7 +23,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;  // 2048 keys per tile
 constexpr int kRadix = 256;
 constexpr int kBoxTile = 1024;  // leaves per bottom-up workgroup (one per lane)
 constexpr int kNoTile = INT32_MIN;  // never a child reference (leaves are ~k with k < 2^30)
-constexpr int kRestructureRounds = 3;  // treelet restructuring passes of algorithm 2
+constexpr int kRestructureRounds = 2;  // treelet restructuring passes of algorithm 2
 
 // ---------------------------------------------------------------- 1. extent
 __global__ __launch_bounds__(1024) void k_mesh_bounds(const float *__restrict__ V, int64_t nv,

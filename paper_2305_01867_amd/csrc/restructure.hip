@@ -6,18 +6,20 @@
 // surface-area-heuristic tree reaches.  Treelet restructuring (Karras & Aila
 // 2013, "Fast parallel construction of high-quality bounding volume
 // hierarchies") improves it in place: bottom-up, each node with enough leaves
-// becomes the root of a treelet of up to 7 leaves (grown by opening the
-// largest-area internal leaf), and the treelet's internal nodes are rebuilt
-// in the topology of least SAH cost, found by dynamic programming over the
-// 127 subsets of its leaves.  The leaves (sorted triangles) do not move; only
-// internal nodes are rewired, so every query result stays the same.
+// becomes the root of a treelet (grown by opening the largest-area internal
+// leaf), and the treelet's internal nodes are rebuilt in the topology of
+// least SAH cost, found by dynamic programming over the subsets of its
+// leaves.  Treelets of 4 leaves (15 subsets) keep that search in one lane's
+// registers, so all treelets of a level run at once; a few passes reach most
+// of what 7-leaf treelets give.  The leaves (sorted triangles) do not move;
+// only internal nodes are rewired, so every query result stays the same.
 //
 // On gfx950 the work is kept inside workgroups: one workgroup loads a whole
 // tile (a subtree of at most 1024 leaves, listed by the radix-tree kernel)
-// into LDS, restructures it level by level (treelets of one level have
-// disjoint subtrees, a wave per treelet), and writes it back; one workgroup
-// then does the same for the nodes above the tiles, with the tiles as fixed
-// leaves.  No cross-workgroup synchronisation at all.
+// into LDS in one step, restructures it in bottom-up climbs (a lane per
+// leaf, a treelet optimised where the second lane arrives), and writes it
+// back; one workgroup then does the same for the nodes above the tiles, with
+// the tiles as fixed leaves.  No cross-workgroup synchronisation at all.
 //
 // After restructuring, an internal node's leaves are no longer a contiguous
 // range of sorted positions: words 14 / 15 of a node then hold the smallest
@@ -28,9 +30,7 @@ namespace rsi {
 namespace {
 
 constexpr int kTile = 1024;            // leaves per tile (= lanes per workgroup)
-constexpr int kTreelet = 7;            // leaves per treelet
-constexpr int kSubsets = 1 << kTreelet;
-constexpr int kWaves = kTile / 64;
+constexpr int kTreelet = 4;            // leaves per treelet (the optimisation runs in one lane's registers)
 constexpr int kMaxLevels = 130;        // > deepest radix tree (97) + treelet growth
 constexpr float kCostNode = 1.2f;      // SAH weight of a node visit (one 64-B node, two box tests)
 constexpr float kCostTri = 1.0f;       // SAH weight of a triangle test
@@ -44,21 +44,16 @@ struct TileLds {
     float in_cost[kTile];      // SAH cost of the subtree
     int in_count[kTile];       // leaves below
     int in_lo[kTile], in_hi[kTile];  // smallest / largest sorted leaf below
-    int order[kTile];          // internal nodes by level
+    int in_parent[kTile];      // local parent, -1 at the root
+    int arrive[kTile];         // arrivals of the bottom-up climb
     int lf_ref[kTile];         // global reference of local leaf j (a leaf ~k, or a fixed subtree)
     float lf_box[6][kTile];
     float lf_cost[kTile];
     int lf_count[kTile];
     int lf_lo[kTile], lf_hi[kTile];
-    int lvl_start[kMaxLevels + 2];
-    int n_in, n_lf, n_levels, overflow;
-    // per-wave scratch of the treelet optimisation
-    float w_area[kWaves][kSubsets];
-    float w_cost[kWaves][kSubsets];
-    unsigned char w_split[kWaves][kSubsets];
-    int w_leaf[kWaves][8];     // treelet leaves (local references)
-    int w_int[kWaves][8];      // treelet internal nodes (local ids), [0] = root
-    int w_m[kWaves];
+    int lf_parent[kTile];
+    int lvl_start[kMaxLevels + 2];  // breadth-first load of the top tree
+    int n_in, n_lf, root, overflow;
 };
 
 __device__ __forceinline__ float half_area(float x0, float y0, float z0, float x1, float y1, float z1) {
@@ -66,10 +61,8 @@ __device__ __forceinline__ float half_area(float x0, float y0, float z0, float x
     return dx * dy + dy * dz + dz * dx;  // half the surface area; the common factor 2 cancels in comparisons
 }
 
-__device__ __forceinline__ void lds_sync_wave() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+__device__ __forceinline__ float tri_cost(const float *b) {
+    return kCostTri * half_area(b[0], b[1], b[2], b[3], b[4], b[5]);
 }
 
 // Box / cost / count / leaf span of a local reference.
@@ -81,45 +74,6 @@ __device__ __forceinline__ int ref_count(const TileLds &T, int r) { return r >= 
 __device__ __forceinline__ int ref_lo(const TileLds &T, int r) { return r >= 0 ? T.in_lo[r] : T.lf_lo[~r]; }
 __device__ __forceinline__ int ref_hi(const TileLds &T, int r) { return r >= 0 ? T.in_hi[r] : T.lf_hi[~r]; }
 
-// Levels of the local tree, top down, into T.order / T.lvl_start.  Block-wide.
-__device__ void compute_levels(TileLds &T) {
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        T.order[0] = 0;
-        T.lvl_start[0] = 0;
-        T.lvl_start[1] = 1;
-        T.n_levels = 1;
-    }
-    __syncthreads();
-    for (int lv = 0; lv < kMaxLevels; ++lv) {
-        const int b0 = T.lvl_start[lv], b1 = T.lvl_start[lv + 1];
-        if (b0 == b1)
-            break;
-        __shared__ int next;
-        if (tid == 0)
-            next = b1;
-        __syncthreads();
-        for (int i = b0 + tid; i < b1; i += blockDim.x) {
-            const int j = T.order[i];
-            for (int side = 0; side < 2; ++side) {
-                const int c = T.in_child[side][j];
-                if (c >= 0 && c < kTile) {
-                    const int slot = atomicAdd(&next, 1);
-                    if (slot < kTile)
-                        T.order[slot] = c;
-                }
-            }
-        }
-        __syncthreads();
-        if (tid == 0) {
-            T.lvl_start[lv + 2] = next < kTile ? next : kTile;
-            if (next > b1)
-                T.n_levels = lv + 2;
-        }
-        __syncthreads();
-    }
-}
-
 // Cost, count and leaf span of internal node j from its children.
 __device__ __forceinline__ float node_cost(const TileLds &T, int j) {
     return kCostNode * half_area(T.in_box[0][j], T.in_box[1][j], T.in_box[2][j], T.in_box[3][j], T.in_box[4][j],
@@ -127,187 +81,223 @@ __device__ __forceinline__ float node_cost(const TileLds &T, int j) {
            ref_cost(T, T.in_child[0][j]) + ref_cost(T, T.in_child[1][j]);
 }
 
-__device__ void refresh_level(TileLds &T, int lv) {
-    for (int i = T.lvl_start[lv] + threadIdx.x; i < T.lvl_start[lv + 1]; i += blockDim.x) {
-        const int j = T.order[i];
-        const int c0 = T.in_child[0][j], c1 = T.in_child[1][j];
-        T.in_cost[j] = node_cost(T, j);
-        T.in_count[j] = ref_count(T, c0) + ref_count(T, c1);
-        T.in_lo[j] = min(ref_lo(T, c0), ref_lo(T, c1));
-        T.in_hi[j] = max(ref_hi(T, c0), ref_hi(T, c1));
+__device__ __forceinline__ void refresh_node(TileLds &T, int j) {
+    const int c0 = T.in_child[0][j], c1 = T.in_child[1][j];
+    T.in_cost[j] = node_cost(T, j);
+    T.in_count[j] = ref_count(T, c0) + ref_count(T, c1);
+    T.in_lo[j] = min(ref_lo(T, c0), ref_lo(T, c1));
+    T.in_hi[j] = max(ref_hi(T, c0), ref_hi(T, c1));
+}
+
+__device__ __forceinline__ void set_parent(TileLds &T, int ref, int j) {
+    if (ref >= 0)
+        T.in_parent[ref] = j;
+    else
+        T.lf_parent[~ref] = j;
+}
+
+// Splits of the subsets of four treelet leaves: {subset, part holding the
+// subset's lowest leaf, last split of this subset}.
+constexpr int kSplitCount = 25;
+__device__ constexpr unsigned char kSplits[kSplitCount][3] = {
+    {3, 1, 1},   {5, 1, 1},   {6, 2, 1},   {9, 1, 1},   {10, 2, 1},  {12, 4, 1},  {7, 1, 0},
+    {7, 3, 0},   {7, 5, 1},   {11, 1, 0},  {11, 3, 0},  {11, 9, 1},  {13, 1, 0},  {13, 5, 0},
+    {13, 9, 1},  {14, 2, 0},  {14, 6, 0},  {14, 10, 1}, {15, 1, 0},  {15, 3, 0},  {15, 5, 0},
+    {15, 7, 0},  {15, 9, 0},  {15, 11, 0}, {15, 13, 1}};
+
+// One lane restructures the treelet of up to kTreelet (4) leaves rooted at
+// local node p: it opens the largest-area internal leaf twice, finds the
+// least-cost topology over the 15 leaf subsets with every subset and split
+// known at compile time (all in registers), and rewires the (at most three)
+// internal nodes when that is cheaper than the current shape.
+__device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
+    int leaf[4] = {T.in_child[0][p], T.in_child[1][p], 0, 0};
+    int inner[3] = {p, -1, -1};
+    int m = 2;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        int best = -1;
+        float best_a = -1.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int r = leaf[i];
+            if (i < m && r >= 0) {
+                const float a = half_area(T.in_box[0][r], T.in_box[1][r], T.in_box[2][r], T.in_box[3][r],
+                                          T.in_box[4][r], T.in_box[5][r]);
+                if (a > best_a) {
+                    best_a = a;
+                    best = i;
+                }
+            }
+        }
+        if (best < 0)
+            break;
+        int r = leaf[0];
+#pragma unroll
+        for (int i = 1; i < 3; ++i)
+            r = best == i ? leaf[i] : r;
+        const int c0 = T.in_child[0][r], c1 = T.in_child[1][r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            leaf[i] = i == best ? c0 : leaf[i];
+            leaf[i] = i == m ? c1 : leaf[i];
+        }
+#pragma unroll
+        for (int i = 1; i < 3; ++i)
+            inner[i] = i == m - 1 ? r : inner[i];
+        ++m;
+    }
+    if (m < 3)
+        return;  // both children are leaves: one shape only
+    float lb[4][6], lc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = i < m ? leaf[i] : leaf[0];
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+            lb[i][a] = ref_box(T, r, a);
+        lc[i] = ref_cost(T, r);
+    }
+    const int full = (1 << m) - 1;
+    float area[16], cost[16], best_sum[16];
+    int split[16];
+#pragma unroll
+    for (int S = 1; S < 16; ++S) {
+        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if ((S >> i) & 1)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    b[a] = fminf(b[a], lb[i][a]);
+                    b[3 + a] = fmaxf(b[3 + a], lb[i][3 + a]);
+                }
+        area[S] = half_area(b[0], b[1], b[2], b[3], b[4], b[5]);
+        cost[S] = best_sum[S] = INFINITY;
+        split[S] = 0;
+    }
+    area[0] = cost[0] = 0.0f;
+    split[0] = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        cost[1 << i] = lc[i];
+    // every split (S, P | S^P) of a subset S of two or more leaves, with P
+    // holding S's lowest leaf so each unordered pair appears once, listed by
+    // subset size so a subset's parts are done before it; the flag marks a
+    // subset's last split
+#pragma unroll
+    for (int e = 0; e < kSplitCount; ++e) {
+        const int S = kSplits[e][0], P = kSplits[e][1];
+        const float c = cost[P] + cost[S ^ P];
+        if (c < best_sum[S]) {
+            best_sum[S] = c;
+            split[S] = P;
+        }
+        if (kSplits[e][2])
+            cost[S] = kCostNode * area[S] + best_sum[S];
+    }
+    const float now = T.in_cost[p];
+    const float best_cost = m == 4 ? cost[15] : cost[7];
+    if (!(best_cost < now * (1.0f - 1e-6f)))
+        return;
+    // mark the subsets the chosen topology uses, from the whole set down (the
+    // table read backwards is by falling subset size); every index below is
+    // known at compile time, so all of this stays in registers
+    bool used[16];
+#pragma unroll
+    for (int S = 0; S < 16; ++S)
+        used[S] = S == full;
+#pragma unroll
+    for (int e = kSplitCount - 1; e >= 0; --e) {
+        const int S = kSplits[e][0], P = kSplits[e][1];
+        if (used[S] && split[S] == P)
+            used[P] = used[S ^ P] = true;
+    }
+    // node ids: the root keeps p, further internal subsets take the opened
+    // nodes in turn
+    int node[16];
+    int taken = 1;
+#pragma unroll
+    for (int S = 15; S >= 3; --S) {
+        node[S] = p;
+        if (__builtin_popcount(S) >= 2 && S != full && used[S]) {
+            node[S] = taken == 1 ? inner[1] : inner[2];
+            ++taken;
+        }
+    }
+    // write each used internal subset
+#pragma unroll
+    for (int S = 3; S < 16; ++S) {
+        if (__builtin_popcount(S) < 2 || !used[S])
+            continue;
+        int child0 = 0, child1 = 0;
+#pragma unroll
+        for (int e = 0; e < kSplitCount; ++e) {
+            if (kSplits[e][0] != S)
+                continue;
+            const int P = kSplits[e][1], Q = S ^ P;
+            if (split[S] == P) {
+                child0 = __builtin_popcount(P) == 1 ? leaf[__builtin_ctz(P)] : node[P];
+                child1 = __builtin_popcount(Q) == 1 ? leaf[__builtin_ctz(Q)] : node[Q];
+            }
+        }
+        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        int count = 0, lo = INT32_MAX, hi = INT32_MIN;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if ((S >> i) & 1) {
+                const int r = leaf[i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    b[a] = fminf(b[a], lb[i][a]);
+                    b[3 + a] = fmaxf(b[3 + a], lb[i][3 + a]);
+                }
+                count += ref_count(T, r);
+                lo = min(lo, ref_lo(T, r));
+                hi = max(hi, ref_hi(T, r));
+            }
+        const int j = node[S];
+        T.in_child[0][j] = child0;
+        T.in_child[1][j] = child1;
+        set_parent(T, child0, j);
+        set_parent(T, child1, j);
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+            T.in_box[a][j] = b[a];
+        T.in_cost[j] = cost[S];
+        T.in_count[j] = count;
+        T.in_lo[j] = lo;
+        T.in_hi[j] = hi;
     }
 }
 
-// Every internal node from its children, deepest level first.  Block-wide.
-__device__ void refresh_bottom_up(TileLds &T) {
-    for (int lv = T.n_levels - 1; lv >= 0; --lv) {
-        refresh_level(T, lv);
+// Restructure the local tree in T (loaded, with parents; costs not yet
+// known).  Each pass is a bottom-up climb, one lane per leaf as in the
+// radix-tree box pass: the second lane to reach a node finds both subtrees
+// final, refreshes the node and optimises the treelet rooted there, and
+// climbs on; the first lane stops.  A node's treelet lies inside its own
+// subtree, which no other lane touches any more, so no barrier is needed
+// between levels, only workgroup-scope acquire / release on the arrivals.
+__device__ __forceinline__ void restructure_local(TileLds &T, int rounds) {
+    for (int round = 0; round < rounds; ++round) {
+        for (int j = threadIdx.x; j < T.n_in; j += blockDim.x)
+            T.arrive[j] = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < T.n_lf; k += blockDim.x) {
+            int j = T.lf_parent[k];
+            for (int step = 0; j >= 0 && step < T.n_in; ++step) {  // a climb is at most n_in nodes long
+                if (__hip_atomic_fetch_add(&T.arrive[j], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+                    break;  // the other subtree is still on its way
+                refresh_node(T, j);
+                if (T.in_count[j] >= kTreelet)
+                    optimize_treelet(T, j);
+                j = T.in_parent[j];
+            }
+        }
         __syncthreads();
     }
 }
 
-// One wave restructures the treelet rooted at local node p (wave-uniform call).
-__device__ void optimize_treelet(TileLds &T, int p, int w) {
-    const int lane = threadIdx.x & 63;
-    float *area = T.w_area[w];
-    float *cost = T.w_cost[w];
-    unsigned char *split = T.w_split[w];
-    if (lane == 0) {
-        int leaf[kTreelet], inner[kTreelet];
-        leaf[0] = T.in_child[0][p];
-        leaf[1] = T.in_child[1][p];
-        inner[0] = p;
-        int m = 2;
-        while (m < kTreelet) {
-            int best = -1;
-            float best_a = -1.0f;
-            for (int i = 0; i < m; ++i) {
-                const int r = leaf[i];
-                if (r >= 0) {
-                    const float a = half_area(T.in_box[0][r], T.in_box[1][r], T.in_box[2][r], T.in_box[3][r],
-                                              T.in_box[4][r], T.in_box[5][r]);
-                    if (a > best_a) {
-                        best_a = a;
-                        best = i;
-                    }
-                }
-            }
-            if (best < 0)
-                break;
-            const int r = leaf[best];
-            inner[m - 1] = r;
-            leaf[best] = T.in_child[0][r];
-            leaf[m] = T.in_child[1][r];
-            ++m;
-        }
-        for (int i = 0; i < m; ++i)
-            T.w_leaf[w][i] = leaf[i];
-        for (int i = 0; i < m - 1; ++i)
-            T.w_int[w][i] = inner[i];
-        T.w_m[w] = m;
-    }
-    lds_sync_wave();
-    const int m = T.w_m[w];
-    const int full = (1 << m) - 1;
-    if (m < 3)
-        return;  // two leaves: one topology only
-    // areas of every subset, and the costs of single leaves
-    for (int S = lane; S <= full; S += 64) {
-        if (S == 0)
-            continue;
-        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-        for (int i = 0; i < m; ++i)
-            if ((S >> i) & 1) {
-                const int r = T.w_leaf[w][i];
-                for (int a = 0; a < 3; ++a) {
-                    b[a] = fminf(b[a], ref_box(T, r, a));
-                    b[3 + a] = fmaxf(b[3 + a], ref_box(T, r, 3 + a));
-                }
-            }
-        area[S] = half_area(b[0], b[1], b[2], b[3], b[4], b[5]);
-        if ((S & (S - 1)) == 0)
-            cost[S] = ref_cost(T, T.w_leaf[w][__builtin_ctz(S)]);
-    }
-    lds_sync_wave();
-    // least cost of every subset of 2 .. m leaves, by size; a split P always
-    // holds the subset's lowest leaf, so each unordered pair is seen once
-    for (int size = 2; size <= m; ++size) {
-        for (int S = lane; S <= full; S += 64) {
-            if (__builtin_popcount(S) != size)
-                continue;
-            const int low = S & -S, rest = S ^ low;
-            float best = INFINITY;
-            int best_p = low;
-            for (int sub = (rest - 1) & rest;; sub = (sub - 1) & rest) {
-                const int P = low | sub;
-                const float c = cost[P] + cost[S ^ P];
-                if (c < best) {
-                    best = c;
-                    best_p = P;
-                }
-                if (sub == 0)
-                    break;
-            }
-            cost[S] = kCostNode * area[S] + best;
-            split[S] = (unsigned char)best_p;
-        }
-        lds_sync_wave();
-    }
-    // rewire only when the treelet gets cheaper than it is now (its subtrees
-    // below may have changed this round: take the children's current costs)
-    if (lane == 0 && cost[full] < node_cost(T, p) * (1.0f - 1e-6f)) {
-        int free_slot = 1;  // T.w_int[w][0] is the root p
-        int stack_set[kTreelet], stack_node[kTreelet], sp = 0;
-        stack_set[sp] = full;
-        stack_node[sp] = p;
-        ++sp;
-        while (sp > 0) {
-            --sp;
-            const int S = stack_set[sp], j = stack_node[sp];
-            const int P = split[S], Q = S ^ P;
-            const int parts[2] = {P, Q};
-            for (int side = 0; side < 2; ++side) {
-                const int part = parts[side];
-                int child;
-                if ((part & (part - 1)) == 0) {
-                    child = T.w_leaf[w][__builtin_ctz(part)];
-                } else {
-                    child = T.w_int[w][free_slot++];
-                    stack_set[sp] = part;
-                    stack_node[sp] = child;
-                    ++sp;
-                }
-                T.in_child[side][j] = child;
-            }
-            float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-            int count = 0, lo = INT32_MAX, hi = INT32_MIN;
-            for (int i = 0; i < m; ++i)
-                if ((S >> i) & 1) {
-                    const int r = T.w_leaf[w][i];
-                    for (int a = 0; a < 3; ++a) {
-                        b[a] = fminf(b[a], ref_box(T, r, a));
-                        b[3 + a] = fmaxf(b[3 + a], ref_box(T, r, 3 + a));
-                    }
-                    count += ref_count(T, r);
-                    lo = min(lo, ref_lo(T, r));
-                    hi = max(hi, ref_hi(T, r));
-                }
-            for (int a = 0; a < 6; ++a)
-                T.in_box[a][j] = b[a];
-            T.in_cost[j] = cost[S];
-            T.in_count[j] = count;
-            T.in_lo[j] = lo;
-            T.in_hi[j] = hi;
-        }
-    }
-    lds_sync_wave();
-}
-
-// Restructure the local tree in T (loaded, costs and levels not yet known).
-__device__ void restructure_local(TileLds &T, int rounds) {
-    const int w = threadIdx.x >> 6;
-    compute_levels(T);
-    refresh_bottom_up(T);
-    for (int round = 0; round < rounds; ++round) {
-        for (int lv = T.n_levels - 1; lv >= 0; --lv) {
-            const int b0 = T.lvl_start[lv], b1 = T.lvl_start[lv + 1];
-            for (int i = b0 + w; i < b1; i += kWaves) {  // wave-uniform
-                const int j = T.order[i];
-                if (T.in_count[j] >= kTreelet)
-                    optimize_treelet(T, j, w);
-            }
-            __syncthreads();
-            refresh_level(T, lv);  // costs above depend on this level's new subtrees
-            __syncthreads();
-        }
-        compute_levels(T);
-        refresh_bottom_up(T);
-    }
-}
-
-// Load the subtree below global node `root` (an internal node) into T; a
-// child becomes a local leaf when it is a leaf or when stop(child) says so
-// (the nodes above the tiles stop at the tile roots).  Block-wide.
 template <typename Stop, typename LeafCost>
 __device__ void load_tree(TileLds &T, const Node *__restrict__ nodes, int root, Stop stop, LeafCost leaf_cost) {
     const int tid = threadIdx.x;
@@ -315,7 +305,9 @@ __device__ void load_tree(TileLds &T, const Node *__restrict__ nodes, int root, 
         T.n_in = 1;
         T.n_lf = 0;
         T.overflow = 0;
+        T.root = 0;
         T.in_slot[0] = root;
+        T.in_parent[0] = -1;
         T.lvl_start[0] = 0;
         T.lvl_start[1] = 1;
     }
@@ -345,6 +337,7 @@ __device__ void load_tree(TileLds &T, const Node *__restrict__ nodes, int root, 
                         continue;
                     }
                     T.in_slot[id] = c;
+                    T.in_parent[id] = j;
                     for (int a = 0; a < 6; ++a)
                         T.in_box[a][id] = cb[side][a];
                     T.in_child[side][j] = id;
@@ -363,6 +356,7 @@ __device__ void load_tree(TileLds &T, const Node *__restrict__ nodes, int root, 
                     T.lf_count[id] = count;
                     T.lf_lo[id] = lo;
                     T.lf_hi[id] = hi;
+                    T.lf_parent[id] = j;
                     T.in_child[side][j] = ~id;
                 }
             }
@@ -375,6 +369,59 @@ __device__ void load_tree(TileLds &T, const Node *__restrict__ nodes, int root, 
 }
 
 // Write the local tree back: node words, parents; returns nothing.  Block-wide.
+// Load the radix-tree subtree rooted at internal node c in one parallel
+// step.  In the radix-tree numbering a subtree over sorted leaves [a, b] is
+// rooted at a or b and holds exactly the internal nodes [a, b - 1] (root a)
+// or [a + 1, b] (root b), so local ids are offsets from that base and no
+// traversal is needed.
+__device__ void load_tile(TileLds &T, const Node *__restrict__ nodes, int c) {
+    const int a = nodes[c].refs.z, b = nodes[c].refs.w;
+    const int base = c == a ? a : a + 1;
+    const int n_in = b - a < kTile ? b - a : 0;  // tiles hold at most kTile leaves
+    for (int j = threadIdx.x; j < n_in; j += blockDim.x) {
+        const Node *nd = nodes + base + j;
+        const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
+        const int4 refs = nd->refs;
+        const float cb[2][6] = {{L.x, L.z, Z.x, L.y, L.w, Z.y}, {R.x, R.z, Z.z, R.y, R.w, Z.w}};
+        T.in_slot[j] = base + j;
+        const int child[2] = {refs.x, refs.y};
+        for (int side = 0; side < 2; ++side) {
+            const int g = child[side];
+            if (g >= 0) {
+                const int id = g - base;
+                T.in_parent[id] = j;
+                for (int e = 0; e < 6; ++e)
+                    T.in_box[e][id] = cb[side][e];
+                T.in_child[side][j] = id;
+            } else {
+                const int id = ~g - a;
+                T.lf_ref[id] = g;
+                T.lf_parent[id] = j;
+                for (int e = 0; e < 6; ++e)
+                    T.lf_box[e][id] = cb[side][e];
+                T.lf_cost[id] = tri_cost(cb[side]);
+                T.lf_count[id] = 1;
+                T.lf_lo[id] = T.lf_hi[id] = ~g;
+                T.in_child[side][j] = ~id;
+            }
+        }
+        if (base + j == c) {
+            T.in_parent[j] = -1;
+            for (int e = 0; e < 3; ++e) {
+                T.in_box[e][j] = fminf(cb[0][e], cb[1][e]);
+                T.in_box[3 + e][j] = fmaxf(cb[0][3 + e], cb[1][3 + e]);
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        T.n_in = n_in;
+        T.n_lf = n_in ? n_in + 1 : 0;
+        T.root = c - base;
+        T.overflow = 0;
+    }
+    __syncthreads();
+}
+
 __device__ void store_tree(const TileLds &T, Node *nodes, int32_t *parent, int n) {
     for (int j = threadIdx.x; j < T.n_in; j += blockDim.x) {
         const int g = T.in_slot[j];
@@ -402,10 +449,6 @@ __device__ void store_tree(const TileLds &T, Node *nodes, int32_t *parent, int n
     }
 }
 
-__device__ __forceinline__ float tri_cost(const float *b) {
-    return kCostTri * half_area(b[0], b[1], b[2], b[3], b[4], b[5]);
-}
-
 // One workgroup per tile of the radix-tree kernel's list.
 __global__ __launch_bounds__(kTile) void k_restructure_tiles(Node *nodes, int32_t *parent, int n,
                                                              const int32_t *__restrict__ tiles,
@@ -418,19 +461,11 @@ __global__ __launch_bounds__(kTile) void k_restructure_tiles(Node *nodes, int32_
         const int c = tiles[e];
         if (c < 0)
             continue;  // a one-leaf tile
-        auto stop = [](int) { return false; };
-        auto leaf_cost = [](int ref, const float *b, int &count, int &lo, int &hi) {
-            count = 1;
-            lo = hi = ~ref;
-            return tri_cost(b);
-        };
-        load_tree(T, nodes, c, stop, leaf_cost);
-        if (!T.overflow) {
-            restructure_local(T, rounds);
-            store_tree(T, nodes, parent, n);
-            if (threadIdx.x == 0)
-                tile_cost[c] = T.in_cost[0];
-        }
+        load_tile(T, nodes, c);
+        restructure_local(T, rounds);
+        store_tree(T, nodes, parent, n);
+        if (threadIdx.x == 0)
+            tile_cost[c] = T.n_in ? T.in_cost[T.root] : 0.0f;
         __syncthreads();  // LDS is reused by the next tile
     }
 }

@@ -233,3 +233,11 @@ def test_restructured_build_is_a_valid_cheaper_tree(case):
             assert sb < 0.95 * sa
         for w in ("nodes", "parents", "counters"):
             assert np.array_equal(export(b, w), export(c, w)), w
+        # parent links agree with the rewired children
+        n_int = F.shape[0] - 1
+        par = export(b, "parents")
+        if n_int > 0:
+            assert par[0] == -1
+            for i in range(n_int):
+                for r in (tb["left"][i], tb["right"][i]):
+                    assert par[r if r >= 0 else n_int + ~r] == i
