@@ -34,7 +34,7 @@ constexpr float kBoundK = 12.0f * 0x1p-24f;  // >= 8 u32 (binary32) + 8 u64 (bin
 constexpr float kBoundTiny = 0x1p-140f;      // absorbs underflow in the products
 constexpr int kMiss = 0, kHit = 1, kUnsure = 2;
 enum { MODE_BOOL = 0, MODE_FIRST = 1, MODE_BARY = 2, MODE_COUNT = 3 };
-constexpr int kCountSlots = 8;  // distinct t a lane keeps in registers in count mode
+constexpr int kCountSlots = 12;  // distinct t a lane keeps in registers in count mode
 
 struct Ray {
     float3 o, d;   // start point, direction E - O (rounded)
@@ -298,8 +298,7 @@ constexpr int kDone = INT32_MIN;  // nothing left for the lane's segment
 // subtree; phase 1 the whole tree with that subtree left out.  Together they
 // visit exactly what the plain order visits, so results do not change.
 template <int MODE, bool CERT, bool STATS, bool PROP>
-__global__ __launch_bounds__(256) void k_traverse(TravParams p) {
-    extern __shared__ int lds_stack[];
+__device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     int *stk = lds_stack + threadIdx.x;
     const int stride = blockDim.x;
     const int lane = threadIdx.x & 63;
@@ -607,6 +606,21 @@ __global__ __launch_bounds__(256) void k_traverse(TravParams p) {
         if (lane == 0 && w)
             atomicAdd(p.counters + 2, (unsigned long long)w);
     }
+}
+
+template <int MODE, bool CERT, bool STATS, bool PROP>
+__global__ __launch_bounds__(256) void k_traverse(TravParams p) {
+    extern __shared__ int lds_stack[];
+    traverse_pass1<MODE, CERT, STATS, PROP>(p, lds_stack);
+}
+
+// Count mode holds its list of distinct t in registers; the register budget
+// is fixed at four waves per SIMD (the default resident count) so the list
+// cannot lower occupancy.
+template <bool CERT, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_traverse_count(TravParams p) {
+    extern __shared__ int lds_stack[];
+    traverse_pass1<MODE_COUNT, CERT, STATS, false>(p, lds_stack);
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -1071,8 +1085,12 @@ void launch_pass1(const TravParams &p, int block, hipStream_t s) {
     int dev = 0, cus = 256, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(&k_traverse<MODE, CERT, STATS, PROP>), block, lds);
+    void (*kern)(TravParams) = nullptr;
+    if constexpr (MODE == MODE_COUNT)
+        kern = &k_traverse_count<CERT, STATS>;
+    else
+        kern = &k_traverse<MODE, CERT, STATS, PROP>;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), block, lds);
     const int cap = p.waves_per_cu / (block / 64);  // resident blocks per CU asked for
     per_cu = per_cu < cap ? per_cu : cap;
     if (per_cu < 1)
@@ -1080,7 +1098,7 @@ void launch_pass1(const TravParams &p, int block, hipStream_t s) {
     const int64_t want = (p.n + block - 1) / block;
     const int64_t resident = (int64_t)cus * per_cu;
     const int grid = (int)(want < resident ? want : resident);
-    k_traverse<MODE, CERT, STATS, PROP><<<grid, block, lds, s>>>(p);
+    kern<<<grid, block, lds, s>>>(p);
 }
 
 template <int MODE, bool STATS>

@@ -30,7 +30,7 @@ def stacked(k):
 
 
 def test_closed_form_scenes():
-    for k in (1, 3, 8, 9, 20, 40):  # more than 8 distinct hits go to the second pass
+    for k in (1, 3, 8, 12, 13, 20, 40):  # more than 12 distinct hits go to the second pass
         V, F = stacked(k)
         O = np.array([[0.5, 0.5, k + 0.5], [0.75, 0.25, k + 0.5], [0.75, 0.25, -0.5], [2.0, 2.0, 1.0]], np.float32)
         E = np.array([[0.5, 0.5, -0.5], [0.75, 0.25, -0.5], [0.75, 0.25, 0.0], [2.0, 2.0, -1.0]], np.float32)
@@ -39,7 +39,7 @@ def test_closed_form_scenes():
         with rsi.rsi_build(dev(V), dev(F)) as mesh:
             got, cnt = gpu_count(mesh, O, E)
             assert got.tolist() == want.tolist(), k
-            if k > 8:
+            if k > 12:
                 assert cnt[3] >= 2  # the two vertical segments outgrew the lane's list
             plain, _ = gpu_count(mesh, O, E, "plain")
             assert plain.tolist() == want.tolist()
