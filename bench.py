@@ -5,9 +5,12 @@ Workload: the paper-scale case -- a 128 x 128 heightfield (32,258 triangles,
 seeded sinusoids + noise) and 1e7 segments with end points uniform in the mesh
 box inflated by 10% (synthetic stand-in for the paper's 29,260-triangle /
 1e7-ray data, which is not available).  One step = the whole path: build the
-BVH (extent, Morton keys, LDS radix sort, radix tree, bottom-up boxes) and
-intersect every segment (traversal, leaf tests, binary64 re-decisions), with
-the inputs already resident in GPU memory.  The metric is Mrays/s.
+BVH (extent, Morton keys, LDS radix sort, radix tree, bottom-up boxes, and by
+default two passes of treelet restructuring, which changes node visits but
+never results) and intersect every segment (traversal, leaf tests, binary64
+re-decisions), with the inputs already resident in GPU memory.  The metric is
+Mrays/s.  --build radix_tree times the paper's own LBVH instead; the
+variants record that step either way.
 
 Printed: one JSON line (rank 0).  Besides the contract fields it carries
   roofline      the traversal launch: algorithmic bytes (segments in, results
@@ -41,6 +44,8 @@ def parse():
     ap.add_argument("--rays", type=int, default=10_000_000)
     ap.add_argument("--mode", default="boolean", choices=["boolean", "first_hit", "barycentric", "intercept_count"])
     ap.add_argument("--precision", default="certified", choices=["plain", "certified"])
+    ap.add_argument("--build", default="restructured", choices=["radix_tree", "restructured", "agglomerative"],
+                    help="BVH build of the timed step")
     ap.add_argument("--cpu-seconds", type=float, default=24.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -71,16 +76,17 @@ def calibrate_copy():
                       "launches": 3}), flush=True)
 
 
-def measured_traffic(mode, precision):
+def measured_traffic(mode, precision, build):
     """HBM bytes per traversal launch from the committed rocprofv3 counter
-    summary, or None when the traversal source changed since it was taken."""
+    summary, or None when the traversal source or the tree build differs
+    from the one it was taken with."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(f"{mode}_{precision}")
-    if not rec:
+    if not rec or rec.get("build") != build:
         return None
     src = open(os.path.join(ROOT, "paper_2305_01867_amd", "csrc", "traverse.hip"), "rb").read()
     if hashlib.sha256(src).hexdigest() != rec["traverse_hip_sha256"]:
@@ -147,8 +153,11 @@ def main():
             o["count"] = torch.empty(n, dtype=torch.int32, device=dev)
         outs[m] = o
 
-    def step(mode=args.mode, precision=args.precision, ev=None):
-        mesh = rsi.rsi_build(dV, dF)
+    def build(gV=None, gF=None, algorithm=args.build):
+        return rsi.rsi_build(dV if gV is None else gV, dF if gF is None else gF, algorithm=algorithm)
+
+    def step(mode=args.mode, precision=args.precision, ev=None, algorithm=args.build):
+        mesh = build(algorithm=algorithm)
         if ev is not None:
             ev[0].record(stream)
         rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision=precision, out=outs[mode])
@@ -185,7 +194,7 @@ def main():
     results = {f"{args.precision} (timed path)": outs[args.mode][key][:keep].cpu().numpy().copy()}
 
     # ---------------- algorithmic bytes of the traversal (instrumented, untimed)
-    with rsi.rsi_build(dV, dF) as mesh:
+    with build() as mesh:
         visits, tests = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision)
         torch.cuda.synchronize()
         mean_visits = float(visits.double().mean().item())
@@ -197,7 +206,8 @@ def main():
     achieved_gbs = n * bytes_per_ray / (intersect_avg * 1e-3) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.mode, args.precision),
+        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(args.mode, args.precision, args.build),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": "k_traverse (+ k_reset, k_finish in the same event pair)",
         "bytes_per_ray": round(bytes_per_ray, 1), "mean_node_visits": round(mean_visits, 2),
@@ -214,7 +224,7 @@ def main():
     # ---------------- per-variant intersect throughput (untimed region)
     variants = {}
     if not args.no_variants:
-        with rsi.rsi_build(dV, dF) as mesh:
+        with build() as mesh:
             for mode in ("boolean", "first_hit", "barycentric", "intercept_count"):
                 for prec in ("plain", "certified"):
                     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -246,20 +256,37 @@ def main():
                 variants[f"{args.mode}/{args.precision}/order={order}"] = {
                     "mrays_s": round(n / (ms * 1e-3) / 1e6, 1), "ms": round(ms, 3)}
                 results[f"{args.precision}, order={order}"] = outs[args.mode][key][:keep].cpu().numpy().copy()
-            b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            b0.record(stream)
-            for _ in range(5):
-                rsi.rsi_build(dV, dF).close()
-            b1.record(stream)
-            torch.cuda.synchronize()
-            variants["build_ms"] = round(b0.elapsed_time(b1) / 5, 4)
-            rsi.rsi_build(dV, dF, algorithm="agglomerative").close()
+            for alg in ("radix_tree", "restructured"):
+                b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                build(algorithm=alg).close()
+                b0.record(stream)
+                for _ in range(5):
+                    build(algorithm=alg).close()
+                b1.record(stream)
+                torch.cuda.synchronize()
+                variants[f"build_ms_{alg}"] = round(b0.elapsed_time(b1) / 5, 4)
+            build(algorithm="agglomerative").close()
             torch.cuda.synchronize()
             t_a = time.perf_counter()
             for _ in range(5):
-                rsi.rsi_build(dV, dF, algorithm="agglomerative").close()  # waits once per build for the root
+                build(algorithm="agglomerative").close()  # waits once per build for the root
             torch.cuda.synchronize()
             variants["build_ms_agglomerative"] = round((time.perf_counter() - t_a) * 1e3 / 5, 4)
+        # the whole step with each tree (same segments, same results)
+        for alg in ("radix_tree", "restructured"):
+            step(algorithm=alg)
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            for _ in range(3):
+                step(algorithm=alg)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - s0) * 1e3 / 3
+            with build(algorithm=alg) as mesh:
+                v_alg, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision)
+                mv = float(v_alg.double().mean().item())
+            variants[f"step/{args.mode}/{args.precision}/build={alg}"] = {
+                "mrays_s": round(n / (ms * 1e-3) / 1e6, 1), "ms": round(ms, 3), "mean_node_visits": round(mv, 2)}
+            results[f"{args.precision}, build={alg}"] = outs[args.mode][key][:keep].cpu().numpy().copy()
 
     # ---------------- learned proposal vs plain order (BVH resident, untimed region)
     learned = None
@@ -267,7 +294,7 @@ def main():
         lo, hi = V.min(axis=0), V.max(axis=0)
         Ot, Et = workloads.rays_in_box(args.train_rays, 23, lo, hi)  # training segments, own seed
         dOt, dEt = torch.from_numpy(Ot).to(dev), torch.from_numpy(Et).to(dev)
-        with rsi.rsi_build(dV, dF) as mesh:
+        with build() as mesh:
             torch.cuda.synchronize()
             t_tr = time.perf_counter()
             loss, n_lab = rsi.rsi_proposal_train(mesh, dOt, dEt, epochs=args.train_epochs, batch=4096, lr=2e-3,
@@ -321,7 +348,7 @@ def main():
             def job():
                 gV, gF = hV.to(dev, non_blocking=True), hF.to(dev, non_blocking=True)
                 gO, gE = hO.to(dev, non_blocking=True), hE.to(dev, non_blocking=True)
-                with rsi.rsi_build(gV, gF) as mesh:
+                with build(gV, gF) as mesh:
                     r = rsi.rsi_intersect(mesh, gO, gE, mode=hmode, precision=args.precision)
                     if hmode == "barycentric":
                         res = tuple(x.cpu() for x in rsi.rsi_compact_hits(gO, gE, r))
@@ -417,7 +444,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "heightfield 128x128 (32,258 triangles), 1e7 segments in the 10%-inflated box",
-                   "mode": args.mode, "precision": args.precision, "n_triangles": int(F.shape[0]),
+                   "mode": args.mode, "precision": args.precision, "build": args.build,
+                   "n_triangles": int(F.shape[0]),
                    "n_rays": int(n), "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
