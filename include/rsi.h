@@ -47,7 +47,9 @@
 extern "C" {
 #endif
 
-#define RSI_ABI_VERSION 4  /* 2: intercept-count mode, rsi_outputs.count; 3: waves_per_cu; 4: build algorithm */
+#define RSI_ABI_VERSION 5  /* 2: intercept-count mode, rsi_outputs.count; 3: waves_per_cu; 4: build algorithm;
+                              5: 4-wide nodes (node_width, rsi_mesh_info.node_width, RSI_EXPORT_WIDE_NODES,
+                              RSI_EXPORT_WIDE_TOP) */
 
 typedef struct rsi_mesh_s *rsi_mesh; /* opaque; owned by the library until rsi_destroy */
 
@@ -108,19 +110,25 @@ typedef struct rsi_build_opts {
                               as in the paper's Case Study 1 dump): the same tree with
                               internal nodes numbered by their split position; the
                               build waits once to learn the root's index.  2: the radix
-                              tree, then three passes of treelet restructuring (Karras
+                              tree, then two passes of treelet restructuring (Karras
                               & Aila 2013): internal nodes rewired to lower the tree's
                               surface-area cost, so queries visit fewer nodes; a node's
                               leaves are then no longer a contiguous range (words 14 /
                               15 of RSI_EXPORT_NODES hold their smallest and largest
-                              sorted position).  Results of rsi_intersect do not
-                              depend on it. */
+                              sorted position).  Algorithms 0 and 2 also collapse the
+                              binary tree into a 4-wide one (RSI_EXPORT_WIDE_NODES)
+                              for the single-mesh traversal; 128 B more per triangle
+                              and 64 KB per mesh.
+                              Results of rsi_intersect do not depend on the algorithm. */
 } rsi_build_opts;
 
 /* Intersection options; pass NULL for defaults. */
 typedef struct rsi_intersect_opts {
     int32_t precision;    /* rsi_precision; default RSI_PRECISION_PLAIN */
-    int32_t block;        /* threads per workgroup: 64, 128 or 256; 0 = 256 */
+    int32_t block;        /* threads per workgroup of the first pass: 64, 128, 256,
+                             512 or 1024; 0 = the library default.  With 4-wide
+                             nodes a larger workgroup keeps more of the tree's top
+                             in its LDS. */
     int32_t stack_depth;  /* traversal stack entries per lane in LDS, 1..64; 0 = 20.
                              Deeper paths are finished exactly by a second pass. */
     int32_t ray_sort;     /* rsi_ray_order: order in which segments are processed.
@@ -133,6 +141,11 @@ typedef struct rsi_intersect_opts {
                              traversal, 1..32 (capped by what registers and LDS
                              allow); 0 = the library default.  Fewer waves share a
                              CU's L1 cache among fewer tree paths. */
+    int32_t node_width;   /* tree the first pass walks: 0 = the widest the mesh has
+                             (4 for build algorithms 0 and 2; binary for algorithm 1,
+                             the batched form and the proposal order), 2 = binary
+                             nodes, 4 = 4-wide nodes (RSI_E_ARG where not built).
+                             Results do not depend on it. */
 } rsi_intersect_opts;
 
 /* Output buffers (device pointers, caller-owned).  Required per mode:
@@ -208,6 +221,8 @@ typedef struct rsi_mesh_info {
     int32_t root;            /* root reference: 0 (internal node 0), ~0 (single leaf), or
                                 INT32_MIN for an empty mesh */
     int64_t device_bytes;    /* device memory held by the mesh */
+    int32_t node_width;      /* 4 when the 4-wide tree is built, else 2 */
+    int32_t reserved;        /* 0 */
 } rsi_mesh_info;
 
 rsi_status rsi_mesh_info_get(rsi_mesh mesh, rsi_mesh_info *info);
@@ -231,8 +246,26 @@ typedef enum rsi_export_what {
                                    node by the bottom-up pass (2 when complete)          */
     RSI_EXPORT_LEAVES = 5,      /* 12 x 32-bit words per sorted leaf, [N_t]: A.xyz,
                                    triangle index (int32), B-A xyz, 0, C-A xyz, 0        */
-    RSI_EXPORT_BOUNDS = 6       /* float [8]: mesh lo xyz, hi xyz, coordinate scale
+    RSI_EXPORT_BOUNDS = 6,      /* float [8]: mesh lo xyz, hi xyz, coordinate scale
                                    (largest |coordinate|), 0                              */
+    RSI_EXPORT_WIDE_NODES = 7,  /* 32 x 32-bit words per slot, [N_t - 1] (nothing when
+                                   node_width is 2): words 0-3 x lo of children 0..3,
+                                   4-7 x hi, 8-11 y lo, 12-15 y hi, 16-19 z lo, 20-23
+                                   z hi, 24-27 child references, word 28 the number of
+                                   children, 29-31 zero.  A child reference r is a leaf
+                                   at sorted position ~r when r < 0, INT32_MIN for an
+                                   unused slot (its box is +inf on every face), the
+                                   top node in slot r of RSI_EXPORT_WIDE_TOP when
+                                   0 <= r < 512, and otherwise the 4-wide node in slot
+                                   r - 512 of this array (the node collapsed from binary
+                                   internal node r - 512).  Only reachable slots are
+                                   defined.                                              */
+    RSI_EXPORT_WIDE_TOP = 8     /* 32 x 32-bit words per slot, [512] (nothing when
+                                   node_width is 2): the first 4-wide nodes in
+                                   breadth-first order from the root (the root in slot
+                                   0), as above, with references to other top nodes
+                                   rewritten to their slots; kept in LDS by the
+                                   traversal.  Slots past the tree's size are undefined. */
 } rsi_export_what;
 
 /* Copy one internal array into dst (device or host memory of dst_bytes bytes,
@@ -243,7 +276,8 @@ rsi_status rsi_mesh_export(rsi_mesh mesh, int32_t what, void *dst, int64_t dst_b
 /*
  * rsi_traversal_stats -- per-segment work of the same traversal rsi_intersect
  * runs with these arguments (an instrumented copy of the kernel; results are
- * not written).  node_visits[i] counts internal nodes fetched, leaf_tests[i]
+ * not written).  node_visits[i] counts internal nodes fetched (4-wide nodes
+ * when the first pass walks them, see node_width), leaf_tests[i]
  * triangles tested; both uint32 [n_rays] device arrays.  Segments finished by
  * the second (deep-stack) pass report the first pass's counts.
  */

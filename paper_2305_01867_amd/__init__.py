@@ -30,10 +30,11 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "librsi.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 MODES = {"boolean": 0, "first_hit": 1, "barycentric": 2, "intercept_count": 3}
 PRECISIONS = {"plain": 0, "certified": 1}
-EXPORTS = {"sorted_keys": 0, "sorted_ids": 1, "nodes": 2, "parents": 3, "counters": 4, "leaves": 5, "bounds": 6}
+EXPORTS = {"sorted_keys": 0, "sorted_ids": 1, "nodes": 2, "parents": 3, "counters": 4, "leaves": 5, "bounds": 6,
+           "wide_nodes": 7, "wide_top": 8}
 STATUS = {0: "RSI_OK", 1: "RSI_E_ARG", 2: "RSI_E_RANGE", 3: "RSI_E_NOMEM", 4: "RSI_E_HIP",
           5: "RSI_E_STATE", 6: "RSI_E_CAPACITY"}
 
@@ -50,7 +51,8 @@ class _BuildOpts(ctypes.Structure):
 
 class _IntersectOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("block", ctypes.c_int32), ("stack_depth", ctypes.c_int32),
-                ("ray_sort", ctypes.c_int32), ("proposal", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+                ("ray_sort", ctypes.c_int32), ("proposal", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("node_width", ctypes.c_int32)]
 
 
 class _Outputs(ctypes.Structure):
@@ -70,7 +72,8 @@ MLP_BUCKETS = 256
 
 class _MeshInfo(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64), ("morton_bits", ctypes.c_int32),
-                ("root", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("root", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("node_width", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -221,7 +224,7 @@ def rsi_destroy(mesh: Mesh):
 RAY_ORDERS = {"input": 0, "midpoint": 1, "origin_octant": 2}
 
 
-def _iopts(precision, block, stack_depth, proposal=False, ray_sort=0, waves_per_cu=0):
+def _iopts(precision, block, stack_depth, proposal=False, ray_sort=0, waves_per_cu=0, node_width=0):
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")
     if isinstance(ray_sort, str):
@@ -229,19 +232,21 @@ def _iopts(precision, block, stack_depth, proposal=False, ray_sort=0, waves_per_
             raise ValueError(f"ray_sort must be one of {list(RAY_ORDERS)}")
         ray_sort = RAY_ORDERS[ray_sort]
     return _IntersectOpts(PRECISIONS[precision], int(block), int(stack_depth), int(ray_sort), int(bool(proposal)),
-                          int(waves_per_cu))
+                          int(waves_per_cu), int(node_width))
 
 
 def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
                   precision: str = "plain", block: int = 0, stack_depth: int = 0, out: dict | None = None,
-                  stream=None, proposal: bool = False, ray_sort=0, waves_per_cu: int = 0) -> dict:
+                  stream=None, proposal: bool = False, ray_sort=0, waves_per_cu: int = 0,
+                  node_width: int = 0) -> dict:
     """Test segments [N, 3] float32 against the mesh.  Returns a dict with the
     outputs of the mode ("hit" uint8, "tri_id" int32, "uvt" float32 [N, 3],
     "count" int32) and "counters" uint64 [4] (re-decided in binary64, past the
     LDS stack, proposal misses, count-mode list overflows).
     `out` may supply preallocated tensors under the same keys.  ray_sort:
     processing order ("input", "midpoint", "origin_octant" or 0 / 1 / 2);
-    results are at input indices in every order."""
+    results are at input indices in every order.  node_width: tree the first
+    pass walks (0 the widest built, 2 binary, 4 the 4-wide tree)."""
     if mode not in MODES:
         raise ValueError(f"mode must be one of {list(MODES)}")
     _need(rays_from, "rays_from", torch.float32, 3)
@@ -275,7 +280,7 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
         return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()
 
     o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"), ptr("count"))
-    opts = _iopts(precision, block, stack_depth, proposal, ray_sort, waves_per_cu)
+    opts = _iopts(precision, block, stack_depth, proposal, ray_sort, waves_per_cu, node_width)
     _check(lib().rsi_intersect(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
                                ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
                                ctypes.byref(o), _stream_handle(stream)))
@@ -284,14 +289,15 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
 
 def rsi_traversal_stats(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
                         precision: str = "plain", block: int = 0, stack_depth: int = 0, stream=None,
-                        proposal: bool = False, ray_sort=0, waves_per_cu: int = 0):
-    """Per-segment (node visits, leaf tests) of the traversal, uint32 -> int64 tensors."""
+                        proposal: bool = False, ray_sort=0, waves_per_cu: int = 0, node_width: int = 0):
+    """Per-segment (node visits, leaf tests) of the traversal (int32 tensors;
+    visits count 4-wide nodes when the first pass walks them)."""
     _need(rays_from, "rays_from", torch.float32, 3)
     _need(rays_to, "rays_to", torch.float32, 3)
     n = rays_from.shape[0]
     visits = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
     tests = torch.zeros(n, dtype=torch.int32, device=rays_from.device)
-    opts = _iopts(precision, block, stack_depth, proposal, ray_sort, waves_per_cu)
+    opts = _iopts(precision, block, stack_depth, proposal, ray_sort, waves_per_cu, node_width)
     _check(lib().rsi_traversal_stats(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
                                      ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
                                      ctypes.c_void_p(visits.data_ptr()), ctypes.c_void_p(tests.data_ptr()),
@@ -393,6 +399,8 @@ def rsi_mesh_export(mesh: Mesh, what: str, stream=None) -> torch.Tensor:
         "nodes": ((max(nt - 1, 0), 16), torch.int32), "parents": ((max(2 * nt - 1, 0),), torch.int32),
         "counters": ((max(nt - 1, 0),), torch.int32), "leaves": ((nt, 12), torch.int32),
         "bounds": ((8 if nt > 0 else 0,), torch.float32),
+        "wide_nodes": ((max(nt - 1, 0) if rsi_mesh_info_get(mesh)["node_width"] == 4 else 0, 32), torch.int32),
+        "wide_top": ((512 if rsi_mesh_info_get(mesh)["node_width"] == 4 else 0, 32), torch.int32),
     }
     if what not in shapes:
         raise ValueError(f"what must be one of {list(shapes)}")

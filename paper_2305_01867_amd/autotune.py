@@ -8,7 +8,8 @@ without timing.  The default grid covers threads per workgroup, the LDS
 stack depth (occupancy against how often a segment overflows to the
 deep-stack pass), the resident waves per CU (fewer waves share a CU's L1
 among fewer tree paths) and the segment processing order; MORTON_BITS can be added
-for a `run` that rebuilds the tree (30-bit against 63-bit keys).
+for a `run` that rebuilds the tree (30-bit against 63-bit keys), NODE_WIDTHS
+for a single-mesh `run` (4-wide against binary nodes).
 """
 from __future__ import annotations
 
@@ -19,11 +20,12 @@ import os
 
 import torch
 
-BLOCKS = (64, 128, 256)
+BLOCKS = (64, 128, 256, 512, 1024)
 STACKS = (8, 12, 16, 20, 24, 32)
 RAY_SORTS = (0, 1, 2)  # input order, midpoint Morton, octant + start Morton
 WAVES_PER_CU = (0, 8, 12, 16, 24)  # 0: as many as registers and LDS allow
 MORTON_BITS = (30, 63)
+NODE_WIDTHS = (0, 2)  # the widest tree built (4-wide for one mesh) against binary nodes
 SPACE = {"block": BLOCKS, "stack_depth": STACKS, "ray_sort": RAY_SORTS, "waves_per_cu": WAVES_PER_CU}
 
 

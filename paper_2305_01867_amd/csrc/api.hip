@@ -118,20 +118,22 @@ size_t round_up(size_t x) { return (x + 255) & ~size_t(255); }
 bool valid_mesh(rsi_mesh m) { return m != nullptr && m->magic == kMagic; }
 
 rsi_status parse_intersect_opts(const rsi_intersect_opts *opts, int &precision, int &block, int &stack,
-                                int &ray_sort, int &waves) {
+                                int &ray_sort, int &waves, int &width) {
     precision = RSI_PRECISION_PLAIN;
-    block = 256;
+    block = 0;  // the library default of the first pass it runs
     stack = 20;
     ray_sort = RSI_RAY_ORDER_INPUT;
     waves = 0;
+    width = 0;
     if (!opts)
         return RSI_OK;
     if (opts->precision != RSI_PRECISION_PLAIN && opts->precision != RSI_PRECISION_CERTIFIED)
         return fail(RSI_E_ARG, "precision must be RSI_PRECISION_PLAIN or RSI_PRECISION_CERTIFIED");
     precision = opts->precision;
     if (opts->block != 0) {
-        if (opts->block != 64 && opts->block != 128 && opts->block != 256)
-            return fail(RSI_E_ARG, "block must be 64, 128 or 256");
+        if (opts->block != 64 && opts->block != 128 && opts->block != 256 && opts->block != 512 &&
+            opts->block != 1024)
+            return fail(RSI_E_ARG, "block must be 64, 128, 256, 512 or 1024");
         block = opts->block;
     }
     if (opts->stack_depth != 0) {
@@ -148,6 +150,9 @@ rsi_status parse_intersect_opts(const rsi_intersect_opts *opts, int &precision, 
     if (opts->waves_per_cu < 0 || opts->waves_per_cu > 32)
         return fail(RSI_E_ARG, "waves_per_cu must be in 0..32");
     waves = opts->waves_per_cu;
+    if (opts->node_width != 0 && opts->node_width != 2 && opts->node_width != 4)
+        return fail(RSI_E_ARG, "node_width must be 0 (widest built), 2 or 4");
+    width = opts->node_width;
     return RSI_OK;
 }
 
@@ -242,10 +247,14 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *t
     const size_t sz_V = round_up(12 * (size_t)n_vertices), sz_F = round_up(12 * (size_t)nt);
     const size_t sz_keys = round_up(kb * nt), sz_ids = round_up(4 * (size_t)nt);
     const size_t sz_nodes = round_up(64 * (size_t)(nt > 1 ? nt - 1 : 1));
+    // the 4-wide tree (one 128-B slot per binary internal node), for the
+    // builds whose tile list it is collapsed with
+    const size_t sz_nodes4 = (algorithm != 1 && nt > 1) ? round_up(128 * (size_t)(nt - 1 + rsi::kTopSlots)) : 0;
     const size_t sz_par = round_up(4 * (size_t)(2 * nt - 1)), sz_cnt = round_up(4 * (size_t)(nt > 1 ? nt - 1 : 1));
     const size_t sz_tris = round_up(48 * (size_t)nt), sz_small = 256;
     const size_t sz_tmp = round_up(rsi::sort_tmp_bytes(nt, bits));
-    const size_t total = sz_V + sz_F + sz_keys + sz_ids + sz_nodes + sz_par + sz_cnt + sz_tris + sz_small + sz_tmp;
+    const size_t total =
+        sz_V + sz_F + sz_keys + sz_ids + sz_nodes + sz_nodes4 + sz_par + sz_cnt + sz_tris + sz_small + sz_tmp;
     hipError_t e = hipMallocAsync(&m->block, total, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -265,6 +274,8 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *t
     d.keys = take(sz_keys);
     d.ids = reinterpret_cast<int32_t *>(take(sz_ids));
     d.nodes = reinterpret_cast<rsi::Node *>(take(sz_nodes));
+    d.nodes4 = sz_nodes4 ? reinterpret_cast<rsi::Node4 *>(take(sz_nodes4)) : nullptr;
+    d.top4 = d.nodes4 ? d.nodes4 + (nt - 1) : nullptr;
     d.parent = reinterpret_cast<int32_t *>(take(sz_par));
     d.counters = reinterpret_cast<int32_t *>(take(sz_cnt));
     d.tris = reinterpret_cast<rsi::Tri *>(take(sz_tris));
@@ -344,14 +355,18 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     rsi_status st = check_ray_args(mesh, from, to, n, mode);
     if (st != RSI_OK)
         return st;
-    int precision, block, stack, ray_sort, waves;
-    if ((st = parse_intersect_opts(opts, precision, block, stack, ray_sort, waves)) != RSI_OK)
+    int precision, block, stack, ray_sort, waves, width;
+    if ((st = parse_intersect_opts(opts, precision, block, stack, ray_sort, waves, width)) != RSI_OK)
         return st;
     const bool use_prop = opts && opts->proposal == 1 && n > 0 && mesh->dev.nt > 0;
     if (use_prop && mode == RSI_MODE_INTERCEPT_COUNT)
         return fail(RSI_E_ARG, "intercept-count mode has no proposal order");
     if (use_prop && !mesh->dev.prop.ready)
         return fail(RSI_E_STATE, "proposal = 1 needs a trained or loaded proposal (rsi_proposal_train / _load)");
+    if (width == 4 && mesh->dev.node_width != 4)
+        return fail(RSI_E_ARG, "node_width = 4 needs a mesh built with algorithm 0 or 2 (more than one triangle)");
+    if (width == 4 && use_prop)
+        return fail(RSI_E_ARG, "the proposal order runs on binary nodes (node_width 0 or 2)");
     if (!stats) {
         if (!out)
             return fail(RSI_E_ARG, "out must not be NULL");
@@ -419,6 +434,7 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     a.block = block;
     a.stack = stack;
     a.waves_per_cu = waves;
+    a.node_width = width;
     uint64_t *ws_counters = reinterpret_cast<uint64_t *>(static_cast<char *>(ws));
     a.queue_len = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + 32);
     a.queue = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + 64);
@@ -574,6 +590,8 @@ rsi_status rsi_mesh_info_get(rsi_mesh mesh, rsi_mesh_info *info) {
     info->morton_bits = mesh->dev.morton_bits;
     info->root = mesh->dev.root;
     info->device_bytes = mesh->dev.bytes;
+    info->node_width = mesh->dev.node_width;
+    info->reserved = 0;
     return RSI_OK;
 }
 
@@ -593,6 +611,8 @@ rsi_status rsi_mesh_export(rsi_mesh mesh, int32_t what, void *dst, int64_t dst_b
     case RSI_EXPORT_COUNTERS: src = d.counters; bytes = nt > 1 ? 4 * (nt - 1) : 0; break;
     case RSI_EXPORT_LEAVES: src = d.tris; bytes = 48 * nt; break;
     case RSI_EXPORT_BOUNDS: src = d.bounds; bytes = nt > 0 ? 32 : 0; break;
+    case RSI_EXPORT_WIDE_NODES: src = d.nodes4; bytes = d.node_width == 4 ? 128 * (nt - 1) : 0; break;
+    case RSI_EXPORT_WIDE_TOP: src = d.top4; bytes = d.node_width == 4 ? 128 * rsi::kTopSlots : 0; break;
     default: return fail(RSI_E_ARG, "unknown export item");
     }
     if (!dst && bytes > 0)
@@ -798,12 +818,14 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
     if (mode != RSI_MODE_BOOLEAN && mode != RSI_MODE_FIRST_HIT && mode != RSI_MODE_BARYCENTRIC &&
         mode != RSI_MODE_INTERCEPT_COUNT)
         return fail(RSI_E_ARG, "unknown mode");
-    int precision, block, stack, ray_sort, waves;
-    rsi_status st = parse_intersect_opts(opts, precision, block, stack, ray_sort, waves);
+    int precision, block, stack, ray_sort, waves, width;
+    rsi_status st = parse_intersect_opts(opts, precision, block, stack, ray_sort, waves, width);
     if (st != RSI_OK)
         return st;
     if (opts && opts->proposal)
         return fail(RSI_E_ARG, "the batched form has no learned proposal");
+    if (width == 4)
+        return fail(RSI_E_ARG, "the batched form traverses binary nodes (node_width 0 or 2)");
     if (!out)
         return fail(RSI_E_ARG, "out must not be NULL");
     if (n > 0 && (!rays_from || !rays_to || !aligned4(rays_from) || !aligned4(rays_to)))
@@ -830,6 +852,7 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
     a.block = block;
     a.stack = stack;
     a.waves_per_cu = waves;
+    a.node_width = width;
     a.hit = out->hit;
     a.tri_id = out->tri_id;
     a.uvt = out->uvt;

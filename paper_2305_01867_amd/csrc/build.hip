@@ -700,8 +700,9 @@ hipError_t build_from_keys(MeshDev &m, int key_bits, hipStream_t s) {
         return hipGetLastError();
     }
     // the sort's scratch is free again: the list of bottom-up tiles
-    int32_t *n_tiles = static_cast<int32_t *>(m.sort_tmp);
-    int32_t *tiles = n_tiles + 64;
+    const BuildLists L = build_lists(m.sort_tmp, nt);
+    int32_t *n_tiles = L.n_tiles;
+    int32_t *tiles = L.tiles;
     if (nt >= 2) {
         k_zero_i32<<<1, 64, 0, s>>>(n_tiles, 1);
         k_radix_tree<K><<<blocks_for(nt - 1, 256), 256, 0, s>>>(keys, (int)nt, m.nodes, m.parent, m.counters, tiles,
@@ -740,7 +741,7 @@ hipError_t launch_morton_batch(MeshDev &m, const int32_t *tri_mesh, const float 
 size_t sort_tmp_bytes(int64_t nt, int morton_bits) {
     const size_t kb = morton_bits > 32 ? 8 : 4;
     const size_t sort = pass_tmp_bytes(nt, kb);
-    const size_t lists = 4 * (size_t)nt + 4 * 64 + 256;  // tile list after the sort (at most one per leaf)
+    const size_t lists = build_lists_bytes(nt);  // lists kept after the sort
     return sort > lists ? sort : lists;
 }
 
@@ -766,6 +767,8 @@ hipError_t launch_build(MeshDev &m, const float *, const int32_t *, hipStream_t 
     hipError_t e = m.morton_bits > 32 ? build_typed<uint64_t>(m, s) : build_typed<uint32_t>(m, s);
     if (e == hipSuccess && m.algorithm == 2)
         e = launch_restructure(m, kRestructureRounds, s);
+    if (e == hipSuccess && m.algorithm != 1 && m.nodes4)
+        e = launch_collapse(m, s);
     return e;
 }
 

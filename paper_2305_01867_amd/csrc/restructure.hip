@@ -506,9 +506,10 @@ size_t restructure_lds_bytes() { return sizeof(TileLds); }
 hipError_t launch_restructure(MeshDev &m, int rounds, hipStream_t s) {
     if (m.nt < kTreelet)
         return hipSuccess;
-    int32_t *n_tiles = static_cast<int32_t *>(m.sort_tmp);  // the radix-tree kernel's tile list
-    int32_t *tiles = n_tiles + 64;
-    float *tile_cost = reinterpret_cast<float *>(tiles + ((m.nt + 63) & ~int64_t(63)));
+    const BuildLists L = build_lists(m.sort_tmp, m.nt);  // the radix-tree kernel's tile list
+    int32_t *n_tiles = L.n_tiles;
+    int32_t *tiles = L.tiles;
+    float *tile_cost = L.tile_cost;
     const size_t lds = sizeof(TileLds);
     static bool attr_set = false;
     if (!attr_set) {

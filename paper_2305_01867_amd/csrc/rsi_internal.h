@@ -18,6 +18,28 @@ struct alignas(16) Node {
 };
 static_assert(sizeof(Node) == 64, "node must be 64 bytes");
 
+// 4-wide node: the boxes of up to four children, stored axis by axis so a
+// lane fetches 112 B (seven 16-byte loads) and tests all four with the same
+// instructions.  A child reference is >= 0 for another 4-wide node (stored at
+// the index of the binary internal node it was collapsed from), < 0 for the
+// leaf at sorted position ~ref, kEmptyChild for an unused slot, whose box is
+// +inf on every face so the slab test always misses it.  128 B: one L2 line.
+struct alignas(16) Node4 {
+    float4 lox, hix;  // x lo, x hi of children 0..3
+    float4 loy, hiy;
+    float4 loz, hiz;
+    int4 child;
+    int4 spare;
+};
+static_assert(sizeof(Node4) == 128, "4-wide node must be 128 bytes");
+constexpr int32_t kEmptyChild = INT32_MIN;
+// The first kTopSlots 4-wide nodes in breadth-first order from the root are
+// also kept in a compact array (top4), which the traversal copies into LDS as
+// far as its LDS budget allows.  A 4-wide child reference r >= 0 names top4[r]
+// when r < kTopSlots and the node collapsed from binary node r - kTopSlots
+// otherwise; the root is top4[0].
+constexpr int kTopSlots = 512;
+
 // Leaf triangle in sorted order: first corner, the two edge vectors from it
 // (rounded once, exactly as computing them on the fly would) and the input
 // triangle index.  48 B, three 16-byte loads.
@@ -70,6 +92,9 @@ struct MeshDev {
     void *keys = nullptr;      // [nt] sorted keys (uint32 or uint64)
     int32_t *ids = nullptr;    // [nt] triangle index at each sorted position
     Node *nodes = nullptr;     // [nt-1]
+    Node4 *nodes4 = nullptr;   // [nt-1] slots; those of binary nodes that start a 4-wide node
+    Node4 *top4 = nullptr;     // [kTopSlots] the top of the 4-wide tree, breadth-first
+    int node_width = 2;        // 4 once the 4-wide tree is built (algorithms 0 and 2)
     int32_t *parent = nullptr; // [2nt-1]
     int32_t *counters = nullptr; // [nt-1]
     Tri *tris = nullptr;       // [nt]
@@ -106,6 +131,28 @@ hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s);
 // Treelet restructuring of a built radix tree (restructure.hip); needs the
 // tile list the radix-tree kernel left in m.sort_tmp.
 hipError_t launch_restructure(MeshDev &m, int rounds, hipStream_t s);
+hipError_t launch_collapse(MeshDev &m, hipStream_t s);  // wide.hip: the 4-wide tree
+
+// Lists kept in a mesh's sort scratch once the sort is done: the tile count
+// and tile list of the radix-tree kernel (subtrees of at most 1024 leaves),
+// a cost per tile (restructuring), a node queue and a flag per internal node
+// (4-wide collapse).
+struct BuildLists {
+    int32_t *n_tiles, *tiles;
+    float *tile_cost;
+    int32_t *queue, *tile_flag;
+};
+inline int64_t round64(int64_t n) { return (n + 63) & ~int64_t(63); }
+inline BuildLists build_lists(void *sort_tmp, int64_t nt) {
+    BuildLists L;
+    L.n_tiles = static_cast<int32_t *>(sort_tmp);
+    L.tiles = L.n_tiles + 64;
+    L.tile_cost = reinterpret_cast<float *>(L.tiles + round64(nt));
+    L.queue = reinterpret_cast<int32_t *>(L.tile_cost + round64(nt));
+    L.tile_flag = L.queue + round64(nt);
+    return L;
+}
+inline size_t build_lists_bytes(int64_t nt) { return 4 * (64 + 4 * (size_t)round64(nt)); }
 size_t restructure_lds_bytes();
 // Stable sort of (32-bit key, id) pairs in place; tmp holds sort_u32_tmp_bytes(n).
 size_t sort_u32_tmp_bytes(int64_t n);
@@ -131,6 +178,7 @@ struct TraverseArgs {
     int block = 256;
     int stack = 24;
     int waves_per_cu = 0;          // 0: library default
+    int node_width = 0;            // 0: the mesh's widest tree, 2: binary nodes
     uint8_t *hit = nullptr;
     int32_t *tri_id = nullptr;
     float *uvt = nullptr;

@@ -244,6 +244,9 @@ __device__ __forceinline__ void write_out(const Outs &o, int64_t i, int mode, in
 
 struct TravParams {
     const Node *__restrict__ nodes;
+    const Node4 *__restrict__ nodes4;  // the 4-wide tree the first pass walks, or NULL
+    const Node4 *__restrict__ top4;    // its first kTopSlots nodes, breadth-first
+    int top_lds;                       // how many of them each workgroup keeps in LDS
     const Tri *__restrict__ tris;
     const float *__restrict__ V;
     const int32_t *__restrict__ F;
@@ -280,6 +283,17 @@ __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why)
     atomicAdd(p.counters + why, 1ull);
 }
 
+// Compare-exchange of (entry t, child) pairs: the nearer first.
+__device__ __forceinline__ void order2(float &ka, int &ca, float &kb, int &cb) {
+    const bool sw = kb < ka;
+    const float lo = fminf(ka, kb), hi = fmaxf(ka, kb);
+    const int cl = sw ? cb : ca, ch = sw ? ca : cb;
+    ka = lo;
+    kb = hi;
+    ca = cl;
+    cb = ch;
+}
+
 // ------------------------------------------------------------------ pass 1
 // Persistent waves.  Each wave owns a contiguous range of segments; a lane
 // whose segment is finished is refilled from that range while the others go
@@ -297,7 +311,7 @@ constexpr int kDone = INT32_MIN;  // nothing left for the lane's segment
 // PROP: proposal-first order.  Phase 0 traverses the predicted frontier
 // subtree; phase 1 the whole tree with that subtree left out.  Together they
 // visit exactly what the plain order visits, so results do not change.
-template <int MODE, bool CERT, bool STATS, bool PROP>
+template <int MODE, bool CERT, bool STATS, bool PROP, bool WIDE>
 __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     int *stk = lds_stack + threadIdx.x;
     const int stride = blockDim.x;
@@ -307,6 +321,15 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     const int n_internal = (int)p.nt - 1;
     const int max_steps = 2 * (int)p.nt + 8;  // N_t < 2^30
     const int depth_lim = p.stack_depth * stride;  // stack offsets are kept in units of lanes
+    // 4-wide: the top of the tree in LDS, after the stacks (read-only once filled)
+    const int ref_lim = WIDE ? n_internal + kTopSlots : n_internal;
+    float4 *top_cache = reinterpret_cast<float4 *>(lds_stack + (p.stack_depth + 3) * stride);
+    if (WIDE) {
+        const float4 *src = reinterpret_cast<const float4 *>(p.top4);
+        for (int i = threadIdx.x; i < 8 * p.top_lds; i += stride)
+            top_cache[i] = src[i];
+        __syncthreads();
+    }
 
     // One mesh: each wave owns a contiguous range of segments and its lanes
     // draw from it.  Batched form: waves take (mesh, segment range) items from
@@ -425,34 +448,80 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
             if (2 * __popcll(waiting) > __popcll(active))
                 break;
             if (want) {
-                if (++steps > max_steps || ref >= n_internal) {
+                if (++steps > max_steps || ref >= ref_lim) {
                     overflow = true;  // cannot happen for a well-formed tree
                     ref = kDone;
                     pend = -1;
                 } else {
                     const int top = stk[sp > 0 ? sp - stride : 0];
-                    const Node *nd = p.nodes + ref;
-                    const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
-                    const int4 refs = nd->refs;
                     if (STATS)
                         ++n_nodes;
-                    float tl, tr;
-                    bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, r, tlimit, tl);
-                    bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, r, tlimit, tr);
-                    if (PROP) {  // in phase 1 the proposed subtree is done already
-                        hl = hl && refs.x != skip;
-                        hr = hr && refs.y != skip;
-                    }
-                    const bool both = hl && hr, any = hl || hr;
-                    const bool left_first = both ? tl <= tr : hl;
-                    stk[sp] = left_first ? refs.y : refs.x;
-                    const int next = left_first ? refs.x : refs.y;
-                    overflow = overflow || (both && sp >= depth_lim);
-                    ref = any ? next : (sp > 0 ? top : kDone);
-                    sp += both ? stride : (!any && sp > 0 ? -stride : 0);
-                    if (both && sp > depth_lim) {
-                        ref = kDone;  // overflow: the segment goes to the deep-stack pass
-                        pend = -1;
+                    if (WIDE) {
+                        // four children: the nearest hit is next, the other
+                        // hits go on the stack farthest first; the three push
+                        // slots are written unconditionally (the lane has
+                        // three spare slots past stack_depth)
+                        float4 lx, hx, ly, hy, lz, hz;
+                        int4 ch;
+                        if (ref < p.top_lds) {  // the top of the tree, from LDS
+                            const float4 *c = top_cache + 8 * ref;
+                            lx = c[0], hx = c[1], ly = c[2], hy = c[3], lz = c[4], hz = c[5];
+                            const float4 cf = c[6];
+                            ch = make_int4(__float_as_int(cf.x), __float_as_int(cf.y), __float_as_int(cf.z),
+                                           __float_as_int(cf.w));
+                        } else {
+                            const Node4 *nd = ref < kTopSlots ? p.top4 + ref : p.nodes4 + (ref - kTopSlots);
+                            lx = nd->lox, hx = nd->hix, ly = nd->loy, hy = nd->hiy, lz = nd->loz, hz = nd->hiz;
+                            ch = nd->child;
+                        }
+                        float k0, k1, k2, k3;
+                        const bool h0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, r, tlimit, k0);
+                        const bool h1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, r, tlimit, k1);
+                        const bool h2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, r, tlimit, k2);
+                        const bool h3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, r, tlimit, k3);
+                        k0 = h0 ? k0 : INFINITY;
+                        k1 = h1 ? k1 : INFINITY;
+                        k2 = h2 ? k2 : INFINITY;
+                        k3 = h3 ? k3 : INFINITY;
+                        int c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
+                        order2(k0, c0, k1, c1);
+                        order2(k2, c2, k3, c3);
+                        order2(k0, c0, k2, c2);
+                        order2(k1, c1, k3, c3);
+                        order2(k1, c1, k2, c2);
+                        const int nh = (int)h0 + (int)h1 + (int)h2 + (int)h3;
+                        stk[sp] = nh == 4 ? c3 : (nh == 3 ? c2 : c1);
+                        stk[sp + stride] = nh == 4 ? c2 : c1;
+                        stk[sp + 2 * stride] = c1;
+                        ref = nh ? c0 : (sp > 0 ? top : kDone);
+                        sp += nh > 1 ? (nh - 1) * stride : (nh == 0 && sp > 0 ? -stride : 0);
+                        if (sp > depth_lim) {
+                            overflow = true;  // the segment goes to the deep-stack pass
+                            ref = kDone;
+                            pend = -1;
+                        }
+                    } else {
+                        const Node *nd = p.nodes + ref;
+                        const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
+                        const int4 refs = nd->refs;
+                        float tl, tr;
+                        bool hl = slab(L.x, L.y, L.z, L.w, Z.x, Z.y, r, tlimit, tl);
+                        bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, r, tlimit, tr);
+                        if (PROP) {  // in phase 1 the proposed subtree is done already
+                            hl = hl && refs.x != skip;
+                            hr = hr && refs.y != skip;
+                        }
+                        const bool both = hl && hr, any = hl || hr;
+                        const bool left_first = both ? tl <= tr : hl;
+                        stk[sp] = left_first ? refs.y : refs.x;
+                        const int next = left_first ? refs.x : refs.y;
+                        overflow = overflow || (both && sp >= depth_lim);
+                        ref = any ? next : (sp > 0 ? top : kDone);
+                        sp += both ? stride : (!any && sp > 0 ? -stride : 0);
+                        if (both && sp > depth_lim) {
+                            ref = kDone;  // overflow: the segment goes to the deep-stack pass
+                            pend = -1;
+                        }
                     }
                 }
             }
@@ -608,19 +677,19 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     }
 }
 
-template <int MODE, bool CERT, bool STATS, bool PROP>
-__global__ __launch_bounds__(256) void k_traverse(TravParams p) {
-    extern __shared__ int lds_stack[];
-    traverse_pass1<MODE, CERT, STATS, PROP>(p, lds_stack);
+template <int MODE, bool CERT, bool STATS, bool PROP, bool WIDE>
+__global__ __launch_bounds__(1024) void k_traverse(TravParams p) {
+    extern __shared__ float4 lds_dyn[];  // 16-byte aligned: the 4-wide top nodes follow the stacks
+    traverse_pass1<MODE, CERT, STATS, PROP, WIDE>(p, reinterpret_cast<int *>(lds_dyn));
 }
 
 // Count mode holds its list of distinct t in registers; the register budget
 // is fixed at four waves per SIMD (the default resident count) so the list
 // cannot lower occupancy.
-template <bool CERT, bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_traverse_count(TravParams p) {
-    extern __shared__ int lds_stack[];
-    traverse_pass1<MODE_COUNT, CERT, STATS, false>(p, lds_stack);
+template <bool CERT, bool STATS, bool WIDE>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void k_traverse_count(TravParams p) {
+    extern __shared__ float4 lds_dyn[];
+    traverse_pass1<MODE_COUNT, CERT, STATS, false, WIDE>(p, reinterpret_cast<int *>(lds_dyn));
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -1079,17 +1148,46 @@ __global__ void k_fill_miss(Outs out, int64_t n, int mode) {
         write_out(out, i, mode, -1, 0.0f, 0.0f, 0.0f);
 }
 
-template <int MODE, bool CERT, bool STATS, bool PROP>
+// Default workgroup size: 256 for binary nodes; 512 for 4-wide ones, whose
+// workgroups keep the top of the tree in LDS (a larger workgroup holds more
+// of it for the same resident waves).
+constexpr int kDefaultBlock = 256, kDefaultBlockWide = 512;
+
+template <int MODE, bool CERT, bool STATS, bool PROP, bool WIDE>
 void launch_pass1(const TravParams &p, int block, hipStream_t s) {
-    const size_t lds = (size_t)(p.stack_depth + 1) * block * sizeof(int);  // + one spare slot per lane
-    int dev = 0, cus = 256, per_cu = 0;
+    if (block == 0)
+        block = WIDE ? kDefaultBlockWide : kDefaultBlock;
+    // spare slots per lane past stack_depth: one for the binary push, three
+    // for the 4-wide one; the 4-wide traversal also keeps the top of the tree
+    // in what is left of the CU's LDS for the resident workgroups asked for
+    int dev = 0, cus = 256, per_cu = 0, lds_cu = 160 * 1024, lds_block = 64 * 1024;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    if (hipDeviceGetAttribute(&lds_block, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess ||
+        lds_block <= 0)
+        (void)hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const size_t stack_bytes = (size_t)(p.stack_depth + (WIDE ? 3 : 1)) * block * sizeof(int);
+    TravParams q = p;
+    q.top_lds = 0;
+    if (WIDE) {
+        int blocks_cu = p.waves_per_cu / (block / 64);
+        blocks_cu = blocks_cu < 1 ? 1 : blocks_cu;
+        int64_t room = lds_cu / blocks_cu;
+        room = room < lds_block ? room : lds_block;
+        room -= (int64_t)stack_bytes;
+        const int64_t slots = room > 0 ? room / (int64_t)sizeof(Node4) : 0;
+        q.top_lds = (int)(slots < kTopSlots ? slots : kTopSlots);
+    }
+    const size_t lds = stack_bytes + (size_t)q.top_lds * sizeof(Node4);
     void (*kern)(TravParams) = nullptr;
     if constexpr (MODE == MODE_COUNT)
-        kern = &k_traverse_count<CERT, STATS>;
+        kern = &k_traverse_count<CERT, STATS, WIDE>;
     else
-        kern = &k_traverse<MODE, CERT, STATS, PROP>;
+        kern = &k_traverse<MODE, CERT, STATS, PROP, WIDE>;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), block, lds);
     const int cap = p.waves_per_cu / (block / 64);  // resident blocks per CU asked for
     per_cu = per_cu < cap ? per_cu : cap;
@@ -1098,15 +1196,27 @@ void launch_pass1(const TravParams &p, int block, hipStream_t s) {
     const int64_t want = (p.n + block - 1) / block;
     const int64_t resident = (int64_t)cus * per_cu;
     const int grid = (int)(want < resident ? want : resident);
-    kern<<<grid, block, lds, s>>>(p);
+    kern<<<grid, block, lds, s>>>(q);
 }
 
+// The 4-wide tree serves the plain order only (the proposal's subtrees are
+// binary nodes); make_params leaves nodes4 NULL otherwise.
 template <int MODE, bool STATS>
 void dispatch_mode(const TravParams &p, bool cert, bool prop, int block, hipStream_t s) {
-    if (cert)
-        prop ? launch_pass1<MODE, true, STATS, true>(p, block, s) : launch_pass1<MODE, true, STATS, false>(p, block, s);
-    else
-        prop ? launch_pass1<MODE, false, STATS, true>(p, block, s) : launch_pass1<MODE, false, STATS, false>(p, block, s);
+    const bool wide = p.nodes4 != nullptr && !prop;
+    if (cert) {
+        if (prop)
+            launch_pass1<MODE, true, STATS, true, false>(p, block, s);
+        else
+            wide ? launch_pass1<MODE, true, STATS, false, true>(p, block, s)
+                 : launch_pass1<MODE, true, STATS, false, false>(p, block, s);
+    } else {
+        if (prop)
+            launch_pass1<MODE, false, STATS, true, false>(p, block, s);
+        else
+            wide ? launch_pass1<MODE, false, STATS, false, true>(p, block, s)
+                 : launch_pass1<MODE, false, STATS, false, false>(p, block, s);
+    }
 }
 
 template <bool STATS>
@@ -1119,14 +1229,21 @@ void dispatch_pass1(const TravParams &p, int mode, bool cert, int block, hipStre
     else if (mode == MODE_BARY)
         dispatch_mode<MODE_BARY, STATS>(p, cert, prop, block, s);
     else if (cert)  // count mode has no proposal order
-        launch_pass1<MODE_COUNT, true, STATS, false>(p, block, s);
+        p.nodes4 ? launch_pass1<MODE_COUNT, true, STATS, false, true>(p, block, s)
+                 : launch_pass1<MODE_COUNT, true, STATS, false, false>(p, block, s);
     else
-        launch_pass1<MODE_COUNT, false, STATS, false>(p, block, s);
+        p.nodes4 ? launch_pass1<MODE_COUNT, false, STATS, false, true>(p, block, s)
+                 : launch_pass1<MODE_COUNT, false, STATS, false, false>(p, block, s);
 }
 
 TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     TravParams p;
     p.nodes = m.nodes;
+    // the 4-wide tree for one mesh in the plain order, unless binary nodes are asked for
+    p.nodes4 = (m.node_width == 4 && a.node_width != 2 && a.items == nullptr && a.bucket == nullptr) ? m.nodes4
+                                                                                                      : nullptr;
+    p.top4 = p.nodes4 ? m.top4 : nullptr;
+    p.top_lds = 0;
     p.tris = m.tris;
     p.V = m.V;
     p.F = m.F;

@@ -1,0 +1,278 @@
+// wide.hip -- collapse of the binary BVH into a 4-wide one on gfx950.
+//
+// The traversal's cost per node is one dependent fetch from L2 plus the box
+// arithmetic; a 4-wide node halves the number of dependent fetches per
+// segment (each tests four children at once) and fits one 128-byte L2 line.
+// The collapse keeps the binary tree's boxes and leaves: a 4-wide node starts
+// at a binary internal node r and takes its two children, then opens the
+// child of largest surface area twice (greedy, as in the usual collapse of
+// binary BVHs into wide ones), so it covers exactly the leaves of r.  It is
+// stored at index r of the 4-wide array, so no renumbering is needed.
+//
+// Work split as in the bottom-up pass: one workgroup per tile (a subtree of
+// at most 1024 leaves listed by the radix-tree kernel), breadth-first from
+// the tile root with the queue in LDS; one workgroup for the nodes above the
+// tiles, which never opens a tile root (every tile root starts a 4-wide node
+// of its own).  Treelet restructuring keeps every tile root and its leaves,
+// so the same tile list serves both builds.
+#include "rsi_internal.h"
+
+namespace rsi {
+namespace {
+
+constexpr int kTileQueue = 1024;  // a tile of <= 1024 leaves has <= 1023 internal nodes
+
+__device__ __forceinline__ float half_area6(const float *b) {
+    const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return dx * dy + dy * dz + dz * dx;
+}
+
+// The two children of binary node r: references and boxes (lo xyz, hi xyz).
+__device__ __forceinline__ void children_of(const Node *__restrict__ nodes, int r, int &l, int &rr, float lb[6],
+                                            float rb[6]) {
+    const Node *nd = nodes + r;
+    const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
+    const int4 refs = nd->refs;
+    l = refs.x;
+    rr = refs.y;
+    lb[0] = L.x, lb[1] = L.z, lb[2] = Z.x, lb[3] = L.y, lb[4] = L.w, lb[5] = Z.y;
+    rb[0] = R.x, rb[1] = R.z, rb[2] = Z.z, rb[3] = R.y, rb[4] = R.w, rb[5] = Z.w;
+}
+
+// Collapse the binary subtree at r into nodes4[r]; returns the internal
+// children that start 4-wide nodes below (stopped ones excluded: they are
+// started by another workgroup).
+__device__ __forceinline__ int collapse_node(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4, int r,
+                                             const int32_t *__restrict__ stop, int kids[4]) {
+    int ref[4] = {0, 0, kEmptyChild, kEmptyChild};
+    float b[4][6];
+#pragma unroll
+    for (int i = 2; i < 4; ++i)
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+            b[i][a] = INFINITY;
+    children_of(nodes, r, ref[0], ref[1], b[0], b[1]);
+    int m = 2;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        int best = -1;
+        float best_a = -1.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool open = i < m && ref[i] >= 0 && !(stop && stop[ref[i]]);
+            const float a = half_area6(b[i]);
+            if (open && a > best_a) {
+                best_a = a;
+                best = i;
+            }
+        }
+        if (best < 0)
+            break;
+        int c = ref[0];
+#pragma unroll
+        for (int i = 1; i < 4; ++i)
+            c = best == i ? ref[i] : c;
+        int l, rr;
+        float lb[6], rb[6];
+        children_of(nodes, c, l, rr, lb, rb);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i == best) {
+                ref[i] = l;
+#pragma unroll
+                for (int a = 0; a < 6; ++a)
+                    b[i][a] = lb[a];
+            }
+            if (i == m) {
+                ref[i] = rr;
+#pragma unroll
+                for (int a = 0; a < 6; ++a)
+                    b[i][a] = rb[a];
+            }
+        }
+        ++m;
+    }
+    Node4 o;
+    o.lox = make_float4(b[0][0], b[1][0], b[2][0], b[3][0]);
+    o.loy = make_float4(b[0][1], b[1][1], b[2][1], b[3][1]);
+    o.loz = make_float4(b[0][2], b[1][2], b[2][2], b[3][2]);
+    o.hix = make_float4(b[0][3], b[1][3], b[2][3], b[3][3]);
+    o.hiy = make_float4(b[0][4], b[1][4], b[2][4], b[3][4]);
+    o.hiz = make_float4(b[0][5], b[1][5], b[2][5], b[3][5]);
+    // internal children are named by binary index + kTopSlots (the top slots
+    // are assigned afterwards by k_top_cache)
+    auto enc = [](int c) { return c >= 0 ? c + kTopSlots : c; };
+    o.child = make_int4(enc(ref[0]), enc(ref[1]), enc(ref[2]), enc(ref[3]));
+    o.spare = make_int4(m, 0, 0, 0);
+    nodes4[r] = o;
+    int nk = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool go = ref[i] >= 0 && !(stop && stop[ref[i]]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (go && k == nk)
+                kids[k] = ref[i];
+        nk += go ? 1 : 0;
+    }
+    return nk;
+}
+
+__global__ void k_clear_flags(int32_t *flag, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        flag[i] = 0;
+}
+
+__global__ void k_mark_tiles(const int32_t *__restrict__ tiles, const int32_t *__restrict__ n_tiles, int32_t *flag,
+                             int64_t n_internal) {
+    const int total = *n_tiles;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int c = tiles[e];
+        if (c >= 0 && c < n_internal)
+            flag[c] = 1;
+    }
+}
+
+// One workgroup per tile: breadth-first from the tile root, a lane per
+// 4-wide node of the current level.
+__global__ __launch_bounds__(256) void k_collapse_tiles(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
+                                                        const int32_t *__restrict__ tiles,
+                                                        const int32_t *__restrict__ n_tiles) {
+    __shared__ int q[kTileQueue];
+    __shared__ int qn;
+    const int total = *n_tiles;
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        const int c = tiles[e];
+        if (c < 0)
+            continue;  // a one-leaf tile: no internal node
+        if (threadIdx.x == 0) {
+            q[0] = c;
+            qn = 1;
+        }
+        __syncthreads();
+        int b0 = 0, b1 = 1;
+        while (b0 < b1) {
+            for (int i = b0 + (int)threadIdx.x; i < b1; i += blockDim.x) {
+                int kids[4];
+                const int nk = collapse_node(nodes, nodes4, q[i], nullptr, kids);
+                for (int k = 0; k < nk; ++k) {
+                    const int slot = atomicAdd(&qn, 1);
+                    if (slot < kTileQueue)
+                        q[slot] = kids[k];
+                }
+            }
+            __syncthreads();
+            b0 = b1;
+            b1 = qn < kTileQueue ? qn : kTileQueue;
+            __syncthreads();  // every lane has read qn before the next level appends
+        }
+    }
+}
+
+// One workgroup: the nodes above the tiles, breadth-first from the root with
+// the queue in global scratch; tile roots are never opened.
+__global__ __launch_bounds__(1024) void k_collapse_top(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
+                                                       const int32_t *__restrict__ tile_flag, int32_t *queue,
+                                                       int64_t n_internal) {
+    __shared__ int qn;
+    if (tile_flag[0])
+        return;  // the whole tree is one tile
+    if (threadIdx.x == 0) {
+        queue[0] = 0;
+        qn = 1;
+    }
+    __syncthreads();
+    int b0 = 0, b1 = 1;
+    while (b0 < b1) {
+        for (int i = b0 + (int)threadIdx.x; i < b1; i += blockDim.x) {
+            int kids[4];
+            const int nk = collapse_node(nodes, nodes4, queue[i], tile_flag, kids);
+            for (int k = 0; k < nk; ++k) {
+                const int slot = atomicAdd(&qn, 1);
+                if (slot < n_internal)
+                    queue[slot] = kids[k];
+            }
+        }
+        __syncthreads();
+        b0 = b1;
+        b1 = qn < n_internal ? qn : (int)n_internal;
+        __syncthreads();
+    }
+}
+
+// One workgroup: the first kTopSlots 4-wide nodes in breadth-first order from
+// the root, copied into top4 with the references of children that also got a
+// slot rewritten to that slot.  Slots follow a block-wide prefix sum over each
+// level, so the layout does not depend on thread timing.
+__global__ __launch_bounds__(1024) void k_top_cache(const Node4 *__restrict__ nodes4, Node4 *__restrict__ top4) {
+    __shared__ int bidx[kTopSlots];  // binary index of the node in each slot
+    __shared__ int scan[1024];
+    const int tid = threadIdx.x;
+    if (tid == 0)
+        bidx[0] = 0;
+    __syncthreads();
+    int b0 = 0, b1 = 1;
+    while (b0 < b1) {
+        const int i = b0 + tid;  // a level has at most kTopSlots <= blockDim nodes
+        Node4 nd;
+        int cnt = 0;
+        if (i < b1) {
+            nd = nodes4[bidx[i]];
+            cnt = (nd.child.x >= 0) + (nd.child.y >= 0) + (nd.child.z >= 0) + (nd.child.w >= 0);
+        }
+        scan[tid] = cnt;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            const int v = tid >= off ? scan[tid - off] : 0;
+            __syncthreads();
+            scan[tid] += v;
+            __syncthreads();
+        }
+        const int total = scan[blockDim.x - 1];
+        if (i < b1) {
+            int slot = b1 + scan[tid] - cnt;
+            int c[4] = {nd.child.x, nd.child.y, nd.child.z, nd.child.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (c[k] >= 0) {
+                    if (slot < kTopSlots) {
+                        bidx[slot] = c[k] - kTopSlots;
+                        c[k] = slot;
+                    }
+                    ++slot;
+                }
+            nd.child = make_int4(c[0], c[1], c[2], c[3]);
+            top4[i] = nd;
+        }
+        __syncthreads();
+        b0 = b1;
+        b1 = b1 + total < kTopSlots ? b1 + total : kTopSlots;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_collapse(MeshDev &m, hipStream_t s) {
+    if (m.nt < 2)
+        return hipSuccess;  // one leaf: nothing to collapse
+    const int64_t n_internal = m.nt - 1;
+    const BuildLists L = build_lists(m.sort_tmp, m.nt);
+    const int blocks = (int)((n_internal + 255) / 256);
+    k_clear_flags<<<blocks, 256, 0, s>>>(L.tile_flag, n_internal);
+    k_mark_tiles<<<blocks, 256, 0, s>>>(L.tiles, L.n_tiles, L.tile_flag, n_internal);
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t want = (m.nt + 1023) / 1024 * 2;  // tiles hold up to 1024 leaves, usually fewer
+    const int grid = (int)(want < 4 * cus ? want : 4 * cus);
+    k_collapse_tiles<<<grid, 256, 0, s>>>(m.nodes, m.nodes4, L.tiles, L.n_tiles);
+    k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, m.nodes4, L.tile_flag, L.queue, n_internal);
+    k_top_cache<<<1, 1024, 0, s>>>(m.nodes4, m.top4);
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        m.node_width = 4;
+    return e;
+}
+
+}  // namespace rsi

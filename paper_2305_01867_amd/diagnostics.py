@@ -176,3 +176,85 @@ def check(tree: dict, contiguous: bool = False) -> list:
     if tree["counter"] is not None and np.any(tree["counter"] != 2):
         problems.append(f"{int(np.sum(tree['counter'] != 2))} internal nodes not completed (counter != 2)")
     return problems
+
+
+def decode_wide(words) -> dict:
+    """Decode exported 4-wide nodes (int32 [m, 32], RSI_EXPORT_WIDE_NODES):
+    lo / hi float [m, 4, 3] per child, child int32 [m, 4], n_children [m]."""
+    w = np.asarray(words, np.int32).reshape(-1, 32)
+    f = w.view(np.float32)
+    lo = np.stack([f[:, 0:4], f[:, 8:12], f[:, 16:20]], axis=2)
+    hi = np.stack([f[:, 4:8], f[:, 12:16], f[:, 20:24]], axis=2)
+    return {"lo": lo, "hi": hi, "child": w[:, 24:28].copy(), "n_children": w[:, 28].copy()}
+
+
+TOP_SLOTS = 512  # 4-wide references below this name top-array slots
+
+
+def check_wide(wide: dict, top: dict, tree: dict) -> list:
+    """The 4-wide tree (main array and top array, both decoded) against the
+    binary tree it was collapsed from; returns a list of problems, empty when
+    sound: walking from top slot 0 reaches every leaf exactly once and no
+    node twice, every node has 2..4 children, each child's box equals the
+    union of its own children's boxes (and, where the child is named by its
+    binary index, the binary tree's box of that node; a leaf's box for a
+    leaf), and unused slots hold INT32_MIN with boxes +inf on every face."""
+    problems = []
+    n_int = tree["left"].shape[0]
+    n_leaf = tree["leaf_tri"].shape[0]
+    if n_leaf <= 1:
+        return problems
+    empty = np.iinfo(np.int32).min
+    seen_leaf = np.zeros(n_leaf, np.int64)
+    seen = {"top": np.zeros(TOP_SLOTS, bool), "wide": np.zeros(n_int, bool)}
+    arrays = {"top": top, "wide": wide}
+
+    def node_of(r):
+        return ("top", r) if r < TOP_SLOTS else ("wide", r - TOP_SLOTS)
+
+    def union_of(arr, i):
+        k = int(arr["n_children"][i])
+        return np.concatenate([arr["lo"][i, :k].min(axis=0), arr["hi"][i, :k].max(axis=0)])
+
+    stack = [("top", 0)]
+    while stack and len(problems) < 20:
+        which, i = stack.pop()
+        arr = arrays[which]
+        if not 0 <= i < seen[which].shape[0]:
+            problems.append(f"{which} node {i} out of range")
+            continue
+        if seen[which][i]:
+            problems.append(f"{which} node {i} reached twice")
+            continue
+        seen[which][i] = True
+        k = int(arr["n_children"][i])
+        if not 2 <= k <= 4:
+            problems.append(f"{which} node {i}: {k} children")
+            continue
+        for j in range(4):
+            c = int(arr["child"][i, j])
+            box = np.concatenate([arr["lo"][i, j], arr["hi"][i, j]])
+            if j >= k:
+                if c != empty or not np.all(np.isposinf(box)):
+                    problems.append(f"{which} node {i}: unused slot {j} is not empty")
+                continue
+            if c < 0:
+                if not 0 <= ~c < n_leaf:
+                    problems.append(f"{which} node {i}: leaf {~c} out of range")
+                    continue
+                seen_leaf[~c] += 1
+                if not np.array_equal(box, tree["leaf_box"][~c]):
+                    problems.append(f"{which} node {i}: child {j} box differs from the leaf's")
+                continue
+            cw, ci = node_of(c)
+            if not 0 <= ci < seen[cw].shape[0]:
+                problems.append(f"{which} node {i}: child {c} out of range")
+                continue
+            if not np.array_equal(box, union_of(arrays[cw], ci)):
+                problems.append(f"{which} node {i}: child {j} box is not the union of its children's")
+            if cw == "wide" and not np.array_equal(box, tree["box"][ci]):
+                problems.append(f"{which} node {i}: child {j} box differs from the binary tree's")
+            stack.append((cw, ci))
+    if np.any(seen_leaf != 1):
+        problems.append(f"{int(np.sum(seen_leaf != 1))} leaves not reached exactly once")
+    return problems

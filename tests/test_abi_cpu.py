@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = rsi.lib()
-    assert L.rsi_abi_version() == 4
+    assert L.rsi_abi_version() == 5
     for code in range(7):
         assert L.rsi_status_string(code).decode().startswith("RSI_")
     assert b"unknown" in L.rsi_status_string(99)

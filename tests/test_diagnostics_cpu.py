@@ -69,3 +69,86 @@ def test_check_finds_planted_faults():
     shrunk = nodes.copy()
     shrunk.view(np.float32)[0, 1] -= 0.5  # a box that no longer holds its child
     assert any("box" in p for p in diagnostics.check(diagnostics.decode(shrunk, leaves, parents, counters)))
+
+
+def collapse_wide(tree):
+    """A 4-wide collapse written here from its definition (each node takes
+    its two children, then opens the largest-area internal child twice), in
+    the export layout: the main array by binary index with references to
+    internal children as binary index + 512, and the top array holding the
+    first nodes in breadth-first order with references among them rewritten
+    to their slots."""
+    n_int = tree["left"].shape[0]
+    T = diagnostics.TOP_SLOTS
+    words = np.zeros((n_int, 32), np.int32)
+    f = words.view(np.float32)
+    box = lambda c: tree["leaf_box"][~c] if c < 0 else tree["box"][c]
+    area = lambda b: (b[3] - b[0]) * (b[4] - b[1]) + (b[4] - b[1]) * (b[5] - b[2]) + (b[5] - b[2]) * (b[3] - b[0])
+    kids_of = {}
+    stack = [tree["root"]]
+    while stack:
+        r = stack.pop()
+        kids = [int(tree["left"][r]), int(tree["right"][r])]
+        for _ in range(2):
+            inner = [c for c in kids if c >= 0]
+            if not inner:
+                break
+            c = max(inner, key=lambda c: area(box(c)))
+            kids[kids.index(c)] = int(tree["left"][c])
+            kids.append(int(tree["right"][c]))
+        kids_of[r] = kids
+        for i in range(4):
+            b = box(kids[i]) if i < len(kids) else np.full(6, np.inf, np.float32)
+            for a in range(3):
+                f[r, 8 * a + i], f[r, 8 * a + 4 + i] = b[a], b[3 + a]
+            words[r, 24 + i] = (kids[i] + T if kids[i] >= 0 else kids[i]) if i < len(kids) else np.iinfo(np.int32).min
+        words[r, 28] = len(kids)
+        stack += [c for c in kids if c >= 0]
+    order = [tree["root"]]
+    for r in order:
+        if len(order) >= T:
+            break
+        order += [c for c in kids_of[r] if c >= 0]
+    order = order[:T]
+    slot = {r: i for i, r in enumerate(order)}
+    top = np.zeros((T, 32), np.int32)
+    for i, r in enumerate(order):
+        top[i] = words[r]
+        for j in range(int(words[r, 28])):
+            c = int(words[r, 24 + j])
+            if c >= 0 and c - T in slot:
+                top[i, 24 + j] = slot[c - T]
+    return words, top, set(order)
+
+
+def test_wide_checker_accepts_a_collapse_and_finds_planted_mistakes():
+    V, F = workloads.heightfield(30, 3)
+    tree = diagnostics.decode(*export_layout(V, F))
+    words, top, cached = collapse_wide(tree)
+    dw = diagnostics.decode_wide
+    assert diagnostics.check_wide(dw(words), dw(top), tree) == []
+    wide = dw(words)
+    r = [q for q in np.nonzero(wide["n_children"] == 4)[0] if q not in cached][0]  # reached in the main array
+    # a child dropped: its leaves are no longer reached
+    bad = words.copy()
+    bad[r, 28] = 3
+    assert diagnostics.check_wide(dw(bad), dw(top), tree) != []
+    # a box shrunk on one face, in the main array and in the top array
+    bad = words.copy()
+    bad.view(np.float32)[r, 0] += 1e-3
+    assert any("box" in p for p in diagnostics.check_wide(dw(bad), dw(top), tree))
+    badt = top.copy()
+    badt.view(np.float32)[0, 0] += 1e-3
+    assert any("box" in p for p in diagnostics.check_wide(dw(words), dw(badt), tree))
+    # a top reference pointing one slot off
+    badt = top.copy()
+    j = int(np.nonzero((badt[0, 24:28] > 0) & (badt[0, 24:28] < diagnostics.TOP_SLOTS))[0][0])
+    badt[0, 24 + j] += 1
+    assert diagnostics.check_wide(dw(words), dw(badt), tree) != []
+    # one leaf referenced twice
+    bad = words.copy()
+    leaf_slots = [(q, i) for q in range(bad.shape[0]) if q not in cached for i in range(int(bad[q, 28]))
+                  if bad[q, 24 + i] < 0]
+    (q0, i0), (q1, i1) = leaf_slots[-2], leaf_slots[-1]
+    bad[q1, 24 + i1] = bad[q0, 24 + i0]
+    assert diagnostics.check_wide(dw(bad), dw(top), tree) != []
