@@ -7,16 +7,18 @@ box inflated by 10% (synthetic stand-in for the paper's 29,260-triangle /
 1e7-ray data, which is not available).  One step = the whole path: build the
 BVH (extent, Morton keys, LDS radix sort, radix tree, bottom-up boxes, and by
 default two passes of treelet restructuring, which changes node visits but
-never results) and intersect every segment (traversal, leaf tests, binary64
+never results, and the collapse into a 4-wide tree) and intersect every
+segment (4-wide traversal with the tree's top in LDS, leaf tests, binary64
 re-decisions), with the inputs already resident in GPU memory.  The metric is
 Mrays/s.  --build radix_tree times the paper's own LBVH instead; the
 variants record that step either way.
 
 Printed: one JSON line (rank 0).  Besides the contract fields it carries
   roofline      the traversal launch: algorithmic bytes (segments in, results
-                out, 64 B per node visited, 48 B per triangle tested, counted
-                by an instrumented run of the same traversal) over its average
-                duration (HIP events on the launch stream), vs 8 TB/s
+                out, per node fetched its loaded bytes -- 112 B for a 4-wide
+                node, 64 B for a binary one -- and 48 B per triangle tested,
+                counted by an instrumented run of the same traversal) over its
+                average duration (HIP events on the launch stream), vs 8 TB/s
   cpu_baseline  the binary64 brute-force oracle timed on the host cores on a
                 bounded sample of the same segments
   variants      Mrays/s of intersect alone per mode and precision
@@ -195,6 +197,7 @@ def main():
 
     # ---------------- algorithmic bytes of the traversal (instrumented, untimed)
     with build() as mesh:
+        node_width = rsi.rsi_mesh_info_get(mesh)["node_width"]
         visits, tests = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision)
         torch.cuda.synchronize()
         mean_visits = float(visits.double().mean().item())
@@ -202,21 +205,23 @@ def main():
         p50_visits = float(visits.double().median().item())
         p99_visits = float(torch.quantile(visits[: min(n, 1 << 24)].double(), 0.99).item())
     out_bytes = {"boolean": 1, "first_hit": 4, "barycentric": 16, "intercept_count": 4}[args.mode]
-    bytes_per_ray = 24 + out_bytes + 64 * mean_visits + 48 * mean_tests
+    node_bytes = 112 if node_width == 4 else 64  # loaded per node fetch (7 or 4 16-byte loads)
+    bytes_per_ray = 24 + out_bytes + node_bytes * mean_visits + 48 * mean_tests
     achieved_gbs = n * bytes_per_ray / (intersect_avg * 1e-3) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
         "traffic": measured_traffic(args.mode, args.precision, args.build),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "kernel": "k_traverse (+ k_reset, k_finish in the same event pair)",
+        "kernel": "k_traverse (+ k_reset, k_finish in the same event pair)", "node_width": node_width,
+        "node_bytes": node_bytes,
         "bytes_per_ray": round(bytes_per_ray, 1), "mean_node_visits": round(mean_visits, 2),
         "p50_node_visits": p50_visits, "p99_node_visits": p99_visits, "mean_leaf_tests": round(mean_tests, 2),
         "stream_only_frac": round(n * (24 + out_bytes) / (intersect_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
         "avg_launch_ms": round(intersect_avg, 4),
-        "reading": "achieved counts the bytes the method touches (64 per node visit, 48 per leaf test, the "
-                   "segment stream); the tree stays in L2, so they exceed the HBM peak; measured_frac is the "
-                   "measured HBM traffic over the same time",
+        "reading": "achieved counts the bytes the method touches (node_bytes per node fetch, 48 per leaf "
+                   "test, the segment stream); the tree is served from LDS (its top) and L2, so they exceed "
+                   "the HBM peak; measured_frac is the measured HBM traffic over the same time",
     }
     if roofline["traffic"]:
         roofline["measured_frac"] = round(roofline["traffic"] / (intersect_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
@@ -242,6 +247,21 @@ def main():
                                                   "stack_overflow": c[1]}
                     if mode == args.mode and prec != args.precision:
                         results[prec] = outs[mode][key][:keep].cpu().numpy().copy()
+            for mode in ("boolean", "first_hit"):  # the same first pass over binary nodes
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                run = lambda: rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision=args.precision, out=outs[mode],
+                                                node_width=2)
+                run()
+                a.record(stream)
+                for _ in range(3):
+                    run()
+                b.record(stream)
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b) / 3
+                variants[f"{mode}/{args.precision}/binary_nodes"] = {"mrays_s": round(n / (ms * 1e-3) / 1e6, 1),
+                                                                     "ms": round(ms, 3)}
+                if mode == args.mode:
+                    results[f"{args.precision}, binary nodes"] = outs[mode][key][:keep].cpu().numpy().copy()
             for order in ("midpoint", "origin_octant"):  # segment processing orders (same results)
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 run = lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision,
