@@ -83,6 +83,24 @@ __device__ __forceinline__ bool slab(float xlo, float xhi, float ylo, float yhi,
     return tmin <= tmax;
 }
 
+// The same test with the near and far face of each axis given (the lower
+// face is the near one for a direction component >= 0, the upper one
+// otherwise, with the matching offsets nn / nf of nra / nrb).  For a box with
+// lo <= hi the sign picks exactly the operands min / max pick in slab(), so
+// the decisions are the same bit for bit; a box that is +inf on every face
+// still misses.
+__device__ __forceinline__ bool slab_nf(float nx, float fx, float ny, float fy, float nz, float fz,
+                                        const float3 &inv, const float3 &nn, const float3 &nf, float tlimit,
+                                        float &tenter) {
+    const float tnx = fmaf(nx, inv.x, nn.x), tfx = fmaf(fx, inv.x, nf.x);
+    const float tny = fmaf(ny, inv.y, nn.y), tfy = fmaf(fy, inv.y, nf.y);
+    const float tnz = fmaf(nz, inv.z, nn.z), tfz = fmaf(fz, inv.z, nf.z);
+    const float tmin = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
+    const float tmax = fminf(fminf(tfx, tfy), fminf(tfz, tlimit));
+    tenter = tmin;
+    return tmin <= tmax;
+}
+
 struct MT32 {
     float det, U, W, T;
     float3 s;
@@ -283,6 +301,15 @@ __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why)
     atomicAdd(p.counters + why, 1ull);
 }
 
+// Pointers into LDS by address space, so reads of the LDS copy of the tree's
+// top compile to ds_read and are not merged with the global path.
+typedef const __attribute__((address_space(3))) char *LdsBytes;
+typedef float F4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 lds_f4(LdsBytes p) {
+    const F4v v = *reinterpret_cast<const __attribute__((address_space(3))) F4v *>(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Compare-exchange of (entry t, child) pairs: the nearer first.
 __device__ __forceinline__ void order2(float &ka, int &ca, float &kb, int &cb) {
     const bool sw = kb < ka;
@@ -300,9 +327,16 @@ __device__ __forceinline__ void order2(float &ka, int &ca, float &kb, int &cb) {
 // on, so a wave's time follows the mean cost of a segment instead of the
 // slowest of its 64 (no atomics: a shared counter across eight XCDs costs more
 // than the imbalance of ~1e3 segments per wave).  Leaf tests are postponed: a lane keeps one leaf
-// aside and continues with internal nodes; the leaf phase runs when half the
-// wave is waiting on a leaf, so the leaf code runs for many lanes at once.
+// aside and continues with internal nodes; the leaf phase runs once a set
+// share of the wave is waiting on a leaf, so the leaf code runs for many lanes
+// at once.
 constexpr int kRefillMin = 8;     // refill when at least this many lanes idle
+// The node phase hands over to the leaf phase once more than 1/kLeafShare of
+// the active lanes wait on a leaf: early for the modes that test few leaves
+// per segment (node steps keep more lanes busy), at half for the count mode,
+// which tests every leaf it reaches (measured on the paper-scale workload).
+template <int MODE>
+constexpr int kLeafShare = MODE == MODE_COUNT ? 2 : 3;
 // Resident waves per CU of the persistent traversal unless asked otherwise:
 // fewer waves than registers allow share the CU's L1 among fewer tree paths.
 constexpr int kDefaultWavesPerCU = 16;
@@ -345,6 +379,11 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
 
     int64_t ray = -1;
     Ray r;
+    // 4-wide: byte offsets in a node of the near-face rows (x lo or hi at 0 /
+    // 16, y at 32 / 48, z at 64 / 80; the far row is the other of each pair)
+    // and the matching slab offsets, fixed per segment by the direction signs
+    int offx = 0, offy = 32, offz = 64;
+    float3 nn = make_float3(0.0f, 0.0f, 0.0f), nf = nn;
     int ref = kDone, pend = -1, sp = 0;  // sp: offset of the next free slot (a multiple of stride)
     float tlimit = 1.0f;
     int best_id = -1;
@@ -419,6 +458,13 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                             write_out(p.out, ray, MODE, -1, 0.0f, 0.0f, 0.0f);
                         }
                         ray = -1;
+                    } else if (WIDE) {
+                        const bool sx = r.inv.x < 0.0f, sy = r.inv.y < 0.0f, sz = r.inv.z < 0.0f;
+                        offx = sx ? 16 : 0;
+                        offy = sy ? 48 : 32;
+                        offz = sz ? 80 : 64;
+                        nn = make_float3(sx ? r.nrb.x : r.nra.x, sy ? r.nrb.y : r.nra.y, sz ? r.nrb.z : r.nra.z);
+                        nf = make_float3(sx ? r.nra.x : r.nrb.x, sy ? r.nra.y : r.nrb.y, sz ? r.nra.z : r.nrb.z);
                     }
                 }
             }
@@ -445,7 +491,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
             if (!w)
                 break;
             const uint64_t waiting = active & ~w;
-            if (2 * __popcll(waiting) > __popcll(active))
+            if (kLeafShare<MODE> * __popcll(waiting) > __popcll(active))
                 break;
             if (want) {
                 if (++steps > max_steps || ref >= ref_lim) {
@@ -457,42 +503,71 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                     if (STATS)
                         ++n_nodes;
                     if (WIDE) {
-                        // four children: the nearest hit is next, the other
-                        // hits go on the stack farthest first; the three push
-                        // slots are written unconditionally (the lane has
-                        // three spare slots past stack_depth)
-                        float4 lx, hx, ly, hy, lz, hz;
+                        // four children per fetch; the hits after the next one
+                        // go on the stack, at most three slots past sp (the
+                        // lane has three spare slots past stack_depth)
+                        // each load fetches a face row of all four children:
+                        // near and far faces chosen by the segment's signs
+                        float4 nx, fx, ny, fy, nz, fz;
                         int4 ch;
-                        if (ref < p.top_lds) {  // the top of the tree, from LDS
-                            const float4 *c = top_cache + 8 * ref;
-                            lx = c[0], hx = c[1], ly = c[2], hy = c[3], lz = c[4], hz = c[5];
-                            const float4 cf = c[6];
+                        if (ref < p.top_lds) {  // the top of the tree, from LDS (ds_read)
+                            const LdsBytes c = (LdsBytes)(top_cache + 8 * ref);  // generic -> LDS
+                            nx = lds_f4(c + offx);
+                            fx = lds_f4(c + (offx ^ 16));
+                            ny = lds_f4(c + offy);
+                            fy = lds_f4(c + (offy ^ 16));
+                            nz = lds_f4(c + offz);
+                            fz = lds_f4(c + (offz ^ 16));
+                            const float4 cf = lds_f4(c + 96);
                             ch = make_int4(__float_as_int(cf.x), __float_as_int(cf.y), __float_as_int(cf.z),
                                            __float_as_int(cf.w));
                         } else {
-                            const Node4 *nd = ref < kTopSlots ? p.top4 + ref : p.nodes4 + (ref - kTopSlots);
-                            lx = nd->lox, hx = nd->hix, ly = nd->loy, hy = nd->hiy, lz = nd->loz, hz = nd->hiz;
-                            ch = nd->child;
+                            const char *c = reinterpret_cast<const char *>(
+                                ref < kTopSlots ? p.top4 + ref : p.nodes4 + (ref - kTopSlots));
+                            nx = *reinterpret_cast<const float4 *>(c + offx);
+                            fx = *reinterpret_cast<const float4 *>(c + (offx ^ 16));
+                            ny = *reinterpret_cast<const float4 *>(c + offy);
+                            fy = *reinterpret_cast<const float4 *>(c + (offy ^ 16));
+                            nz = *reinterpret_cast<const float4 *>(c + offz);
+                            fz = *reinterpret_cast<const float4 *>(c + (offz ^ 16));
+                            ch = *reinterpret_cast<const int4 *>(c + 96);
                         }
                         float k0, k1, k2, k3;
-                        const bool h0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, r, tlimit, k0);
-                        const bool h1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, r, tlimit, k1);
-                        const bool h2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, r, tlimit, k2);
-                        const bool h3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, r, tlimit, k3);
-                        k0 = h0 ? k0 : INFINITY;
-                        k1 = h1 ? k1 : INFINITY;
-                        k2 = h2 ? k2 : INFINITY;
-                        k3 = h3 ? k3 : INFINITY;
+                        const bool h0 = slab_nf(nx.x, fx.x, ny.x, fy.x, nz.x, fz.x, r.inv, nn, nf, tlimit, k0);
+                        const bool h1 = slab_nf(nx.y, fx.y, ny.y, fy.y, nz.y, fz.y, r.inv, nn, nf, tlimit, k1);
+                        const bool h2 = slab_nf(nx.z, fx.z, ny.z, fy.z, nz.z, fz.z, r.inv, nn, nf, tlimit, k2);
+                        const bool h3 = slab_nf(nx.w, fx.w, ny.w, fy.w, nz.w, fz.w, r.inv, nn, nf, tlimit, k3);
                         int c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
-                        order2(k0, c0, k1, c1);
-                        order2(k2, c2, k3, c3);
-                        order2(k0, c0, k2, c2);
-                        order2(k1, c1, k3, c3);
-                        order2(k1, c1, k2, c2);
                         const int nh = (int)h0 + (int)h1 + (int)h2 + (int)h3;
-                        stk[sp] = nh == 4 ? c3 : (nh == 3 ? c2 : c1);
-                        stk[sp + stride] = nh == 4 ? c2 : c1;
-                        stk[sp + 2 * stride] = c1;
+                        if (MODE != MODE_COUNT) {
+                            // nearest first: a boolean segment meets a hit
+                            // sooner, the nearest-hit modes' shrinking t limit
+                            // prunes the rest
+                            k0 = h0 ? k0 : INFINITY;
+                            k1 = h1 ? k1 : INFINITY;
+                            k2 = h2 ? k2 : INFINITY;
+                            k3 = h3 ? k3 : INFINITY;
+                            order2(k0, c0, k1, c1);
+                            order2(k2, c2, k3, c3);
+                            order2(k0, c0, k2, c2);
+                            order2(k1, c1, k3, c3);
+                            order2(k1, c1, k2, c2);
+                            stk[sp] = nh == 4 ? c3 : (nh == 3 ? c2 : c1);
+                            stk[sp + stride] = nh == 4 ? c2 : c1;
+                            stk[sp + 2 * stride] = c1;
+                        } else {
+                            // count mode visits every candidate whatever the
+                            // order: the first hit child is next, the others go
+                            // on the stack in child order
+                            const int p1 = h0, p2 = p1 + h1, p3 = p2 + h2;
+                            if (h1 && p1)
+                                stk[sp] = c1;
+                            if (h2 && p2)
+                                stk[sp + (p2 - 1) * stride] = c2;
+                            if (h3 && p3)
+                                stk[sp + (p3 - 1) * stride] = c3;
+                            c0 = h0 ? c0 : (h1 ? c1 : (h2 ? c2 : c3));
+                        }
                         ref = nh ? c0 : (sp > 0 ? top : kDone);
                         sp += nh > 1 ? (nh - 1) * stride : (nh == 0 && sp > 0 ? -stride : 0);
                         if (sp > depth_lim) {
