@@ -752,8 +752,14 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     }
 }
 
+// Workgroup bound per node width: the binary kernels keep 256 (a larger
+// bound changed their code and cost the batched form 18%); the 4-wide ones
+// take up to 1024 threads, whose workgroups keep more of the tree's top.
+template <bool WIDE>
+constexpr int kMaxBlock = WIDE ? 1024 : 256;
+
 template <int MODE, bool CERT, bool STATS, bool PROP, bool WIDE>
-__global__ __launch_bounds__(1024) void k_traverse(TravParams p) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kMaxBlock<WIDE>))) void k_traverse(TravParams p) {
     extern __shared__ float4 lds_dyn[];  // 16-byte aligned: the 4-wide top nodes follow the stacks
     traverse_pass1<MODE, CERT, STATS, PROP, WIDE>(p, reinterpret_cast<int *>(lds_dyn));
 }
@@ -762,7 +768,8 @@ __global__ __launch_bounds__(1024) void k_traverse(TravParams p) {
 // is fixed at four waves per SIMD (the default resident count) so the list
 // cannot lower occupancy.
 template <bool CERT, bool STATS, bool WIDE>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void k_traverse_count(TravParams p) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kMaxBlock<WIDE>), amdgpu_waves_per_eu(4))) void k_traverse_count(
+    TravParams p) {
     extern __shared__ float4 lds_dyn[];
     traverse_pass1<MODE_COUNT, CERT, STATS, false, WIDE>(p, reinterpret_cast<int *>(lds_dyn));
 }
@@ -1232,6 +1239,8 @@ template <int MODE, bool CERT, bool STATS, bool PROP, bool WIDE>
 void launch_pass1(const TravParams &p, int block, hipStream_t s) {
     if (block == 0)
         block = WIDE ? kDefaultBlockWide : kDefaultBlock;
+    if (block > kMaxBlock<WIDE>)
+        block = kMaxBlock<WIDE>;
     // spare slots per lane past stack_depth: one for the binary push, three
     // for the 4-wide one; the 4-wide traversal also keeps the top of the tree
     // in what is left of the CU's LDS for the resident workgroups asked for
