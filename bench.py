@@ -334,24 +334,28 @@ def main():
 
             o = outs[args.mode]
             ms_plain = timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision, out=o))
+            ms_plain2 = timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision, out=o,
+                                                        node_width=2))
             ms_learned = timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision,
                                                          out=o, proposal=True))
             late = int(o["counters"][2].item())
             results[f"{args.precision} + learned proposal"] = o[key][:keep].cpu().numpy().copy()
             n_hit = int(o["hit"].sum().item()) if args.mode == "boolean" else int((o["tri_id"] >= 0).sum().item())
             ms_mlp = timed(lambda: rsi.rsi_proposal_predict(mesh, dO, dE))
-            v_p, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision)
+            # the proposal order walks binary nodes: compare node fetches on binary nodes
+            v_p, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision, node_width=2)
             v_l, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision, proposal=True)
             learned = {
                 "train_segments": args.train_rays, "labelled": n_lab, "epochs": args.train_epochs,
                 "train_s": round(t_tr, 2), "epoch_loss": [round(x, 4) for x in loss.tolist()],
                 "proposal_miss_rate": round(late / max(n_hit, 1), 4),
                 "intersect_mrays_s_plain_order": round(n / (ms_plain * 1e-3) / 1e6, 1),
+                "intersect_mrays_s_plain_order_binary_nodes": round(n / (ms_plain2 * 1e-3) / 1e6, 1),
                 "intersect_mrays_s_learned": round(n / (ms_learned * 1e-3) / 1e6, 1),
                 "mlp_inference_ms": round(ms_mlp, 3),
                 "mlp_tflops": round(n * 2 * 253952 / (ms_mlp * 1e-3) / 1e12, 1),
-                "mean_node_visits_plain_order": round(float(v_p.double().mean().item()), 2),
-                "mean_node_visits_learned": round(float(v_l.double().mean().item()), 2),
+                "mean_binary_node_visits_plain_order": round(float(v_p.double().mean().item()), 2),
+                "mean_binary_node_visits_learned": round(float(v_l.double().mean().item()), 2),
                 "mode": args.mode, "precision": args.precision,
             }
         print(f"[bench] learned: {learned}", file=sys.stderr, flush=True)
