@@ -127,8 +127,10 @@ typedef struct rsi_intersect_opts {
     int32_t precision;    /* rsi_precision; default RSI_PRECISION_PLAIN */
     int32_t block;        /* threads per workgroup of the first pass: 64, 128, 256,
                              512 or 1024 (binary nodes: at most 256, larger values
-                             run as 256); 0 = the library default (512 for 4-wide
-                             nodes, 256 for binary ones).  With 4-wide nodes a
+                             run as 256; a workgroup whose LDS stacks would not fit
+                             runs with half as many threads until they do); 0 = the
+                             library default (512 for 4-wide nodes, 256 for binary
+                             ones).  With 4-wide nodes a
                              larger workgroup keeps more of the tree's top in its
                              LDS. */
     int32_t stack_depth;  /* traversal stack entries per lane in LDS, 1..64; 0 = 20.

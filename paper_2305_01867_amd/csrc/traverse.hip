@@ -1251,7 +1251,11 @@ void launch_pass1(const TravParams &p, int block, hipStream_t s) {
     if (hipDeviceGetAttribute(&lds_block, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess ||
         lds_block <= 0)
         (void)hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    const size_t stack_bytes = (size_t)(p.stack_depth + (WIDE ? 3 : 1)) * block * sizeof(int);
+    // a workgroup whose stacks do not fit in LDS runs with fewer threads
+    const size_t lane_bytes = (size_t)(p.stack_depth + (WIDE ? 3 : 1)) * sizeof(int);
+    while (block > 64 && lane_bytes * block > (size_t)lds_block)
+        block /= 2;
+    const size_t stack_bytes = lane_bytes * block;
     TravParams q = p;
     q.top_lds = 0;
     if (WIDE) {

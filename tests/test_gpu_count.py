@@ -109,11 +109,13 @@ def test_grid_vertices_and_edges():
 
 
 def test_paper_scale_sampled():
+    """1e7 segments on the benchmark's tree (restructured, 4-wide first pass),
+    sampled against the oracle."""
     V, F, O, E = workloads.paper_scale_config()
     rng = np.random.default_rng(8)
     idx = rng.choice(O.shape[0], 2500, replace=False)
     want = oracle.intercept_count(V, F, O[idx], E[idx])
-    with rsi.rsi_build(dev(V), dev(F)) as mesh:
+    with rsi.rsi_build(dev(V), dev(F), algorithm="restructured") as mesh:
         r = rsi.rsi_intersect(mesh, dev(O), dev(E), mode="intercept_count", precision="certified")
         got = host(r["count"])
         cnt = host(r["counters"])

@@ -73,7 +73,7 @@ def test_empty_and_all_miss():
 
 def test_paper_scale_sampled():
     V, F, O, E = workloads.paper_scale_config()
-    with rsi.rsi_build(dev(V), dev(F)) as mesh:
+    with rsi.rsi_build(dev(V), dev(F), algorithm="restructured") as mesh:  # the benchmark's tree
         dO, dE = dev(O), dev(E)
         r = rsi.rsi_intersect(mesh, dO, dE, mode="barycentric", precision="certified")
         idx, dist, tri, pts = (host(x) for x in rsi.rsi_compact_hits(dO, dE, r))

@@ -200,7 +200,7 @@ def test_stack_depth_one_and_block_sizes_stay_exact():
     hit, ids, uvt, _ = oracle.intersect(V, F, O, E)
     with rsi.rsi_build(dev(V), dev(F)) as mesh:
         for stack in (1, 2, 5, 64):
-            for block in (64, 128, 256):
+            for block in (64, 128, 256, 512, 1024):  # 4-wide first pass; binary runs at most 256
                 say(f"  stack={stack} block={block}")
                 for mode in MODES:
                     got = intersect(mesh, O, E, mode, "certified", stack_depth=stack, block=block)
@@ -300,13 +300,15 @@ def test_non_finite_segments_are_misses():
 
 def test_paper_scale_sampled():
     """128 x 128 heightfield (32,258 triangles), 1e7 segments, the launch
-    configuration the benchmark times.  Every segment where PLAIN and
-    CERTIFIED disagree, plus a random sample, is checked against the oracle."""
+    configuration the benchmark times (restructured tree, 4-wide first pass,
+    default launch).  Every segment where PLAIN and CERTIFIED disagree, plus a
+    random sample, is checked against the oracle."""
     V, F, O, E = workloads.paper_scale_config()
     say(f"[intersect] paper scale: {F.shape[0]} triangles, {O.shape[0]} segments")
     rng = np.random.default_rng(0)
     sample = rng.choice(O.shape[0], 3000, replace=False)
-    with rsi.rsi_build(dev(V), dev(F)) as mesh:
+    with rsi.rsi_build(dev(V), dev(F), algorithm="restructured") as mesh:
+        assert rsi.rsi_mesh_info_get(mesh)["node_width"] == 4
         dO, dE = dev(O), dev(E)
         for mode in MODES:
             cert = rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision="certified")
@@ -323,13 +325,16 @@ def test_paper_scale_sampled():
             if mode == "boolean":
                 frac = float(c.mean())
                 say(f"  hit fraction {frac:.4f}")
-                with rsi.rsi_build(dev(V), dev(F), algorithm="restructured") as rmesh:
+                with rsi.rsi_build(dev(V), dev(F)) as rmesh:  # the paper's radix tree
                     r = host(rsi.rsi_intersect(rmesh, dO, dE, mode=mode, precision="certified")["hit"])
-                    assert np.array_equal(r, c), "restructured tree"
-                    v0, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=mode, precision="certified")
-                    v1, _ = rsi.rsi_traversal_stats(rmesh, dO, dE, mode=mode, precision="certified")
+                    assert np.array_equal(r, c), "radix tree"
+                    r = host(rsi.rsi_intersect(rmesh, dO, dE, mode=mode, precision="certified",
+                                               node_width=2)["hit"])
+                    assert np.array_equal(r, c), "radix tree, binary nodes"
+                    v0, _ = rsi.rsi_traversal_stats(rmesh, dO, dE, mode=mode, precision="certified")
+                    v1, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=mode, precision="certified")
                     m0, m1 = float(v0.double().mean()), float(v1.double().mean())
-                    say(f"  mean node visits: radix tree {m0:.2f}, restructured {m1:.2f}")
+                    say(f"  mean 4-wide node fetches: radix tree {m0:.2f}, restructured {m1:.2f}")
                     assert m1 < m0
                 for order in ("midpoint", "origin_octant"):  # the multi-block scan path of the sort
                     srt = host(rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision="certified",
