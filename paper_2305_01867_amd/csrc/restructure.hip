@@ -149,7 +149,9 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
     }
     if (m < 3)
         return;  // both children are leaves: one shape only
+    // the treelet leaves' box, cost, leaf count and leaf span, read once
     float lb[4][6], lc[4];
+    int ln[4], llo[4], lhi[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = i < m ? leaf[i] : leaf[0];
@@ -157,6 +159,9 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
         for (int a = 0; a < 6; ++a)
             lb[i][a] = ref_box(T, r, a);
         lc[i] = ref_cost(T, r);
+        ln[i] = ref_count(T, r);
+        llo[i] = ref_lo(T, r);
+        lhi[i] = ref_hi(T, r);
     }
     const int full = (1 << m) - 1;
     float area[16], cost[16], best_sum[16];
@@ -246,15 +251,14 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if ((S >> i) & 1) {
-                const int r = leaf[i];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     b[a] = fminf(b[a], lb[i][a]);
                     b[3 + a] = fmaxf(b[3 + a], lb[i][3 + a]);
                 }
-                count += ref_count(T, r);
-                lo = min(lo, ref_lo(T, r));
-                hi = max(hi, ref_hi(T, r));
+                count += ln[i];
+                lo = min(lo, llo[i]);
+                hi = max(hi, lhi[i]);
             }
         const int j = node[S];
         T.in_child[0][j] = child0;

@@ -205,33 +205,42 @@ __global__ __launch_bounds__(1024) void k_collapse_top(const Node *__restrict__ 
 // the root, copied into top4 with the references of children that also got a
 // slot rewritten to that slot.  Slots follow a block-wide prefix sum over each
 // level, so the layout does not depend on thread timing.
-__global__ __launch_bounds__(1024) void k_top_cache(const Node4 *__restrict__ nodes4, Node4 *__restrict__ top4) {
+__global__ __launch_bounds__(kTopSlots) void k_top_cache(const Node4 *__restrict__ nodes4, Node4 *__restrict__ top4) {
+    constexpr int kWaves = kTopSlots / 64;
     __shared__ int bidx[kTopSlots];  // binary index of the node in each slot
-    __shared__ int scan[1024];
-    const int tid = threadIdx.x;
+    __shared__ int wave_sum[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0)
         bidx[0] = 0;
     __syncthreads();
     int b0 = 0, b1 = 1;
     while (b0 < b1) {
-        const int i = b0 + tid;  // a level has at most kTopSlots <= blockDim nodes
+        const int i = b0 + tid;  // a level has at most kTopSlots = blockDim nodes
         Node4 nd;
         int cnt = 0;
         if (i < b1) {
             nd = nodes4[bidx[i]];
             cnt = (nd.child.x >= 0) + (nd.child.y >= 0) + (nd.child.z >= 0) + (nd.child.w >= 0);
         }
-        scan[tid] = cnt;
-        __syncthreads();
-        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-            const int v = tid >= off ? scan[tid - off] : 0;
-            __syncthreads();
-            scan[tid] += v;
-            __syncthreads();
+        // inclusive prefix sum of cnt: within the wave by shuffles, then across waves
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off);
+            incl += lane >= off ? t : 0;
         }
-        const int total = scan[blockDim.x - 1];
+        if (lane == 63)
+            wave_sum[w] = incl;
+        __syncthreads();
+        int total = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            const int x = wave_sum[k];
+            incl += k < w ? x : 0;
+            total += x;
+        }
         if (i < b1) {
-            int slot = b1 + scan[tid] - cnt;
+            int slot = b1 + incl - cnt;
             int c[4] = {nd.child.x, nd.child.y, nd.child.z, nd.child.w};
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -245,7 +254,7 @@ __global__ __launch_bounds__(1024) void k_top_cache(const Node4 *__restrict__ no
             nd.child = make_int4(c[0], c[1], c[2], c[3]);
             top4[i] = nd;
         }
-        __syncthreads();
+        __syncthreads();  // bidx of the next level written, wave_sum read
         b0 = b1;
         b1 = b1 + total < kTopSlots ? b1 + total : kTopSlots;
     }
@@ -268,7 +277,7 @@ hipError_t launch_collapse(MeshDev &m, hipStream_t s) {
     const int grid = (int)(want < 4 * cus ? want : 4 * cus);
     k_collapse_tiles<<<grid, 256, 0, s>>>(m.nodes, m.nodes4, L.tiles, L.n_tiles);
     k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, m.nodes4, L.tile_flag, L.queue, n_internal);
-    k_top_cache<<<1, 1024, 0, s>>>(m.nodes4, m.top4);
+    k_top_cache<<<1, kTopSlots, 0, s>>>(m.nodes4, m.top4);
     const hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         m.node_width = 4;
