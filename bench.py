@@ -117,7 +117,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the path shards by segments with the BVH replicated, and no multi-GPU run is part of this build",
+              "the path shards by segments with the BVH replicated; runs on more than one GPU are not supported",
               file=sys.stderr)
         sys.exit(2)
 
