@@ -51,7 +51,7 @@ __global__ void k_batch_prepare(const float *__restrict__ Vin, int64_t nv, const
     }
 }
 
-// Extent of each mesh (one workgroup per mesh), as k_mesh_bounds does for one.
+// Extent of each mesh (one workgroup per mesh), as the extent kernels of the single-mesh build do.
 __global__ __launch_bounds__(256) void k_batch_bounds(const float *__restrict__ V, const int64_t *__restrict__ v_off,
                                                       float *__restrict__ mesh_bounds) {
     const int m = blockIdx.x;

@@ -26,17 +26,14 @@ constexpr int kNoTile = INT32_MIN;  // never a child reference (leaves are ~k wi
 constexpr int kRestructureRounds = 2;  // treelet restructuring passes of algorithm 2
 
 // ---------------------------------------------------------------- 1. extent
-__global__ __launch_bounds__(1024) void k_mesh_bounds(const float *__restrict__ V, int64_t nv,
-                                                      float *__restrict__ bounds) {
-    float lo[3] = {INFINITY, INFINITY, INFINITY};
-    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = threadIdx.x; i < nv; i += blockDim.x) {
-        for (int a = 0; a < 3; ++a) {
-            float x = V[3 * i + a];
-            lo[a] = fminf(lo[a], x);
-            hi[a] = fmaxf(hi[a], x);
-        }
-    }
+// Min / max are exact in any order, so the extent is reduced in two steps:
+// up to kBoundsParts workgroups each reduce a strided share of the vertices,
+// then one workgroup combines their partial boxes and the coordinate scale.
+constexpr int kBoundsParts = 256;
+
+// Block-wide min / max of six values (lo xyz, hi xyz); the result is valid in
+// thread 0.
+__device__ __forceinline__ void block_minmax(float lo[3], float hi[3]) {
     for (int off = 32; off > 0; off >>= 1)
         for (int a = 0; a < 3; ++a) {
             lo[a] = fminf(lo[a], __shfl_xor(lo[a], off));
@@ -57,6 +54,38 @@ __global__ __launch_bounds__(1024) void k_mesh_bounds(const float *__restrict__ 
                 lo[a] = fminf(lo[a], red[k][a]);
                 hi[a] = fmaxf(hi[a], red[k][3 + a]);
             }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_mesh_bounds_part(const float *__restrict__ V, int64_t nv,
+                                                           float *__restrict__ partial) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
+        for (int a = 0; a < 3; ++a) {
+            const float x = V[3 * i + a];
+            lo[a] = fminf(lo[a], x);
+            hi[a] = fmaxf(hi[a], x);
+        }
+    block_minmax(lo, hi);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) {
+            partial[6 * blockIdx.x + a] = lo[a];
+            partial[6 * blockIdx.x + 3 + a] = hi[a];
+        }
+}
+
+__global__ __launch_bounds__(kBoundsParts) void k_mesh_bounds_final(const float *__restrict__ partial, int parts,
+                                                                    float *__restrict__ bounds) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if ((int)threadIdx.x < parts)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = partial[6 * threadIdx.x + a];
+            hi[a] = partial[6 * threadIdx.x + 3 + a];
+        }
+    block_minmax(lo, hi);
+    if (threadIdx.x == 0) {
         float scale = 0.0f;
         for (int a = 0; a < 3; ++a) {
             bounds[a] = lo[a];
@@ -742,7 +771,9 @@ size_t sort_tmp_bytes(int64_t nt, int morton_bits) {
     const size_t kb = morton_bits > 32 ? 8 : 4;
     const size_t sort = pass_tmp_bytes(nt, kb);
     const size_t lists = build_lists_bytes(nt);  // lists kept after the sort
-    return sort > lists ? sort : lists;
+    const size_t parts = 6 * sizeof(float) * kBoundsParts;  // extent partials before the sort
+    const size_t most = sort > lists ? sort : lists;
+    return most > parts ? most : parts;
 }
 
 size_t sort_u32_tmp_bytes(int64_t n) { return pass_tmp_bytes(n, 4); }
@@ -763,7 +794,12 @@ hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s) { return b
 
 hipError_t launch_build(MeshDev &m, const float *, const int32_t *, hipStream_t s, size_t) {
     k_zero_i32<<<1, 64, 0, s>>>(m.flags, 4);
-    k_mesh_bounds<<<1, 1024, 0, s>>>(m.V, m.nv, m.bounds);
+    // the sort scratch is free until the keys are sorted
+    const int64_t want = (m.nv + 1023) / 1024;
+    const int parts = (int)(want < 1 ? 1 : (want < kBoundsParts ? want : kBoundsParts));
+    float *partial = static_cast<float *>(m.sort_tmp);
+    k_mesh_bounds_part<<<parts, 1024, 0, s>>>(m.V, m.nv, partial);
+    k_mesh_bounds_final<<<1, kBoundsParts, 0, s>>>(partial, parts, m.bounds);
     hipError_t e = m.morton_bits > 32 ? build_typed<uint64_t>(m, s) : build_typed<uint32_t>(m, s);
     if (e == hipSuccess && m.algorithm == 2)
         e = launch_restructure(m, kRestructureRounds, s);
