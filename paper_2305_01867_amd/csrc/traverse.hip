@@ -265,6 +265,7 @@ struct TravParams {
     const Node4 *__restrict__ nodes4;  // the 4-wide tree the first pass walks, or NULL
     const Node4 *__restrict__ top4;    // its first kTopSlots nodes, breadth-first
     int top_lds;                       // how many of them each workgroup keeps in LDS
+    int bary_after;                    // certified barycentric, one mesh: (u, v, t) by k_bary64
     const Tri *__restrict__ tris;
     const float *__restrict__ V;
     const int32_t *__restrict__ F;
@@ -733,9 +734,15 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
             } else if (CERT && flagged) {
                 enqueue(p, ray, 0);
             } else if (CERT && MODE == MODE_BARY && best_id >= 0) {
-                const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
-                const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, best_id);
-                write_out(p.out, ray, MODE, best_id - lane_toff, (float)h.u, (float)h.v, (float)h.t);
+                if (p.bary_after) {  // (u, v, t) after both passes, a lane per segment
+                    if (p.out.hit)
+                        p.out.hit[ray] = 1;
+                    p.out.id[ray] = best_id - lane_toff;
+                } else {
+                    const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
+                    const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, best_id);
+                    write_out(p.out, ray, MODE, best_id - lane_toff, (float)h.u, (float)h.v, (float)h.t);
+                }
             } else {
                 write_out(p.out, ray, MODE, best_id >= 0 ? best_id - lane_toff : -1, best_u, best_v, best_t);
             }
@@ -1224,6 +1231,26 @@ __global__ void k_reset(uint32_t *queue_len, unsigned long long *counters) {
         counters[threadIdx.x] = 0;
 }
 
+// Certified barycentric output of one mesh: the binary64 (u, v, t) of each
+// segment's nearest triangle, from the original corners in the oracle's
+// operation order.  Run after both passes with a lane per segment, so the
+// binary64 work is not spread over the traversal's divergent lanes.
+__global__ void k_bary64(const float *__restrict__ from, const float *__restrict__ to, const float *__restrict__ V,
+                         const int32_t *__restrict__ F, const int32_t *__restrict__ tri_id, float *__restrict__ uvt,
+                         int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int id = tri_id[i];
+    if (id < 0)
+        return;  // a miss: written by the passes
+    const MT64 h = mt64(from[3 * i], from[3 * i + 1], from[3 * i + 2], to[3 * i], to[3 * i + 1], to[3 * i + 2], V, F,
+                        id);
+    uvt[3 * i] = (float)h.u;
+    uvt[3 * i + 1] = (float)h.v;
+    uvt[3 * i + 2] = (float)h.t;
+}
+
 __global__ void k_fill_miss(Outs out, int64_t n, int mode) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
@@ -1332,6 +1359,7 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
                                                                                                       : nullptr;
     p.top4 = p.nodes4 ? m.top4 : nullptr;
     p.top_lds = 0;
+    p.bary_after = (a.mode == MODE_BARY && a.certified && a.items == nullptr && a.uvt != nullptr) ? 1 : 0;
     p.tris = m.tris;
     p.V = m.V;
     p.F = m.F;
@@ -1408,6 +1436,8 @@ hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t
         a.certified ? k_finish<MODE_BARY, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_BARY, false><<<grid2, kFinishThreads, 0, s>>>(p);
     else
         a.certified ? k_finish<MODE_COUNT, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_COUNT, false><<<grid2, kFinishThreads, 0, s>>>(p);
+    if (p.bary_after)
+        k_bary64<<<(int)((a.n + 255) / 256), 256, 0, s>>>(a.from, a.to, m.V, m.F, a.tri_id, a.uvt, a.n);
     return hipGetLastError();
 }
 
