@@ -395,9 +395,11 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     int phase = 1, skip = kDone;  // kDone never equals a child reference
     bool best_late = false;       // best hit found in phase 1 (a proposal miss)
     uint32_t n_late = 0;          // this lane's proposal misses, summed per wave at exit
-    // count mode: the distinct t found so far (binary64 when certified)
-    using TCount = typename std::conditional<CERT, double, float>::type;
-    TCount tk[kCountSlots];
+    // count mode: the distinct t found so far -- binary32 values (plain), or
+    // intervals that each hold one hit's binary64 t (certified): disjoint
+    // intervals hold distinct values, so only overlapping ones need the exact
+    // second pass
+    float tk[kCountSlots], tk_hi[kCountSlots];
     int nk = 0;
     bool list_full = false;
 
@@ -618,34 +620,57 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                 const int id = __float_as_int(tri.a.w);
                 if (MODE == MODE_COUNT) {
                     // every hit counts once per distinct t; no early exit, no pruning
-                    bool hit = false;
-                    TCount t = 0;
                     if (!CERT) {
-                        hit = decide32(m);
-                        t = (TCount)(m.T / m.det);
+                        if (decide32(m)) {
+                            const float t = m.T / m.det;
+                            bool dup = false;
+#pragma unroll
+                            for (int k = 0; k < kCountSlots; ++k)
+                                dup = dup || (k < nk && tk[k] == t);
+                            if (!dup) {
+                                if (nk == kCountSlots) {
+                                    list_full = true;  // finished by the second pass
+                                    ref = kDone;
+                                } else {
+#pragma unroll
+                                    for (int k = 0; k < kCountSlots; ++k)
+                                        if (k == nk)
+                                            tk[k] = t;
+                                    ++nk;
+                                }
+                            }
+                        }
                     } else {
-                        float lo, hi;
-                        if (classify(m, tri, r, lo, hi) != kMiss && valid_tri(p.F, p.nv, id)) {
+                        // a sure hit brings an interval holding its binary64 t;
+                        // an unsure pair is decided in binary64 here
+                        float lo = 0.0f, hi = 0.0f;
+                        const int c = classify(m, tri, r, lo, hi);
+                        bool take = c == kHit;
+                        if (c == kUnsure && valid_tri(p.F, p.nv, id)) {
                             const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
                             const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, id);
-                            hit = h.hit;
-                            t = (TCount)h.t;
+                            take = h.hit;
+                            lo = __double2float_rd(h.t);
+                            hi = __double2float_ru(h.t);
                         }
-                    }
-                    if (hit) {
-                        bool dup = false;
+                        if (take) {
+                            bool meet = false;
 #pragma unroll
-                        for (int k = 0; k < kCountSlots; ++k)
-                            dup = dup || (k < nk && tk[k] == t);
-                        if (!dup) {
-                            if (nk == kCountSlots) {
-                                list_full = true;  // finished by the second pass
+                            for (int k = 0; k < kCountSlots; ++k)
+                                meet = meet || (k < nk && !(hi < tk[k] || lo > tk_hi[k]));
+                            if (meet) {
+                                flagged = true;  // equal or nearly equal t: counted exactly by the second pass
+                                ref = kDone;
+                            } else if (nk == kCountSlots) {
+                                list_full = true;
                                 ref = kDone;
                             } else {
 #pragma unroll
                                 for (int k = 0; k < kCountSlots; ++k)
-                                    if (k == nk)
-                                        tk[k] = t;
+                                    if (k == nk) {
+                                        tk[k] = lo;
+                                        tk_hi[k] = hi;
+                                    }
                                 ++nk;
                             }
                         }
@@ -718,6 +743,8 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                     enqueue(p, ray, 1);
                 else if (list_full)
                     enqueue(p, ray, 3);
+                else if (CERT && flagged)
+                    enqueue(p, ray, 0);
                 else
                     write_count(p.out, ray, nk);
             } else if (MODE == MODE_BOOL) {

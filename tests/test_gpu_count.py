@@ -39,8 +39,15 @@ def test_closed_form_scenes():
         with rsi.rsi_build(dev(V), dev(F)) as mesh:
             got, cnt = gpu_count(mesh, O, E)
             assert got.tolist() == want.tolist(), k
-            if k > 12:
-                assert cnt[3] >= 2  # the two vertical segments outgrew the lane's list
+            # the segment on the layers' diagonal meets two triangles at one t
+            # in every layer: overlapping intervals send it to the exact second
+            # pass (counter 0) -- unless, past 12 layers, it fills the lane's
+            # list first (counter 3); the other vertical one outgrows the list
+            # past 12 distinct t
+            if k <= 12:
+                assert cnt[0] >= 1
+            else:
+                assert cnt[3] >= 1 and cnt[0] + cnt[3] >= 2
             plain, _ = gpu_count(mesh, O, E, "plain")
             assert plain.tolist() == want.tolist()
             hit = host(rsi.rsi_intersect(mesh, dev(O), dev(E), mode="intercept_count",
