@@ -16,9 +16,9 @@
 //
 // On gfx950 the work is kept inside workgroups: one workgroup loads a whole
 // tile (a subtree of at most 1024 leaves, listed by the radix-tree kernel)
-// into LDS in one step, restructures it in bottom-up climbs (a lane per
-// leaf, a treelet optimised where the second lane arrives), and writes it
-// back; one workgroup then does the same for the nodes above the tiles, with
+// into LDS in one step, restructures it height by height (the nodes of one
+// height compacted onto consecutive lanes, a treelet optimised per node), and
+// writes it back; one workgroup then does the same for the nodes above the tiles, with
 // the tiles as fixed leaves.  No cross-workgroup synchronisation at all.
 //
 // After restructuring, an internal node's leaves are no longer a contiguous
@@ -29,7 +29,8 @@
 namespace rsi {
 namespace {
 
-constexpr int kTile = 1024;            // leaves per tile (= lanes per workgroup)
+constexpr int kTile = 1024;            // leaves per tile
+constexpr int kThreads = 512;          // lanes per workgroup (256 VGPRs per lane, no spills)
 constexpr int kTreelet = 4;            // leaves per treelet (the optimisation runs in one lane's registers)
 constexpr int kMaxLevels = 130;        // > deepest radix tree (97) + treelet growth
 constexpr float kCostNode = 1.2f;      // SAH weight of a node visit (one 64-B node, two box tests)
@@ -45,7 +46,10 @@ struct TileLds {
     int in_count[kTile];       // leaves below
     int in_lo[kTile], in_hi[kTile];  // smallest / largest sorted leaf below
     int in_parent[kTile];      // local parent, -1 at the root
-    int arrive[kTile];         // arrivals of the bottom-up climb
+    int arrive[kTile + 2];     // arrivals of the height climb, then per-height counters
+    int height[kTile];         // 1 + the larger child height (a leaf is 0)
+    int order[kTile];          // internal nodes by rising height
+    int h_start[kTile + 2];    // order[h_start[h] .. h_start[h + 1]) have height h
     int lf_ref[kTile];         // global reference of local leaf j (a leaf ~k, or a fixed subtree)
     float lf_box[6][kTile];
     float lf_cost[kTile];
@@ -53,7 +57,7 @@ struct TileLds {
     int lf_lo[kTile], lf_hi[kTile];
     int lf_parent[kTile];
     int lvl_start[kMaxLevels + 2];  // breadth-first load of the top tree
-    int n_in, n_lf, root, overflow;
+    int n_in, n_lf, root, overflow, max_height;
 };
 
 __device__ __forceinline__ float half_area(float x0, float y0, float z0, float x1, float y1, float z1) {
@@ -275,30 +279,100 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
     }
 }
 
+// Heights of the local internal nodes by a bottom-up climb, one lane per
+// leaf: the second lane to reach a node finds both child heights final.
+// Integer work only, so the divergence of the climb costs little.
+__device__ __forceinline__ void local_heights(TileLds &T) {
+    for (int j = threadIdx.x; j < T.n_in; j += blockDim.x) {
+        T.arrive[j] = 0;
+        T.height[j] = 0;
+    }
+    if (threadIdx.x == 0)
+        T.max_height = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < T.n_lf; k += blockDim.x) {
+        int j = T.lf_parent[k];
+        for (int step = 0; j >= 0 && step < T.n_in; ++step) {  // a climb is at most n_in nodes long
+            if (__hip_atomic_fetch_add(&T.arrive[j], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+                break;  // the other subtree is still on its way
+            const int c0 = T.in_child[0][j], c1 = T.in_child[1][j];
+            const int h = 1 + max(c0 >= 0 ? T.height[c0] : 0, c1 >= 0 ? T.height[c1] : 0);
+            T.height[j] = h;
+            if (T.in_parent[j] < 0)
+                T.max_height = h;  // the local root is the highest node
+            j = T.in_parent[j];
+        }
+    }
+    __syncthreads();
+}
+
+// Internal nodes grouped by height into T.order, with T.h_start[h] the first
+// position of height h (a counting sort in LDS; the order inside a height
+// does not matter, its nodes are independent).
+__device__ __forceinline__ void order_by_height(TileLds &T) {
+    const int H = T.max_height;
+    for (int h = threadIdx.x; h <= H; h += blockDim.x)
+        T.arrive[h] = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < T.n_in; j += blockDim.x) {
+        const int h = T.height[j];
+        if (h >= 1 && h <= H)  // always, in a tree the climb reached whole
+            atomicAdd(&T.arrive[h], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {  // exclusive scan of the counts by the first wave
+        const int lane = threadIdx.x;
+        int carry = 0;
+        for (int base = 0; base <= H + 1; base += 64) {
+            const int h = base + lane;
+            const int v = h <= H ? T.arrive[h] : 0;
+            int incl = v;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int u = __shfl_up(incl, d, 64);
+                incl += lane >= d ? u : 0;
+            }
+            if (h <= H + 1)
+                T.h_start[h] = carry + incl - v;
+            carry += __shfl(incl, 63, 64);
+        }
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h <= H; h += blockDim.x)
+        T.arrive[h] = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < T.n_in; j += blockDim.x) {
+        const int h = T.height[j];
+        if (h >= 1 && h <= H)
+            T.order[T.h_start[h] + atomicAdd(&T.arrive[h], 1)] = j;
+    }
+    __syncthreads();
+}
+
 // Restructure the local tree in T (loaded, with parents; costs not yet
-// known).  Each pass is a bottom-up climb, one lane per leaf as in the
-// radix-tree box pass: the second lane to reach a node finds both subtrees
-// final, refreshes the node and optimises the treelet rooted there, and
-// climbs on; the first lane stops.  A node's treelet lies inside its own
-// subtree, which no other lane touches any more, so no barrier is needed
-// between levels, only workgroup-scope acquire / release on the arrivals.
+// known).  Each pass visits the internal nodes by rising height (the heights
+// of the tree the pass starts from), so both subtrees of a node are final
+// when it is visited, and the nodes of one height, whose subtrees are
+// disjoint, run side by side on consecutive lanes: each refreshes its box
+// cost and optimises the treelet rooted there, which lies inside its own
+// subtree.  Compacting a height onto consecutive lanes keeps the long
+// treelet optimisation from running once per wave for a few active lanes,
+// as a climb from the leaves would.
 __device__ __forceinline__ void restructure_local(TileLds &T, int rounds) {
     for (int round = 0; round < rounds; ++round) {
-        for (int j = threadIdx.x; j < T.n_in; j += blockDim.x)
-            T.arrive[j] = 0;
-        __syncthreads();
-        for (int k = threadIdx.x; k < T.n_lf; k += blockDim.x) {
-            int j = T.lf_parent[k];
-            for (int step = 0; j >= 0 && step < T.n_in; ++step) {  // a climb is at most n_in nodes long
-                if (__hip_atomic_fetch_add(&T.arrive[j], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
-                    break;  // the other subtree is still on its way
+        local_heights(T);
+        order_by_height(T);
+        const int H = T.max_height;
+        for (int h = 1; h <= H; ++h) {
+            const int e = T.h_start[h + 1];
+            for (int i = T.h_start[h] + threadIdx.x; i < e; i += blockDim.x) {
+                const int j = T.order[i];
                 refresh_node(T, j);
                 if (T.in_count[j] >= kTreelet)
                     optimize_treelet(T, j);
-                j = T.in_parent[j];
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -454,7 +528,7 @@ __device__ void store_tree(const TileLds &T, Node *nodes, int32_t *parent, int n
 }
 
 // One workgroup per tile of the radix-tree kernel's list.
-__global__ __launch_bounds__(kTile) void k_restructure_tiles(Node *nodes, int32_t *parent, int n,
+__global__ __launch_bounds__(kThreads) void k_restructure_tiles(Node *nodes, int32_t *parent, int n,
                                                              const int32_t *__restrict__ tiles,
                                                              const int32_t *__restrict__ n_tiles,
                                                              float *__restrict__ tile_cost, int rounds) {
@@ -476,7 +550,7 @@ __global__ __launch_bounds__(kTile) void k_restructure_tiles(Node *nodes, int32_
 
 // One workgroup: the nodes above the tiles (more than kTile leaves each),
 // with the tiles as fixed leaves.  Skipped when they do not fit in LDS.
-__global__ __launch_bounds__(kTile) void k_restructure_top(Node *nodes, int32_t *parent, int n,
+__global__ __launch_bounds__(kThreads) void k_restructure_top(Node *nodes, int32_t *parent, int n,
                                                            const float *__restrict__ tile_cost, int rounds) {
     extern __shared__ char lds[];
     TileLds &T = *reinterpret_cast<TileLds *>(lds);
@@ -528,8 +602,8 @@ hipError_t launch_restructure(MeshDev &m, int rounds, hipStream_t s) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t want = (m.nt + kTile - 1) / kTile * 2;  // tiles hold up to kTile leaves, usually fewer
     const int grid = (int)(want < cus ? want : cus);
-    k_restructure_tiles<<<grid, kTile, lds, s>>>(m.nodes, m.parent, (int)m.nt, tiles, n_tiles, tile_cost, rounds);
-    k_restructure_top<<<1, kTile, lds, s>>>(m.nodes, m.parent, (int)m.nt, tile_cost, rounds);
+    k_restructure_tiles<<<grid, kThreads, lds, s>>>(m.nodes, m.parent, (int)m.nt, tiles, n_tiles, tile_cost, rounds);
+    k_restructure_top<<<1, kThreads, lds, s>>>(m.nodes, m.parent, (int)m.nt, tile_cost, rounds);
     return hipGetLastError();
 }
 
