@@ -327,10 +327,10 @@ __device__ __forceinline__ void order2(float &ka, int &ca, float &kb, int &cb) {
 // whose segment is finished is refilled from that range while the others go
 // on, so a wave's time follows the mean cost of a segment instead of the
 // slowest of its 64 (no atomics: a shared counter across eight XCDs costs more
-// than the imbalance of ~1e3 segments per wave).  Leaf tests are postponed: a lane keeps one leaf
-// aside and continues with internal nodes; the leaf phase runs once a set
-// share of the wave is waiting on a leaf, so the leaf code runs for many lanes
-// at once.
+// than the imbalance of ~1e3 segments per wave).  Leaf tests are postponed: a lane holds up to
+// kPend leaves aside and continues with internal nodes; the leaf phase runs
+// once a set share of the wave is waiting (on a further leaf, or done), so the
+// leaf code runs for many lanes at once.
 constexpr int kRefillMin = 8;     // refill when at least this many lanes idle
 // The node phase hands over to the leaf phase once more than 1/kLeafShare of
 // the active lanes wait on a leaf: early for the modes that test few leaves
@@ -338,6 +338,11 @@ constexpr int kRefillMin = 8;     // refill when at least this many lanes idle
 // which tests every leaf it reaches (measured on the paper-scale workload).
 template <int MODE>
 constexpr int kLeafShare = MODE == MODE_COUNT ? 2 : 3;
+// Leaves a lane may hold aside while it goes on with internal nodes: two
+// keep more lanes in the node phase (boolean -2%, intercept count -5% at the
+// paper's scale against one; three gain nothing more).
+template <int MODE>
+constexpr int kPend = 2;
 // Resident waves per CU of the persistent traversal unless asked otherwise:
 // fewer waves than registers allow share the CU's L1 among fewer tree paths.
 constexpr int kDefaultWavesPerCU = 16;
@@ -385,7 +390,23 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     // and the matching slab offsets, fixed per segment by the direction signs
     int offx = 0, offy = 32, offz = 64;
     float3 nn = make_float3(0.0f, 0.0f, 0.0f), nf = nn;
-    int ref = kDone, pend = -1, sp = 0;  // sp: offset of the next free slot (a multiple of stride)
+    int ref = kDone, sp = 0;  // sp: offset of the next free slot (a multiple of stride)
+    int held[kPend<MODE>];    // leaves held aside (-1: free), tested in this order
+#pragma unroll
+    for (int k = 0; k < kPend<MODE>; ++k)
+        held[k] = -1;
+    auto none_held = [&]() {
+        bool none = true;
+#pragma unroll
+        for (int k = 0; k < kPend<MODE>; ++k)
+            none = none && held[k] < 0;
+        return none;
+    };
+    auto drop_held = [&]() {
+#pragma unroll
+        for (int k = 0; k < kPend<MODE>; ++k)
+            held[k] = -1;
+    };
     float tlimit = 1.0f;
     int best_id = -1;
     float best_t = INFINITY, best_lo = INFINITY, best_hi = INFINITY, best_u = 0.0f, best_v = 0.0f;
@@ -434,7 +455,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                     lane_root = cur_root;
                     lane_toff = cur_toff;
                     ref = lane_root;
-                    pend = -1;
+                    drop_held();
                     sp = 0;
                     tlimit = 1.0f;
                     best_id = -1;
@@ -485,9 +506,16 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
         // (a slot at or above sp holds nothing live), and the top of stack is
         // read ahead of the node fetch and used only if the node yields nothing.
         for (;;) {
-            if (ray >= 0 && pend < 0 && ref < 0 && ref != kDone) {
-                pend = ~ref;
-                ref = pop();
+            if (ray >= 0 && ref < 0 && ref != kDone) {  // a leaf: hold it aside if a slot is free
+                bool put = false;
+#pragma unroll
+                for (int k = 0; k < kPend<MODE>; ++k)
+                    if (!put && held[k] < 0) {
+                        held[k] = ~ref;
+                        put = true;
+                    }
+                if (put)
+                    ref = pop();
             }
             const bool want = ray >= 0 && ref >= 0;
             const uint64_t w = __ballot(want);
@@ -500,7 +528,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                 if (++steps > max_steps || ref >= ref_lim) {
                     overflow = true;  // cannot happen for a well-formed tree
                     ref = kDone;
-                    pend = -1;
+                    drop_held();
                 } else {
                     const int top = stk[sp > 0 ? sp - stride : 0];
                     if (STATS)
@@ -576,7 +604,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                         if (sp > depth_lim) {
                             overflow = true;  // the segment goes to the deep-stack pass
                             ref = kDone;
-                            pend = -1;
+                            drop_held();
                         }
                     } else {
                         const Node *nd = p.nodes + ref;
@@ -598,17 +626,16 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                         sp += both ? stride : (!any && sp > 0 ? -stride : 0);
                         if (both && sp > depth_lim) {
                             ref = kDone;  // overflow: the segment goes to the deep-stack pass
-                            pend = -1;
+                            drop_held();
                         }
                     }
                 }
             }
         }
 
-        // ---- leaf phase
-        if (ray >= 0 && pend >= 0) {
-            const int leaf = pend;
-            pend = -1;
+        // ---- leaf phase: the leaves held aside, in the order they were met;
+        // a decided segment drops the rest
+        auto test_leaf = [&](const int leaf) {
             if (leaf >= p.nt) {
                 overflow = true;  // cannot happen for a well-formed tree
                 ref = kDone;
@@ -723,16 +750,24 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                     }
                 }
             }
-        }
+        };
+#pragma unroll
+        for (int k = 0; k < kPend<MODE>; ++k)
+            if (ray >= 0 && held[k] >= 0) {
+                const int leaf = held[k];
+                held[k] = -1;
+                if (!(found || flagged || list_full || overflow))
+                    test_leaf(leaf);
+            }
 
         // ---- proposal: the predicted subtree is exhausted, go on with the rest
-        if (PROP && ray >= 0 && ref == kDone && pend < 0 && phase == 0 && !found && !flagged && !overflow) {
+        if (PROP && ray >= 0 && ref == kDone && none_held() && phase == 0 && !found && !flagged && !overflow) {
             phase = 1;
             ref = lane_root == skip ? kDone : lane_root;
         }
 
         // ---- finish lanes whose segment is decided
-        if (ray >= 0 && ref == kDone && pend < 0) {
+        if (ray >= 0 && ref == kDone && none_held()) {
             if (PROP && !STATS && best_late && (found || (MODE != MODE_BOOL && best_id >= 0 && !flagged && !overflow)))
                 ++n_late;  // the proposal did not hold the answer
             if (STATS) {
