@@ -247,8 +247,8 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *t
     const size_t sz_V = round_up(12 * (size_t)n_vertices), sz_F = round_up(12 * (size_t)nt);
     const size_t sz_keys = round_up(kb * nt), sz_ids = round_up(4 * (size_t)nt);
     const size_t sz_nodes = round_up(64 * (size_t)(nt > 1 ? nt - 1 : 1));
-    // the 4-wide tree (one 128-B slot per binary internal node), for the
-    // builds whose tile list it is collapsed with
+    // the 4-wide tree (its top, then one 128-B slot per binary internal
+    // node), for the builds whose tile list it is collapsed with
     const size_t sz_nodes4 = (algorithm != 1 && nt > 1) ? round_up(128 * (size_t)(nt - 1 + rsi::kTopSlots)) : 0;
     const size_t sz_par = round_up(4 * (size_t)(2 * nt - 1)), sz_cnt = round_up(4 * (size_t)(nt > 1 ? nt - 1 : 1));
     const size_t sz_tris = round_up(48 * (size_t)nt), sz_small = 256;
@@ -274,8 +274,9 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *t
     d.keys = take(sz_keys);
     d.ids = reinterpret_cast<int32_t *>(take(sz_ids));
     d.nodes = reinterpret_cast<rsi::Node *>(take(sz_nodes));
-    d.nodes4 = sz_nodes4 ? reinterpret_cast<rsi::Node4 *>(take(sz_nodes4)) : nullptr;
-    d.top4 = d.nodes4 ? d.nodes4 + (nt - 1) : nullptr;
+    // top4 directly before nodes4, so a 4-wide reference r addresses top4[r] in both ranges
+    d.top4 = sz_nodes4 ? reinterpret_cast<rsi::Node4 *>(take(sz_nodes4)) : nullptr;
+    d.nodes4 = d.top4 ? d.top4 + rsi::kTopSlots : nullptr;
     d.parent = reinterpret_cast<int32_t *>(take(sz_par));
     d.counters = reinterpret_cast<int32_t *>(take(sz_cnt));
     d.tris = reinterpret_cast<rsi::Tri *>(take(sz_tris));

@@ -37,7 +37,8 @@ constexpr int32_t kEmptyChild = INT32_MIN;
 // also kept in a compact array (top4), which the traversal copies into LDS as
 // far as its LDS budget allows.  A 4-wide child reference r >= 0 names top4[r]
 // when r < kTopSlots and the node collapsed from binary node r - kTopSlots
-// otherwise; the root is top4[0].
+// otherwise; the root is top4[0].  nodes4 directly follows top4 in memory
+// (nodes4 = top4 + kTopSlots), so top4[r] addresses either kind.
 constexpr int kTopSlots = 512;
 
 // Leaf triangle in sorted order: first corner, the two edge vectors from it

@@ -553,8 +553,8 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                             ch = make_int4(__float_as_int(cf.x), __float_as_int(cf.y), __float_as_int(cf.z),
                                            __float_as_int(cf.w));
                         } else {
-                            const char *c = reinterpret_cast<const char *>(
-                                ref < kTopSlots ? p.top4 + ref : p.nodes4 + (ref - kTopSlots));
+                            // nodes4 follows top4: one address for both kinds of reference
+                            const char *c = reinterpret_cast<const char *>(p.top4 + ref);
                             nx = *reinterpret_cast<const float4 *>(c + offx);
                             fx = *reinterpret_cast<const float4 *>(c + (offx ^ 16));
                             ny = *reinterpret_cast<const float4 *>(c + offy);
