@@ -282,19 +282,41 @@ __global__ __launch_bounds__(256) void k_init_params(float *__restrict__ P, __bf
 }
 
 // ------------------------------------------------ fused inference kernel
-// 64 segments per tile; four waves, wave w producing output columns
-// [64 w, 64 w + 64) of every layer for all 64 rows (16 MFMA per k step, so
-// each weight fragment fetched from L2 feeds 4 row tiles).  Activations stay
-// in LDS (two bf16 buffers, 66 KB: two workgroups per CU); the next k step's weight fragments are
-// loaded while the current step multiplies.  The accumulation order over k is
+// 96 segments per tile; four waves, wave w producing output columns
+// [64 w, 64 w + 64) of every layer for all 96 rows (24 MFMA per k step, so
+// each weight fragment fetched from L2 feeds 6 row tiles).  Activations stay
+// in LDS in one bf16 buffer that each layer overwrites once every wave has
+// read it (54 KB with the argmax scratch: two workgroups per CU, 246 VGPRs
+// and two waves per SIMD; 112 or 128 rows spill).  The next k step's weight
+// fragments are loaded while the current step multiplies (measured at the
+// paper's scale: 64 rows with two buffers and a one-step register copy 11.0
+// ms per 1e7 segments, this layout 8.1 ms).  The accumulation order over k is
 // the one k_gemm uses, so the logits are bit-identical to the training
 // forward pass.
-constexpr int kPRows = 64;
+constexpr int kPRows = 96;
 constexpr int kPPitch = kMlpHidden + 8;
 constexpr int kPRowTiles = kPRows / 16;
 
-__device__ __forceinline__ void layer_tile(const __bf16 *__restrict__ Xin, int K, const __bf16 *__restrict__ Wt,
-                                           int wave, int lane, f32x4 (&acc)[kPRowTiles][4]) {
+__device__ __forceinline__ void tile_step(const __bf16 *__restrict__ xrow, int k0, const bf16x8 (&fb)[4],
+                                          f32x4 (&acc)[kPRowTiles][4]) {
+#pragma unroll
+    for (int a = 0; a < kPRowTiles; ++a) {
+        const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(xrow + 16 * a * kPPitch + k0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            acc[a][b] = mfma16(fa, fb[b], acc[a][b]);
+    }
+}
+
+// K (224 or 256) is known at compile time and the k loop fully unrolled, so
+// every step's weight fragments are registers of their own: the next step's
+// loads are issued before the current step multiplies and stay in flight
+// across it, with no register copy that would wait for them.
+template <int K>
+__device__ __forceinline__ void layer_tile(const __bf16 *__restrict__ Xin, const __bf16 *__restrict__ Wt, int wave,
+                                           int lane, f32x4 (&acc)[kPRowTiles][4]) {
+    static_assert(K % 32 == 0, "K must be a multiple of 32");
+    constexpr int kSteps = K / 32;
 #pragma unroll
     for (int a = 0; a < kPRowTiles; ++a)
 #pragma unroll
@@ -303,37 +325,28 @@ __device__ __forceinline__ void layer_tile(const __bf16 *__restrict__ Xin, int K
     const int kq = 8 * (lane >> 4);
     const __bf16 *wrow = Wt + (int64_t)(64 * wave + (lane & 15)) * K + kq;
     const __bf16 *xrow = Xin + (lane & 15) * kPPitch + kq;
-    bf16x8 fb[4], nb[4];
+    bf16x8 f[kSteps][4];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-        fb[b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K);
-#pragma unroll 1
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        const int kn = k0 + 32 < K ? k0 + 32 : k0;  // last step re-reads (harmless)
+        f[0][b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K);
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            nb[b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K + kn);
-#pragma unroll
-        for (int a = 0; a < kPRowTiles; ++a) {
-            const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(xrow + 16 * a * kPPitch + k0);
+    for (int st = 0; st < kSteps; ++st) {
+        if (st + 1 < kSteps)
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                acc[a][b] = mfma16(fa, fb[b], acc[a][b]);
-        }
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-            fb[b] = nb[b];
+                f[st + 1][b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K + 32 * (st + 1));
+        tile_step(xrow, 32 * st, f[st], acc);
+        __builtin_amdgcn_sched_barrier(0);  // keep each step's loads in its step: no hoisting past the register budget
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_propose(const float *__restrict__ from, const float *__restrict__ to,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_propose(const float *__restrict__ from, const float *__restrict__ to,
                                                      int64_t n, const float *__restrict__ bounds,
                                                      const __bf16 *__restrict__ Wb, const float *__restrict__ P,
                                                      int nb, uint8_t *__restrict__ bucket) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    __bf16 *X0 = reinterpret_cast<__bf16 *>(lds_raw);
-    __bf16 *X1 = X0 + kPRows * kPPitch;
-    float *best_v = reinterpret_cast<float *>(X1 + kPRows * kPPitch);  // [4][kPRows]
+    __bf16 *X = reinterpret_cast<__bf16 *>(lds_raw);  // activations, overwritten layer by layer
+    float *best_v = reinterpret_cast<float *>(X + kPRows * kPPitch);  // [4][kPRows]
     int *best_i = reinterpret_cast<int *>(best_v + 4 * kPRows);        // [4][kPRows]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float *bias = P + kMlpWeights;
@@ -341,11 +354,11 @@ __global__ __launch_bounds__(256) void k_mlp_propose(const float *__restrict__ f
 #pragma unroll 1
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t r0 = tile * kPRows;
-        // features -> X0 (pitch kPPitch)
+        // features -> X (pitch kPPitch)
 #pragma unroll 1
         for (int q = tid; q < kPRows * 7; q += 256) {
             const int r = q / 7, part = q % 7;
-            __bf16 *row = X0 + r * kPPitch;
+            __bf16 *row = X + r * kPPitch;
             if (part == 6) {
                 for (int j = kMlpFeat; j < kMlpIn; ++j)
                     row[j] = (__bf16)0.0f;
@@ -356,15 +369,23 @@ __global__ __launch_bounds__(256) void k_mlp_propose(const float *__restrict__ f
             coord_features(x, part, row);
         }
         __syncthreads();
+        // the four layers through one call site, so the accumulators keep one
+        // register set; a layer's outputs go over its inputs in X once every
+        // wave has read them
         f32x4 acc[kPRowTiles][4];
 #pragma unroll 1
-        for (int l = 0; l < 3; ++l) {
-            const __bf16 *in = (l & 1) ? X1 : X0;
-            __bf16 *out = (l & 1) ? X0 : X1;
+        for (int l = 0; l < 4; ++l) {
+            const __bf16 *in = X;
+            __bf16 *out = X;
             const int64_t woff = l == 0 ? 0 : (int64_t)kMlpOut * kMlpIn + (int64_t)(l - 1) * kMlpHidden * kMlpHidden;
-            layer_tile(in, l == 0 ? kMlpIn : kMlpHidden, Wb + woff, wave, lane, acc);
+            if (l == 0)
+                layer_tile<kMlpIn>(in, Wb + woff, wave, lane, acc);
+            else
+                layer_tile<kMlpHidden>(in, Wb + woff, wave, lane, acc);
+            if (l == 3)
+                break;
             const float *bl = bias + l * kMlpHidden;
-            __syncthreads();  // every wave has read `in`; layer 2 writes over X0
+            __syncthreads();  // every wave has read `in` before it is overwritten
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int col = 64 * wave + 16 * b + (lane & 15);
@@ -379,8 +400,6 @@ __global__ __launch_bounds__(256) void k_mlp_propose(const float *__restrict__ f
             }
             __syncthreads();
         }
-        // the third hidden layer wrote X1
-        layer_tile(X1, kMlpHidden, Wb + (int64_t)kMlpOut * kMlpIn + 2LL * kMlpHidden * kMlpHidden, wave, lane, acc);
         const float *b4 = bias + 3 * kMlpHidden;
         float b4v[4];
 #pragma unroll
@@ -435,7 +454,7 @@ __global__ __launch_bounds__(256) void k_mlp_propose(const float *__restrict__ f
     }
 }
 
-constexpr size_t kProposeLds = 2 * (size_t)kPRows * kPPitch * sizeof(__bf16) + 8 * (size_t)kPRows * 4;
+constexpr size_t kProposeLds = (size_t)kPRows * kPPitch * sizeof(__bf16) + 8 * (size_t)kPRows * 4;
 
 // ------------------------------------------------ frontier and labels
 // Left-to-right frontier of the tree at depth 8: internal nodes at depth 8
