@@ -348,6 +348,10 @@ def main():
             learned = {
                 "train_segments": args.train_rays, "labelled": n_lab, "epochs": args.train_epochs,
                 "train_s": round(t_tr, 2), "epoch_loss": [round(x, 4) for x in loss.tolist()],
+                # GEMM work per labelled segment and epoch: forward 2 x 253,952, weight
+                # gradients the same, input gradients 2 x 3 x 65,536 FLOP; over train_s,
+                # which includes labelling the segments
+                "train_tflops": round(args.train_epochs * n_lab * (4 * 253952 + 6 * 65536) / t_tr / 1e12, 2),
                 "proposal_miss_rate": round(late / max(n_hit, 1), 4),
                 "intersect_mrays_s_plain_order": round(n / (ms_plain * 1e-3) / 1e6, 1),
                 "intersect_mrays_s_plain_order_binary_nodes": round(n / (ms_plain2 * 1e-3) / 1e6, 1),

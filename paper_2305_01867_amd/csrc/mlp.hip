@@ -111,35 +111,92 @@ struct GemmArgs {
     float *Cf;
     __bf16 *Cb;
     int64_t c_m, c_n;
+    // split over K: workgroup z covers k in [z k_chunk, (z + 1) k_chunk) and
+    // writes its raw sums to partial[z][M][N]; k_gemm_reduce adds them up
+    float *partial;
+    int k_chunk;
+    // operand layouts, set by gemm(): 0 element by element, 1 contiguous in
+    // k (16-byte loads along k), 2 contiguous in m / n (16-byte loads along
+    // m / n, transposed into LDS)
+    int a_mode, b_mode;
 };
 
 constexpr int kGT = 64, kGK = 32, kGPad = 8;
 
+// One operand's 64 x 32 tile of this k step: each lane fetches 8 elements
+// (one 16-byte load in the vector layouts) into registers; put_tile stores
+// them into LDS as S[m or n][k].  Out-of-range elements are zero.
+__device__ __forceinline__ bf16x8 get_tile(const __bf16 *__restrict__ P, int64_t s_mn, int64_t s_k, int mode,
+                                           int mn0, int MN, int k0, int kend, int tid) {
+    bf16x8 v;
+    if (mode == 1) {
+        const int mn = tid >> 2, kk = (tid & 3) * 8;
+        if (mn0 + mn < MN && k0 + kk < kend)  // kend and kk are multiples of 8
+            v = *reinterpret_cast<const bf16x8 *>(P + (int64_t)(mn0 + mn) * s_mn + (k0 + kk));
+        else
+            v = bf16x8{};
+    } else if (mode == 2) {
+        const int kk = tid >> 3, mn = (tid & 7) * 8;
+        if (k0 + kk < kend && mn0 + mn < MN)  // MN and mn are multiples of 8
+            v = *reinterpret_cast<const bf16x8 *>(P + (int64_t)(k0 + kk) * s_k + (mn0 + mn));
+        else
+            v = bf16x8{};
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int idx = tid + 256 * r;
+            const int mn = idx / kGK, kk = idx % kGK;
+            const int gm = mn0 + mn, gk = k0 + kk;
+            v[r] = (gm < MN && gk < kend) ? P[gm * s_mn + gk * s_k] : (__bf16)0.0f;
+        }
+    }
+    return v;
+}
+
+__device__ __forceinline__ void put_tile(__bf16 (*S)[kGK + kGPad], int mode, bf16x8 v, int tid) {
+    if (mode == 1) {
+        *reinterpret_cast<bf16x8 *>(&S[tid >> 2][(tid & 3) * 8]) = v;
+    } else if (mode == 2) {
+        const int kk = tid >> 3, mn = (tid & 7) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            S[mn + i][kk] = v[i];
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int idx = tid + 256 * r;
+            S[idx / kGK][idx % kGK] = v[r];
+        }
+    }
+}
+
+// C = A B on MFMA: a 64 x 64 tile per workgroup, four waves of 32 x 32.  The
+// next k step's operand tiles load into registers while the current step
+// multiplies out of LDS; the sum over k runs in k order.
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __shared__ __bf16 As[kGT][kGK + kGPad];
     __shared__ __bf16 Bs[kGT][kGK + kGPad];  // stored [n][k]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int kb = g.partial ? blockIdx.z * g.k_chunk : 0;
+    const int ke = g.partial ? min(g.K, kb + g.k_chunk) : g.K;
     f32x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const bool a_kfast = g.a_k == 1, b_kfast = g.b_k == 1;
-    for (int k0 = 0; k0 < g.K; k0 += kGK) {
-        for (int r = 0; r < (kGT * kGK) / 256; ++r) {
-            const int idx = tid + 256 * r;
-            int mm, kk;
-            if (a_kfast) { mm = idx / kGK; kk = idx % kGK; } else { mm = idx % kGT; kk = idx / kGT; }
-            const int gm = m0 + mm, gk = k0 + kk;
-            As[mm][kk] = (gm < g.M && gk < g.K) ? g.A[gm * g.a_m + gk * g.a_k] : (__bf16)0.0f;
-            int nn;
-            if (b_kfast) { nn = idx / kGK; kk = idx % kGK; } else { nn = idx % kGT; kk = idx / kGT; }
-            const int gn = n0 + nn, gk2 = k0 + kk;
-            Bs[nn][kk] = (gn < g.N && gk2 < g.K) ? g.B[gk2 * g.b_k + gn * g.b_n] : (__bf16)0.0f;
-        }
+    bf16x8 va = get_tile(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, kb, ke, tid);
+    bf16x8 vb = get_tile(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, kb, ke, tid);
+    const int kq = 8 * (lane >> 4);
+    for (int k0 = kb; k0 < ke; k0 += kGK) {
+        __syncthreads();  // the previous step's reads of As / Bs are done
+        put_tile(As, g.a_mode, va, tid);
+        put_tile(Bs, g.b_mode, vb, tid);
         __syncthreads();
-        const int kq = 8 * (lane >> 4);
+        if (k0 + kGK < ke) {
+            va = get_tile(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, k0 + kGK, ke, tid);
+            vb = get_tile(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, k0 + kGK, ke, tid);
+        }
         for (int a = 0; a < 2; ++a) {
             const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * a + (lane & 15)][kq]);
             for (int b = 0; b < 2; ++b) {
@@ -147,7 +204,6 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                 acc[a][b] = mfma16(fa, fb, acc[a][b]);
             }
         }
-        __syncthreads();
     }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
@@ -157,6 +213,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                 if (m >= g.M || n >= g.N)
                     continue;
                 float v = acc[a][b][i];
+                if (g.partial) {
+                    g.partial[((int64_t)blockIdx.z * g.M + m) * g.N + n] = v;
+                    continue;
+                }
                 if (g.bias)
                     v += g.bias[n];
                 if (g.relu)
@@ -168,6 +228,20 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                 if (g.Cb)
                     g.Cb[m * g.c_m + n * g.c_n] = (__bf16)v;
             }
+}
+
+// Cf = the split-K partial sums added in chunk order (deterministic).
+__global__ __launch_bounds__(256) void k_gemm_reduce(const float *__restrict__ partial, int chunks, int M, int N,
+                                                     float *__restrict__ Cf, int64_t c_m, int64_t c_n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t mn = (int64_t)M * N;
+    if (i >= mn)
+        return;
+    float s = 0.0f;
+    for (int z = 0; z < chunks; ++z)
+        s += partial[z * mn + i];
+    const int m = (int)(i / N), n = (int)(i % N);
+    Cf[m * c_m + n * c_n] = s;
 }
 
 // ------------------------------------------------- softmax cross-entropy
@@ -550,9 +624,36 @@ __global__ void k_labels(const int32_t *__restrict__ tri_id, int64_t n, const in
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-void gemm(const GemmArgs &g, hipStream_t s) {
-    dim3 grid(cdiv(g.N, kGT), cdiv(g.M, kGT));
+// Operand layout for k_gemm's loads: 16-byte loads need 8 contiguous
+// elements at 16-byte aligned addresses.
+int operand_mode(const __bf16 *P, int64_t s_mn, int64_t s_k, int MN, int K) {
+    const bool al = (reinterpret_cast<uintptr_t>(P) & 15) == 0;
+    if (al && s_k == 1 && s_mn % 8 == 0 && K % 8 == 0)
+        return 1;
+    if (al && s_mn == 1 && s_k % 8 == 0 && MN % 8 == 0)
+        return 2;
+    return 0;
+}
+
+constexpr int kSplitMax = 16;  // split-K chunks of a long contraction (the weight gradients)
+
+// split: a buffer of kSplitMax * M * N floats for a split over K, or NULL
+void gemm(GemmArgs g, hipStream_t s, float *split = nullptr) {
+    g.a_mode = operand_mode(g.A, g.a_m, g.a_k, g.M, g.K);
+    g.b_mode = operand_mode(g.B, g.b_n, g.b_k, g.N, g.K);
+    int chunks = 1;
+    if (split && g.K > 2 * 256 && !g.bias && !g.relu && !g.mask && !g.Cb && g.Cf) {
+        chunks = cdiv(g.K, 256) < kSplitMax ? cdiv(g.K, 256) : kSplitMax;
+        g.k_chunk = cdiv(cdiv(g.K, chunks), kGK) * kGK;
+        chunks = cdiv(g.K, g.k_chunk);
+        g.partial = split;
+    }
+    dim3 grid(cdiv(g.N, kGT), cdiv(g.M, kGT), chunks);
     k_gemm<<<grid, 256, 0, s>>>(g);
+    if (g.partial) {
+        const int64_t mn = (int64_t)g.M * g.N;
+        k_gemm_reduce<<<cdiv(mn, 256), 256, 0, s>>>(g.partial, chunks, g.M, g.N, g.Cf, g.c_m, g.c_n);
+    }
 }
 
 }  // namespace
@@ -610,6 +711,7 @@ hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from
     __bf16 *dZa = H3 + (int64_t)rows * kMlpHidden;
     __bf16 *dZb = dZa + (int64_t)rows * kMlpOut;
     float *Z4 = reinterpret_cast<float *>(dZb + (int64_t)rows * kMlpOut);
+    float *split = Z4 + (int64_t)rows * kMlpOut;  // kSplitMax x 256 x 256 partial sums of a weight gradient
     const __bf16 *W1 = pr.Wb, *W2 = W1 + kMlpOut * kMlpIn, *W3 = W2 + kMlpHidden * kMlpHidden,
                  *W4 = W3 + kMlpHidden * kMlpHidden;
     const float *bias = pr.P + kMlpWeights;
@@ -647,7 +749,7 @@ hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from
         g.B = ins[l]; g.b_k = K; g.b_n = 1;
         g.M = kMlpOut; g.N = K; g.K = rows;
         g.Cf = gWs[l]; g.c_m = K; g.c_n = 1;
-        gemm(g, s);
+        gemm(g, s, split);
         const int nblk = cdiv(rows, kColRows);
         k_col_partial<<<nblk, kMlpOut, 0, s>>>(dZ, rows, Z4);  // the logits in Z4 are spent by now
         k_col_final<<<1, kMlpOut, 0, s>>>(Z4, nblk, gb + l * kMlpHidden);
@@ -691,7 +793,8 @@ hipError_t proposal_set_params(Proposal &pr, hipStream_t s) {
 }
 
 size_t proposal_batch_scratch(int rows) {
-    return (size_t)rows * (kMlpIn + 3 * kMlpHidden + 2 * kMlpOut) * 2 + (size_t)rows * kMlpOut * 4 + 256;
+    return (size_t)rows * (kMlpIn + 3 * kMlpHidden + 2 * kMlpOut) * 2 + (size_t)rows * kMlpOut * 4 +
+           (size_t)kSplitMax * kMlpOut * kMlpHidden * 4 + 256;
 }
 
 hipError_t proposal_features(const MeshDev &m, const float *from, const float *to, int64_t n, __bf16 *X,

@@ -61,11 +61,14 @@ def _random_params(seed, scale=1.0):
     return P
 
 
-def test_gradient_matches_reference(tiny):
+@pytest.mark.parametrize("rows", [512, 2900])
+def test_gradient_matches_reference(tiny, rows):
+    """512 rows: each weight gradient in one pass over the rows; 2900 rows:
+    split over 12 row chunks (the last one ragged) and summed in order."""
     V, F, O, E, mesh = tiny
     P = _random_params(3)
     rsi.rsi_proposal_params(mesh, dev(P))
-    rows = 512
+    assert O.shape[0] >= rows
     nb = len(host(rsi.rsi_proposal_frontier(mesh)[0]))
     labels = np.random.default_rng(4).integers(0, nb, rows).astype(np.int32)
     dO, dE = dev(O[:rows]), dev(E[:rows])
@@ -91,7 +94,7 @@ def test_fused_inference_equals_forward_argmax(tiny):
     V, F, O, E, mesh = tiny
     rsi.rsi_proposal_params(mesh, dev(_random_params(5)))
     nb = len(host(rsi.rsi_proposal_frontier(mesh)[0]))
-    rows = 4000  # not a multiple of the 64-row tile
+    rows = 4000  # not a multiple of the row tile
     dO, dE = dev(O[:rows]), dev(E[:rows])
     _, logits, _ = rsi.rsi_proposal_gradient(mesh, dO, dE, dev(np.zeros(rows, np.int32)))
     lg = host(logits)[:, :nb]
