@@ -1017,7 +1017,8 @@ rsi_status rsi_proposal_train(rsi_mesh mesh, const float *rays_from, const float
     // labels from the exact first-hit pass
     void *tmp = nullptr;
     const size_t scratch = rsi::proposal_batch_scratch(batch);
-    const size_t tmp_bytes = round_up(12 * (size_t)n_rays + 64) + scratch + round_up(4 * (size_t)epochs + 4);
+    const size_t lab_bytes = round_up(rsi::proposal_label_scratch(n_rays));
+    const size_t tmp_bytes = round_up(12 * (size_t)n_rays + 64) + scratch + round_up(4 * (size_t)epochs + 4) + lab_bytes;
     hipError_t e = hipMallocAsync(&tmp, tmp_bytes, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -1030,6 +1031,7 @@ rsi_status rsi_proposal_train(rsi_mesh mesh, const float *rays_from, const float
     uint32_t *count = reinterpret_cast<uint32_t *>(lab + n_rays);
     char *ws = t + round_up(12 * (size_t)n_rays + 64);
     float *loss_sink = reinterpret_cast<float *>(ws + scratch);
+    int32_t *lab_blk = reinterpret_cast<int32_t *>(ws + scratch + round_up(4 * (size_t)epochs + 4));
     auto bail = [&](rsi_status code) {
         (void)hipFreeAsync(tmp, s);
         return code;
@@ -1041,7 +1043,7 @@ rsi_status rsi_proposal_train(rsi_mesh mesh, const float *rays_from, const float
     uint32_t n_lab = 0;
     e = hipMemsetAsync(count, 0, 4, s);
     if (e == hipSuccess && n_rays > 0)
-        e = rsi::proposal_labels(mesh->dev, pr, tri, n_rays, seg, lab, count, s);
+        e = rsi::proposal_labels(mesh->dev, pr, tri, n_rays, seg, lab, count, lab_blk, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&n_lab, count, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)

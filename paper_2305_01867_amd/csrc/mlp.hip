@@ -246,11 +246,11 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const float *__restrict__ p
 
 // ------------------------------------------------- softmax cross-entropy
 // One row per wave: p = softmax(z over the first nb logits); the gradient of
-// the mean loss is (p - onehot(y)) / rows (0 for masked columns).  Adds the
-// row's loss times loss_scale to *loss.
+// the mean loss is (p - onehot(y)) / rows (0 for masked columns).  Writes the
+// row's loss times loss_scale to row_loss[row] (k_loss_sum adds them up).
 __global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z, const int32_t *__restrict__ y,
                                                     int rows, int nb, float inv_rows, float loss_scale,
-                                                    __bf16 *__restrict__ dZ, float *__restrict__ loss) {
+                                                    __bf16 *__restrict__ dZ, float *__restrict__ row_loss) {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= rows)
@@ -278,8 +278,28 @@ __global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z,
             g = (expf(v[j] - mx) / s - (c == label ? 1.0f : 0.0f)) * inv_rows;
         dZ[(int64_t)row * kMlpOut + c] = (__bf16)g;
     }
-    if (lane == 0 && label >= 0 && label < nb)
-        atomicAdd(loss, (logf(s) + mx - z[label]) * loss_scale);
+    if (lane == 0)
+        row_loss[row] = label >= 0 && label < nb ? (logf(s) + mx - z[label]) * loss_scale : 0.0f;
+}
+
+// *loss += the sum of row_loss[0 .. rows) in a fixed order (one workgroup:
+// strided sums per lane, then a fixed tree), so the reported loss does not
+// depend on scheduling.
+__global__ __launch_bounds__(256) void k_loss_sum(const float *__restrict__ row_loss, int rows,
+                                                  float *__restrict__ loss) {
+    __shared__ float part[256];
+    float v = 0.0f;
+    for (int r = threadIdx.x; r < rows; r += 256)
+        v += row_loss[r];
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *loss += part[0];
 }
 
 // db[n] = sum over rows of dZ[row][n] (fp32 from bf16), in two fixed-order
@@ -606,20 +626,87 @@ __global__ void k_rank(const int32_t *__restrict__ ids, int nt, int32_t *__restr
         rank[ids[k]] = k;
 }
 
-// For every segment with a first hit: its bucket (the frontier subtree that
-// holds the hit leaf), appended with the segment index to the training list.
-__global__ void k_labels(const int32_t *__restrict__ tri_id, int64_t n, const int32_t *__restrict__ rank,
-                         const uint8_t *__restrict__ leaf_bucket, int32_t *__restrict__ seg_out,
-                         int32_t *__restrict__ label_out, uint32_t *__restrict__ count) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    const int t = tri_id[i];
-    if (t < 0)
-        return;
-    const uint32_t slot = atomicAdd(count, 1u);
-    seg_out[slot] = (int32_t)i;
-    label_out[slot] = leaf_bucket[rank[t]];
+// The training list: for every segment with a first hit, in segment order,
+// the segment and its bucket (the frontier subtree that holds the hit leaf).
+// A stable compaction -- per-workgroup counts, one scan of them, then each
+// workgroup writes at its offset in order -- so the list, and the training
+// that walks it batch by batch, do not depend on scheduling.
+constexpr int kLabSeg = 16;                   // segments per lane
+constexpr int kLabPerBlock = 256 * kLabSeg;   // per workgroup of 256
+
+// Exclusive prefix sum of v over a 256-lane workgroup; total = the sum.
+__device__ __forceinline__ int block_excl_scan(int v, int &total) {
+    __shared__ int wsum[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(incl, d, 64);
+        incl += lane >= d ? u : 0;
+    }
+    if (lane == 63)
+        wsum[w] = incl;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        off += k < w ? wsum[k] : 0;
+        total += wsum[k];
+    }
+    __syncthreads();  // wsum is reused by the next call
+    return off + incl - v;
+}
+
+__device__ __forceinline__ int lane_hits(const int32_t *__restrict__ tri_id, int64_t n, int64_t base) {
+    int c = 0;
+    for (int j = 0; j < kLabSeg; ++j)
+        c += base + j < n && tri_id[base + j] >= 0;
+    return c;
+}
+
+__global__ __launch_bounds__(256) void k_label_count(const int32_t *__restrict__ tri_id, int64_t n,
+                                                     int32_t *__restrict__ blk) {
+    const int64_t base = (int64_t)blockIdx.x * kLabPerBlock + (int64_t)threadIdx.x * kLabSeg;
+    int total;
+    block_excl_scan(lane_hits(tri_id, n, base), total);
+    if (threadIdx.x == 0)
+        blk[blockIdx.x] = total;
+}
+
+// blk[b] = the list position of workgroup b's first entry; *count = the total.
+__global__ __launch_bounds__(256) void k_label_scan(int32_t *__restrict__ blk, int nblk, uint32_t *__restrict__ count) {
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 256) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < nblk ? blk[b] : 0;
+        int total;
+        const int ex = block_excl_scan(v, total);
+        if (b < nblk)
+            blk[b] = (int32_t)(carry + ex);
+        carry += (uint32_t)total;
+    }
+    if (threadIdx.x == 0)
+        *count = carry;
+}
+
+__global__ __launch_bounds__(256) void k_labels(const int32_t *__restrict__ tri_id, int64_t n,
+                                                const int32_t *__restrict__ rank,
+                                                const uint8_t *__restrict__ leaf_bucket,
+                                                const int32_t *__restrict__ blk, int32_t *__restrict__ seg_out,
+                                                int32_t *__restrict__ label_out) {
+    const int64_t base = (int64_t)blockIdx.x * kLabPerBlock + (int64_t)threadIdx.x * kLabSeg;
+    int total;
+    int pos = blk[blockIdx.x] + block_excl_scan(lane_hits(tri_id, n, base), total);
+    for (int j = 0; j < kLabSeg; ++j) {
+        const int64_t i = base + j;
+        const int t = i < n ? tri_id[i] : -1;
+        if (t >= 0) {
+            seg_out[pos] = (int32_t)i;
+            label_out[pos] = leaf_bucket[rank[t]];
+            ++pos;
+        }
+    }
 }
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -673,9 +760,16 @@ hipError_t proposal_init(Proposal &pr, uint64_t seed, hipStream_t s) {
     return hipGetLastError();
 }
 
+size_t proposal_label_scratch(int64_t n) { return 4 * (size_t)(n / kLabPerBlock + 1); }
+
 hipError_t proposal_labels(const MeshDev &m, Proposal &pr, const int32_t *tri_id, int64_t n, int32_t *seg,
-                           int32_t *label, uint32_t *count, hipStream_t s) {
-    k_labels<<<cdiv(n, 256), 256, 0, s>>>(tri_id, n, pr.rank, pr.leaf_bucket, seg, label, count);
+                           int32_t *label, uint32_t *count, int32_t *blk, hipStream_t s) {
+    const int nblk = (int)((n + kLabPerBlock - 1) / kLabPerBlock);
+    if (nblk == 0)
+        return hipSuccess;
+    k_label_count<<<nblk, 256, 0, s>>>(tri_id, n, blk);
+    k_label_scan<<<1, 256, 0, s>>>(blk, nblk, count);
+    k_labels<<<nblk, 256, 0, s>>>(tri_id, n, pr.rank, pr.leaf_bucket, blk, seg, label);
     return hipGetLastError();
 }
 
@@ -737,7 +831,8 @@ hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from
         gemm(g, s);
     }
     k_softmax_ce<<<cdiv(rows, 4), 256, 0, s>>>(logits_out ? logits_out : Z4, lab + r0, rows, nb, 1.0f / rows,
-                                              loss_scale > 0.0f ? loss_scale : 1.0f / rows, dZa, loss);
+                                              loss_scale > 0.0f ? loss_scale : 1.0f / rows, dZa, split);
+    k_loss_sum<<<1, 256, 0, s>>>(split, rows, loss);  // before the weight gradients reuse `split`
     // backward
     __bf16 *dZ = dZa, *dZn = dZb;
     float *gWs[4] = {gW1, gW2, gW3, gW4};

@@ -213,8 +213,11 @@ hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
 // Learned proposal (mlp.hip).
 hipError_t proposal_frontier(const MeshDev &m, Proposal &pr, hipStream_t s);
 hipError_t proposal_init(Proposal &pr, uint64_t seed, hipStream_t s);
+// Training list of the segments with a first hit, in segment order; blk holds
+// proposal_label_scratch(n) bytes.
+size_t proposal_label_scratch(int64_t n);
 hipError_t proposal_labels(const MeshDev &m, Proposal &pr, const int32_t *tri_id, int64_t n, int32_t *seg,
-                           int32_t *label, uint32_t *count, hipStream_t s);
+                           int32_t *label, uint32_t *count, int32_t *blk, hipStream_t s);
 hipError_t proposal_predict(const MeshDev &m, const Proposal &pr, const float *from, const float *to, int64_t n,
                             int nb, uint8_t *bucket, hipStream_t s);
 hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from, const float *to,

@@ -165,3 +165,21 @@ def test_proposal_on_a_restructured_tree():
             got = host(rsi.rsi_intersect(mesh, dev(Ot), dev(Et), mode=mode, precision="certified",
                                          proposal=True)[key])
             assert np.array_equal(got, want), mode
+
+
+def test_training_is_deterministic():
+    """The training list is compacted in segment order, the weight gradients
+    and the loss are summed in fixed orders: two trainings from the same seed
+    give bit-identical parameters and losses."""
+    V, F = workloads.heightfield(64, 12)
+    O, E = workloads.rays_in_box(40000, 35, V.min(0), V.max(0))
+    runs = []
+    with rsi.rsi_build(dev(V), dev(F)) as mesh:
+        for _ in range(2):
+            loss, n_lab = rsi.rsi_proposal_train(mesh, dev(O), dev(E), epochs=2, batch=2048, lr=2e-3, seed=9,
+                                                 reinit=True)
+            runs.append((loss.numpy().copy(), n_lab, host(rsi.rsi_proposal_params(mesh)).copy()))
+    say(f"  labelled {runs[0][1]}, epoch loss {runs[0][0].tolist()}")
+    assert runs[0][1] == runs[1][1] > 2048
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][2].view(np.uint32), runs[1][2].view(np.uint32))
