@@ -16,14 +16,23 @@ from gpu_helpers import dev, host, say
 pytestmark = pytest.mark.gpu
 
 
-def test_precision_form_exact():
+@pytest.mark.parametrize("algorithm", ["radix_tree", "restructured"])
+def test_precision_form_exact(algorithm):
     V, F, O, E, kind = workloads.precision_config()
-    say(f"[precision form] {F.shape[0]} triangles, {O.shape[0]} segments, groups {np.bincount(kind).tolist()}")
+    say(f"[precision form, {algorithm}] {F.shape[0]} triangles, {O.shape[0]} segments, "
+        f"groups {np.bincount(kind).tolist()}")
     rng = np.random.default_rng(5)
     sample = np.concatenate([rng.choice(np.nonzero(kind == k)[0], c, replace=False)
                              for k, c in ((0, 600), (1, 1500), (2, 900))])
-    with rsi.rsi_build(dev(V), dev(F)) as mesh:
+    with rsi.rsi_build(dev(V), dev(F), algorithm=algorithm) as mesh:
+        assert rsi.rsi_mesh_info_get(mesh)["node_width"] == 4
         dO, dE = dev(O), dev(E)
+        cnt = rsi.rsi_intersect(mesh, dO, dE, mode="intercept_count", precision="certified")
+        got = host(cnt["count"])[sample]
+        del cnt
+        want = oracle.intercept_count(V, F, O[sample], E[sample])
+        say(f"  intercept_count: {sample.size} sampled segments, {int(want.sum())} distinct hits")
+        assert np.array_equal(got, want)
         for mode in ("boolean", "first_hit", "barycentric"):
             key = "hit" if mode == "boolean" else "tri_id"
             cert = rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision="certified")
