@@ -129,7 +129,7 @@ typedef struct rsi_intersect_opts {
                              512 or 1024 (binary nodes: at most 256, larger values
                              run as 256; a workgroup whose LDS stacks would not fit
                              runs with half as many threads until they do); 0 = the
-                             library default (512 for 4-wide nodes, 256 for binary
+                             library default (1024 for 4-wide nodes, 256 for binary
                              ones).  With 4-wide nodes a
                              larger workgroup keeps more of the tree's top in its
                              LDS. */
