@@ -34,7 +34,10 @@ constexpr float kBoundK = 12.0f * 0x1p-24f;  // >= 8 u32 (binary32) + 8 u64 (bin
 constexpr float kBoundTiny = 0x1p-140f;      // absorbs underflow in the products
 constexpr int kMiss = 0, kHit = 1, kUnsure = 2;
 enum { MODE_BOOL = 0, MODE_FIRST = 1, MODE_BARY = 2, MODE_COUNT = 3 };
-constexpr int kCountSlots = 12;  // distinct t a lane keeps in registers in count mode
+// distinct t a lane keeps in registers in count mode: binary32 values (plain),
+// or intervals of two floats each (certified)
+template <bool CERT>
+constexpr int kCountSlots = CERT ? 12 : 12;
 
 struct Ray {
     float3 o, d;   // start point, direction E - O (rounded)
@@ -420,7 +423,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     // intervals that each hold one hit's binary64 t (certified): disjoint
     // intervals hold distinct values, so only overlapping ones need the exact
     // second pass
-    float tk[kCountSlots], tk_hi[kCountSlots];
+    float tk[kCountSlots<CERT>], tk_hi[kCountSlots<CERT>];
     int nk = 0;
     bool list_full = false;
 
@@ -652,15 +655,15 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                             const float t = m.T / m.det;
                             bool dup = false;
 #pragma unroll
-                            for (int k = 0; k < kCountSlots; ++k)
+                            for (int k = 0; k < kCountSlots<CERT>; ++k)
                                 dup = dup || (k < nk && tk[k] == t);
                             if (!dup) {
-                                if (nk == kCountSlots) {
+                                if (nk == kCountSlots<CERT>) {
                                     list_full = true;  // finished by the second pass
                                     ref = kDone;
                                 } else {
 #pragma unroll
-                                    for (int k = 0; k < kCountSlots; ++k)
+                                    for (int k = 0; k < kCountSlots<CERT>; ++k)
                                         if (k == nk)
                                             tk[k] = t;
                                     ++nk;
@@ -683,17 +686,17 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                         if (take) {
                             bool meet = false;
 #pragma unroll
-                            for (int k = 0; k < kCountSlots; ++k)
+                            for (int k = 0; k < kCountSlots<CERT>; ++k)
                                 meet = meet || (k < nk && !(hi < tk[k] || lo > tk_hi[k]));
                             if (meet) {
                                 flagged = true;  // equal or nearly equal t: counted exactly by the second pass
                                 ref = kDone;
-                            } else if (nk == kCountSlots) {
+                            } else if (nk == kCountSlots<CERT>) {
                                 list_full = true;
                                 ref = kDone;
                             } else {
 #pragma unroll
-                                for (int k = 0; k < kCountSlots; ++k)
+                                for (int k = 0; k < kCountSlots<CERT>; ++k)
                                     if (k == nk) {
                                         tk[k] = lo;
                                         tk_hi[k] = hi;
@@ -857,13 +860,19 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, kMaxBlock<WIDE>), amdgp
 //     visited node.
 //   long queue: one lane per segment with a private deep stack (throughput).
 constexpr int kFinishThreads = 64;
-constexpr int kCountList = 2048;  // hits a wave collects per segment in count mode
+constexpr int kCountList = 256;  // hits a wave collects per segment in count mode (more: rounds)
 constexpr int kWaveFinishMax = 8192;                      // queue length up to which a wave takes a segment
 constexpr int kWaveStack = kDeepStack * kFinishThreads;  // shared entries (same LDS as the private stacks)
-// Steps that pop k entries push at most 2k; popping at most (kWaveSoft - size)
-// keeps the stack at or below kWaveSoft, and above it single pops (a plain
-// depth-first walk) add at most one entry per tree level.
-constexpr int kWaveSoft = kWaveStack - kDeepStack;
+// Steps that pop k entries push at most 2k; popping at most (soft - size),
+// soft = capacity - kDeepStack, keeps the stack at or below soft, and above it
+// single pops (a plain depth-first walk) add at most one entry per tree level.
+// Count mode always takes the wave shape, so its blocks need only the shared
+// stack (a soft limit of 1024 entries plus the depth-first headroom) and a
+// short hit list: about 7 KB of LDS instead of 48, so eight times as many
+// segments are in flight (its queue holds every segment with more distinct
+// hits than the first pass keeps, ~14k of 1e7 at the paper's scale).
+template <int MODE>
+constexpr int kWaveCap = MODE == MODE_COUNT ? 1024 + kDeepStack : kWaveStack;
 
 template <int MODE, bool CERT>
 struct Finish {
@@ -1038,7 +1047,7 @@ __device__ void wave_search(const TravParams &p, Finish<MODE, CERT> &f, bool ok,
         __syncthreads();
         const int64_t max_steps = 2 * p.nt + 8;  // every step pops at least one of < 2 nt subtrees
         for (int64_t step = 0; step < max_steps && size > 0; ++step) {
-            const int room = kWaveSoft - size;
+            const int room = (kWaveCap<MODE> - kDeepStack) - size;
             int k = room < 1 ? 1 : (room < 64 ? room : 64);
             k = k < size ? k : size;
             const int ref = lane < k ? stk[size - 1 - lane] : kDone;
@@ -1064,12 +1073,12 @@ __device__ void wave_search(const TravParams &p, Finish<MODE, CERT> &f, bool ok,
             }
             const uint64_t m0 = __ballot(c0 != kDone), m1 = __ballot(c1 != kDone);
             const int o = size + __popcll(m0 & lt_mask) + __popcll(m1 & lt_mask);
-            if (c0 != kDone && o < kWaveStack)
+            if (c0 != kDone && o < kWaveCap<MODE>)
                 stk[o] = c0;
-            if (c1 != kDone && o + 1 < kWaveStack)
+            if (c1 != kDone && o + 1 < kWaveCap<MODE>)
                 stk[o + 1] = c1;
             size += __popcll(m0) + __popcll(m1);
-            size = size < kWaveStack ? size : kWaveStack;
+            size = size < kWaveCap<MODE> ? size : kWaveCap<MODE>;
             __syncthreads();
             if (MODE == MODE_BOOL) {
                 if (__ballot(f.done))
@@ -1210,7 +1219,7 @@ __device__ void finish_lane(const TravParams &p, int64_t i, int *stk) {
 
 template <int MODE, bool CERT>
 __global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
-    __shared__ int deep[kWaveStack];
+    __shared__ int deep[kWaveCap<MODE>];
     const uint32_t count = *p.queue_len;
     if (MODE == MODE_COUNT || count <= (uint32_t)kWaveFinishMax) {
         for (uint32_t qi = blockIdx.x; qi < count; qi += gridDim.x)
@@ -1490,8 +1499,10 @@ hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t
         return e;
     dispatch_pass1<false>(p, a.mode, a.certified != 0, a.block, s);
     // enough blocks for one per segment of a short queue; a long queue is
-    // taken 64 segments per block
-    const int grid2 = (int)(a.n < 2048 ? a.n : 2048);
+    // taken 64 segments per block (count mode: a wave per segment, with
+    // small blocks that fit many per CU)
+    const int64_t cap2 = a.mode == MODE_COUNT ? 8192 : 2048;
+    const int grid2 = (int)(a.n < cap2 ? a.n : cap2);
     if (a.mode == MODE_BOOL)
         a.certified ? k_finish<MODE_BOOL, true><<<grid2, kFinishThreads, 0, s>>>(p) : k_finish<MODE_BOOL, false><<<grid2, kFinishThreads, 0, s>>>(p);
     else if (a.mode == MODE_FIRST)

@@ -55,11 +55,13 @@ def test_closed_form_scenes():
             assert hit.tolist() == [1, 1, 1, 0]
 
 
-def test_more_hits_than_the_wave_list():
-    """1100 stacked split layers: a vertical segment through the diagonals
-    meets 2200 triangles at 1100 points (more hits than the pass-2 list holds:
-    the round-by-round count); one inside the triangles meets 1100."""
-    k = 1100
+@pytest.mark.parametrize("k", [200, 1100])
+def test_more_hits_than_the_wave_list(k):
+    """k stacked split layers: a vertical segment through the diagonals meets
+    2k triangles at k points, one inside the triangles meets k.  The pass-2
+    list holds 256 hits: at k = 200 the diagonal one (400 hits) is counted
+    round by round and the other (200) from the list; at k = 1100 both take
+    rounds."""
     V, F = stacked(k)
     O = np.array([[0.5, 0.5, k + 0.5], [0.75, 0.25, k + 0.5]], np.float32)
     E = np.array([[0.5, 0.5, -0.5], [0.75, 0.25, -0.5]], np.float32)
