@@ -66,7 +66,7 @@ rsi_status check_device() {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(RSI_E_STATE, std::string("library built for gfx950, device is ") + prop.gcnArchName);
     // keep freed stream-ordered memory in the pool instead of returning it to
-    // the driver at every synchronisation
+    // the HIP runtime at every synchronisation
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
         uint64_t keep = UINT64_MAX;
