@@ -312,7 +312,8 @@ __global__ __launch_bounds__(256) void k_col_partial(const __bf16 *__restrict__ 
     const int n = threadIdx.x, b = blockIdx.x;
     const int r1 = min(rows, (b + 1) * kColRows);
     float s = 0.0f;
-    for (int r = b * kColRows; r < r1; ++r)
+#pragma unroll 16
+    for (int r = b * kColRows; r < r1; ++r)  // unrolled: the loads issue ahead of the in-order adds
         s += (float)dZ[(int64_t)r * kMlpOut + n];
     partial[(int64_t)b * kMlpOut + n] = s;
 }
@@ -321,6 +322,7 @@ __global__ __launch_bounds__(256) void k_col_final(const float *__restrict__ par
                                                    float *__restrict__ db) {
     const int n = threadIdx.x;
     float s = 0.0f;
+#pragma unroll 16
     for (int b = 0; b < nblk; ++b)
         s += partial[(int64_t)b * kMlpOut + n];
     db[n] = s;
@@ -782,12 +784,7 @@ hipError_t proposal_predict(const MeshDev &m, const Proposal &pr, const float *f
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t tiles = (n + kPRows - 1) / kPRows;
     const int grid = (int)(tiles < 2 * cus ? tiles : 2 * cus);
-    static bool lds_set = false;
-    if (!lds_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mlp_propose),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kProposeLds);
-        lds_set = true;
-    }
+    static_assert(kProposeLds <= 64 * 1024, "the fused inference kernel fits the default dynamic LDS");
     k_mlp_propose<<<grid, 256, kProposeLds, s>>>(from, to, n, m.bounds, pr.Wb, pr.P, nb, bucket);
     return hipGetLastError();
 }

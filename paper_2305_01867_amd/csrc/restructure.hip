@@ -589,14 +589,15 @@ hipError_t launch_restructure(MeshDev &m, int rounds, hipStream_t s) {
     int32_t *tiles = L.tiles;
     float *tile_cost = L.tile_cost;
     const size_t lds = sizeof(TileLds);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_restructure_tiles),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_restructure_top),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr_set = true;
-    }
+    // above the default 64 KB of dynamic LDS: set per call (cheap on the host,
+    // and right for whichever device is current; no shared flag between threads)
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_restructure_tiles),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_restructure_top),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
