@@ -383,67 +383,74 @@ __global__ __launch_bounds__(256) void k_init_params(float *__restrict__ P, __bf
 // each weight fragment fetched from L2 feeds 6 row tiles).  Activations stay
 // in LDS in one bf16 buffer that each layer overwrites once every wave has
 // read it (54 KB with the argmax scratch: two workgroups per CU, 246 VGPRs
-// and two waves per SIMD; 112 or 128 rows spill).  The next k step's weight
-// fragments are loaded while the current step multiplies (measured at the
-// paper's scale: 64 rows with two buffers and a one-step register copy 11.0
-// ms per 1e7 segments, this layout 8.1 ms).  The accumulation order over k is
+// and two waves per SIMD; 112 or 128 rows spill).  Weight fragments load two
+// k steps ahead of the multiplies that use them (measured at the paper's
+// scale: 64 rows with two buffers and a one-step register copy 11.0 ms per
+// 1e7 segments, this layout 7.6 ms; eight waves of 32 columns each, at four
+// waves per SIMD, are no faster).  The accumulation order over k is
 // the one k_gemm uses, so the logits are bit-identical to the training
 // forward pass.
 constexpr int kPRows = 96;
 constexpr int kPPitch = kMlpHidden + 8;
 constexpr int kPRowTiles = kPRows / 16;
+constexpr int kPWaves = 4;                          // waves per workgroup, each owning a column slice
+constexpr int kPThreads = 64 * kPWaves;
+constexpr int kPColTiles = kMlpHidden / 16 / kPWaves;  // 16-column tiles per wave
+constexpr int kPAhead = 2;                          // k steps the weight loads run ahead (1: 8.0 ms, 2: 7.6, 3: 7.6, 4: 7.7)
 
-__device__ __forceinline__ void tile_step(const __bf16 *__restrict__ xrow, int k0, const bf16x8 (&fb)[4],
-                                          f32x4 (&acc)[kPRowTiles][4]) {
+__device__ __forceinline__ void tile_step(const __bf16 *__restrict__ xrow, int k0, const bf16x8 (&fb)[kPColTiles],
+                                          f32x4 (&acc)[kPRowTiles][kPColTiles]) {
 #pragma unroll
     for (int a = 0; a < kPRowTiles; ++a) {
         const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(xrow + 16 * a * kPPitch + k0);
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < kPColTiles; ++b)
             acc[a][b] = mfma16(fa, fb[b], acc[a][b]);
     }
 }
 
 // K (224 or 256) is known at compile time and the k loop fully unrolled, so
-// every step's weight fragments are registers of their own: the next step's
-// loads are issued before the current step multiplies and stay in flight
-// across it, with no register copy that would wait for them.
+// every step's weight fragments are registers of their own: step st + kPAhead's
+// loads are issued before step st multiplies and stay in flight across it,
+// with no register copy that would wait for them.
 template <int K>
 __device__ __forceinline__ void layer_tile(const __bf16 *__restrict__ Xin, const __bf16 *__restrict__ Wt, int wave,
-                                           int lane, f32x4 (&acc)[kPRowTiles][4]) {
+                                           int lane, f32x4 (&acc)[kPRowTiles][kPColTiles]) {
     static_assert(K % 32 == 0, "K must be a multiple of 32");
     constexpr int kSteps = K / 32;
 #pragma unroll
     for (int a = 0; a < kPRowTiles; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < kPColTiles; ++b)
             acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const int kq = 8 * (lane >> 4);
-    const __bf16 *wrow = Wt + (int64_t)(64 * wave + (lane & 15)) * K + kq;
+    const __bf16 *wrow = Wt + (int64_t)(16 * kPColTiles * wave + (lane & 15)) * K + kq;
     const __bf16 *xrow = Xin + (lane & 15) * kPPitch + kq;
-    bf16x8 f[kSteps][4];
+    bf16x8 f[kSteps][kPColTiles];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-        f[0][b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K);
+    for (int st = 0; st < kPAhead && st < kSteps; ++st)
+#pragma unroll
+        for (int b = 0; b < kPColTiles; ++b)
+            f[st][b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K + 32 * st);
 #pragma unroll
     for (int st = 0; st < kSteps; ++st) {
-        if (st + 1 < kSteps)
+        if (st + kPAhead < kSteps)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                f[st + 1][b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K + 32 * (st + 1));
+            for (int b = 0; b < kPColTiles; ++b)
+                f[st + kPAhead][b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K + 32 * (st + kPAhead));
         tile_step(xrow, 32 * st, f[st], acc);
         __builtin_amdgcn_sched_barrier(0);  // keep each step's loads in its step: no hoisting past the register budget
     }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_propose(const float *__restrict__ from, const float *__restrict__ to,
+__global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(kPWaves / 2))) void k_mlp_propose(const float *__restrict__ from, const float *__restrict__ to,
                                                      int64_t n, const float *__restrict__ bounds,
                                                      const __bf16 *__restrict__ Wb, const float *__restrict__ P,
                                                      int nb, uint8_t *__restrict__ bucket) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __bf16 *X = reinterpret_cast<__bf16 *>(lds_raw);  // activations, overwritten layer by layer
-    float *best_v = reinterpret_cast<float *>(X + kPRows * kPPitch);  // [4][kPRows]
-    int *best_i = reinterpret_cast<int *>(best_v + 4 * kPRows);        // [4][kPRows]
+    float *best_v = reinterpret_cast<float *>(X + kPRows * kPPitch);  // [kPWaves][kPRows]
+    int *best_i = reinterpret_cast<int *>(best_v + kPWaves * kPRows);  // [kPWaves][kPRows]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float *bias = P + kMlpWeights;
     const int64_t tiles = (n + kPRows - 1) / kPRows;
@@ -452,7 +459,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int64_t r0 = tile * kPRows;
         // features -> X (pitch kPPitch)
 #pragma unroll 1
-        for (int q = tid; q < kPRows * 7; q += 256) {
+        for (int q = tid; q < kPRows * 7; q += kPThreads) {
             const int r = q / 7, part = q % 7;
             __bf16 *row = X + r * kPPitch;
             if (part == 6) {
@@ -468,7 +475,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         // the four layers through one call site, so the accumulators keep one
         // register set; a layer's outputs go over its inputs in X once every
         // wave has read them
-        f32x4 acc[kPRowTiles][4];
+        f32x4 acc[kPRowTiles][kPColTiles];
 #pragma unroll 1
         for (int l = 0; l < 4; ++l) {
             const __bf16 *in = X;
@@ -483,8 +490,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             const float *bl = bias + l * kMlpHidden;
             __syncthreads();  // every wave has read `in` before it is overwritten
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int col = 64 * wave + 16 * b + (lane & 15);
+            for (int b = 0; b < kPColTiles; ++b) {
+                const int col = 16 * kPColTiles * wave + 16 * b + (lane & 15);
                 const float bv = bl[col];
 #pragma unroll
                 for (int a = 0; a < kPRowTiles; ++a)
@@ -497,10 +504,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             __syncthreads();
         }
         const float *b4 = bias + 3 * kMlpHidden;
-        float b4v[4];
+        float b4v[kPColTiles];
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            b4v[b] = b4[64 * wave + 16 * b + (lane & 15)];
+        for (int b = 0; b < kPColTiles; ++b)
+            b4v[b] = b4[16 * kPColTiles * wave + 16 * b + (lane & 15)];
         // argmax over valid buckets (smallest index on ties)
 #pragma unroll
         for (int a = 0; a < kPRowTiles; ++a)
@@ -509,8 +516,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 float bv = -INFINITY;
                 int bi = INT32_MAX;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int col = 64 * wave + 16 * b + (lane & 15);
+                for (int b = 0; b < kPColTiles; ++b) {
+                    const int col = 16 * kPColTiles * wave + 16 * b + (lane & 15);
                     const float v = acc[a][b][i] + b4v[b];
                     if (col < nb && (v > bv || (v == bv && col < bi))) {
                         bv = v;
@@ -536,7 +543,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (tid < kPRows && r0 + tid < n) {
             float bv = best_v[tid];
             int bi = best_i[tid];
-            for (int w = 1; w < 4; ++w) {
+            for (int w = 1; w < kPWaves; ++w) {
                 const float v = best_v[w * kPRows + tid];
                 const int i2 = best_i[w * kPRows + tid];
                 if (v > bv || (v == bv && i2 < bi)) {
@@ -550,7 +557,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 }
 
-constexpr size_t kProposeLds = (size_t)kPRows * kPPitch * sizeof(__bf16) + 8 * (size_t)kPRows * 4;
+constexpr size_t kProposeLds = (size_t)kPRows * kPPitch * sizeof(__bf16) + 2 * kPWaves * (size_t)kPRows * 4;
 
 // ------------------------------------------------ frontier and labels
 // Left-to-right frontier of the tree at depth 8: internal nodes at depth 8
@@ -785,7 +792,7 @@ hipError_t proposal_predict(const MeshDev &m, const Proposal &pr, const float *f
     const int64_t tiles = (n + kPRows - 1) / kPRows;
     const int grid = (int)(tiles < 2 * cus ? tiles : 2 * cus);
     static_assert(kProposeLds <= 64 * 1024, "the fused inference kernel fits the default dynamic LDS");
-    k_mlp_propose<<<grid, 256, kProposeLds, s>>>(from, to, n, m.bounds, pr.Wb, pr.P, nb, bucket);
+    k_mlp_propose<<<grid, kPThreads, kProposeLds, s>>>(from, to, n, m.bounds, pr.Wb, pr.P, nb, bucket);
     return hipGetLastError();
 }
 
