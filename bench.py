@@ -79,21 +79,21 @@ def calibrate_copy():
 
 
 def measured_traffic(mode, precision, build):
-    """HBM bytes per traversal launch from the committed rocprofv3 counter
-    summary, or None when the traversal source or the tree build differs
-    from the one it was taken with."""
+    """(HBM bytes per traversal launch, the counter view beside them) from the
+    committed rocprofv3 counter summary, or (None, None) when the traversal
+    source or the tree build differs from the one it was taken with."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     rec = json.load(open(path)).get(f"{mode}_{precision}")
     if not rec or rec.get("build") != build:
-        return None
+        return None, None
     src = open(os.path.join(ROOT, "paper_2305_01867_amd", "csrc", "traverse.hip"), "rb").read()
     if hashlib.sha256(src).hexdigest() != rec["traverse_hip_sha256"]:
-        return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+        return None, None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"], rec.get("counters")
 
 
 def host_cpu():
@@ -208,10 +208,11 @@ def main():
     node_bytes = 112 if node_width == 4 else 64  # loaded per node fetch (7 or 4 16-byte loads)
     bytes_per_ray = 24 + out_bytes + node_bytes * mean_visits + 48 * mean_tests
     achieved_gbs = n * bytes_per_ray / (intersect_avg * 1e-3) / 1e9
+    traffic, counter_view = measured_traffic(args.mode, args.precision, args.build)
     roofline = {
         "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(args.mode, args.precision, args.build),
+        "traffic": traffic,
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": "k_traverse (+ k_reset, k_finish in the same event pair)", "node_width": node_width,
         "node_bytes": node_bytes,
@@ -225,6 +226,9 @@ def main():
     }
     if roofline["traffic"]:
         roofline["measured_frac"] = round(roofline["traffic"] / (intersect_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
+    if counter_view:
+        # what bounds the kernel: VALU issue, per the same profile (its counters, not live)
+        roofline["counters_from_profile"] = counter_view
 
     # ---------------- per-variant intersect throughput (untimed region)
     variants = {}
