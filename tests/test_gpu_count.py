@@ -30,7 +30,7 @@ def stacked(k):
 
 
 def test_closed_form_scenes():
-    for k in (1, 3, 8, 12, 13, 20, 40):  # more than 12 distinct hits go to the second pass
+    for k in (1, 3, 8, 11, 12, 13, 20, 40):  # more distinct hits than a lane keeps (certified 11, plain 12) go to the second pass
         V, F = stacked(k)
         O = np.array([[0.5, 0.5, k + 0.5], [0.75, 0.25, k + 0.5], [0.75, 0.25, -0.5], [2.0, 2.0, 1.0]], np.float32)
         E = np.array([[0.5, 0.5, -0.5], [0.75, 0.25, -0.5], [0.75, 0.25, 0.0], [2.0, 2.0, -1.0]], np.float32)
