@@ -14,11 +14,15 @@ Mrays/s.  --build radix_tree times the paper's own LBVH instead; the
 variants record that step either way.
 
 Printed: one JSON line (rank 0).  Besides the contract fields it carries
-  roofline      the traversal launch: algorithmic bytes (segments in, results
-                out, per node fetched its loaded bytes -- 112 B for a 4-wide
-                node, 64 B for a binary one -- and 48 B per triangle tested,
-                counted by an instrumented run of the same traversal) over its
-                average duration (HIP events on the launch stream), vs 8 TB/s
+  roofline      the traversal launch, which is bound by vector-ALU issue:
+                algorithmic fp32 FLOP (per node fetched and per triangle
+                tested, counted by an instrumented run of the same traversal)
+                over its average duration (HIP events on the launch stream),
+                against the 157.3 TFLOP/s fp32 vector peak; beside it the
+                VALU issue rate from the committed rocprofv3 counters, and the
+                memory view: measured HBM traffic against the achievable
+                bandwidth of the library's streaming copy kernel (measured in
+                the same run), and the bytes the method touches
   cpu_baseline  the binary64 brute-force oracle timed on the host cores on a
                 bounded sample of the same segments
   variants      Mrays/s of intersect alone per mode and precision
@@ -35,7 +39,21 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X vendor HBM3E peak
+FP32_PEAK_TFLOPS = 157.3       # MI355X fp32 vector peak (FMA = 2 FLOP)
+VALU_ISSUE_PEAK = 256 * 2.4e9  # wave64 VALU instructions per second: one per CU per cycle
+                               # (4 SIMD x 16 lanes, a wave64 instruction every 4 cycles each)
+# fp32 operations of the method per step of the traversal, counted from the
+# kernel source (FMA = 2, add / mul / min / max / compare / abs = 1):
+#   segment set-up (direction, scale, widened reciprocal, slab offsets)  41
+#   4-wide node: 4 children x (6 FMA + 3 max + 3 min + 1 compare)        76
+#   binary node: 2 children x (6 FMA + 12 min/max + 1 compare)           50
+#   leaf test, binary32 Moller-Trumbore (differences, two cross products,
+#   four dot products)                                                   41
+#     + plain decision (sign flips, five comparisons)                    12
+#     + certified: magnitude sums of the bound (58) and classification (44)
+FLOP_SETUP, FLOP_NODE4, FLOP_NODE2 = 41, 76, 50
+FLOP_TEST = {"plain": 41 + 12, "certified": 41 + 58 + 44}
 
 
 def parse():
@@ -62,26 +80,61 @@ def parse():
 
 
 def calibrate_copy():
-    """A plain device-to-device copy of known size: 1 GiB read + 1 GiB written
+    """The library's streaming copy of known size: 1 GiB read + 1 GiB written
     per launch.  Its FETCH_SIZE / WRITE_SIZE readings scale the counters of
     the other kernels to bytes."""
     import torch
+
+    import paper_2305_01867_amd as rsi
 
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
     a.fill_(1.0)
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     for _ in range(3):
-        b.copy_(a)
+        rsi.rsi_stream_copy(b, a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read_per_launch": a.numel() * 4, "copy_bytes_written_per_launch": b.numel() * 4,
                       "launches": 3}), flush=True)
 
 
+def achievable_hbm(reps: int = 5):
+    """Achievable HBM bandwidth: the library's streaming copy of 4 GiB into
+    another 4 GiB buffer (8 GiB moved per launch), timed with HIP events on the
+    launch stream.  Returns GB/s (and torch's own device copy beside it)."""
+    import torch
+
+    import paper_2305_01867_amd as rsi
+
+    n = 1 << 30  # float32 elements: 4 GiB
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("stream_copy", lambda: rsi.rsi_stream_copy(b, a)), ("torch_copy", lambda: b.copy_(a))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = round(2 * 4 * n / (ms * 1e-3) / 1e9, 1)
+    ok = bool(torch.equal(a, b))
+    del a, b
+    torch.cuda.empty_cache()
+    out["copy_verified"] = ok
+    out["bytes_per_launch"] = 2 * 4 * n
+    return out
+
+
 def measured_traffic(mode, precision, build):
     """(HBM bytes per traversal launch, the counter view beside them) from the
     committed rocprofv3 counter summary, or (None, None) when the traversal
-    source or the tree build differs from the one it was taken with."""
+    source or the tree build differs from the one it was taken with (counters
+    of another kernel say nothing about this one)."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -94,6 +147,38 @@ def measured_traffic(mode, precision, build):
     if hashlib.sha256(src).hexdigest() != rec["traverse_hip_sha256"]:
         return None, None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"], rec.get("counters")
+
+
+def full_check(mode, out, n):
+    """Compare the whole output of the timed path with the binary64 oracle's
+    stored per-chunk digests of the same workload (tests/golden, written by
+    the oracle alone).  None when no complete fixture covers this workload."""
+    import importlib.util
+
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", "make_full_fixtures.py")
+    if not os.path.exists(os.path.join(ROOT, "tests", "golden", "full_paper_scale.txt")):
+        return None
+    spec = importlib.util.spec_from_file_location("full_fixtures", path)
+    fx = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fx)
+    head, rows = fx.read("paper_scale")
+    if int(head["n_segments"]) != n or len(rows) * int(head["chunk"]) < n:
+        return None
+    cols = {"boolean": [("hit", 0)], "first_hit": [("tri_id", 1)], "barycentric": [("tri_id", 1), ("uvt", 2)],
+            "intercept_count": [("count", 3)]}[mode]
+    res = {"segments": n, "chunks": len(rows), "source": "tests/golden/full_paper_scale.txt"}
+    for key, col in cols:
+        a = out[key].cpu().numpy()
+        equal = 0
+        for c, (s0, m, _, *dig) in rows.items():
+            x = a[s0:s0 + m]
+            d = fx.digest(x.astype(np.uint8)) if key == "hit" else (
+                fx.digest(fx.uvt_f32(x)) if key == "uvt" else fx.digest(x.astype("<i4")))
+            equal += d == dig[col]
+        res[f"{key}_chunks_equal"] = equal
+    return res
 
 
 def host_cpu():
@@ -190,6 +275,10 @@ def main():
         hit_frac = float(outs["boolean"]["hit"].float().mean().item())
     print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, intersect {intersect_avg:.3f} ms "
           f"-> {value:.1f} Mrays/s", file=sys.stderr, flush=True)
+    # the whole timed output against the oracle's stored digests (every segment)
+    full = full_check(args.mode, outs[args.mode], n) if n == 10_000_000 else None
+    if full:
+        print(f"[bench] every segment vs the oracle's digests: {full}", file=sys.stderr, flush=True)
     # results of each path on the leading segments, for the oracle comparison below
     key = {"boolean": "hit", "intercept_count": "count"}.get(args.mode, "tri_id")
     keep = min(n, 1 << 22)
@@ -206,29 +295,56 @@ def main():
         p99_visits = float(torch.quantile(visits[: min(n, 1 << 24)].double(), 0.99).item())
     out_bytes = {"boolean": 1, "first_hit": 4, "barycentric": 16, "intercept_count": 4}[args.mode]
     node_bytes = 112 if node_width == 4 else 64  # loaded per node fetch (7 or 4 16-byte loads)
+    flop_node = FLOP_NODE4 if node_width == 4 else FLOP_NODE2
+    flop_per_ray = FLOP_SETUP + flop_node * mean_visits + FLOP_TEST[args.precision] * mean_tests
+    achieved_tflops = n * flop_per_ray / (intersect_avg * 1e-3) / 1e12
     bytes_per_ray = 24 + out_bytes + node_bytes * mean_visits + 48 * mean_tests
-    achieved_gbs = n * bytes_per_ray / (intersect_avg * 1e-3) / 1e9
     traffic, counter_view = measured_traffic(args.mode, args.precision, args.build)
+    print("[bench] achievable HBM: streaming copy of 4 GiB", file=sys.stderr, flush=True)
+    hbm = achievable_hbm()
+    hbm_gbs = hbm["stream_copy"]
     roofline = {
-        "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+        "bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
         "traffic": traffic,
-        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by the streaming copy's "
+                        "readings)",
         "kernel": "k_traverse (+ k_reset, k_finish in the same event pair)", "node_width": node_width,
-        "node_bytes": node_bytes,
-        "bytes_per_ray": round(bytes_per_ray, 1), "mean_node_visits": round(mean_visits, 2),
-        "p50_node_visits": p50_visits, "p99_node_visits": p99_visits, "mean_leaf_tests": round(mean_tests, 2),
-        "stream_only_frac": round(n * (24 + out_bytes) / (intersect_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-        "avg_launch_ms": round(intersect_avg, 4),
-        "reading": "achieved counts the bytes the method touches (node_bytes per node fetch, 48 per leaf "
-                   "test, the segment stream); the tree is served from LDS (its top) and L2, so they exceed "
-                   "the HBM peak; measured_frac is the measured HBM traffic over the same time",
+        "flop_per_segment": round(flop_per_ray, 1),
+        "flop_counting": f"{FLOP_SETUP} per segment + {flop_node} per node fetch + {FLOP_TEST[args.precision]} per "
+                         "leaf test (FMA = 2)",
+        "mean_node_visits": round(mean_visits, 2), "p50_node_visits": p50_visits, "p99_node_visits": p99_visits,
+        "mean_leaf_tests": round(mean_tests, 2), "avg_launch_ms": round(intersect_avg, 4),
+        "reading": "the traversal is bound by VALU issue, not by HBM: divergent lanes (about half of a wave "
+                   "active per instruction) and the control, stack and address work around the method's "
+                   "arithmetic fill the issue slots; the tree lives in LDS (its top) and L2, so HBM carries "
+                   "little more than the segment stream",
     }
-    if roofline["traffic"]:
-        roofline["measured_frac"] = round(roofline["traffic"] / (intersect_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
     if counter_view:
-        # what bounds the kernel: VALU issue, per the same profile (its counters, not live)
+        # issue-slot use of the same kernel, from the committed profile (its own launch time)
+        insts = counter_view.get("sq_insts_valu_per_launch")
+        us = counter_view.get("avg_launch_us_trace")
+        if insts and us:
+            roofline["valu_issue"] = {
+                "insts_per_launch": insts, "rate_per_s": round(insts / (us * 1e-6), 1),
+                "peak_per_s": VALU_ISSUE_PEAK, "frac": round(insts / (us * 1e-6) / VALU_ISSUE_PEAK, 4),
+                "valu_busy_pct": counter_view.get("VALUBusy_pct"),
+                "active_lanes_pct": counter_view.get("VALUUtilization_pct"),
+                "source": "profiles/ counters of this kernel (SQ_INSTS_VALU over its traced launch time)"}
         roofline["counters_from_profile"] = counter_view
+    roofline["hbm"] = {
+        "achievable_gbs": hbm_gbs, "achievable_from": "rsi_stream_copy, 4 GiB -> 4 GiB, HIP events",
+        "torch_copy_gbs": hbm["torch_copy"], "vendor_peak_gbs": HBM_PEAK_GBS,
+        "achievable_over_vendor": round(hbm_gbs / HBM_PEAK_GBS, 4),
+        "measured_gbs": round(traffic / (intersect_avg * 1e-3) / 1e9, 1) if traffic else None,
+        "measured_frac": round(traffic / (intersect_avg * 1e-3) / 1e9 / hbm_gbs, 5) if traffic else None,
+        "stream_bytes_per_segment": 24 + out_bytes,
+        "stream_frac": round(n * (24 + out_bytes) / (intersect_avg * 1e-3) / 1e9 / hbm_gbs, 5),
+        "touched_bytes_per_segment": round(bytes_per_ray, 1),
+        "touched_gbs": round(n * bytes_per_ray / (intersect_avg * 1e-3) / 1e9, 1),
+        "touched_note": f"{node_bytes} B per node fetch + 48 B per leaf test + the stream; served from LDS and L2 "
+                        "(it exceeds what HBM could deliver), so it is no HBM fraction",
+    }
 
     # ---------------- per-variant intersect throughput (untimed region)
     variants = {}
@@ -466,7 +582,8 @@ def main():
                "kind": "oracle",
                "sample": f"first {m} of the {n} segments x all {F.shape[0]} triangles "
                          f"(binary64 brute force, all three modes in one pass), {dt:.1f} s",
-               "host": host_cpu(), "mismatches_vs_oracle": mismatches}
+               "host": host_cpu(), "mismatches_vs_oracle": mismatches,
+               "timed_path_every_segment_vs_oracle": full}
         print(f"[bench] cpu oracle: {cpu['value']} Mrays/s on {cpu['cores']} threads", file=sys.stderr,
               flush=True)
 
@@ -484,6 +601,7 @@ def main():
         "intersect_ms": {"avg": round(intersect_avg, 4), "min": round(intersect_ms[0], 4),
                          "median": round(intersect_ms[len(intersect_ms) // 2], 4)},
         "counters": {"redecided_fp64": counters[0], "stack_overflow": counters[1]},
+        "every_segment_vs_oracle": full,
         "hit_fraction": hit_frac,
         "variants": variants,
         "learned_vs_plain": learned,

@@ -47,9 +47,10 @@
 extern "C" {
 #endif
 
-#define RSI_ABI_VERSION 5  /* 2: intercept-count mode, rsi_outputs.count; 3: waves_per_cu; 4: build algorithm;
+#define RSI_ABI_VERSION 6  /* 2: intercept-count mode, rsi_outputs.count; 3: waves_per_cu; 4: build algorithm;
                               5: 4-wide nodes (node_width, rsi_mesh_info.node_width, RSI_EXPORT_WIDE_NODES,
-                              RSI_EXPORT_WIDE_TOP) */
+                              RSI_EXPORT_WIDE_TOP); 6: RSI_EXPORT_MESH_ROOTS = 9 (was 7, the value of
+                              RSI_EXPORT_WIDE_NODES), rsi_stream_copy */
 
 typedef struct rsi_mesh_s *rsi_mesh; /* opaque; owned by the library until rsi_destroy */
 
@@ -167,8 +168,9 @@ typedef struct rsi_outputs {
     uint64_t *counters; /* optional [4]: [0] segments re-decided in binary64, [1] segments
                            that outgrew the LDS stack, [2] hitting segments whose answer
                            was not in the proposed bucket (proposal misses), [3] count-mode
-                           segments with more distinct hits than a lane keeps (8), finished
-                           by the second pass.  Zeroed by the call before it counts. */
+                           segments with more distinct hits than a lane keeps in registers
+                           (11 in CERTIFIED precision, 12 in PLAIN), finished by the second
+                           pass.  Zeroed by the call before it counts. */
     int32_t *count;     /* [N_r] intercept-count mode: distinct intersections, 0 on a miss */
 } rsi_outputs;
 
@@ -435,9 +437,20 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
                                const rsi_intersect_opts *opts, const rsi_outputs *out, void *stream);
 /* The combined BVH's arrays as rsi_mesh_export, plus RSI_EXPORT_MESH_ROOTS:
  * int32 [n_meshes], each mesh's subtree root (INT32_MIN for an empty mesh). */
-#define RSI_EXPORT_MESH_ROOTS 7
+#define RSI_EXPORT_MESH_ROOTS 9
 rsi_status rsi_batch_export(rsi_batch batch, int32_t what, void *dst, int64_t dst_bytes, void *stream);
 rsi_status rsi_batch_destroy(rsi_batch batch);
+
+/* ------------------------------------------------------------------------
+ * Measurement helper: the achievable HBM bandwidth that the traversal's
+ * measured memory traffic is compared with.  Copies `bytes` (a multiple of
+ * 16) from src to dst, both 16-byte aligned device buffers that do not
+ * overlap, with a streaming kernel: each lane moves 16-byte words in a
+ * grid-stride loop, four in flight, non-temporal loads and stores, eight
+ * 256-thread workgroups per compute unit.  Queued on `stream`; RSI_E_ARG for a
+ * size, alignment or pointer that breaks these rules.
+ * ---------------------------------------------------------------------- */
+rsi_status rsi_stream_copy(void *dst, const void *src, int64_t bytes, void *stream);
 
 const char *rsi_status_string(rsi_status status);
 const char *rsi_last_error(void);   /* message of this thread's last failure, "" if none */

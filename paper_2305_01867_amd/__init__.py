@@ -25,16 +25,17 @@ __all__ = [
     "rsi_proposal_features", "rsi_proposal_frontier", "rsi_proposal_save", "rsi_proposal_load",
     "MLP_PARAMS", "MLP_INPUTS", "MLP_BUCKETS",
     "Batch", "rsi_batch_create", "rsi_batch_build", "rsi_batch_intersect", "rsi_batch_export", "rsi_batch_destroy",
+    "rsi_stream_copy",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "librsi.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 MODES = {"boolean": 0, "first_hit": 1, "barycentric": 2, "intercept_count": 3}
 PRECISIONS = {"plain": 0, "certified": 1}
 EXPORTS = {"sorted_keys": 0, "sorted_ids": 1, "nodes": 2, "parents": 3, "counters": 4, "leaves": 5, "bounds": 6,
-           "wide_nodes": 7, "wide_top": 8}
+           "wide_nodes": 7, "wide_top": 8, "mesh_roots": 9}
 STATUS = {0: "RSI_OK", 1: "RSI_E_ARG", 2: "RSI_E_RANGE", 3: "RSI_E_NOMEM", 4: "RSI_E_HIP",
           5: "RSI_E_STATE", 6: "RSI_E_CAPACITY"}
 
@@ -111,12 +112,13 @@ def lib():
     L.rsi_batch_intersect.argtypes = [P, P, P, I32, ctypes.POINTER(_IntersectOpts), ctypes.POINTER(_Outputs), P]
     L.rsi_batch_export.argtypes = [P, I32, P, I64, P]
     L.rsi_batch_destroy.argtypes = [P]
+    L.rsi_stream_copy.argtypes = [P, P, I64, P]
     for f in ("rsi_batch_create", "rsi_batch_build", "rsi_batch_intersect", "rsi_batch_export", "rsi_batch_destroy"):
         getattr(L, f).restype = ctypes.c_int
     for f in ("rsi_build", "rsi_intersect", "rsi_destroy", "rsi_mesh_info_get", "rsi_mesh_export",
               "rsi_traversal_stats", "rsi_proposal_train", "rsi_proposal_predict", "rsi_proposal_params",
               "rsi_proposal_gradient", "rsi_proposal_features", "rsi_proposal_frontier", "rsi_proposal_save",
-              "rsi_proposal_load", "rsi_debug_certify", "rsi_derive", "rsi_compact_hits"):
+              "rsi_proposal_load", "rsi_debug_certify", "rsi_derive", "rsi_compact_hits", "rsi_stream_copy"):
         getattr(L, f).restype = ctypes.c_int
     L.rsi_status_string.argtypes = [ctypes.c_int]
     L.rsi_status_string.restype = ctypes.c_char_p
@@ -598,7 +600,8 @@ def rsi_batch_export(batch: Batch, what: str, stream=None) -> torch.Tensor:
     """Arrays of the combined BVH (as rsi_mesh_export) or "mesh_roots"."""
     if what == "mesh_roots":
         dst = torch.empty(batch.n_meshes, dtype=torch.int32, device="cuda")
-        _check(lib().rsi_batch_export(batch.handle, 7, _p(dst), dst.numel() * 4, _stream_handle(stream)))
+        _check(lib().rsi_batch_export(batch.handle, EXPORTS["mesh_roots"], _p(dst), dst.numel() * 4,
+                                      _stream_handle(stream)))
         return dst
     view = Mesh(None, batch.vertex_offsets[-1], batch.triangle_offsets[-1], 63, stream)
     nt = view.n_triangles
@@ -617,3 +620,16 @@ def rsi_batch_export(batch: Batch, what: str, stream=None) -> torch.Tensor:
 
 def rsi_batch_destroy(batch: Batch):
     batch.close()
+
+
+# --------------------------------------------------------------- measurement
+def rsi_stream_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    """Copy src into dst (contiguous GPU tensors of the same byte size, a
+    multiple of 16) with the library's streaming copy kernel."""
+    for t, name in ((dst, "dst"), (src, "src")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous GPU tensor")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src must have the same size in bytes")
+    _check(lib().rsi_stream_copy(_p(dst), _p(src), nbytes, _stream_handle(stream)))

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librsi.so")
-SOURCES = ["api.hip", "build.hip", "traverse.hip", "mlp.hip", "batch.hip", "derive.hip", "restructure.hip", "wide.hip"]
+SOURCES = ["api.hip", "build.hip", "traverse.hip", "mlp.hip", "batch.hip", "derive.hip", "restructure.hip", "wide.hip", "membw.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1277,6 +1277,25 @@ rsi_status rsi_proposal_load(rsi_mesh mesh, const char *path) {
     return RSI_OK;
 }
 
+rsi_status rsi_stream_copy(void *dst, const void *src, int64_t bytes, void *stream) {
+    g_error.clear();
+    if (bytes < 0 || (bytes & 15) != 0)
+        return fail(RSI_E_ARG, "bytes must be a non-negative multiple of 16");
+    if (bytes == 0)
+        return RSI_OK;
+    if (!dst || !src || (reinterpret_cast<uintptr_t>(dst) & 15u) || (reinterpret_cast<uintptr_t>(src) & 15u))
+        return fail(RSI_E_ARG, "dst / src must be non-NULL and 16-byte aligned");
+    rsi_status st = check_device();
+    if (st != RSI_OK)
+        return st;
+    if ((st = check_dev_ptr(dst, "dst")) != RSI_OK || (st = check_dev_ptr(src, "src")) != RSI_OK)
+        return st;
+    if ((st = pending_error("before rsi_stream_copy")) != RSI_OK)
+        return st;
+    const hipError_t e = rsi::launch_stream_copy(dst, src, bytes / 16, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RSI_OK : fail_hip(e, "rsi_stream_copy launch");
+}
+
 const char *rsi_status_string(rsi_status status) {
     switch (status) {
     case RSI_OK: return "RSI_OK";

@@ -595,7 +595,7 @@ __global__ void k_frontier(const Node *__restrict__ nodes, const int32_t *__rest
         int r = cur[b];
         bucket_ref[b] = r;
         int x = r;
-        for (int guard = 0; x >= 0 && guard < kDeepStack; ++guard)
+        for (int guard = 0; x >= 0 && guard < nt; ++guard)  // a path has fewer than nt internal nodes
             x = nodes[x].refs.x;
         bucket_first[b] = ~x;
         // mark every leaf of the bucket's subtree: a walk without a stack (down

@@ -51,7 +51,10 @@ struct alignas(16) Tri {
 };
 static_assert(sizeof(Tri) == 48, "leaf triangle must be 48 bytes");
 
-constexpr int kDeepStack = 128;  // exceeds the radix tree's largest possible depth (97)
+// Entries of the second pass's private stack per lane: above the radix tree's largest
+// possible depth (97).  A restructured tree may be deeper; the second pass then
+// tests the leaves of a subtree that finds no room, so no push is ever dropped.
+constexpr int kDeepStack = 128;
 
 // Learned proposal (mlp.hip): sizes of the network and its parameter vector
 // [W1 (256 x 224), W2, W3, W4 (256 x 256), b1..b4 (256 each)], weights stored
@@ -209,6 +212,9 @@ hipError_t launch_debug_certify(const float *from, const float *to, const float 
                                 int32_t *cls, hipStream_t s);
 hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
 hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s);
+
+// Streaming copy of n16 16-byte words (membw.hip).
+hipError_t launch_stream_copy(void *dst, const void *src, int64_t n16, hipStream_t s);
 
 // Learned proposal (mlp.hip).
 hipError_t proposal_frontier(const MeshDev &m, Proposal &pr, hipStream_t s);

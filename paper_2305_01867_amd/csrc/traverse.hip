@@ -24,6 +24,7 @@
 // particular any binary64 hit of a non-grazing segment.
 #include "rsi_internal.h"
 
+#include <cstdlib>
 #include <type_traits>
 
 namespace rsi {
@@ -299,6 +300,8 @@ struct TravParams {
     const int32_t *mesh_toff;
     const int32_t *ray_off;
     const int32_t *order;  // segment at each processing position (NULL: input order)
+    int deep_cap;          // second pass: entries of a lane's private stack (<= kDeepStack)
+    int wave_cap;          // second pass: entries of a wave's shared stack (<= its LDS array)
 };
 
 __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why) {
@@ -966,6 +969,23 @@ struct Finish {
         }
     }
 
+    // Every leaf of subtree c, exactly: the second pass's answer when a
+    // subtree finds no room on the stack (a tree deeper than the stack), so a
+    // push is never dropped.  The span [smallest, largest sorted leaf] holds
+    // the subtree's leaves (after treelet restructuring it may hold others of
+    // the same mesh too; testing a triangle twice or one outside the subtree
+    // never changes a result: each is decided exactly, and equal t count once).
+    __device__ void test_span(const TravParams &p, int c) {
+        int first = ~c, last = ~c;
+        if (c >= 0) {
+            const int4 r = p.nodes[c].refs;
+            first = r.z;
+            last = r.w;
+        }
+        for (int leaf = first; leaf <= last && leaf >= 0 && leaf < p.nt && !done; ++leaf)
+            test_leaf(p, leaf);
+    }
+
     __device__ void append(double t) {
         const int k = atomicAdd(list_len, 1);
         if (k < kCountList)
@@ -1048,8 +1068,12 @@ __device__ void wave_search(const TravParams &p, Finish<MODE, CERT> &f, bool ok,
             stk[0] = root;
         __syncthreads();
         const int64_t max_steps = 2 * p.nt + 8;  // every step pops at least one of < 2 nt subtrees
+        // soft limit: a step that pops k entries pushes at most 2k, and past
+        // the soft limit single pops add at most one entry per tree level
+        const int cap = p.wave_cap;
+        const int soft = cap - (kDeepStack < cap / 2 ? kDeepStack : cap / 2);
         for (int64_t step = 0; step < max_steps && size > 0; ++step) {
-            const int room = (kWaveCap<MODE> - kDeepStack) - size;
+            const int room = soft - size;
             int k = room < 1 ? 1 : (room < 64 ? room : 64);
             k = k < size ? k : size;
             const int ref = lane < k ? stk[size - 1 - lane] : kDone;
@@ -1075,12 +1099,21 @@ __device__ void wave_search(const TravParams &p, Finish<MODE, CERT> &f, bool ok,
             }
             const uint64_t m0 = __ballot(c0 != kDone), m1 = __ballot(c1 != kDone);
             const int o = size + __popcll(m0 & lt_mask) + __popcll(m1 & lt_mask);
-            if (c0 != kDone && o < kWaveCap<MODE>)
-                stk[o] = c0;
-            if (c1 != kDone && o + 1 < kWaveCap<MODE>)
-                stk[o + 1] = c1;
+            // a subtree past the stack's capacity is searched leaf by leaf here
+            if (c0 != kDone) {
+                if (o < cap)
+                    stk[o] = c0;
+                else
+                    f.test_span(p, c0);
+            }
+            if (c1 != kDone) {
+                if (o + 1 < cap)
+                    stk[o + 1] = c1;
+                else
+                    f.test_span(p, c1);
+            }
             size += __popcll(m0) + __popcll(m1);
-            size = size < kWaveCap<MODE> ? size : kWaveCap<MODE>;
+            size = size < cap ? size : cap;
             __syncthreads();
             if (MODE == MODE_BOOL) {
                 if (__ballot(f.done))
@@ -1197,8 +1230,13 @@ __device__ void finish_lane(const TravParams &p, int64_t i, int *stk) {
                 const bool hr = slab(R.x, R.y, R.z, R.w, Z.z, Z.w, f.r, f.tlimit, tr);
                 if (hl && hr) {
                     const bool left_first = tl <= tr;
-                    if (sp < kDeepStack)
-                        stk[(sp++) * kFinishThreads] = left_first ? refs.y : refs.x;
+                    const int far = left_first ? refs.y : refs.x;
+                    if (sp < p.deep_cap)
+                        stk[(sp++) * kFinishThreads] = far;
+                    else
+                        f.test_span(p, far);  // deeper than the stack: that subtree leaf by leaf
+                    if (f.done)
+                        break;
                     ref = left_first ? refs.x : refs.y;
                     continue;
                 }
@@ -1463,6 +1501,18 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.mesh_toff = a.mesh_toff;
     p.ray_off = a.ray_off;
     p.order = nullptr;
+    p.deep_cap = kDeepStack;
+    p.wave_cap = a.mode == MODE_COUNT ? kWaveCap<MODE_COUNT> : kWaveCap<MODE_BOOL>;
+    // RSI_DEBUG_PASS2_STACK=k (2..kDeepStack) shrinks both second-pass stacks
+    // to k entries, so tests reach the leaf-span path that a tree deeper than
+    // the stacks takes; results do not change
+    if (const char *env = getenv("RSI_DEBUG_PASS2_STACK")) {
+        const int k = atoi(env);
+        if (k >= 2 && k <= kDeepStack) {
+            p.deep_cap = k;
+            p.wave_cap = k;
+        }
+    }
     return p;
 }
 

@@ -128,12 +128,37 @@ def to_dot(tree: dict, name: str = "bvh") -> str:
     return "\n".join(lines) + "\n"
 
 
+SECOND_PASS_STACK = 128  # entries of a lane's private stack in the exact second pass
+
+
+def max_depth(tree: dict) -> int:
+    """Number of internal nodes on the longest root-to-leaf path (0 for a
+    tree of one leaf), by a breadth-first walk from the root."""
+    n_int = tree["left"].shape[0]
+    if n_int == 0 or tree["root"] < 0:
+        return 0
+    level, depth, seen = [tree["root"]], 0, 0
+    while level:
+        depth += 1
+        seen += len(level)
+        if seen > n_int:
+            return -1  # a cycle: not a tree
+        nxt = []
+        for i in level:
+            for r in (tree["left"][i], tree["right"][i]):
+                if 0 <= r < n_int:
+                    nxt.append(int(r))
+        level = nxt
+    return depth
+
+
 def check(tree: dict, contiguous: bool = False) -> list:
     """Structural checks of a decoded tree (the connectivity the paper's
     debugging looked for); returns a list of problems, empty when sound:
     every leaf and non-root internal node has exactly one parent, the
     children's leaf spans make up the parent's, each box contains its
-    children's boxes, and counters (if present) read 2.  With contiguous=True
+    children's boxes, counters (if present) read 2, and the depth stays
+    within the exact second pass's stack.  With contiguous=True
     (radix-tree numbering) the spans must also split the parent's range."""
     problems = []
     n_int = tree["left"].shape[0]
@@ -175,6 +200,12 @@ def check(tree: dict, contiguous: bool = False) -> list:
         problems.append(f"{bad.size} nodes without exactly one parent")
     if tree["counter"] is not None and np.any(tree["counter"] != 2):
         problems.append(f"{int(np.sum(tree['counter'] != 2))} internal nodes not completed (counter != 2)")
+    depth = max_depth(tree)
+    if depth < 0:
+        problems.append("the child references form a cycle")
+    elif depth > SECOND_PASS_STACK:
+        # still exact, but the second pass tests leaf spans where the stack runs out
+        problems.append(f"depth {depth} exceeds the second pass's stack of {SECOND_PASS_STACK} entries")
     return problems
 
 

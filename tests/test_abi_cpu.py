@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = rsi.lib()
-    assert L.rsi_abi_version() == 5
+    assert L.rsi_abi_version() == 6
     for code in range(7):
         assert L.rsi_status_string(code).decode().startswith("RSI_")
     assert b"unknown" in L.rsi_status_string(99)
@@ -101,3 +101,21 @@ def test_python_wrapper_refuses_int64_indices_and_host_tensors():
         rsi.rsi_build(V, torch.zeros((1, 3), dtype=torch.int32))   # not on the GPU
     with pytest.raises(TypeError):
         rsi.rsi_build(V.double(), torch.zeros((1, 3), dtype=torch.int32))
+
+
+def test_stream_copy_argument_errors_need_no_gpu():
+    L = rsi.lib()
+    assert L.rsi_stream_copy(None, None, 0, None) == 0      # nothing to copy
+    assert L.rsi_stream_copy(None, None, -16, None) == 1    # negative size
+    assert L.rsi_stream_copy(None, None, 24, None) == 1     # not a multiple of 16
+    assert L.rsi_stream_copy(None, None, 32, None) == 1     # NULL buffers
+    assert b"16-byte" in L.rsi_last_error()
+
+
+def test_export_codes_are_distinct():
+    text = open(os.path.join(ROOT, "include", "rsi.h")).read()
+    codes = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(RSI_EXPORT_[A-Z_]+)\s*=\s*(\d+)", text)}
+    codes.update({m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(RSI_EXPORT_[A-Z_]+)\s+(\d+)", text)})
+    assert "RSI_EXPORT_MESH_ROOTS" in codes and len(codes) >= 10
+    assert len(set(codes.values())) == len(codes), codes
+    assert codes == {k.upper().join(("RSI_EXPORT_", "")): v for k, v in rsi.EXPORTS.items()}

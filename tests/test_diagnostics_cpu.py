@@ -152,3 +152,62 @@ def test_wide_checker_accepts_a_collapse_and_finds_planted_mistakes():
     (q0, i0), (q1, i1) = leaf_slots[-2], leaf_slots[-1]
     bad[q1, 24 + i1] = bad[q0, 24 + i0]
     assert diagnostics.check_wide(dw(bad), dw(top), tree) != []
+
+
+def test_depth_of_chains_and_the_check():
+    """A tree that is one chain (each internal node has a leaf and the next
+    node as children) is as deep as it has internal nodes; the check names a
+    depth past the exact second pass's stack, and a cycle."""
+    def chain(n_int):
+        left = np.array([~i for i in range(n_int)], np.int32)
+        right = np.array(list(range(1, n_int)) + [~n_int], np.int32)
+        return {"left": left, "right": right, "root": 0}
+
+    assert diagnostics.max_depth(chain(1)) == 1
+    assert diagnostics.max_depth(chain(97)) == 97
+    # the paper's scene: root and two internal children
+    V, F, _, _ = workloads.appendix_scene()
+    tree = diagnostics.decode(*export_layout(V, F))
+    assert diagnostics.max_depth(tree) == 2
+    # a 64-triangle geometric chain with 63-bit keys: one internal node per level
+    s = oracle.build_structure(*_geometric(64), 63)
+    t = s["tree"]
+    tree = {"left": np.where(t["left_leaf"] == 1, ~t["left"], t["left"]),
+            "right": np.where(t["right_leaf"] == 1, ~t["right"], t["right"]), "root": 0}
+    assert diagnostics.max_depth(tree) == 63
+    # check() on a sound chain of 150 internal nodes: only the depth is named
+    n_int = 150
+    t = chain(n_int)
+    leaf_box = np.array([[k, 0, 0, k + 1, 1, 1] for k in range(n_int + 1)], np.float32)
+    box = np.array([[i, 0, 0, n_int + 1, 1, 1] for i in range(n_int)], np.float32)
+    t.update({"first": np.arange(n_int, dtype=np.int32), "last": np.full(n_int, n_int, np.int32),
+              "leaf_box": leaf_box, "box": box, "left_box": leaf_box[:n_int],
+              "right_box": np.concatenate([box[1:], leaf_box[n_int:]]), "counter": np.full(n_int, 2, np.int32),
+              "leaf_tri": np.arange(n_int + 1, dtype=np.int32)})
+    assert diagnostics.check(t) == [f"depth {n_int} exceeds the second pass's stack of 128 entries"]
+    t97 = chain(97)
+    t97.update({k: (v[:97] if k not in ("leaf_box", "leaf_tri") else v[:98]) for k, v in t.items()
+                if k not in ("left", "right", "root")})
+    t97["last"] = np.full(97, 97, np.int32)
+    t97["box"] = np.array([[i, 0, 0, 98, 1, 1] for i in range(97)], np.float32)
+    t97["right_box"] = np.concatenate([t97["box"][1:], leaf_box[97:98]])
+    assert diagnostics.check(t97) == []
+    cyc = chain(5)
+    cyc["right"] = cyc["right"].copy()
+    cyc["right"][4] = 0
+    assert diagnostics.max_depth(cyc) == -1
+
+
+def _geometric(m):
+    """m triangles shrinking by 2^(-1/3) towards a corner, plus one spanning the unit box."""
+    V, F = [], []
+    for k in range(m):
+        c = 0.9 * np.array([2.0 ** -(k / 3.0), 2.0 ** -((k + 1) / 3.0), 2.0 ** -((k + 2) / 3.0)])
+        s = 0.3 * 2.0 ** -(k / 3.0 + 2)
+        b = len(V)
+        V += [c + [-s, -s, 0], c + [s, -s, 0.1 * s], c + [0, s, -0.1 * s]]
+        F.append([b, b + 1, b + 2])
+    b = len(V)
+    V += [[0, 0, 0], [1, 0, 0], [0, 1, 1]]
+    F.append([b, b + 1, b + 2])
+    return np.array(V, np.float32), np.array(F, np.int32)

@@ -1,6 +1,8 @@
 """Pins of the CPU reference of the learned proposal: finite differences of
 the binary64 network, bf16 rounding against torch's conversion, feature and
 frontier closed forms."""
+import math
+
 import numpy as np
 import torch
 
@@ -81,3 +83,67 @@ def test_frontier_reference():
         last = ~r if r < 0 else t["last"][r]
         nxt = first[b + 1] if b + 1 < len(refs) else F.shape[0]
         assert last + 1 == nxt
+
+
+def test_zero_network_loss_is_log_of_bucket_count_and_gradient_is_softmax_minus_onehot():
+    """All weights and biases zero: every logit is 0, the softmax is uniform
+    over the n unmasked buckets, so the loss is ln n for any labels, and
+    dL/dz = (softmax - onehot) / rows gives the last bias gradient
+    1/n - (share of rows with label k) in bucket k (0 for masked buckets);
+    nothing reaches the other parameters, whose inputs or upstream gradients
+    are all zero."""
+    rng = np.random.default_rng(7)
+    rows, nb = 37, 150
+    X = rng.normal(0, 1, (rows, ref.INPUTS))
+    y = rng.integers(0, nb, rows)
+    for rnd in (False, True):
+        loss, logits, grad = ref.forward_backward(X, y, np.zeros(ref.N_PARAMS), nb, round_bf16=rnd)
+        assert np.all(logits == 0)
+        assert abs(loss - np.log(nb)) <= 1e-15
+        Ws, bs = ref.unpack(grad)
+        want = np.zeros(ref.OUT)
+        want[:nb] = 1.0 / nb
+        np.subtract.at(want, y, 1.0 / rows)
+        # with bf16 rounding each row's (p - y) / rows is rounded once (2^-9 relative)
+        tol = 1e-15 if not rnd else rows * 2.0 ** -9 / rows
+        assert np.allclose(bs[3], want, rtol=0, atol=tol)
+        assert np.all(bs[3][nb:] == 0)
+        for W in Ws:
+            assert np.all(W == 0)
+        for b in bs[:3]:
+            assert np.all(b == 0)
+
+
+def test_hand_computed_two_row_network():
+    """A 2-2-2-2-3 network whose every value is worked out by hand:
+    X = [[1, 2], [-1, 0.5]];  layer 1 identity, b1 = 0  -> relu [[1, 2], [0, 0.5]]
+    layer 2 identity, b2 = (-0.5, 0)                    -> relu [[0.5, 2], [0, 0.5]]
+    layer 3 [[1, 1], [0, 1]], b3 = 0                     -> [[2.5, 2], [0.5, 0.5]]
+    layer 4 [[1, 0], [0, 1], [1, -1]], b4 = (0, 0, 0.25) -> logits [[2.5, 2, 0.75], [0.5, 0.5, 0.25]]
+    labels (0, 2): loss = mean(log(e^2.5 + e^2 + e^0.75) - 2.5, log(2 e^0.5 + e^0.25) - 0.25).
+    With only 2 buckets the third logit is masked: loss = mean(log(e^2.5 + e^2) - 2.5,
+    log(2 e^0.5) - 0.5) for labels (0, 1)."""
+    shapes = [(2, 2), (2, 2), (2, 2), (3, 2)]
+    W1, W2, W3 = [1, 0, 0, 1], [1, 0, 0, 1], [1, 1, 0, 1]
+    W4 = [1, 0, 0, 1, 1, -1]
+    b = [0, 0, -0.5, 0, 0, 0, 0, 0, 0.25]
+    params = np.array(W1 + W2 + W3 + W4 + b, np.float64)
+    X = np.array([[1.0, 2.0], [-1.0, 0.5]])
+    loss, logits, grad = ref.forward_backward(X, np.array([0, 2]), params, 3, round_bf16=False, shapes=shapes)
+    assert np.array_equal(logits, [[2.5, 2.0, 0.75], [0.5, 0.5, 0.25]])
+    e = math.exp
+    want = 0.5 * ((math.log(e(2.5) + e(2.0) + e(0.75)) - 2.5) + (math.log(2 * e(0.5) + e(0.25)) - 0.25))
+    assert abs(loss - want) <= 1e-15
+    # dL/db4 = mean over rows of softmax - onehot
+    p0 = np.array([e(2.5), e(2.0), e(0.75)]) / (e(2.5) + e(2.0) + e(0.75))
+    p1 = np.array([e(0.5), e(0.5), e(0.25)]) / (2 * e(0.5) + e(0.25))
+    want_b4 = 0.5 * ((p0 - [1, 0, 0]) + (p1 - [0, 0, 1]))
+    _, bs = ref.unpack(grad, shapes)
+    assert np.allclose(bs[3], want_b4, rtol=0, atol=1e-15)
+    # dL/dW4 = dZ^T h3 with h3 = [[2.5, 2], [0.5, 0.5]]
+    Ws, _ = ref.unpack(grad, shapes)
+    dZ = 0.5 * np.stack([p0 - [1, 0, 0], p1 - [0, 0, 1]])
+    assert np.allclose(Ws[3], dZ.T @ np.array([[2.5, 2.0], [0.5, 0.5]]), rtol=0, atol=1e-15)
+    loss2, _, _ = ref.forward_backward(X, np.array([0, 1]), params, 2, round_bf16=False, shapes=shapes)
+    want2 = 0.5 * ((math.log(e(2.5) + e(2.0)) - 2.5) + (math.log(2 * e(0.5)) - 0.5))
+    assert abs(loss2 - want2) <= 1e-15
