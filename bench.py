@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the learned form (5.26e5 triangles) leg")
+    ap.add_argument("--c5-train-rays", type=int, default=10_000_000)
     ap.add_argument("--no-host", action="store_true", help="skip the host-resident (PCIe-inclusive) runs")
     ap.add_argument("--train-rays", type=int, default=2_000_000)
     ap.add_argument("--train-epochs", type=int, default=3)
@@ -193,6 +195,102 @@ def host_cpu():
     except OSError:
         pass
     return {"model": model, "nproc": os.cpu_count()}
+
+
+def _timed(fn, stream, reps=3):
+    import torch
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def learned_leg(rsi, dV, dF, Ot, Et, dO, dE, o, mode, precision, build, epochs, stream):
+    """Train the proposal on (Ot, Et), then time the intersection of (dO, dE)
+    in the plain and the proposal order on the same mesh (4-wide trees and
+    binary nodes), the inference alone, and count node fetches of both."""
+    import torch
+    n = dO.shape[0]
+    dOt, dEt = torch.from_numpy(Ot).to(dO.device), torch.from_numpy(Et).to(dO.device)
+    with rsi.rsi_build(dV, dF, algorithm=build) as mesh:
+        torch.cuda.synchronize()
+        t_tr = time.perf_counter()
+        loss, n_lab = rsi.rsi_proposal_train(mesh, dOt, dEt, epochs=epochs, batch=4096, lr=2e-3, seed=1)
+        t_tr = time.perf_counter() - t_tr
+        del dOt, dEt
+        run = lambda **kw: rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision=precision, out=o, **kw)
+        ms = {}
+        for width in (4, 2):
+            ms["plain", width] = _timed(lambda: run(node_width=width), stream)
+            ms["learned", width] = _timed(lambda: run(proposal=True, node_width=width), stream)
+        late = int(o["counters"][2].item())
+        n_hit = int(o["hit"].sum().item()) if mode == "boolean" else int((o["tri_id"] >= 0).sum().item())
+        run(proposal=True)  # leave the default (4-wide) proposal order's results in o
+        ms_mlp = _timed(lambda: rsi.rsi_proposal_predict(mesh, dO, dE), stream)
+        visits = {}
+        for width in (4, 2):
+            for order, kw in (("plain", {}), ("learned", {"proposal": True})):
+                v, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=mode, precision=precision, node_width=width, **kw)
+                visits[order, width] = round(float(v.double().mean().item()), 2)
+                del v
+    saved = ms["plain", 4] - (ms["learned", 4] - ms_mlp)
+    return {
+        "train_segments": int(Ot.shape[0]), "labelled": n_lab, "epochs": epochs,
+        "train_s": round(t_tr, 2), "epoch_loss": [round(x, 4) for x in loss.tolist()],
+        # GEMM work per labelled segment and epoch: forward 2 x 253,952, weight
+        # gradients the same, input gradients 2 x 3 x 65,536 FLOP; over train_s,
+        # which includes labelling the segments
+        "train_tflops": round(epochs * n_lab * (4 * 253952 + 6 * 65536) / t_tr / 1e12, 2),
+        "proposal_miss_rate": round(late / max(n_hit, 1), 4),
+        "intersect_mrays_s_plain_order": round(n / (ms["plain", 4] * 1e-3) / 1e6, 1),
+        "intersect_mrays_s_learned": round(n / (ms["learned", 4] * 1e-3) / 1e6, 1),
+        "intersect_mrays_s_plain_order_binary_nodes": round(n / (ms["plain", 2] * 1e-3) / 1e6, 1),
+        "intersect_mrays_s_learned_binary_nodes": round(n / (ms["learned", 2] * 1e-3) / 1e6, 1),
+        "intersect_ms": {f"{k[0]}/{k[1]}-wide": round(v, 3) for k, v in ms.items()},
+        "mlp_inference_ms": round(ms_mlp, 3),
+        "mlp_tflops": round(n * 2 * 253952 / (ms_mlp * 1e-3) / 1e12, 1),
+        "traversal_ms_saved_by_the_order": round(saved, 3),
+        "break_even": "the learned order pays when the traversal time it saves exceeds the inference time",
+        "mean_node_fetches": {f"{k[0]}/{k[1]}-wide": v for k, v in visits.items()},
+        "mode": mode, "precision": precision, "_result": True,
+    }
+
+
+def learned_form(rsi, workloads, args, stream):
+    """The learned-proposal form: a 512 x 512 heightfield with two folded
+    sheets (about 5.26e5 triangles), the proposal trained on segments of the
+    same distribution, evaluated on one chunk of 1e7 segments (boolean mode,
+    early exit), against the plain order; a sample checked against the oracle."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    V, F = workloads.learned_mesh()
+    print(f"[bench] learned form: {F.shape[0]} triangles, training on {args.c5_train_rays} segments",
+          file=sys.stderr, flush=True)
+    Ot, Et = workloads.learned_rays(args.c5_train_rays, 5001)
+    O, E = workloads.learned_rays(10_000_000, 5100)
+    dV, dF = torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev)
+    dO, dE = torch.from_numpy(O).to(dev), torch.from_numpy(E).to(dev)
+    o = {"hit": torch.empty(O.shape[0], dtype=torch.uint8, device=dev),
+         "counters": torch.zeros(4, dtype=torch.int64, device=dev)}
+    res = learned_leg(rsi, dV, dF, Ot, Et, dO, dE, o, "boolean", args.precision, args.build, 2, stream)
+    res.pop("_result", None)
+    got = o["hit"].cpu().numpy()
+    res["hit_fraction"] = round(float(got.mean()), 4)
+    res["workload"] = (f"learned form: 512x512 heightfield + two folded sheets ({F.shape[0]} triangles), "
+                       f"evaluation chunk of {O.shape[0]} segments (seed 5100)")
+    if not args.no_cpu_baseline:
+        import oracle
+        idx = np.random.default_rng(7).choice(O.shape[0], 2000, replace=False)
+        want, _, _, _ = oracle.intersect(V, F, O[idx], E[idx])
+        res["oracle_sample"] = {"segments": int(idx.size), "mismatches": int(np.sum(got[idx] != want))}
+    del dV, dF, dO, dE, o
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -433,56 +531,17 @@ def main():
     if not args.no_learned and args.mode != "intercept_count":
         lo, hi = V.min(axis=0), V.max(axis=0)
         Ot, Et = workloads.rays_in_box(args.train_rays, 23, lo, hi)  # training segments, own seed
-        dOt, dEt = torch.from_numpy(Ot).to(dev), torch.from_numpy(Et).to(dev)
-        with build() as mesh:
-            torch.cuda.synchronize()
-            t_tr = time.perf_counter()
-            loss, n_lab = rsi.rsi_proposal_train(mesh, dOt, dEt, epochs=args.train_epochs, batch=4096, lr=2e-3,
-                                                 seed=1)
-            t_tr = time.perf_counter() - t_tr
-            del dOt, dEt
-
-            def timed(fn, reps=3):
-                fn()
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                for _ in range(reps):
-                    fn()
-                b.record(stream)
-                torch.cuda.synchronize()
-                return a.elapsed_time(b) / reps
-
-            o = outs[args.mode]
-            ms_plain = timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision, out=o))
-            ms_plain2 = timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision, out=o,
-                                                        node_width=2))
-            ms_learned = timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=args.mode, precision=args.precision,
-                                                         out=o, proposal=True))
-            late = int(o["counters"][2].item())
-            results[f"{args.precision} + learned proposal"] = o[key][:keep].cpu().numpy().copy()
-            n_hit = int(o["hit"].sum().item()) if args.mode == "boolean" else int((o["tri_id"] >= 0).sum().item())
-            ms_mlp = timed(lambda: rsi.rsi_proposal_predict(mesh, dO, dE))
-            # the proposal order walks binary nodes: compare node fetches on binary nodes
-            v_p, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision, node_width=2)
-            v_l, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode=args.mode, precision=args.precision, proposal=True)
-            learned = {
-                "train_segments": args.train_rays, "labelled": n_lab, "epochs": args.train_epochs,
-                "train_s": round(t_tr, 2), "epoch_loss": [round(x, 4) for x in loss.tolist()],
-                # GEMM work per labelled segment and epoch: forward 2 x 253,952, weight
-                # gradients the same, input gradients 2 x 3 x 65,536 FLOP; over train_s,
-                # which includes labelling the segments
-                "train_tflops": round(args.train_epochs * n_lab * (4 * 253952 + 6 * 65536) / t_tr / 1e12, 2),
-                "proposal_miss_rate": round(late / max(n_hit, 1), 4),
-                "intersect_mrays_s_plain_order": round(n / (ms_plain * 1e-3) / 1e6, 1),
-                "intersect_mrays_s_plain_order_binary_nodes": round(n / (ms_plain2 * 1e-3) / 1e6, 1),
-                "intersect_mrays_s_learned": round(n / (ms_learned * 1e-3) / 1e6, 1),
-                "mlp_inference_ms": round(ms_mlp, 3),
-                "mlp_tflops": round(n * 2 * 253952 / (ms_mlp * 1e-3) / 1e12, 1),
-                "mean_binary_node_visits_plain_order": round(float(v_p.double().mean().item()), 2),
-                "mean_binary_node_visits_learned": round(float(v_l.double().mean().item()), 2),
-                "mode": args.mode, "precision": args.precision,
-            }
+        learned = learned_leg(rsi, dV, dF, Ot, Et, dO, dE, outs[args.mode], args.mode, args.precision, args.build,
+                              args.train_epochs, stream)
+        del Ot, Et
+        if learned.pop("_result", None) is not None:
+            results[f"{args.precision} + learned proposal"] = outs[args.mode][key][:keep].cpu().numpy().copy()
+        learned["workload"] = "the headline mesh and segments; proposal trained on other segments of the same box"
         print(f"[bench] learned: {learned}", file=sys.stderr, flush=True)
+    learned_c5 = None
+    if not args.no_learned and not args.no_c5 and args.mode == "boolean":
+        learned_c5 = learned_form(rsi, workloads, args, stream)
+        print(f"[bench] learned form: {learned_c5}", file=sys.stderr, flush=True)
 
     # ---------------- host-resident runs: host arrays in, host results out (PCIe included)
     host = None
@@ -531,9 +590,23 @@ def main():
         if args.mode == "barycentric":
             bout["uvt"] = torch.empty((nb, 3), dtype=torch.float32, device=dev)
         with rsi.rsi_batch_create(vo, to, ro) as b:
+            # launch choices tuned once for this size class (untimed), then captured
+            rsi.rsi_batch_build(b, dVb, dFb)
+            from paper_2305_01867_amd import autotune
+            space = {"block": (256, 512, 1024), "stack_depth": (12, 16, 20, 24), "waves_per_cu": (0, 8, 16),
+                     "ray_sort": (0, 1, 2), "node_width": (0, 2)}
+            run = lambda **c: rsi.rsi_batch_intersect(b, dOb, dEb, mode=args.mode, precision=args.precision,
+                                                      out=bout, **c)
+            key = autotune.size_class(args.mode, args.precision, 64, Fb.shape[0], nb)
+            choice, timings = autotune.tune(run, key, None, space=space, reps=2)
+            choice = {k: v for k, v in choice.items() if k != "ms"}
+            ms_default = min(t["ms"] for t in timings if t["block"] == 1024 and t["stack_depth"] == 20
+                             and t["waves_per_cu"] == 0 and t["ray_sort"] == 0 and t["node_width"] == 0)
+            ms_binary = min(t["ms"] for t in timings if t["node_width"] == 2)
+
             def bstep():
                 rsi.rsi_batch_build(b, dVb, dFb)
-                rsi.rsi_batch_intersect(b, dOb, dEb, mode=args.mode, precision=args.precision, out=bout)
+                rsi.rsi_batch_intersect(b, dOb, dEb, mode=args.mode, precision=args.precision, out=bout, **choice)
             bstep()
             torch.cuda.synchronize()
             g = torch.cuda.CUDAGraph()
@@ -556,7 +629,11 @@ def main():
             batched = {"workload": f"64 heightfields, {Fb.shape[0]} triangles, {nb} segments",
                        "graph_replay_ms": round(ms_b, 3), "mrays_s": round(nb / (ms_b * 1e-3) / 1e6, 1),
                        "redecided_fp64": int(bout["counters"][0].item()), "mode": args.mode,
-                       "precision": args.precision}
+                       "precision": args.precision, "tuned_choice": choice,
+                       "tuned_over": f"{len(timings)} launch choices, intersect only",
+                       "intersect_ms_tuned": round(min(t["ms"] for t in timings), 3),
+                       "intersect_ms_library_default": round(ms_default, 3),
+                       "intersect_ms_best_binary_nodes": round(ms_binary, 3)}
         print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
         del dVb, dFb, dOb, dEb, bout
 
@@ -605,6 +682,7 @@ def main():
         "hit_fraction": hit_frac,
         "variants": variants,
         "learned_vs_plain": learned,
+        "learned_form": learned_c5,
         "batched": batched,
         "host_resident": host,
     }

@@ -567,8 +567,10 @@ def rsi_batch_build(batch: Batch, vertices: torch.Tensor, triangles: torch.Tenso
 
 def rsi_batch_intersect(batch: Batch, rays_from, rays_to, mode: str = "boolean", precision: str = "plain",
                         block: int = 0, stack_depth: int = 0, out: dict | None = None, stream=None,
-                        ray_sort=0, waves_per_cu: int = 0) -> dict:
-    """Outputs over all segments (triangle indices relative to each mesh)."""
+                        ray_sort=0, waves_per_cu: int = 0, node_width: int = 0) -> dict:
+    """Outputs over all segments (triangle indices relative to each mesh).
+    node_width: 0 the 4-wide tree (built for batches of more than one
+    triangle), 2 binary nodes, 4 the 4-wide tree."""
     if mode not in MODES:
         raise ValueError(f"mode must be one of {list(MODES)}")
     n = _rays(rays_from, rays_to)
@@ -590,7 +592,7 @@ def rsi_batch_intersect(batch: Batch, rays_from, rays_to, mode: str = "boolean",
         return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()
 
     o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"), ptr("count"))
-    opts = _iopts(precision, block, stack_depth, False, ray_sort, waves_per_cu)
+    opts = _iopts(precision, block, stack_depth, False, ray_sort, waves_per_cu, node_width)
     _check(lib().rsi_batch_intersect(batch.handle, _p(rays_from), _p(rays_to), MODES[mode], ctypes.byref(opts),
                                      ctypes.byref(o), _stream_handle(stream)))
     return out

@@ -366,8 +366,6 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
         return fail(RSI_E_STATE, "proposal = 1 needs a trained or loaded proposal (rsi_proposal_train / _load)");
     if (width == 4 && mesh->dev.node_width != 4)
         return fail(RSI_E_ARG, "node_width = 4 needs a mesh built with algorithm 0 or 2 (more than one triangle)");
-    if (width == 4 && use_prop)
-        return fail(RSI_E_ARG, "the proposal order runs on binary nodes (node_width 0 or 2)");
     if (!stats) {
         if (!out)
             return fail(RSI_E_ARG, "out must not be NULL");
@@ -710,6 +708,9 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     const size_t sz_V = round_up(12 * (size_t)nv + 4), sz_F = round_up(12 * (size_t)nt + 4);
     const size_t sz_keys = round_up(8 * (size_t)nt + 8), sz_ids = round_up(4 * (size_t)nt + 4);
     const size_t sz_nodes = round_up(64 * (size_t)(nt > 1 ? nt - 1 : 1));
+    // the 4-wide tree (top slots, then one slot per binary internal node)
+    const size_t sz_nodes4 = nt > 1 ? round_up(128 * (size_t)(nt - 1 + rsi::kTopSlots)) : 0;
+    const size_t sz_roots4 = round_up(4 * (size_t)M) + round_up(4 * (size_t)rsi::kTopSlots);
     const size_t sz_par = round_up(4 * (size_t)(nt > 0 ? 2 * nt - 1 : 1)), sz_cnt = round_up(4 * (size_t)(nt > 1 ? nt - 1 : 1));
     const size_t sz_tris = round_up(48 * (size_t)nt + 48), sz_small = 256;
     const size_t sz_tmp = round_up(rsi::sort_tmp_bytes(nt, 63));
@@ -718,8 +719,8 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     const size_t sz_items = round_up(16 * (size_t)(b.n_items + 1));
     const size_t sz_q = round_up(4 * (size_t)b.n_rays + 4) + 256;
     const size_t sz_order = round_up(rsi::ray_sort_ws_bytes(b.n_rays));
-    const size_t total = sz_V + sz_F + sz_keys + sz_ids + sz_nodes + sz_par + sz_cnt + sz_tris + sz_small + sz_tmp +
-                         sz_off + sz_tm + sz_mb + sz_items + sz_q + sz_order;
+    const size_t total = sz_V + sz_F + sz_keys + sz_ids + sz_nodes + sz_nodes4 + sz_roots4 + sz_par + sz_cnt +
+                         sz_tris + sz_small + sz_tmp + sz_off + sz_tm + sz_mb + sz_items + sz_q + sz_order;
     hipError_t e = hipMallocAsync(&bt->block, total, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -738,6 +739,10 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     d.keys = take(sz_keys);
     d.ids = reinterpret_cast<int32_t *>(take(sz_ids));
     d.nodes = reinterpret_cast<rsi::Node *>(take(sz_nodes));
+    d.top4 = sz_nodes4 ? reinterpret_cast<rsi::Node4 *>(take(sz_nodes4)) : nullptr;
+    d.nodes4 = d.top4 ? d.top4 + rsi::kTopSlots : nullptr;
+    b.roots4 = reinterpret_cast<int32_t *>(take(round_up(4 * (size_t)M)));
+    b.slot_bin = reinterpret_cast<int32_t *>(take(round_up(4 * (size_t)rsi::kTopSlots)));
     d.parent = reinterpret_cast<int32_t *>(take(sz_par));
     d.counters = reinterpret_cast<int32_t *>(take(sz_cnt));
     d.tris = reinterpret_cast<rsi::Tri *>(take(sz_tris));
@@ -825,8 +830,8 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
         return st;
     if (opts && opts->proposal)
         return fail(RSI_E_ARG, "the batched form has no learned proposal");
-    if (width == 4)
-        return fail(RSI_E_ARG, "the batched form traverses binary nodes (node_width 0 or 2)");
+    if (width == 4 && batch->dev.node_width != 4)
+        return fail(RSI_E_ARG, "node_width = 4 needs a batch of more than one triangle");
     if (!out)
         return fail(RSI_E_ARG, "out must not be NULL");
     if (n > 0 && (!rays_from || !rays_to || !aligned4(rays_from) || !aligned4(rays_to)))
@@ -865,6 +870,7 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
     a.n_items = b.n_items;
     a.n_meshes = b.M;
     a.mesh_root = b.roots;
+    a.mesh_root4 = batch->dev.node_width == 4 ? b.roots4 : nullptr;
     a.mesh_toff = b.mesh_toff;
     a.ray_off = b.r_off;
     if (ray_sort != RSI_RAY_ORDER_INPUT) {
@@ -929,7 +935,11 @@ static rsi_status ensure_proposal(rsi_mesh mesh, hipStream_t s, uint64_t seed, b
         const size_t wb = round_up(2 * (size_t)rsi::kMlpWeights);
         const size_t small = round_up(4 * 256) * 2 + 256;
         const size_t rk = round_up(4 * (size_t)d.nt), lbk = round_up((size_t)d.nt);
-        hipError_t e = hipMallocAsync(&pr.block, 4 * f + wb + small + rk + lbk, s);
+        // the proposal order's 4-wide tree, where the mesh has one
+        const bool wide = d.node_width == 4 && d.nt > 1;
+        const size_t w4 = wide ? sizeof(rsi::Node4) * (size_t)(rsi::kTopSlots + d.nt - 1) : 0;
+        const size_t wsmall = wide ? round_up(4 * 256) + round_up(4 * rsi::kTopSlots) + 2 * rk : 0;
+        hipError_t e = hipMallocAsync(&pr.block, 4 * f + wb + small + rk + lbk + w4 + wsmall, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             pr.block = nullptr;
@@ -945,8 +955,17 @@ static rsi_status ensure_proposal(rsi_mesh mesh, hipStream_t s, uint64_t seed, b
         pr.bucket_first = reinterpret_cast<int32_t *>(p); p += round_up(4 * 256);
         pr.dev_n_buckets = reinterpret_cast<int32_t *>(p); p += 256;
         pr.rank = reinterpret_cast<int32_t *>(p); p += rk;
-        pr.leaf_bucket = reinterpret_cast<uint8_t *>(p);
+        pr.leaf_bucket = reinterpret_cast<uint8_t *>(p); p += lbk;
+        if (wide) {
+            pr.top4 = reinterpret_cast<rsi::Node4 *>(p); p += w4;
+            pr.bucket_ref4 = reinterpret_cast<int32_t *>(p); p += round_up(4 * 256);
+            pr.slot_bin = reinterpret_cast<int32_t *>(p); p += round_up(4 * rsi::kTopSlots);
+            pr.wide_flag = reinterpret_cast<int32_t *>(p); p += rk;
+            pr.wide_queue = reinterpret_cast<int32_t *>(p);
+        }
         e = rsi::proposal_frontier(d, pr, s);
+        if (e == hipSuccess && wide)
+            e = rsi::launch_collapse_proposal(d, pr, s);
         int32_t nb = 0;
         if (e == hipSuccess)
             e = hipMemcpyAsync(&nb, pr.dev_n_buckets, 4, hipMemcpyDeviceToHost, s);

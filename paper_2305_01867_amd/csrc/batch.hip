@@ -160,7 +160,8 @@ hipError_t launch_batch_build(MeshDev &m, BatchDev &b, const float *V, const int
     if (e != hipSuccess)
         return e;
     k_mesh_roots<<<blocks(m.nt, 256), 256, 0, s>>>(m.nodes, static_cast<const uint64_t *>(m.keys), m.nt, b.roots);
-    return hipGetLastError();
+    e = hipGetLastError();
+    return e == hipSuccess ? launch_collapse_batch(m, b, s) : e;
 }
 
 }  // namespace rsi

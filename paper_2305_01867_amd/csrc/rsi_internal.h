@@ -81,6 +81,14 @@ struct Proposal {
     int32_t *dev_n_buckets = nullptr; // [1]
     int32_t *rank = nullptr;          // [nt] sorted position of each triangle
     uint8_t *leaf_bucket = nullptr;   // [nt] bucket of each sorted leaf
+    // 4-wide tree of the proposal order (meshes with a 4-wide tree): the
+    // plain collapse with every frontier node starting a 4-wide node of its
+    // own, laid out as the mesh's (kTopSlots top slots, then nt - 1 slots)
+    Node4 *top4 = nullptr;
+    int32_t *bucket_ref4 = nullptr;   // [256] frontier node reference per bucket in that tree
+    int32_t *slot_bin = nullptr;      // [kTopSlots] binary index of each top slot
+    int32_t *wide_flag = nullptr;     // [nt] collapse flags
+    int32_t *wide_queue = nullptr;    // [nt] collapse queue
     void *block = nullptr;
 };
 
@@ -116,6 +124,8 @@ struct BatchDev {
     int32_t *r_off = nullptr;                    // device [M + 1] first segment of each mesh
     int32_t *mesh_toff = nullptr;                // device [M] first triangle of each mesh
     int32_t *roots = nullptr;                    // device [M] subtree root (INT32_MIN: empty)
+    int32_t *roots4 = nullptr;                   // device [M] the same as 4-wide references
+    int32_t *slot_bin = nullptr;                 // device [kTopSlots] binary node of each top slot
     int32_t *tri_mesh = nullptr;                 // device [nt]
     float *mesh_bounds = nullptr;                // device [M][8]
     int4 *items = nullptr;                       // device [n_items] (mesh, first, end, 0)
@@ -127,6 +137,7 @@ struct BatchDev {
     int64_t n_rays = 0;
 };
 hipError_t launch_batch_build(MeshDev &m, BatchDev &b, const float *V, const int32_t *F, hipStream_t s);
+hipError_t launch_collapse_batch(MeshDev &m, BatchDev &b, hipStream_t s);  // wide.hip
 
 // Build steps (build.hip).  All asynchronous on `s`.
 hipError_t launch_build(MeshDev &m, const float *V, const int32_t *F, hipStream_t s, size_t sort_tmp_bytes);
@@ -136,6 +147,7 @@ hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s);
 // tile list the radix-tree kernel left in m.sort_tmp.
 hipError_t launch_restructure(MeshDev &m, int rounds, hipStream_t s);
 hipError_t launch_collapse(MeshDev &m, hipStream_t s);  // wide.hip: the 4-wide tree
+hipError_t launch_collapse_proposal(const MeshDev &m, Proposal &pr, hipStream_t s);  // ... of the proposal order
 
 // Lists kept in a mesh's sort scratch once the sort is done: the tile count
 // and tile list of the radix-tree kernel (subtrees of at most 1024 leaves),
@@ -199,6 +211,7 @@ struct TraverseArgs {
     int n_items = 0;
     int n_meshes = 0;
     const int32_t *mesh_root = nullptr;   // subtree root per mesh (INT32_MIN: empty)
+    const int32_t *mesh_root4 = nullptr;  // the same in the 4-wide tree (NULL: binary nodes only)
     const int32_t *mesh_toff = nullptr;   // first triangle of each mesh
     const int32_t *ray_off = nullptr;     // [n_meshes + 1] first segment of each mesh
     // segment order: 0 input order, 1 Morton code of the midpoint, 2 direction

@@ -297,9 +297,11 @@ struct TravParams {
     int n_items;
     int n_meshes;
     const int32_t *mesh_root;
+    const int32_t *mesh_root4;  // the mesh roots as 4-wide references (first pass over 4-wide nodes)
     const int32_t *mesh_toff;
     const int32_t *ray_off;
     const int32_t *order;  // segment at each processing position (NULL: input order)
+    int stage_ok;          // boolean results may be staged per wave (4-byte aligned output)
     int deep_cap;          // second pass: entries of a lane's private stack (<= kDeepStack)
     int wave_cap;          // second pass: entries of a wave's shared stack (<= its LDS array)
 };
@@ -356,6 +358,16 @@ constexpr int kPend = 2;
 constexpr int kDefaultWavesPerCU = 16;
 constexpr int kDone = INT32_MIN;  // nothing left for the lane's segment
 
+// Boolean results of one mesh in input order are staged per wave in LDS and
+// written out a window of kStageWin segments at a time (whole lines instead
+// of single bytes as segments finish): two windows per wave, each a value
+// and a done bitmap and a count of finished segments.  A wave's range starts
+// at a multiple of 4, so a window's groups of four are 4-byte aligned (a
+// coarser alignment would unbalance the waves' ranges).
+constexpr int kStageWin = 256;
+constexpr int kStageWords = 2 * kStageWin / 32 + 1;  // value bits, done bits, count
+constexpr int kStageWaveWords = 2 * kStageWords + 2;  // two windows, padded to 16 bytes
+
 // PROP: proposal-first order.  Phase 0 traverses the predicted frontier
 // subtree; phase 1 the whole tree with that subtree left out.  Together they
 // visit exactly what the plain order visits, so results do not change.
@@ -385,8 +397,62 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     const bool batch = p.items != nullptr;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // boolean results staged in LDS (one mesh, input order, 4-byte aligned output)
+    const bool stage = MODE == MODE_BOOL && !STATS && !batch && p.order == nullptr && p.stage_ok;
     int64_t cursor = batch ? 0 : p.n * wave_id / waves;
     int64_t range_end = batch ? 0 : p.n * (wave_id + 1) / waves;
+    if (stage) {  // ranges start at multiples of 4
+        cursor &= ~int64_t(3);
+        range_end = wave_id + 1 == waves ? p.n : (range_end & ~int64_t(3));
+    }
+    uint32_t *stage_w = nullptr;  // this wave's two windows
+    int64_t win_base = cursor;    // first segment of the older window
+    int win_old = 0;              // which of the two holds the older window
+    if (stage) {
+        // after the stacks (stack_depth + 3 entries per lane with 4-wide nodes,
+        // + 1 with binary ones) and the top nodes
+        stage_w = reinterpret_cast<uint32_t *>(lds_stack + (p.stack_depth + (WIDE ? 3 : 1)) * stride +
+                                               32 * p.top_lds) +
+                  (threadIdx.x >> 6) * kStageWaveWords;
+        if (lane < kStageWaveWords)
+            stage_w[lane] = 0u;
+    }
+    // write the finished entries of the older window (all of them once its
+    // count is complete) and make the newer one the older
+    auto stage_flush = [&]() {
+        const uint32_t *W = stage_w + win_old * kStageWords;
+        const int j = 4 * lane;
+        const uint32_t v = (W[j >> 5] >> (j & 31)) & 0xfu, d = (W[8 + (j >> 5)] >> (j & 31)) & 0xfu;
+        const int64_t i = win_base + j;
+        if (d == 0xfu && i + 3 < range_end) {
+            const uint32_t word = (v & 1u) | ((v >> 1) & 1u) << 8 | ((v >> 2) & 1u) << 16 | ((v >> 3) & 1u) << 24;
+            *reinterpret_cast<uint32_t *>(p.out.hit + i) = word;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (((d >> k) & 1u) && i + k < range_end)
+                    p.out.hit[i + k] = (uint8_t)((v >> k) & 1u);
+        }
+        if (lane < kStageWords)
+            stage_w[win_old * kStageWords + lane] = 0u;  // read above by every lane first (in wave order)
+        win_base += kStageWin;
+        win_old ^= 1;
+    };
+    // a finished boolean segment: into its window, or straight out if its
+    // window has been written already (a segment that outlasted it)
+    auto put_hit = [&](int64_t i, uint32_t v) {
+        const int64_t off = i - win_base;
+        if (stage && off >= 0 && off < 2 * kStageWin) {
+            uint32_t *W = stage_w + ((win_old + (int)(off >> 8)) & 1) * kStageWords;
+            const int j = (int)(off & (kStageWin - 1));
+            if (v)
+                atomicOr(W + (j >> 5), 1u << (j & 31));
+            atomicOr(W + 8 + (j >> 5), 1u << (j & 31));
+            atomicAdd(W + 16, 1u);
+        } else {
+            p.out.hit[i] = (uint8_t)v;
+        }
+    };
     bool items_left = batch;
     int cur_root = p.root, cur_toff = 0;
     int lane_root = p.root, lane_toff = 0;  // of the lane's current segment
@@ -446,7 +512,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                 const int4 it = p.items[k];
                 cursor = it.y;
                 range_end = it.z;
-                cur_root = p.mesh_root[it.x];
+                cur_root = WIDE ? p.mesh_root4[it.x] : p.mesh_root[it.x];
                 cur_toff = p.mesh_toff[it.x];
             } else {
                 items_left = false;
@@ -454,6 +520,8 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
         }
         if (cursor < range_end && idle && (__popcll(idle) >= kRefillMin || idle == ~0ull)) {
             const int cnt = __popcll(idle);
+            if (stage && cursor + cnt > win_base + 2 * kStageWin)
+                stage_flush();  // the older window waits on a slow segment: write what is done
             const int64_t base = cursor;
             cursor = base + cnt < range_end ? base + cnt : range_end;
             if (ray < 0) {
@@ -486,6 +554,10 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                             p.tests[ray] = 0;
                         } else if (CERT) {
                             enqueue(p, ray, 0);
+                            if (MODE == MODE_BOOL)
+                                put_hit(ray, 0u);  // written again by the second pass
+                        } else if (MODE == MODE_BOOL) {
+                            put_hit(ray, 0u);
                         } else {
                             write_out(p.out, ray, MODE, -1, 0.0f, 0.0f, 0.0f);
                         }
@@ -572,11 +644,17 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                             ch = *reinterpret_cast<const int4 *>(c + 96);
                         }
                         float k0, k1, k2, k3;
-                        const bool h0 = slab_nf(nx.x, fx.x, ny.x, fy.x, nz.x, fz.x, r.inv, nn, nf, tlimit, k0);
-                        const bool h1 = slab_nf(nx.y, fx.y, ny.y, fy.y, nz.y, fz.y, r.inv, nn, nf, tlimit, k1);
-                        const bool h2 = slab_nf(nx.z, fx.z, ny.z, fy.z, nz.z, fz.z, r.inv, nn, nf, tlimit, k2);
-                        const bool h3 = slab_nf(nx.w, fx.w, ny.w, fy.w, nz.w, fz.w, r.inv, nn, nf, tlimit, k3);
+                        bool h0 = slab_nf(nx.x, fx.x, ny.x, fy.x, nz.x, fz.x, r.inv, nn, nf, tlimit, k0);
+                        bool h1 = slab_nf(nx.y, fx.y, ny.y, fy.y, nz.y, fz.y, r.inv, nn, nf, tlimit, k1);
+                        bool h2 = slab_nf(nx.z, fx.z, ny.z, fy.z, nz.z, fz.z, r.inv, nn, nf, tlimit, k2);
+                        bool h3 = slab_nf(nx.w, fx.w, ny.w, fy.w, nz.w, fz.w, r.inv, nn, nf, tlimit, k3);
                         int c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
+                        if (PROP) {  // in phase 1 the proposed subtree is done already
+                            h0 = h0 && c0 != skip;
+                            h1 = h1 && c1 != skip;
+                            h2 = h2 && c2 != skip;
+                            h3 = h3 && c3 != skip;
+                        }
                         const int nh = (int)h0 + (int)h1 + (int)h2 + (int)h3;
                         if (MODE != MODE_COUNT) {
                             // nearest first: a boolean segment meets a hit
@@ -791,14 +869,13 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                 else
                     write_count(p.out, ray, nk);
             } else if (MODE == MODE_BOOL) {
-                if (found)
-                    p.out.hit[ray] = 1;
-                else if (overflow)
+                // a queued segment counts as finished here (0); the second
+                // pass writes its result after this kernel
+                if (!found && overflow)
                     enqueue(p, ray, 1);
-                else if (CERT && unsure)
+                else if (!found && CERT && unsure)
                     enqueue(p, ray, 0);
-                else
-                    p.out.hit[ray] = 0;
+                put_hit(ray, found ? 1u : 0u);
             } else if (overflow) {
                 enqueue(p, ray, 1);
             } else if (CERT && flagged) {
@@ -818,6 +895,20 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
             }
             ray = -1;
         }
+        if (stage) {  // a complete older window goes out whole (then perhaps the next one)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int64_t need = range_end - win_base < kStageWin ? range_end - win_base : kStageWin;
+                if (need > 0 && stage_w[win_old * kStageWords + 16] == (uint32_t)need)
+                    stage_flush();
+            }
+        }
+    }
+    if (stage) {  // every segment is finished: whatever is left in the windows
+        if (win_base < range_end)
+            stage_flush();
+        if (win_base < range_end)
+            stage_flush();
     }
     if (PROP && !STATS) {
         // one atomic per wave: a shared counter across eight XCDs is costly
@@ -1393,21 +1484,26 @@ void launch_pass1(const TravParams &p, int block, hipStream_t s) {
         (void)hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     // a workgroup whose stacks do not fit in LDS runs with fewer threads
     const size_t lane_bytes = (size_t)(p.stack_depth + (WIDE ? 3 : 1)) * sizeof(int);
-    while (block > 64 && lane_bytes * block > (size_t)lds_block)
+    // the boolean staging windows (per wave), after the stacks and the top nodes
+    const bool staged = MODE == MODE_BOOL && !STATS && p.stage_ok && p.items == nullptr && p.order == nullptr;
+    const size_t wave_stage = staged ? kStageWaveWords * sizeof(uint32_t) : 0;
+    while (block > 64 && lane_bytes * block + wave_stage * (block / 64) > (size_t)lds_block)
         block /= 2;
     const size_t stack_bytes = lane_bytes * block;
+    const size_t stage_bytes = wave_stage * (size_t)(block / 64);
     TravParams q = p;
     q.top_lds = 0;
+    q.stage_ok = stage_bytes > 0 ? 1 : 0;
     if (WIDE) {
         int blocks_cu = p.waves_per_cu / (block / 64);
         blocks_cu = blocks_cu < 1 ? 1 : blocks_cu;
         int64_t room = lds_cu / blocks_cu;
         room = room < lds_block ? room : lds_block;
-        room -= (int64_t)stack_bytes;
+        room -= (int64_t)(stack_bytes + stage_bytes);
         const int64_t slots = room > 0 ? room / (int64_t)sizeof(Node4) : 0;
         q.top_lds = (int)(slots < kTopSlots ? slots : kTopSlots);
     }
-    const size_t lds = stack_bytes + (size_t)q.top_lds * sizeof(Node4);
+    const size_t lds = stack_bytes + (size_t)q.top_lds * sizeof(Node4) + stage_bytes;
     void (*kern)(TravParams) = nullptr;
     if constexpr (MODE == MODE_COUNT)
         kern = &k_traverse_count<CERT, STATS, WIDE>;
@@ -1427,24 +1523,22 @@ void launch_pass1(const TravParams &p, int block, hipStream_t s) {
     kern<<<grid, block, lds, s>>>(q);
 }
 
-// The 4-wide tree serves the plain order only (the proposal's subtrees are
-// binary nodes); make_params leaves nodes4 NULL otherwise.
+// make_params leaves nodes4 NULL where the binary tree is walked; with the
+// proposal order it names the proposal's own 4-wide tree.
+template <int MODE, bool STATS, bool CERT>
+void dispatch_order(const TravParams &p, bool prop, int block, hipStream_t s) {
+    const bool wide = p.nodes4 != nullptr;
+    if (prop)
+        wide ? launch_pass1<MODE, CERT, STATS, true, true>(p, block, s)
+             : launch_pass1<MODE, CERT, STATS, true, false>(p, block, s);
+    else
+        wide ? launch_pass1<MODE, CERT, STATS, false, true>(p, block, s)
+             : launch_pass1<MODE, CERT, STATS, false, false>(p, block, s);
+}
+
 template <int MODE, bool STATS>
 void dispatch_mode(const TravParams &p, bool cert, bool prop, int block, hipStream_t s) {
-    const bool wide = p.nodes4 != nullptr && !prop;
-    if (cert) {
-        if (prop)
-            launch_pass1<MODE, true, STATS, true, false>(p, block, s);
-        else
-            wide ? launch_pass1<MODE, true, STATS, false, true>(p, block, s)
-                 : launch_pass1<MODE, true, STATS, false, false>(p, block, s);
-    } else {
-        if (prop)
-            launch_pass1<MODE, false, STATS, true, false>(p, block, s);
-        else
-            wide ? launch_pass1<MODE, false, STATS, false, true>(p, block, s)
-                 : launch_pass1<MODE, false, STATS, false, false>(p, block, s);
-    }
+    cert ? dispatch_order<MODE, STATS, true>(p, prop, block, s) : dispatch_order<MODE, STATS, false>(p, prop, block, s);
 }
 
 template <bool STATS>
@@ -1467,10 +1561,20 @@ void dispatch_pass1(const TravParams &p, int mode, bool cert, int block, hipStre
 TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     TravParams p;
     p.nodes = m.nodes;
-    // the 4-wide tree for one mesh in the plain order, unless binary nodes are asked for
-    p.nodes4 = (m.node_width == 4 && a.node_width != 2 && a.items == nullptr && a.bucket == nullptr) ? m.nodes4
-                                                                                                      : nullptr;
-    p.top4 = p.nodes4 ? m.top4 : nullptr;
+    // the 4-wide tree for one mesh unless binary nodes are asked for: the
+    // mesh's own in the plain order, the proposal's (frontier nodes start
+    // 4-wide nodes) in the proposal order
+    const bool wide = m.node_width == 4 && a.node_width != 2 && (a.items == nullptr || a.mesh_root4 != nullptr);
+    if (wide && a.bucket == nullptr) {
+        p.nodes4 = m.nodes4;
+        p.top4 = m.top4;
+    } else if (wide && m.prop.top4 != nullptr) {
+        p.nodes4 = m.prop.top4 + kTopSlots;
+        p.top4 = m.prop.top4;
+    } else {
+        p.nodes4 = nullptr;
+        p.top4 = nullptr;
+    }
     p.top_lds = 0;
     p.bary_after = (a.mode == MODE_BARY && a.certified && a.items == nullptr && a.uvt != nullptr) ? 1 : 0;
     p.tris = m.tris;
@@ -1493,14 +1597,16 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.visits = a.visits;
     p.tests = a.tests;
     p.bucket = a.bucket;
-    p.bucket_ref = a.bucket_ref;
+    p.bucket_ref = p.nodes4 && a.bucket ? m.prop.bucket_ref4 : a.bucket_ref;
     p.items = a.items;
     p.n_items = a.n_items;
     p.n_meshes = a.n_meshes;
     p.mesh_root = a.mesh_root;
+    p.mesh_root4 = p.nodes4 ? a.mesh_root4 : nullptr;
     p.mesh_toff = a.mesh_toff;
     p.ray_off = a.ray_off;
     p.order = nullptr;
+    p.stage_ok = (reinterpret_cast<uintptr_t>(a.hit) & 3u) == 0 ? 1 : 0;
     p.deep_cap = kDeepStack;
     p.wave_cap = a.mode == MODE_COUNT ? kWaveCap<MODE_COUNT> : kWaveCap<MODE_BOOL>;
     // RSI_DEBUG_PASS2_STACK=k (2..kDeepStack) shrinks both second-pass stacks

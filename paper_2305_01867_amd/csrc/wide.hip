@@ -40,10 +40,13 @@ __device__ __forceinline__ void children_of(const Node *__restrict__ nodes, int 
 }
 
 // Collapse the binary subtree at r into nodes4[r]; returns the internal
-// children that start 4-wide nodes below (stopped ones excluded: they are
-// started by another workgroup).
+// children that start 4-wide nodes below.  flag (may be NULL) marks nodes:
+// one whose flag shares a bit with no_open is never opened (it starts a
+// 4-wide node of its own); one whose flag shares a bit with no_start is not
+// returned either (another workgroup starts it).
 __device__ __forceinline__ int collapse_node(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4, int r,
-                                             const int32_t *__restrict__ stop, int kids[4]) {
+                                             const int32_t *__restrict__ flag, int no_open, int no_start,
+                                             int kids[4]) {
     int ref[4] = {0, 0, kEmptyChild, kEmptyChild};
     float b[4][6];
 #pragma unroll
@@ -59,7 +62,7 @@ __device__ __forceinline__ int collapse_node(const Node *__restrict__ nodes, Nod
         float best_a = -1.0f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const bool open = i < m && ref[i] >= 0 && !(stop && stop[ref[i]]);
+            const bool open = i < m && ref[i] >= 0 && !(flag && (flag[ref[i]] & no_open));
             const float a = half_area6(b[i]);
             if (open && a > best_a) {
                 best_a = a;
@@ -108,7 +111,7 @@ __device__ __forceinline__ int collapse_node(const Node *__restrict__ nodes, Nod
     int nk = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const bool go = ref[i] >= 0 && !(stop && stop[ref[i]]);
+        const bool go = ref[i] >= 0 && !(flag && (flag[ref[i]] & no_start));
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (go && k == nk)
@@ -138,7 +141,8 @@ __global__ void k_mark_tiles(const int32_t *__restrict__ tiles, const int32_t *_
 // 4-wide node of the current level.
 __global__ __launch_bounds__(256) void k_collapse_tiles(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
                                                         const int32_t *__restrict__ tiles,
-                                                        const int32_t *__restrict__ n_tiles) {
+                                                        const int32_t *__restrict__ n_tiles,
+                                                        const int32_t *__restrict__ flag, int no_open) {
     __shared__ int q[kTileQueue];
     __shared__ int qn;
     const int total = *n_tiles;
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(256) void k_collapse_tiles(const Node *__restrict__
         while (b0 < b1) {
             for (int i = b0 + (int)threadIdx.x; i < b1; i += blockDim.x) {
                 int kids[4];
-                const int nk = collapse_node(nodes, nodes4, q[i], nullptr, kids);
+                const int nk = collapse_node(nodes, nodes4, q[i], flag, no_open, 0, kids);
                 for (int k = 0; k < nk; ++k) {
                     const int slot = atomicAdd(&qn, 1);
                     if (slot < kTileQueue)
@@ -170,13 +174,17 @@ __global__ __launch_bounds__(256) void k_collapse_tiles(const Node *__restrict__
     }
 }
 
-// One workgroup: the nodes above the tiles, breadth-first from the root with
-// the queue in global scratch; tile roots are never opened.
+// One workgroup: breadth-first from the root with the queue in global
+// scratch.  The nodes above the tiles (tile roots flagged kTileRoot: never
+// opened, started by the tile workgroups), or the whole tree with the
+// frontier of the learned proposal flagged kFrontier (each frontier node
+// starts a 4-wide node, so the proposal order can start and skip it).
+constexpr int kTileRoot = 1, kFrontier = 2, kMeshRoot = 4;
 __global__ __launch_bounds__(1024) void k_collapse_top(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
-                                                       const int32_t *__restrict__ tile_flag, int32_t *queue,
-                                                       int64_t n_internal) {
+                                                       const int32_t *__restrict__ flag, int no_open, int no_start,
+                                                       int32_t *queue, int64_t n_internal) {
     __shared__ int qn;
-    if (tile_flag[0])
+    if (flag[0] & no_start)
         return;  // the whole tree is one tile
     if (threadIdx.x == 0) {
         queue[0] = 0;
@@ -187,7 +195,7 @@ __global__ __launch_bounds__(1024) void k_collapse_top(const Node *__restrict__ 
     while (b0 < b1) {
         for (int i = b0 + (int)threadIdx.x; i < b1; i += blockDim.x) {
             int kids[4];
-            const int nk = collapse_node(nodes, nodes4, queue[i], tile_flag, kids);
+            const int nk = collapse_node(nodes, nodes4, queue[i], flag, no_open, no_start, kids);
             for (int k = 0; k < nk; ++k) {
                 const int slot = atomicAdd(&qn, 1);
                 if (slot < n_internal)
@@ -205,7 +213,10 @@ __global__ __launch_bounds__(1024) void k_collapse_top(const Node *__restrict__ 
 // the root, copied into top4 with the references of children that also got a
 // slot rewritten to that slot.  Slots follow a block-wide prefix sum over each
 // level, so the layout does not depend on thread timing.
-__global__ __launch_bounds__(kTopSlots) void k_top_cache(const Node4 *__restrict__ nodes4, Node4 *__restrict__ top4) {
+// slot_bin (may be NULL) receives the binary index of the node in each slot,
+// -1 for unused slots.
+__global__ __launch_bounds__(kTopSlots) void k_top_cache(const Node4 *__restrict__ nodes4, Node4 *__restrict__ top4,
+                                                         int32_t *__restrict__ slot_bin) {
     constexpr int kWaves = kTopSlots / 64;
     __shared__ int bidx[kTopSlots];  // binary index of the node in each slot
     __shared__ int wave_sum[kWaves];
@@ -258,6 +269,43 @@ __global__ __launch_bounds__(kTopSlots) void k_top_cache(const Node4 *__restrict
         b0 = b1;
         b1 = b1 + total < kTopSlots ? b1 + total : kTopSlots;
     }
+    if (slot_bin)
+        slot_bin[tid] = tid < b1 ? bidx[tid] : -1;
+}
+
+__global__ void k_mark_frontier(const int32_t *__restrict__ bucket_ref, const int32_t *__restrict__ n_buckets,
+                                int32_t *flag, int64_t n_internal) {
+    const int b = threadIdx.x;
+    if (b < *n_buckets) {
+        const int c = bucket_ref[b];
+        if (c >= 0 && c < n_internal)
+            flag[c] |= kFrontier;
+    }
+}
+
+__global__ void k_mark_mesh_roots(const int32_t *__restrict__ roots, int M, int32_t *flag, int64_t n_internal) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < M) {
+        const int c = roots[m];
+        if (c >= 0 && c < n_internal)
+            flag[c] |= kMeshRoot;
+    }
+}
+
+// The reference under which each bucket's frontier node appears in the
+// 4-wide tree: its top slot if it has one, else binary index + kTopSlots;
+// a leaf keeps its leaf reference.
+// (The same for each mesh root of the batched form, n_buckets = NULL: count M.)
+__global__ void k_bucket_ref4(const int32_t *__restrict__ bucket_ref, const int32_t *__restrict__ n_buckets, int M,
+                              const int32_t *__restrict__ slot_bin, int32_t *__restrict__ ref4) {
+    const int b = threadIdx.x;
+    if (b >= (n_buckets ? *n_buckets : M))
+        return;
+    const int c = bucket_ref[b];
+    int r = c >= 0 ? c + kTopSlots : c;
+    for (int k = 0; k < kTopSlots; ++k)
+        r = c >= 0 && slot_bin[k] == c ? k : r;
+    ref4[b] = r;
 }
 
 }  // namespace
@@ -275,12 +323,56 @@ hipError_t launch_collapse(MeshDev &m, hipStream_t s) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t want = (m.nt + 1023) / 1024 * 2;  // tiles hold up to 1024 leaves, usually fewer
     const int grid = (int)(want < 4 * cus ? want : 4 * cus);
-    k_collapse_tiles<<<grid, 256, 0, s>>>(m.nodes, m.nodes4, L.tiles, L.n_tiles);
-    k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, m.nodes4, L.tile_flag, L.queue, n_internal);
-    k_top_cache<<<1, kTopSlots, 0, s>>>(m.nodes4, m.top4);
+    k_collapse_tiles<<<grid, 256, 0, s>>>(m.nodes, m.nodes4, L.tiles, L.n_tiles, nullptr, 0);
+    k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, m.nodes4, L.tile_flag, kTileRoot, kTileRoot, L.queue, n_internal);
+    k_top_cache<<<1, kTopSlots, 0, s>>>(m.nodes4, m.top4, nullptr);
     const hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         m.node_width = 4;
+    return e;
+}
+
+hipError_t launch_collapse_proposal(const MeshDev &m, Proposal &pr, hipStream_t s) {
+    if (m.nt < 2 || m.node_width != 4 || !pr.top4)
+        return hipSuccess;
+    const int64_t n_internal = m.nt - 1;
+    const int blocks = (int)((n_internal + 255) / 256);
+    k_clear_flags<<<blocks, 256, 0, s>>>(pr.wide_flag, n_internal);
+    k_mark_frontier<<<1, kMlpOut, 0, s>>>(pr.bucket_ref, pr.dev_n_buckets, pr.wide_flag, n_internal);
+    // one workgroup over the whole tree: a one-off set-up, not on the hot path
+    k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, pr.top4 + kTopSlots, pr.wide_flag, kFrontier, 0, pr.wide_queue,
+                                      n_internal);
+    k_top_cache<<<1, kTopSlots, 0, s>>>(pr.top4 + kTopSlots, pr.top4, pr.slot_bin);
+    k_bucket_ref4<<<1, kMlpOut, 0, s>>>(pr.bucket_ref, pr.dev_n_buckets, 0, pr.slot_bin, pr.bucket_ref4);
+    return hipGetLastError();
+}
+
+// Batched form: the collapse of the combined tree with every mesh's subtree
+// root starting a 4-wide node (never opened from above), so a segment starts
+// at its mesh root's 4-wide node.
+hipError_t launch_collapse_batch(MeshDev &m, BatchDev &b, hipStream_t s) {
+    if (m.nt < 2 || !m.nodes4 || !b.roots4) {
+        m.node_width = 2;
+        return hipSuccess;
+    }
+    const int64_t n_internal = m.nt - 1;
+    const BuildLists L = build_lists(m.sort_tmp, m.nt);
+    const int blocks = (int)((n_internal + 255) / 256);
+    k_clear_flags<<<blocks, 256, 0, s>>>(L.tile_flag, n_internal);
+    k_mark_tiles<<<blocks, 256, 0, s>>>(L.tiles, L.n_tiles, L.tile_flag, n_internal);
+    k_mark_mesh_roots<<<1, 64, 0, s>>>(b.roots, b.M, L.tile_flag, n_internal);
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t want = (m.nt + 1023) / 1024 * 2;
+    const int grid = (int)(want < 4 * cus ? want : 4 * cus);
+    k_collapse_tiles<<<grid, 256, 0, s>>>(m.nodes, m.nodes4, L.tiles, L.n_tiles, L.tile_flag, kMeshRoot);
+    k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, m.nodes4, L.tile_flag, kTileRoot | kMeshRoot, kTileRoot, L.queue,
+                                      n_internal);
+    k_top_cache<<<1, kTopSlots, 0, s>>>(m.nodes4, m.top4, b.slot_bin);
+    k_bucket_ref4<<<1, 64, 0, s>>>(b.roots, nullptr, b.M, b.slot_bin, b.roots4);
+    const hipError_t e = hipGetLastError();
+    m.node_width = e == hipSuccess ? 4 : 2;
     return e;
 }
 

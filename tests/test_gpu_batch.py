@@ -49,9 +49,10 @@ def test_batch_equals_single_mesh_and_oracle():
     with rsi.rsi_batch_create(vo, to, ro) as b:
         rsi.rsi_batch_build(b, dev(V), dev(F))
         dO, dE = dev(O), dev(E)
-        for mode in MODES:
-            for prec in ("certified", "plain"):
-                got = {k: host(v) for k, v in rsi.rsi_batch_intersect(b, dO, dE, mode=mode, precision=prec).items()}
+        for mode, prec, width in [(m, p, w) for m in MODES for p in ("certified", "plain") for w in (0, 2)]:
+            if True:
+                got = {k: host(v) for k, v in rsi.rsi_batch_intersect(b, dO, dE, mode=mode, precision=prec,
+                                                                      node_width=width).items()}
                 for m, (Vm, Fm, Om, Em) in enumerate(parts):
                     sl = slice(ro[m], ro[m + 1])
                     if len(Om) == 0:
@@ -61,7 +62,7 @@ def test_batch_equals_single_mesh_and_oracle():
                                                                         precision=prec).items()}
                     for k in one:
                         if k != "counters":
-                            assert np.array_equal(got[k][sl], one[k], equal_nan=True), (mode, prec, m, k)
+                            assert np.array_equal(got[k][sl], one[k], equal_nan=True), (mode, prec, width, m, k)
                     if prec == "certified":
                         hit, ids, uvt, _ = oracle.intersect(Vm, Fm, Om, Em) if len(Fm) else (
                             np.zeros(len(Om), np.uint8), np.full(len(Om), -1, np.int32), None, None)
@@ -180,18 +181,34 @@ def test_autotuner_picks_and_caches():
 
 def test_batched_workload_sampled():
     """64 heightfields of log-uniform size with their own segment batches
-    (~1.4e7 segments): sampled segments of every mesh against the oracle."""
+    (~1.4e7 segments), on the 4-wide tree and on binary nodes: 1000 sampled
+    segments of every mesh against the oracle in the boolean, first-hit and
+    barycentric modes (u, v, t equal to the oracle's rounded once)."""
     V, F, O, E, vo, to, ro = workloads.batched_config()
     say(f"[batch] 64 meshes, {F.shape[0]} triangles, {O.shape[0]} segments")
     rng = np.random.default_rng(1)
+    idx = [np.sort(rng.choice(np.arange(ro[m], ro[m + 1]), 1000, replace=False)) for m in range(64)]
+    want = []
+    for m in range(64):
+        Vm, Fm = V[vo[m]:vo[m + 1]], F[to[m]:to[m + 1]]
+        hit, ids, uvt, _ = oracle.intersect(Vm, Fm, O[idx[m]], E[idx[m]])
+        # the oracle's ids are per mesh; the batch reports each mesh's own indices
+        want.append((hit, ids, uvt.astype(np.float32)))
     with rsi.rsi_batch_create(vo, to, ro) as b:
         rsi.rsi_batch_build(b, dev(V), dev(F))
         dO, dE = dev(O), dev(E)
-        for mode in ("boolean", "first_hit"):
-            got = host(rsi.rsi_batch_intersect(b, dO, dE, mode=mode, precision="certified")
-                       ["hit" if mode == "boolean" else "tri_id"])
-            for m in range(64):
-                Vm, Fm = V[vo[m]:vo[m + 1]], F[to[m]:to[m + 1]]
-                idx = rng.choice(np.arange(ro[m], ro[m + 1]), 24, replace=False)
-                hit, ids, _, _ = oracle.intersect(Vm, Fm, O[idx], E[idx])
-                assert np.array_equal(got[idx], hit if mode == "boolean" else ids), (mode, m)
+        for width in (0, 2):
+            for mode in ("boolean", "first_hit", "barycentric"):
+                r = rsi.rsi_batch_intersect(b, dO, dE, mode=mode, precision="certified", node_width=width)
+                got = host(r["hit" if mode == "boolean" else "tri_id"])
+                uvt = host(r["uvt"]) if mode == "barycentric" else None
+                del r
+                for m in range(64):
+                    hit, ids, w_uvt = want[m]
+                    assert np.array_equal(got[idx[m]], hit if mode == "boolean" else ids), (width, mode, m)
+                    if uvt is not None:
+                        g = uvt[idx[m]]
+                        assert np.array_equal(np.isnan(g), np.isnan(w_uvt)), (width, m)
+                        ok = ~np.isnan(w_uvt)
+                        assert np.array_equal(g[ok], w_uvt[ok]), (width, m)
+                say(f"  width {width or 'widest'}, {mode}: 64 x 1000 segments equal the oracle")

@@ -153,22 +153,26 @@ def test_training_lowers_loss_and_keeps_results_exact():
         assert n_lab > 30000
         assert loss[0] < 1.2 * np.log(256) and loss[-1] < 0.8 * loss[0]
         dO, dE = dev(Ot), dev(Et)
-        for mode in ("boolean", "first_hit", "barycentric"):
-            for prec in ("plain", "certified"):
-                a = intersect(mesh, Ot, Et, mode, prec)
-                b = {k: host(v) for k, v in rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision=prec,
-                                                              proposal=True).items()}
-                for k in a:
-                    if k != "counters":
-                        assert np.array_equal(a[k], b[k], equal_nan=True), (mode, prec, k)
-                if prec == "certified":
-                    key = "hit" if mode == "boolean" else "tri_id"
-                    want = hit if mode == "boolean" else ids
-                    assert np.array_equal(b[key], want)
+        for width in (0, 2):  # the proposal order on its own 4-wide tree, and on binary nodes
+            for mode in ("boolean", "first_hit", "barycentric"):
+                for prec in ("plain", "certified"):
+                    a = intersect(mesh, Ot, Et, mode, prec)
+                    b = {k: host(v) for k, v in rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision=prec,
+                                                                  proposal=True, node_width=width).items()}
+                    for k in a:
+                        if k != "counters":
+                            assert np.array_equal(a[k], b[k], equal_nan=True), (width, mode, prec, k)
+                    if prec == "certified":
+                        key = "hit" if mode == "boolean" else "tri_id"
+                        want = hit if mode == "boolean" else ids
+                        assert np.array_equal(b[key], want)
         # the gain: work per segment with the trained, an untrained and no
-        # proposal, all on binary nodes (the proposal order walks binary nodes)
-        v_none, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode="boolean", node_width=2)
-        v_trained, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode="boolean", proposal=True)
+        # proposal, on 4-wide nodes (node fetches) and on binary nodes
+        visits = {}
+        for width in (4, 2):
+            visits["none", width] = rsi.rsi_traversal_stats(mesh, dO, dE, mode="boolean", node_width=width)[0]
+            visits["trained", width] = rsi.rsi_traversal_stats(mesh, dO, dE, mode="boolean", proposal=True,
+                                                               node_width=width)[0]
         got = rsi.rsi_intersect(mesh, dO, dE, mode="boolean", proposal=True)
         n_hit = int(host(got["hit"]).sum())
         miss_rate = float(host(got["counters"])[2]) / max(n_hit, 1)
@@ -178,15 +182,18 @@ def test_training_lowers_loss_and_keeps_results_exact():
             P_trained = host(rsi.rsi_proposal_params(mesh))
             buckets = host(rsi.rsi_proposal_predict(mesh, dO, dE))
             rsi.rsi_proposal_train(mesh, dO[:64], dE[:64], epochs=1, reinit=True, seed=99)
-            v_untrained, _ = rsi.rsi_traversal_stats(mesh, dO, dE, mode="boolean", proposal=True)
+            for width in (4, 2):
+                visits["untrained", width] = rsi.rsi_traversal_stats(mesh, dO, dE, mode="boolean", proposal=True,
+                                                                     node_width=width)[0]
             rsi.rsi_proposal_load(mesh, path)
             assert np.array_equal(host(rsi.rsi_proposal_params(mesh)), P_trained)
             assert np.array_equal(host(rsi.rsi_proposal_predict(mesh, dO, dE)), buckets)
-        m = [float(host(v).mean()) for v in (v_none, v_untrained, v_trained)]
-        say(f"  mean node visits: none {m[0]:.2f}, untrained {m[1]:.2f}, trained {m[2]:.2f}; "
-            f"proposal miss rate {miss_rate:.3f}")
-        assert m[2] < m[1]
-        assert m[2] < m[0]  # the trained proposal saves node visits over the plain order
+        for width in (4, 2):
+            m = [float(host(visits[k, width]).mean()) for k in ("none", "untrained", "trained")]
+            say(f"  mean node visits ({width}-wide): none {m[0]:.2f}, untrained {m[1]:.2f}, trained {m[2]:.2f}; "
+                f"proposal miss rate {miss_rate:.3f}")
+            assert m[2] < m[1]
+            assert m[2] < m[0]  # the trained proposal saves node visits over the plain order
         assert miss_rate < 0.95  # chance level is 1 - 1/(number of buckets) ~ 0.996
 
 
@@ -202,10 +209,11 @@ def test_proposal_on_a_restructured_tree():
         loss, n_lab = rsi.rsi_proposal_train(mesh, dev(O), dev(E), epochs=3, batch=2048, lr=2e-3, seed=8)
         say(f"  restructured tree: labelled {n_lab}, epoch loss {loss.tolist()}")
         assert n_lab > 20000 and loss[-1] < 0.8 * loss[0]
-        for mode, key, want in (("boolean", "hit", hit), ("first_hit", "tri_id", ids)):
-            got = host(rsi.rsi_intersect(mesh, dev(Ot), dev(Et), mode=mode, precision="certified",
-                                         proposal=True)[key])
-            assert np.array_equal(got, want), mode
+        for width in (0, 2):
+            for mode, key, want in (("boolean", "hit", hit), ("first_hit", "tri_id", ids)):
+                got = host(rsi.rsi_intersect(mesh, dev(Ot), dev(Et), mode=mode, precision="certified",
+                                             proposal=True, node_width=width)[key])
+                assert np.array_equal(got, want), (width, mode)
 
 
 def test_training_is_deterministic():
