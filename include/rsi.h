@@ -47,10 +47,10 @@
 extern "C" {
 #endif
 
-#define RSI_ABI_VERSION 6  /* 2: intercept-count mode, rsi_outputs.count; 3: waves_per_cu; 4: build algorithm;
+#define RSI_ABI_VERSION 7  /* 2: intercept-count mode, rsi_outputs.count; 3: waves_per_cu; 4: build algorithm;
                               5: 4-wide nodes (node_width, rsi_mesh_info.node_width, RSI_EXPORT_WIDE_NODES,
                               RSI_EXPORT_WIDE_TOP); 6: RSI_EXPORT_MESH_ROOTS = 9 (was 7, the value of
-                              RSI_EXPORT_WIDE_NODES), rsi_stream_copy */
+                              RSI_EXPORT_WIDE_NODES), rsi_stream_copy; 7: rsi_intersect_noalloc */
 
 typedef struct rsi_mesh_s *rsi_mesh; /* opaque; owned by the library until rsi_destroy */
 
@@ -214,6 +214,29 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices,
 rsi_status rsi_intersect(rsi_mesh mesh, const float *rays_from, const float *rays_to,
                          int64_t n_rays, int32_t mode, const rsi_intersect_opts *opts,
                          const rsi_outputs *out, void *stream);
+
+/*
+ * rsi_intersect_noalloc -- rsi_intersect for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results as
+ * rsi_intersect; the caller still provides the inputs and outputs.  The
+ * temporary memory comes from one 64 MiB device array of the library instead
+ * of an allocation, so the call allocates nothing (no hipMalloc / hipFree of
+ * any kind).  It needs 4 n_rays + 64 bytes rounded up to 256, plus n_rays
+ * rounded up to 256 with opts->proposal = 1, plus 16 n_rays with a segment
+ * order (ray_sort != 0): at most 16,777,200 segments in input order without
+ * the proposal.  A call needing more returns RSI_E_CAPACITY before any GPU
+ * work.  Every GPU the library runs on holds its own copy of the array until
+ * the process ends; the array's address on the current device is looked up
+ * the first time this is called there.  All calls on one GPU share that
+ * array: calls that may overlap on one GPU (different streams without
+ * ordering between them, or different threads) race and give wrong results;
+ * order them on one stream.  What must start at zero is cleared by the call's
+ * own first kernel.
+ */
+rsi_status rsi_intersect_noalloc(rsi_mesh mesh, const float *rays_from, const float *rays_to,
+                                 int64_t n_rays, int32_t mode, const rsi_intersect_opts *opts,
+                                 const rsi_outputs *out, void *stream);
 
 /* rsi_destroy -- free a mesh (stream-ordered on the stream it was built on).
  * NULL is accepted and ignored. */

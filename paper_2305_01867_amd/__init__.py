@@ -25,13 +25,13 @@ __all__ = [
     "rsi_proposal_features", "rsi_proposal_frontier", "rsi_proposal_save", "rsi_proposal_load",
     "MLP_PARAMS", "MLP_INPUTS", "MLP_BUCKETS",
     "Batch", "rsi_batch_create", "rsi_batch_build", "rsi_batch_intersect", "rsi_batch_export", "rsi_batch_destroy",
-    "rsi_stream_copy",
+    "rsi_stream_copy", "rsi_intersect_noalloc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "librsi.so")
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 MODES = {"boolean": 0, "first_hit": 1, "barycentric": 2, "intercept_count": 3}
 PRECISIONS = {"plain": 0, "certified": 1}
 EXPORTS = {"sorted_keys": 0, "sorted_ids": 1, "nodes": 2, "parents": 3, "counters": 4, "leaves": 5, "bounds": 6,
@@ -92,6 +92,7 @@ def lib():
     P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     L.rsi_build.argtypes = [P, I64, P, I64, ctypes.POINTER(_BuildOpts), P, ctypes.POINTER(P)]
     L.rsi_intersect.argtypes = [P, P, P, I64, I32, ctypes.POINTER(_IntersectOpts), ctypes.POINTER(_Outputs), P]
+    L.rsi_intersect_noalloc.argtypes = [P, P, P, I64, I32, ctypes.POINTER(_IntersectOpts), ctypes.POINTER(_Outputs), P]
     L.rsi_destroy.argtypes = [P]
     L.rsi_mesh_info_get.argtypes = [P, ctypes.POINTER(_MeshInfo)]
     L.rsi_mesh_export.argtypes = [P, I32, P, I64, P]
@@ -240,7 +241,7 @@ def _iopts(precision, block, stack_depth, proposal=False, ray_sort=0, waves_per_
 def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",
                   precision: str = "plain", block: int = 0, stack_depth: int = 0, out: dict | None = None,
                   stream=None, proposal: bool = False, ray_sort=0, waves_per_cu: int = 0,
-                  node_width: int = 0) -> dict:
+                  node_width: int = 0, _noalloc: bool = False) -> dict:
     """Test segments [N, 3] float32 against the mesh.  Returns a dict with the
     outputs of the mode ("hit" uint8, "tri_id" int32, "uvt" float32 [N, 3],
     "count" int32) and "counters" uint64 [4] (re-decided in binary64, past the
@@ -283,10 +284,25 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
 
     o = _Outputs(ptr("hit"), ptr("tri_id"), ptr("uvt"), ptr("counters"), ptr("count"))
     opts = _iopts(precision, block, stack_depth, proposal, ray_sort, waves_per_cu, node_width)
-    _check(lib().rsi_intersect(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()),
-                               ctypes.c_void_p(rays_to.data_ptr()), n, MODES[mode], ctypes.byref(opts),
-                               ctypes.byref(o), _stream_handle(stream)))
+    fn = lib().rsi_intersect_noalloc if _noalloc else lib().rsi_intersect
+    _check(fn(mesh.handle, ctypes.c_void_p(rays_from.data_ptr()), ctypes.c_void_p(rays_to.data_ptr()), n,
+              MODES[mode], ctypes.byref(opts), ctypes.byref(o), _stream_handle(stream)))
     return out
+
+
+def rsi_intersect_noalloc(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, out: dict,
+                          mode: str = "boolean", precision: str = "plain", stream=None, **opts) -> dict:
+    """rsi_intersect through the entry point that allocates no device memory
+    (its temporary memory is one fixed 64 MiB array of the library, shared by
+    every call on the GPU).  `out` must hold every output tensor the mode
+    needs and "counters"; options as rsi_intersect."""
+    need = {"boolean": ("hit",), "first_hit": ("tri_id",), "barycentric": ("tri_id", "uvt"),
+            "intercept_count": ("count",)}[mode] + ("counters",)
+    missing = [k for k in need if k not in out]
+    if missing:
+        raise ValueError(f"rsi_intersect_noalloc allocates nothing: out needs {missing}")
+    return rsi_intersect(mesh, rays_from, rays_to, mode=mode, precision=precision, out=out, stream=stream,
+                         _noalloc=True, **opts)
 
 
 def rsi_traversal_stats(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mode: str = "boolean",

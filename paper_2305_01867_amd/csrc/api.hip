@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "rsi.h"
 #include "rsi_internal.h"
@@ -182,6 +183,47 @@ __global__ void k_widen_keys(const uint32_t *in, uint64_t *out, int64_t n) {
 
 }  // namespace
 
+// Workspace of rsi_intersect_noalloc: the pass-2 queue and its counters, the
+// proposal's buckets and the segment order, in one array that every GPU the
+// library runs on holds until the process ends.  Host code never uses the
+// array's name as an address (on the host it is only a stand-in for the
+// symbol): each device's address comes from hipGetSymbolAddress.
+static constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device with
+// that device current.
+rsi_status noalloc_scratch(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RSI_E_STATE, std::string("no usable HIP device: ") + hipGetErrorString(e));
+    }
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(RSI_E_STATE, "device index beyond the library's per-device table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(RSI_E_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RSI_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *triangles, int64_t n_triangles,
@@ -349,9 +391,13 @@ rsi_status rsi_destroy(rsi_mesh mesh) {
     return RSI_OK;
 }
 
+// scratch_ptr / scratch_cap: NULL -- the workspace is allocated and freed
+// stream-ordered; otherwise it is this device buffer of scratch_cap bytes and
+// nothing is allocated.
 static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, int64_t n, int32_t mode,
                            const rsi_intersect_opts *opts, const rsi_outputs *out, uint32_t *visits,
-                           uint32_t *tests, void *stream, bool stats) {
+                           uint32_t *tests, void *stream, bool stats, void *scratch_ptr = nullptr,
+                           size_t scratch_cap = 0) {
     g_error.clear();
     rsi_status st = check_ray_args(mesh, from, to, n, mode);
     if (st != RSI_OK)
@@ -418,11 +464,22 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     const size_t b_bytes = use_prop ? ((size_t)n + 511) & ~size_t(255) : 0;
     const bool sorted = ray_sort != RSI_RAY_ORDER_INPUT && n > 1 && mesh->dev.nt > 0;
     const size_t ws_bytes = q_bytes + b_bytes + (sorted ? rsi::ray_sort_ws_bytes(n) : 0);
-    hipError_t e = hipMallocAsync(&ws, ws_bytes, s);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(e == hipErrorOutOfMemory ? RSI_E_NOMEM : RSI_E_HIP,
-                    std::string("hipMallocAsync failed: ") + hipGetErrorString(e));
+    const bool own_ws = scratch_ptr == nullptr;
+    hipError_t e = hipSuccess;
+    if (own_ws) {
+        e = hipMallocAsync(&ws, ws_bytes, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e == hipErrorOutOfMemory ? RSI_E_NOMEM : RSI_E_HIP,
+                        std::string("hipMallocAsync failed: ") + hipGetErrorString(e));
+        }
+    } else {
+        if (ws_bytes > scratch_cap)
+            return fail(RSI_E_CAPACITY, "this call needs " + std::to_string(ws_bytes) +
+                                            " bytes of scratch, more than the " + std::to_string(scratch_cap) +
+                                            " the no-allocation entry point holds (4 bytes per segment, plus 1 "
+                                            "with the proposal and 16 with a segment order)");
+        ws = scratch_ptr;
     }
     rsi::TraverseArgs a;
     a.from = from;
@@ -446,7 +503,8 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
         uint8_t *bucket = static_cast<uint8_t *>(ws) + q_bytes;
         e = rsi::proposal_predict(mesh->dev, mesh->dev.prop, from, to, n, mesh->dev.prop.n_buckets, bucket, s);
         if (e != hipSuccess) {
-            (void)hipFreeAsync(ws, s);
+            if (own_ws)
+                (void)hipFreeAsync(ws, s);
             return fail_hip(e, "proposal inference");
         }
         a.bucket = bucket;
@@ -465,7 +523,7 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
         a.counters = out->counters ? out->counters : ws_counters;
         e = rsi::launch_intersect(mesh->dev, a, s);
     }
-    hipError_t e2 = hipFreeAsync(ws, s);
+    const hipError_t e2 = own_ws ? hipFreeAsync(ws, s) : hipSuccess;
     if (e != hipSuccess)
         return fail_hip(e, stats ? "rsi_traversal_stats launch" : "rsi_intersect launch");
     if (e2 != hipSuccess)
@@ -476,6 +534,23 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
 rsi_status rsi_intersect(rsi_mesh mesh, const float *rays_from, const float *rays_to, int64_t n_rays, int32_t mode,
                          const rsi_intersect_opts *opts, const rsi_outputs *out, void *stream) {
     return run_rays(mesh, rays_from, rays_to, n_rays, mode, opts, out, nullptr, nullptr, stream, false);
+}
+
+rsi_status rsi_intersect_noalloc(rsi_mesh mesh, const float *rays_from, const float *rays_to, int64_t n_rays,
+                                 int32_t mode, const rsi_intersect_opts *opts, const rsi_outputs *out,
+                                 void *stream) {
+    g_error.clear();
+    // argument errors first, as rsi_intersect reports them
+    rsi_status st = check_ray_args(mesh, rays_from, rays_to, n_rays, mode);
+    if (st != RSI_OK)
+        return st;
+    if ((st = check_device()) != RSI_OK)
+        return st;
+    void *ptr = nullptr;
+    if ((st = noalloc_scratch(&ptr)) != RSI_OK)
+        return st;
+    return run_rays(mesh, rays_from, rays_to, n_rays, mode, opts, out, nullptr, nullptr, stream, false, ptr,
+                    kNoAllocScratchBytes);
 }
 
 rsi_status rsi_traversal_stats(rsi_mesh mesh, const float *rays_from, const float *rays_to, int64_t n_rays,

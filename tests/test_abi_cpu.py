@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = rsi.lib()
-    assert L.rsi_abi_version() == 6
+    assert L.rsi_abi_version() == 7
     for code in range(7):
         assert L.rsi_status_string(code).decode().startswith("RSI_")
     assert b"unknown" in L.rsi_status_string(99)
@@ -63,6 +63,7 @@ def test_intersect_argument_errors_need_no_gpu():
     outs = rsi._Outputs()
     # NULL / bogus handle
     assert L.rsi_intersect(None, None, None, 0, 0, None, ctypes.byref(outs), None) == 5
+    assert L.rsi_intersect_noalloc(None, None, None, 0, 0, None, ctypes.byref(outs), None) == 5
     assert L.rsi_destroy(None) == 0
     assert L.rsi_mesh_info_get(None, None) == 5
     assert L.rsi_mesh_export(None, 0, None, 0, None) == 5
