@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the learned form (5.26e5 triangles) leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the tiny-case and precision-form leg")
     ap.add_argument("--c5-train-rays", type=int, default=10_000_000)
     ap.add_argument("--no-host", action="store_true", help="skip the host-resident (PCIe-inclusive) runs")
     ap.add_argument("--train-rays", type=int, default=2_000_000)
@@ -151,7 +152,7 @@ def measured_traffic(mode, precision, build):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"], rec.get("counters")
 
 
-def full_check(mode, out, n):
+def full_check(mode, out, n, workload="paper_scale"):
     """Compare the whole output of the timed path with the binary64 oracle's
     stored per-chunk digests of the same workload (tests/golden, written by
     the oracle alone).  None when no complete fixture covers this workload."""
@@ -160,17 +161,17 @@ def full_check(mode, out, n):
     import numpy as np
 
     path = os.path.join(ROOT, "tests", "golden", "make_full_fixtures.py")
-    if not os.path.exists(os.path.join(ROOT, "tests", "golden", "full_paper_scale.txt")):
+    if not os.path.exists(os.path.join(ROOT, "tests", "golden", f"full_{workload}.txt")):
         return None
     spec = importlib.util.spec_from_file_location("full_fixtures", path)
     fx = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(fx)
-    head, rows = fx.read("paper_scale")
+    head, rows = fx.read(workload)
     if int(head["n_segments"]) != n or len(rows) * int(head["chunk"]) < n:
         return None
     cols = {"boolean": [("hit", 0)], "first_hit": [("tri_id", 1)], "barycentric": [("tri_id", 1), ("uvt", 2)],
             "intercept_count": [("count", 3)]}[mode]
-    res = {"segments": n, "chunks": len(rows), "source": "tests/golden/full_paper_scale.txt"}
+    res = {"segments": n, "chunks": len(rows), "source": f"tests/golden/full_{workload}.txt"}
     for key, col in cols:
         a = out[key].cpu().numpy()
         equal = 0
@@ -195,6 +196,69 @@ def host_cpu():
     except OSError:
         pass
     return {"model": model, "nproc": os.cpu_count()}
+
+
+def other_configs(rsi, workloads, args, stream):
+    """The tiny case and the precision form: intersect time of the binary32
+    and the certified path (boolean and first hit, restructured tree, 4-wide
+    first pass), segments re-decided in binary64, and mismatches against the
+    oracle -- the tiny case in full, the precision form against the oracle's
+    stored per-chunk digests of all 1e7 segments where they exist, else on a
+    stratified sample."""
+    import numpy as np
+    import torch
+
+    import oracle
+    dev = torch.device("cuda:0")
+    res = {}
+    for name in ("tiny", "precision"):
+        if name == "tiny":
+            V, F, O, E = workloads.tiny_config()
+            label = "64x64 heightfield (7,938 triangles), 1e4 crossing-mix segments"
+        else:
+            V, F, O, E, kind = workloads.precision_config()
+            label = ("folded 256x256 heightfield (130,050 triangles), 1e7 segments: 75% in the box, 20% aimed "
+                     "within 1e-7 of edges and vertices, 5% within 1e-6 rad of parallel")
+        dO, dE = torch.from_numpy(O).to(dev), torch.from_numpy(E).to(dev)
+        n = O.shape[0]
+        r = {"workload": label, "n_triangles": int(F.shape[0]), "n_segments": int(n)}
+        with rsi.rsi_build(torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev),
+                           algorithm=args.build) as mesh:
+            for mode, key in (("boolean", "hit"), ("first_hit", "tri_id")):
+                got = {}
+                for prec in ("plain", "certified"):
+                    o = rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision=prec)
+                    ms = _timed(lambda: rsi.rsi_intersect(mesh, dO, dE, mode=mode, precision=prec, out=o), stream)
+                    got[prec] = o[key].cpu().numpy()
+                    r[f"{mode}/{prec}"] = {"ms": round(ms, 4), "mrays_s": round(n / (ms * 1e-3) / 1e6, 1),
+                                           "redecided_fp64": int(o["counters"][0].item())}
+                    if name == "precision" and prec == "certified":
+                        full = full_check(mode, o, n, "precision")
+                        if full:
+                            r[f"{mode}/certified"]["every_segment_vs_oracle"] = full
+                    del o
+                if name == "tiny":
+                    hit, ids, _, _ = oracle.intersect(V, F, O, E)
+                    want = hit if mode == "boolean" else ids
+                    r[f"{mode}/mismatches_vs_oracle"] = {p: int(np.sum(got[p] != want)) for p in got}
+                    r[f"{mode}/oracle_segments"] = int(n)
+                else:
+                    # binary32 against the certified path (equal to the oracle where
+                    # the digests say so), and a stratified oracle sample
+                    r[f"{mode}/plain_differs_from_certified"] = int(np.sum(got["plain"] != got["certified"]))
+                    if not args.no_cpu_baseline:
+                        rng = np.random.default_rng(17)
+                        idx = np.concatenate([rng.choice(np.nonzero(kind == k)[0], c, replace=False)
+                                              for k, c in ((0, 300), (1, 800), (2, 400))])
+                        hit, ids, _, _ = oracle.intersect(V, F, O[idx], E[idx])
+                        want = hit if mode == "boolean" else ids
+                        r[f"{mode}/sample_mismatches_vs_oracle"] = {
+                            p: int(np.sum(got[p][idx] != want)) for p in got}
+                        r[f"{mode}/sample_segments"] = int(idx.size)
+        res[name] = r
+        del dO, dE
+        torch.cuda.empty_cache()
+    return res
 
 
 def _timed(fn, stream, reps=3):
@@ -543,6 +607,12 @@ def main():
         learned_c5 = learned_form(rsi, workloads, args, stream)
         print(f"[bench] learned form: {learned_c5}", file=sys.stderr, flush=True)
 
+    # ---------------- the tiny case and the precision form (untimed region)
+    configs = None
+    if not args.no_configs:
+        configs = other_configs(rsi, workloads, args, stream)
+        print(f"[bench] configs: {configs}", file=sys.stderr, flush=True)
+
     # ---------------- host-resident runs: host arrays in, host results out (PCIe included)
     host = None
     if not args.no_host:
@@ -683,6 +753,7 @@ def main():
         "variants": variants,
         "learned_vs_plain": learned,
         "learned_form": learned_c5,
+        "configs": configs,
         "batched": batched,
         "host_resident": host,
     }

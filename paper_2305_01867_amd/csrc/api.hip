@@ -2,6 +2,7 @@
 // memory, stream-ordered launches and error reporting.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -774,10 +775,34 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     d.root = d.nt >= 2 ? 0 : (d.nt == 1 ? ~0 : INT32_MIN);
     b.M = M;
     b.n_rays = ray_offsets[M];
+    // work items of at most kBatchChunk segments, grouped per XCD: meshes go
+    // to the group with the least estimated cost so far (largest first; cost
+    // ~ segments x log2 triangles), each group's items mesh by mesh
+    std::vector<int> order(M), group_of(M);
+    std::vector<double> cost(M), load(rsi::kItemGroups, 0.0);
+    for (int m = 0; m < M; ++m) {
+        order[m] = m;
+        cost[m] = (double)(ray_offsets[m + 1] - ray_offsets[m]) *
+                  std::log2((double)(triangle_offsets[m + 1] - triangle_offsets[m]) + 2.0);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    for (int m : order) {
+        int g = 0;
+        for (int h = 1; h < rsi::kItemGroups; ++h)
+            g = load[h] < load[g] ? h : g;
+        group_of[m] = g;
+        load[g] += cost[m];
+    }
     std::vector<int4> items;
-    for (int m = 0; m < M; ++m)
-        for (int64_t a = ray_offsets[m]; a < ray_offsets[m + 1]; a += kBatchChunk)
-            items.push_back(make_int4(m, (int)a, (int)std::min(a + kBatchChunk, ray_offsets[m + 1]), 0));
+    std::vector<int32_t> group_start(rsi::kItemGroups + 1, 0);
+    for (int g = 0; g < rsi::kItemGroups; ++g) {
+        group_start[g] = (int32_t)items.size();
+        for (int m = 0; m < M; ++m)
+            if (group_of[m] == g)
+                for (int64_t a = ray_offsets[m]; a < ray_offsets[m + 1]; a += kBatchChunk)
+                    items.push_back(make_int4(m, (int)a, (int)std::min(a + kBatchChunk, ray_offsets[m + 1]), 0));
+    }
+    group_start[rsi::kItemGroups] = (int32_t)items.size();
     b.n_items = (int)items.size();
     const int64_t nt = d.nt, nv = d.nv;
     const size_t sz_V = round_up(12 * (size_t)nv + 4), sz_F = round_up(12 * (size_t)nt + 4);
@@ -791,7 +816,7 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     const size_t sz_tmp = round_up(rsi::sort_tmp_bytes(nt, 63));
     const size_t sz_off = round_up(8 * (size_t)(M + 1)) * 2 + round_up(4 * (size_t)(M + 1)) + round_up(4 * (size_t)M) * 2;
     const size_t sz_tm = round_up(4 * (size_t)nt + 4), sz_mb = round_up(32 * (size_t)M);
-    const size_t sz_items = round_up(16 * (size_t)(b.n_items + 1));
+    const size_t sz_items = round_up(16 * (size_t)(b.n_items + 1)) + round_up(4 * (rsi::kItemGroups + 1));
     const size_t sz_q = round_up(4 * (size_t)b.n_rays + 4) + 256;
     const size_t sz_order = round_up(rsi::ray_sort_ws_bytes(b.n_rays));
     const size_t total = sz_V + sz_F + sz_keys + sz_ids + sz_nodes + sz_nodes4 + sz_roots4 + sz_par + sz_cnt +
@@ -832,7 +857,8 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     b.roots = reinterpret_cast<int32_t *>(take(round_up(4 * (size_t)M)));
     b.tri_mesh = reinterpret_cast<int32_t *>(take(sz_tm));
     b.mesh_bounds = reinterpret_cast<float *>(take(sz_mb));
-    b.items = reinterpret_cast<int4 *>(take(sz_items));
+    b.items = reinterpret_cast<int4 *>(take(round_up(16 * (size_t)(b.n_items + 1))));
+    b.group_start = reinterpret_cast<int32_t *>(take(round_up(4 * (rsi::kItemGroups + 1))));
     char *q = take(sz_q);
     b.counters = reinterpret_cast<uint64_t *>(q);
     b.queue_len = reinterpret_cast<uint32_t *>(q + 32);
@@ -853,6 +879,9 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
         e = hipMemcpyAsync(b.mesh_toff, toff.data(), 4 * (size_t)M, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && b.n_items > 0)
         e = hipMemcpyAsync(b.items, items.data(), 16 * (size_t)b.n_items, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b.group_start, group_start.data(), 4 * (size_t)(rsi::kItemGroups + 1),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);  // the host vectors go out of scope
     if (e != hipSuccess) {
@@ -943,6 +972,8 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
     a.queue_len = b.queue_len;
     a.items = b.items;
     a.n_items = b.n_items;
+    a.group_start = b.group_start;
+    a.n_groups = rsi::kItemGroups;
     a.n_meshes = b.M;
     a.mesh_root = b.roots;
     a.mesh_root4 = batch->dev.node_width == 4 ? b.roots4 : nullptr;

@@ -117,7 +117,14 @@ struct MeshDev {
     Proposal prop;
 };
 
-// Batched form (batch.hip): many meshes in one BVH.
+// Batched form (batch.hip): many meshes in one BVH.  Its work items are
+// grouped, one group per XCD of the MI355X: the meshes are spread over the
+// groups by estimated cost, so each XCD's L2 holds the trees of a few meshes.
+constexpr int kItemGroups = 8;
+// Index in the traversal's queue words (after the queue length and the next
+// segment) of the first per-group item counter; the batch's queue area holds
+// them before its queue.
+constexpr int kGroupNext = 8;
 struct BatchDev {
     int M = 0;
     int64_t *v_off = nullptr, *t_off = nullptr;  // device [M + 1]
@@ -128,8 +135,9 @@ struct BatchDev {
     int32_t *slot_bin = nullptr;                 // device [kTopSlots] binary node of each top slot
     int32_t *tri_mesh = nullptr;                 // device [nt]
     float *mesh_bounds = nullptr;                // device [M][8]
-    int4 *items = nullptr;                       // device [n_items] (mesh, first, end, 0)
+    int4 *items = nullptr;                       // device [n_items] (mesh, first, end, 0), grouped
     int n_items = 0;
+    int32_t *group_start = nullptr;              // device [kItemGroups + 1] first item of each group
     int32_t *queue = nullptr;                    // device [n_rays]
     void *sort_ws = nullptr;                     // device ray_sort_ws_bytes(n_rays): segment order
     uint32_t *queue_len = nullptr;               // device [2]
@@ -209,6 +217,8 @@ struct TraverseArgs {
     // batched form (NULL items: one mesh)
     const int4 *items = nullptr;          // (mesh, first segment, end segment, 0)
     int n_items = 0;
+    const int32_t *group_start = nullptr; // [n_groups + 1] items grouped per XCD (NULL: one queue)
+    int n_groups = 0;
     int n_meshes = 0;
     const int32_t *mesh_root = nullptr;   // subtree root per mesh (INT32_MIN: empty)
     const int32_t *mesh_root4 = nullptr;  // the same in the 4-wide tree (NULL: binary nodes only)

@@ -295,6 +295,8 @@ struct TravParams {
     const int32_t *bucket_ref;
     const int4 *items;
     int n_items;
+    const int32_t *group_start;  // [n_groups + 1] first item of each group, or NULL: one queue
+    int n_groups;
     int n_meshes;
     const int32_t *mesh_root;
     const int32_t *mesh_root4;  // the mesh roots as 4-wide references (first pass over 4-wide nodes)
@@ -454,6 +456,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
         }
     };
     bool items_left = batch;
+    uint32_t groups_done = 0;  // item groups found empty (wave-uniform)
     int cur_root = p.root, cur_toff = 0;
     int lane_root = p.root, lane_toff = 0;  // of the lane's current segment
 
@@ -504,12 +507,36 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
         // ---- refill idle lanes
         const uint64_t idle = __ballot(ray < 0);
         if (items_left && cursor >= range_end && idle) {
-            uint32_t k = 0;
-            if (lane == 0)
-                k = atomicAdd(p.next_ray, 1u);
-            k = __shfl(k, 0);
-            if (k < (uint32_t)p.n_items) {
-                const int4 it = p.items[k];
+            int item = -1;
+            if (p.group_start) {
+                // items are grouped by XCD (workgroups are spread over the
+                // eight XCDs in turn): this workgroup's group first, so each
+                // XCD's L2 serves a few meshes; then the others, so no XCD
+                // idles while work is left
+#pragma unroll 1
+                for (int t = 0; t < p.n_groups && item < 0; ++t) {
+                    const int g = (int)((blockIdx.x + t) % p.n_groups);
+                    if (groups_done & (1u << g))
+                        continue;
+                    uint32_t k = 0;
+                    if (lane == 0)
+                        k = atomicAdd(p.queue_len + kGroupNext + g, 1u);
+                    k = __shfl(k, 0);
+                    const int first = p.group_start[g], count = p.group_start[g + 1] - first;
+                    if (k < (uint32_t)count)
+                        item = first + (int)k;
+                    else
+                        groups_done |= 1u << g;
+                }
+            } else {
+                uint32_t k = 0;
+                if (lane == 0)
+                    k = atomicAdd(p.next_ray, 1u);
+                k = __shfl(k, 0);
+                item = k < (uint32_t)p.n_items ? (int)k : -1;
+            }
+            if (item >= 0) {
+                const int4 it = p.items[item];
                 cursor = it.y;
                 range_end = it.z;
                 cur_root = WIDE ? p.mesh_root4[it.x] : p.mesh_root[it.x];
@@ -1426,9 +1453,11 @@ __global__ void k_ray_keys(const float *__restrict__ from, const float *__restri
     ids[i] = (int32_t)i;
 }
 
-__global__ void k_reset(uint32_t *queue_len, unsigned long long *counters) {
+__global__ void k_reset(uint32_t *queue_len, unsigned long long *counters, int n_groups) {
     if (threadIdx.x < 2)
         queue_len[threadIdx.x] = 0;  // queue length, next segment of pass 1
+    if (threadIdx.x < n_groups)
+        queue_len[kGroupNext + threadIdx.x] = 0;  // next item of each group
     if (threadIdx.x < 4)
         counters[threadIdx.x] = 0;
 }
@@ -1600,6 +1629,8 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.bucket_ref = p.nodes4 && a.bucket ? m.prop.bucket_ref4 : a.bucket_ref;
     p.items = a.items;
     p.n_items = a.n_items;
+    p.group_start = a.items ? a.group_start : nullptr;
+    p.n_groups = p.group_start ? a.n_groups : 0;
     p.n_meshes = a.n_meshes;
     p.mesh_root = a.mesh_root;
     p.mesh_root4 = p.nodes4 ? a.mesh_root4 : nullptr;
@@ -1645,7 +1676,7 @@ size_t ray_sort_ws_bytes(int64_t n) {
 
 hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t s) {
     TravParams p = make_params(m, a);
-    k_reset<<<1, 64, 0, s>>>(a.queue_len, p.counters);
+    k_reset<<<1, 64, 0, s>>>(a.queue_len, p.counters, p.group_start ? p.n_groups : 0);
     if (a.n == 0)
         return hipGetLastError();
     if (m.nt == 0) {
@@ -1712,7 +1743,7 @@ hipError_t launch_debug_certify(const float *from, const float *to, const float 
 
 hipError_t launch_stats(const MeshDev &m, const TraverseArgs &a, hipStream_t s) {
     TravParams p = make_params(m, a);
-    k_reset<<<1, 64, 0, s>>>(a.queue_len, p.counters);
+    k_reset<<<1, 64, 0, s>>>(a.queue_len, p.counters, p.group_start ? p.n_groups : 0);
     if (m.nt == 0 || a.n == 0)
         return hipGetLastError();
     const hipError_t e = order_segments(a, p, s);
