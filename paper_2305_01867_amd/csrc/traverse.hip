@@ -304,6 +304,9 @@ struct TravParams {
     const int32_t *ray_off;
     const int32_t *order;  // segment at each processing position (NULL: input order)
     int stage_ok;          // boolean results may be staged per wave (4-byte aligned output)
+    int4 *retest;          // certified, one mesh: (segment, candidate ids) decided after pass 1, or NULL
+    uint32_t *retest_len;  // records appended (may exceed retest_cap: those went to the second pass)
+    uint32_t retest_cap;
     int deep_cap;          // second pass: entries of a lane's private stack (<= kDeepStack)
     int wave_cap;          // second pass: entries of a wave's shared stack (<= its LDS array)
 };
@@ -313,6 +316,24 @@ __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why)
     p.queue[slot] = (int32_t)i;
     atomicAdd(p.counters + why, 1ull);
 }
+
+// A certified segment whose answer hangs only on a few listed candidates
+// (unsure pairs, and in the nearest-hit modes the best sure hit): appended
+// for k_retest, which decides them in binary64.  False when the list is full
+// (the segment then goes to the second pass).
+__device__ __forceinline__ bool retest_push(const TravParams &p, int4 rec) {
+    if (!p.retest)
+        return false;
+    const uint32_t slot = atomicAdd(p.retest_len, 1u);
+    if (slot >= p.retest_cap)
+        return false;
+    p.retest[slot] = rec;
+    atomicAdd(p.counters, 1ull);  // re-decided in binary64
+    return true;
+}
+// unsure pairs a lane lists for k_retest: three (boolean) or two beside the best sure hit
+template <int MODE>
+constexpr int kUnsureSlots = MODE == MODE_BOOL ? 3 : 2;
 
 // Pointers into LDS by address space, so reads of the LDS copy of the tree's
 // top compile to ds_read and are not merged with the global path.
@@ -488,6 +509,16 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     int best_id = -1;
     float best_t = INFINITY, best_lo = INFINITY, best_hi = INFINITY, best_u = 0.0f, best_v = 0.0f;
     bool found = false, unsure = false, flagged = false, overflow = false;
+    // certified: the unsure pairs met so far (input triangle ids), for k_retest
+    int uns[3] = {-1, -1, -1};
+    int n_uns = 0;
+    auto note_unsure = [&](int id) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k == n_uns)
+                uns[k] = id;
+        ++n_uns;
+    };
     uint32_t n_nodes = 0, n_tests = 0;
     int steps = 0;
     int phase = 1, skip = kDone;  // kDone never equals a child reference
@@ -565,6 +596,8 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                     best_t = best_lo = best_hi = INFINITY;
                     best_u = best_v = 0.0f;
                     found = unsure = flagged = overflow = false;
+                    uns[0] = uns[1] = uns[2] = -1;
+                    n_uns = 0;
                     n_nodes = n_tests = 0;
                     nk = 0;
                     list_full = false;
@@ -845,10 +878,18 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                             ref = kDone;
                         } else if (c == kUnsure) {
                             unsure = true;
+                            note_unsure(id);
                         }
                     } else if (c == kUnsure) {
-                        flagged = true;
-                        ref = kDone;
+                        // go on and list it (the answer is then the nearest of
+                        // the listed pairs and the best sure hit, in binary64),
+                        // or hand the segment to the second pass
+                        if (p.retest && n_uns < kUnsureSlots<MODE>) {
+                            note_unsure(id);
+                        } else {
+                            flagged = true;
+                            ref = kDone;
+                        }
                     } else if (c == kHit) {
                         if (best_id < 0 || hi < best_lo) {
                             best_lo = lo;
@@ -900,13 +941,17 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                 // pass writes its result after this kernel
                 if (!found && overflow)
                     enqueue(p, ray, 1);
-                else if (!found && CERT && unsure)
+                else if (!found && CERT && unsure &&
+                         !(n_uns <= kUnsureSlots<MODE> && retest_push(p, make_int4((int)ray, uns[0], uns[1], uns[2]))))
                     enqueue(p, ray, 0);
                 put_hit(ray, found ? 1u : 0u);
             } else if (overflow) {
                 enqueue(p, ray, 1);
             } else if (CERT && flagged) {
                 enqueue(p, ray, 0);
+            } else if (CERT && n_uns > 0) {
+                if (!retest_push(p, make_int4((int)ray, best_id, uns[0], uns[1])))
+                    enqueue(p, ray, 0);
             } else if (CERT && MODE == MODE_BARY && best_id >= 0) {
                 if (p.bary_after) {  // (u, v, t) after both passes, a lane per segment
                     if (p.out.hit)
@@ -1375,6 +1420,48 @@ __device__ void finish_lane(const TravParams &p, int64_t i, int *stk) {
     f.write(p, i, toff);
 }
 
+// The listed segments of a certified first pass: each one's answer is
+// decided by its listed candidates alone (every other candidate it reached
+// was a proven binary32 miss, or -- in the nearest-hit modes -- a sure hit
+// no nearer than the listed best sure hit), each tested in binary64 with the
+// oracle's operation order.  A lane per segment.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_retest(TravParams p) {
+    const uint32_t len = *p.retest_len;
+    const uint32_t count = len < p.retest_cap ? len : p.retest_cap;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < count; q += gridDim.x * blockDim.x) {
+        const int4 rec = p.retest[q];
+        const int64_t i = rec.x;
+        const float *o = p.from + 3 * i, *e = p.to + 3 * i;
+        const double ox = o[0], oy = o[1], oz = o[2], ex = e[0], ey = e[1], ez = e[2];
+        const int cand[3] = {rec.y, rec.z, rec.w};
+        int best = -1;
+        double bu = 0.0, bv = 0.0, bt = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int id = cand[k];
+            if (id < 0 || !valid_tri(p.F, p.nv, id) || (MODE == MODE_BOOL && best >= 0))
+                continue;
+            const MT64 h = mt64(ox, oy, oz, ex, ey, ez, p.V, p.F, id);
+            if (h.hit && (best < 0 || h.t < bt || (h.t == bt && id < best))) {
+                best = id;
+                bu = h.u;
+                bv = h.v;
+                bt = h.t;
+            }
+        }
+        if (MODE == MODE_BOOL) {
+            p.out.hit[i] = best >= 0 ? 1 : 0;
+        } else if (p.bary_after && best >= 0) {  // (u, v, t) follow from the id after both passes
+            if (p.out.hit)
+                p.out.hit[i] = 1;
+            p.out.id[i] = best;
+        } else {  // a miss (NaN u, v, t), or the values themselves
+            write_out(p.out, i, MODE, best, (float)bu, (float)bv, (float)bt);
+        }
+    }
+}
+
 template <int MODE, bool CERT>
 __global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
     __shared__ int deep[kWaveCap<MODE>];
@@ -1454,8 +1541,8 @@ __global__ void k_ray_keys(const float *__restrict__ from, const float *__restri
 }
 
 __global__ void k_reset(uint32_t *queue_len, unsigned long long *counters, int n_groups) {
-    if (threadIdx.x < 2)
-        queue_len[threadIdx.x] = 0;  // queue length, next segment of pass 1
+    if (threadIdx.x < 3)
+        queue_len[threadIdx.x] = 0;  // queue length, next segment of pass 1, listed segments
     if (threadIdx.x < n_groups)
         queue_len[kGroupNext + threadIdx.x] = 0;  // next item of each group
     if (threadIdx.x < 4)
@@ -1638,6 +1725,11 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.ray_off = a.ray_off;
     p.order = nullptr;
     p.stage_ok = (reinterpret_cast<uintptr_t>(a.hit) & 3u) == 0 ? 1 : 0;
+    // the candidate list: certified, one mesh, modes other than the count
+    const bool listed = a.certified && a.retest && a.items == nullptr && a.mode != MODE_COUNT;
+    p.retest = listed ? a.retest : nullptr;
+    p.retest_len = a.queue_len + 2;
+    p.retest_cap = listed ? a.retest_cap : 0;
     p.deep_cap = kDeepStack;
     p.wave_cap = a.mode == MODE_COUNT ? kWaveCap<MODE_COUNT> : kWaveCap<MODE_BOOL>;
     // RSI_DEBUG_PASS2_STACK=k (2..kDeepStack) shrinks both second-pass stacks
@@ -1687,6 +1779,16 @@ hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t
     if (e != hipSuccess)
         return e;
     dispatch_pass1<false>(p, a.mode, a.certified != 0, a.block, s);
+    if (p.retest) {  // the listed segments, a lane each
+        const int64_t want = ((int64_t)p.retest_cap + 255) / 256;
+        const int grid_r = (int)(want < 1024 ? (want < 1 ? 1 : want) : 1024);
+        if (a.mode == MODE_BOOL)
+            k_retest<MODE_BOOL><<<grid_r, 256, 0, s>>>(p);
+        else if (a.mode == MODE_FIRST)
+            k_retest<MODE_FIRST><<<grid_r, 256, 0, s>>>(p);
+        else
+            k_retest<MODE_BARY><<<grid_r, 256, 0, s>>>(p);
+    }
     // enough blocks for one per segment of a short queue; a long queue is
     // taken 64 segments per block (count mode: a wave per segment, with
     // small blocks that fit many per CU)
