@@ -122,6 +122,11 @@ struct GemmArgs {
 };
 
 constexpr int kGT = 64, kGK = 32, kGPad = 8;
+// k steps of kGK staged through LDS together, so a workgroup synchronises
+// once per kGSub * kGK of the contraction (each wave: 4 * kGSub MFMA per stage)
+constexpr int kGSub = 4;
+constexpr int kGStage = kGK * kGSub;
+constexpr int kGPitch = kGStage + kGPad;
 
 // One operand's 64 x 32 tile of this k step: each lane fetches 8 elements
 // (one 16-byte load in the vector layouts) into registers; put_tile stores
@@ -153,19 +158,20 @@ __device__ __forceinline__ bf16x8 get_tile(const __bf16 *__restrict__ P, int64_t
     return v;
 }
 
-__device__ __forceinline__ void put_tile(__bf16 (*S)[kGK + kGPad], int mode, bf16x8 v, int tid) {
+// Stores one 64 x 32 tile (columns [c0, c0 + 32) of the stage) into S.
+__device__ __forceinline__ void put_tile(__bf16 (*S)[kGPitch], int c0, int mode, bf16x8 v, int tid) {
     if (mode == 1) {
-        *reinterpret_cast<bf16x8 *>(&S[tid >> 2][(tid & 3) * 8]) = v;
+        *reinterpret_cast<bf16x8 *>(&S[tid >> 2][c0 + (tid & 3) * 8]) = v;
     } else if (mode == 2) {
         const int kk = tid >> 3, mn = (tid & 7) * 8;
 #pragma unroll
         for (int i = 0; i < 8; ++i)
-            S[mn + i][kk] = v[i];
+            S[mn + i][c0 + kk] = v[i];
     } else {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int idx = tid + 256 * r;
-            S[idx / kGK][idx % kGK] = v[r];
+            S[idx / kGK][c0 + idx % kGK] = v[r];
         }
     }
 }
@@ -173,37 +179,55 @@ __device__ __forceinline__ void put_tile(__bf16 (*S)[kGK + kGPad], int mode, bf1
 // C = A B on MFMA: a 64 x 64 tile per workgroup, four waves of 32 x 32.  The
 // next k step's operand tiles load into registers while the current step
 // multiplies out of LDS; the sum over k runs in k order.
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-    __shared__ __bf16 As[kGT][kGK + kGPad];
-    __shared__ __bf16 Bs[kGT][kGK + kGPad];  // stored [n][k]
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int bz, __bf16 (*As)[kGPitch],
+                                          __bf16 (*Bs)[kGPitch]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
+    const int m0 = by * kGT, n0 = bx * kGT;
+    if (m0 >= g.M || n0 >= g.N)
+        return;  // a grouped launch covers the largest operand; uniform per workgroup
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int kb = g.partial ? blockIdx.z * g.k_chunk : 0;
+    const int kb = g.partial ? bz * g.k_chunk : 0;
     const int ke = g.partial ? min(g.K, kb + g.k_chunk) : g.K;
     f32x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    bf16x8 va = get_tile(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, kb, ke, tid);
-    bf16x8 vb = get_tile(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, kb, ke, tid);
+    // a stage: kGSub k steps of 32, loaded into registers while the previous
+    // stage multiplies (tiles past ke are zero)
+    bf16x8 va[kGSub], vb[kGSub];
+#pragma unroll
+    for (int j = 0; j < kGSub; ++j) {
+        va[j] = get_tile(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, kb + kGK * j, ke, tid);
+        vb[j] = get_tile(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, kb + kGK * j, ke, tid);
+    }
     const int kq = 8 * (lane >> 4);
-    for (int k0 = kb; k0 < ke; k0 += kGK) {
-        __syncthreads();  // the previous step's reads of As / Bs are done
-        put_tile(As, g.a_mode, va, tid);
-        put_tile(Bs, g.b_mode, vb, tid);
-        __syncthreads();
-        if (k0 + kGK < ke) {
-            va = get_tile(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, k0 + kGK, ke, tid);
-            vb = get_tile(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, k0 + kGK, ke, tid);
+    for (int k0 = kb; k0 < ke; k0 += kGStage) {
+        __syncthreads();  // the previous stage's reads of As / Bs are done
+#pragma unroll
+        for (int j = 0; j < kGSub; ++j) {
+            put_tile(As, kGK * j, g.a_mode, va[j], tid);
+            put_tile(Bs, kGK * j, g.b_mode, vb[j], tid);
         }
-        for (int a = 0; a < 2; ++a) {
-            const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * a + (lane & 15)][kq]);
-            for (int b = 0; b < 2; ++b) {
-                const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * b + (lane & 15)][kq]);
-                acc[a][b] = mfma16(fa, fb, acc[a][b]);
+        __syncthreads();
+        if (k0 + kGStage < ke) {
+#pragma unroll
+            for (int j = 0; j < kGSub; ++j) {
+                va[j] = get_tile(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, k0 + kGStage + kGK * j, ke, tid);
+                vb[j] = get_tile(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, k0 + kGStage + kGK * j, ke, tid);
             }
         }
+        // the k steps in k order (the sum over k runs in the same order as
+        // with one step per stage); steps past ke hold zeros
+        const int steps = min(kGSub, (ke - k0 + kGK - 1) / kGK);
+        for (int j = 0; j < steps; ++j)
+            for (int a = 0; a < 2; ++a) {
+                const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * a + (lane & 15)][kGK * j + kq]);
+                for (int b = 0; b < 2; ++b) {
+                    const bf16x8 fb =
+                        *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * b + (lane & 15)][kGK * j + kq]);
+                    acc[a][b] = mfma16(fa, fb, acc[a][b]);
+                }
+            }
     }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
@@ -214,7 +238,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                     continue;
                 float v = acc[a][b][i];
                 if (g.partial) {
-                    g.partial[((int64_t)blockIdx.z * g.M + m) * g.N + n] = v;
+                    g.partial[((int64_t)bz * g.M + m) * g.N + n] = v;
                     continue;
                 }
                 if (g.bias)
@@ -230,10 +254,26 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             }
 }
 
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+    __shared__ __bf16 As[kGT][kGPitch];
+    __shared__ __bf16 Bs[kGT][kGPitch];  // stored [n][k]
+    gemm_tile(g, blockIdx.x, blockIdx.y, blockIdx.z, As, Bs);
+}
+
+// The four layers' weight gradients in one launch: z = layer x split chunk.
+struct GemmArgs4 {
+    GemmArgs g[4];
+};
+__global__ __launch_bounds__(256) void k_gemm4(GemmArgs4 gs, int chunks) {
+    __shared__ __bf16 As[kGT][kGPitch];
+    __shared__ __bf16 Bs[kGT][kGPitch];
+    const int layer = blockIdx.z / chunks;
+    gemm_tile(gs.g[layer], blockIdx.x, blockIdx.y, blockIdx.z % chunks, As, Bs);
+}
+
 // Cf = the split-K partial sums added in chunk order (deterministic).
-__global__ __launch_bounds__(256) void k_gemm_reduce(const float *__restrict__ partial, int chunks, int M, int N,
-                                                     float *__restrict__ Cf, int64_t c_m, int64_t c_n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void reduce_split(const float *__restrict__ partial, int chunks, int M, int N,
+                                             float *__restrict__ Cf, int64_t c_m, int64_t c_n, int64_t i) {
     const int64_t mn = (int64_t)M * N;
     if (i >= mn)
         return;
@@ -242,6 +282,18 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const float *__restrict__ p
         s += partial[z * mn + i];
     const int m = (int)(i / N), n = (int)(i % N);
     Cf[m * c_m + n * c_n] = s;
+}
+
+__global__ __launch_bounds__(256) void k_gemm_reduce(const float *__restrict__ partial, int chunks, int M, int N,
+                                                     float *__restrict__ Cf, int64_t c_m, int64_t c_n) {
+    reduce_split(partial, chunks, M, N, Cf, c_m, c_n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_reduce4(GemmArgs4 gs, int chunks) {
+    const GemmArgs &g = gs.g[blockIdx.y];
+    if (!g.partial)
+        return;
+    reduce_split(g.partial, chunks, g.M, g.N, g.Cf, g.c_m, g.c_n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------- softmax cross-entropy
@@ -307,9 +359,12 @@ __global__ __launch_bounds__(256) void k_loss_sum(const float *__restrict__ row_
 // order -- deterministic, and 64x more parallel than one pass.
 constexpr int kColRows = 64;
 
+// (blockIdx.y = layer: dZ and partial advance by rows x 256 and nblk x 256)
 __global__ __launch_bounds__(256) void k_col_partial(const __bf16 *__restrict__ dZ, int rows,
                                                      float *__restrict__ partial) {
     const int n = threadIdx.x, b = blockIdx.x;
+    dZ += (int64_t)blockIdx.y * rows * kMlpOut;
+    partial += (int64_t)blockIdx.y * gridDim.x * kMlpOut;
     const int r1 = min(rows, (b + 1) * kColRows);
     float s = 0.0f;
 #pragma unroll 16
@@ -318,9 +373,12 @@ __global__ __launch_bounds__(256) void k_col_partial(const __bf16 *__restrict__ 
     partial[(int64_t)b * kMlpOut + n] = s;
 }
 
+// (blockIdx.x = layer)
 __global__ __launch_bounds__(256) void k_col_final(const float *__restrict__ partial, int nblk,
                                                    float *__restrict__ db) {
     const int n = threadIdx.x;
+    partial += (int64_t)blockIdx.x * nblk * kMlpOut;
+    db += (int64_t)blockIdx.x * kMlpHidden;
     float s = 0.0f;
 #pragma unroll 16
     for (int b = 0; b < nblk; ++b)
@@ -734,16 +792,23 @@ int operand_mode(const __bf16 *P, int64_t s_mn, int64_t s_k, int MN, int K) {
 constexpr int kSplitMax = 16;  // split-K chunks of a long contraction (the weight gradients)
 
 // split: a buffer of kSplitMax * M * N floats for a split over K, or NULL
-void gemm(GemmArgs g, hipStream_t s, float *split = nullptr) {
+// Operand layouts of g, and its split over K when `split` is given and the
+// contraction is long (raw sums, no epilogue); returns the number of chunks.
+int prepare_split(GemmArgs &g, float *split) {
     g.a_mode = operand_mode(g.A, g.a_m, g.a_k, g.M, g.K);
     g.b_mode = operand_mode(g.B, g.b_n, g.b_k, g.N, g.K);
     int chunks = 1;
     if (split && g.K > 2 * 256 && !g.bias && !g.relu && !g.mask && !g.Cb && g.Cf) {
         chunks = cdiv(g.K, 256) < kSplitMax ? cdiv(g.K, 256) : kSplitMax;
-        g.k_chunk = cdiv(cdiv(g.K, chunks), kGK) * kGK;
+        g.k_chunk = cdiv(cdiv(g.K, chunks), kGStage) * kGStage;
         chunks = cdiv(g.K, g.k_chunk);
         g.partial = split;
     }
+    return chunks;
+}
+
+void gemm(GemmArgs g, hipStream_t s, float *split = nullptr) {
+    const int chunks = prepare_split(g, split);
     dim3 grid(cdiv(g.N, kGT), cdiv(g.M, kGT), chunks);
     k_gemm<<<grid, 256, 0, s>>>(g);
     if (g.partial) {
@@ -806,16 +871,16 @@ hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from
     __bf16 *H1 = X0 + (int64_t)rows * kMlpIn;
     __bf16 *H2 = H1 + (int64_t)rows * kMlpHidden;
     __bf16 *H3 = H2 + (int64_t)rows * kMlpHidden;
-    __bf16 *dZa = H3 + (int64_t)rows * kMlpHidden;
-    __bf16 *dZb = dZa + (int64_t)rows * kMlpOut;
-    float *Z4 = reinterpret_cast<float *>(dZb + (int64_t)rows * kMlpOut);
-    float *split = Z4 + (int64_t)rows * kMlpOut;  // kSplitMax x 256 x 256 partial sums of a weight gradient
+    __bf16 *dZ0 = H3 + (int64_t)rows * kMlpHidden;  // dZ of layer l at dZ0 + l rows 256
+    float *Z4 = reinterpret_cast<float *>(dZ0 + 4 * (int64_t)rows * kMlpOut);
+    float *split = Z4 + (int64_t)rows * kMlpOut;  // 4 x kSplitMax x 256 x 256 partial sums of the weight gradients
     const __bf16 *W1 = pr.Wb, *W2 = W1 + kMlpOut * kMlpIn, *W3 = W2 + kMlpHidden * kMlpHidden,
                  *W4 = W3 + kMlpHidden * kMlpHidden;
     const float *bias = pr.P + kMlpWeights;
     float *G = pr.G;
     float *gW1 = G, *gW2 = gW1 + kMlpOut * kMlpIn, *gW3 = gW2 + kMlpHidden * kMlpHidden,
           *gW4 = gW3 + kMlpHidden * kMlpHidden, *gb = G + kMlpWeights;
+    auto dZ = [&](int l) { return dZ0 + (int64_t)l * rows * kMlpOut; };
 
     k_features<<<cdiv((int64_t)rows * 7, 256), 256, 0, s>>>(from, to, seg, r0, rows, m.bounds, X0);
     // forward: Z = H W (W stored [out][in]), ReLU on hidden layers
@@ -835,37 +900,42 @@ hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from
         gemm(g, s);
     }
     k_softmax_ce<<<cdiv(rows, 4), 256, 0, s>>>(logits_out ? logits_out : Z4, lab + r0, rows, nb, 1.0f / rows,
-                                              loss_scale > 0.0f ? loss_scale : 1.0f / rows, dZa, split);
+                                              loss_scale > 0.0f ? loss_scale : 1.0f / rows, dZ(3), split);
     k_loss_sum<<<1, 256, 0, s>>>(split, rows, loss);  // before the weight gradients reuse `split`
-    // backward
-    __bf16 *dZ = dZa, *dZn = dZb;
+    // backward, first the chain of input gradients: dZ(l - 1) = (dZ(l) W_l) masked by H_l > 0
+    for (int l = 3; l > 0; --l) {
+        GemmArgs h{};
+        h.A = dZ(l); h.a_m = kMlpOut; h.a_k = 1;
+        h.B = Ws[l]; h.b_k = kMlpHidden; h.b_n = 1;
+        h.M = rows; h.N = kMlpHidden; h.K = kMlpOut;
+        h.mask = ins[l]; h.mask_m = kMlpHidden; h.mask_n = 1;
+        h.Cb = dZ(l - 1); h.c_m = kMlpHidden; h.c_n = 1;
+        gemm(h, s);
+    }
+    // then every layer's weight gradient in one launch (split over the rows,
+    // the chunks added in order by one reduce launch) and every bias gradient
+    // in two: dW^T[n][k] = sum_r H[r][k] dZ[r][n]
     float *gWs[4] = {gW1, gW2, gW3, gW4};
-    for (int l = 3; l >= 0; --l) {
+    GemmArgs4 gs{};
+    int chunks = 1;
+    for (int l = 0; l < 4; ++l) {
         const int K = l == 0 ? kMlpIn : kMlpHidden;
-        // dW^T[n][k] = sum_r H[r][k] dZ[r][n]  -> M = 256 (n), N = K (k), contraction over rows
-        GemmArgs g{};
-        g.A = dZ; g.a_m = 1; g.a_k = kMlpOut;
+        GemmArgs &g = gs.g[l];
+        g.A = dZ(l); g.a_m = 1; g.a_k = kMlpOut;
         g.B = ins[l]; g.b_k = K; g.b_n = 1;
         g.M = kMlpOut; g.N = K; g.K = rows;
         g.Cf = gWs[l]; g.c_m = K; g.c_n = 1;
-        gemm(g, s, split);
-        const int nblk = cdiv(rows, kColRows);
-        k_col_partial<<<nblk, kMlpOut, 0, s>>>(dZ, rows, Z4);  // the logits in Z4 are spent by now
-        k_col_final<<<1, kMlpOut, 0, s>>>(Z4, nblk, gb + l * kMlpHidden);
-        if (l > 0) {
-            // dH[r][k] = sum_n dZ[r][n] W[n][k], masked by H > 0
-            GemmArgs h{};
-            h.A = dZ; h.a_m = kMlpOut; h.a_k = 1;
-            h.B = Ws[l]; h.b_k = K; h.b_n = 1;
-            h.M = rows; h.N = K; h.K = kMlpOut;
-            h.mask = ins[l]; h.mask_m = K; h.mask_n = 1;
-            h.Cb = dZn; h.c_m = K; h.c_n = 1;
-            gemm(h, s);
-            __bf16 *t = dZ;
-            dZ = dZn;
-            dZn = t;
-        }
+        chunks = prepare_split(g, split + (int64_t)l * kSplitMax * kMlpOut * kMlpHidden);
     }
+    k_gemm4<<<dim3(cdiv(kMlpHidden, kGT), cdiv(kMlpOut, kGT), 4 * chunks), 256, 0, s>>>(gs, chunks);
+    // a batch of at most 512 rows is not split (its sums go straight to the
+    // gradient, partial stays NULL): there is nothing to add up then
+    if (gs.g[0].partial)
+        k_gemm_reduce4<<<dim3(cdiv((int64_t)kMlpOut * kMlpHidden, 256), 4), 256, 0, s>>>(gs, chunks);
+    const int nblk = cdiv(rows, kColRows);
+    // (the split partial sums are spent by now: the bias partials go there)
+    k_col_partial<<<dim3(nblk, 4), kMlpOut, 0, s>>>(dZ0, rows, split);
+    k_col_final<<<4, kMlpOut, 0, s>>>(split, nblk, gb);
     return hipGetLastError();
 }
 
@@ -892,8 +962,8 @@ hipError_t proposal_set_params(Proposal &pr, hipStream_t s) {
 }
 
 size_t proposal_batch_scratch(int rows) {
-    return (size_t)rows * (kMlpIn + 3 * kMlpHidden + 2 * kMlpOut) * 2 + (size_t)rows * kMlpOut * 4 +
-           (size_t)kSplitMax * kMlpOut * kMlpHidden * 4 + 256;
+    return (size_t)rows * (kMlpIn + 3 * kMlpHidden + 4 * kMlpOut) * 2 + (size_t)rows * kMlpOut * 4 +
+           4 * (size_t)kSplitMax * kMlpOut * kMlpHidden * 4 + 256;
 }
 
 hipError_t proposal_features(const MeshDev &m, const float *from, const float *to, int64_t n, __bf16 *X,

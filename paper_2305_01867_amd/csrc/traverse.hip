@@ -321,19 +321,24 @@ __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why)
 // (unsure pairs, and in the nearest-hit modes the best sure hit): appended
 // for k_retest, which decides them in binary64.  False when the list is full
 // (the segment then goes to the second pass).
-__device__ __forceinline__ bool retest_push(const TravParams &p, int4 rec) {
+// A record is two int4: (segment, c0, c1, c2), (c3, c4, c5, c6), candidate
+// ids or -1.
+__device__ __forceinline__ bool retest_push(const TravParams &p, int4 a, int4 b) {
     if (!p.retest)
         return false;
     const uint32_t slot = atomicAdd(p.retest_len, 1u);
     if (slot >= p.retest_cap)
         return false;
-    p.retest[slot] = rec;
+    p.retest[2 * slot] = a;
+    p.retest[2 * slot + 1] = b;
     atomicAdd(p.counters, 1ull);  // re-decided in binary64
     return true;
 }
-// unsure pairs a lane lists for k_retest: three (boolean) or two beside the best sure hit
+// unsure pairs a lane lists for k_retest: seven (boolean), or six beside the
+// best sure hit (a segment aimed at a vertex meets the triangles around it)
+constexpr int kUnsureMax = 7;
 template <int MODE>
-constexpr int kUnsureSlots = MODE == MODE_BOOL ? 3 : 2;
+constexpr int kUnsureSlots = MODE == MODE_BOOL ? 7 : 6;
 
 // Pointers into LDS by address space, so reads of the LDS copy of the tree's
 // top compile to ds_read and are not merged with the global path.
@@ -510,11 +515,14 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     float best_t = INFINITY, best_lo = INFINITY, best_hi = INFINITY, best_u = 0.0f, best_v = 0.0f;
     bool found = false, unsure = false, flagged = false, overflow = false;
     // certified: the unsure pairs met so far (input triangle ids), for k_retest
-    int uns[3] = {-1, -1, -1};
+    int uns[kUnsureMax];
+#pragma unroll
+    for (int k = 0; k < kUnsureMax; ++k)
+        uns[k] = -1;
     int n_uns = 0;
     auto note_unsure = [&](int id) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < kUnsureMax; ++k)
             if (k == n_uns)
                 uns[k] = id;
         ++n_uns;
@@ -596,7 +604,9 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                     best_t = best_lo = best_hi = INFINITY;
                     best_u = best_v = 0.0f;
                     found = unsure = flagged = overflow = false;
-                    uns[0] = uns[1] = uns[2] = -1;
+#pragma unroll
+                    for (int k = 0; k < kUnsureMax; ++k)
+                        uns[k] = -1;
                     n_uns = 0;
                     n_nodes = n_tests = 0;
                     nk = 0;
@@ -942,7 +952,9 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                 if (!found && overflow)
                     enqueue(p, ray, 1);
                 else if (!found && CERT && unsure &&
-                         !(n_uns <= kUnsureSlots<MODE> && retest_push(p, make_int4((int)ray, uns[0], uns[1], uns[2]))))
+                         !(n_uns <= kUnsureSlots<MODE> &&
+                           retest_push(p, make_int4((int)ray, uns[0], uns[1], uns[2]),
+                                       make_int4(uns[3], uns[4], uns[5], uns[6]))))
                     enqueue(p, ray, 0);
                 put_hit(ray, found ? 1u : 0u);
             } else if (overflow) {
@@ -950,7 +962,8 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
             } else if (CERT && flagged) {
                 enqueue(p, ray, 0);
             } else if (CERT && n_uns > 0) {
-                if (!retest_push(p, make_int4((int)ray, best_id, uns[0], uns[1])))
+                if (!retest_push(p, make_int4((int)ray, best_id, uns[0], uns[1]),
+                                 make_int4(uns[2], uns[3], uns[4], uns[5])))
                     enqueue(p, ray, 0);
             } else if (CERT && MODE == MODE_BARY && best_id >= 0) {
                 if (p.bary_after) {  // (u, v, t) after both passes, a lane per segment
@@ -1430,15 +1443,15 @@ __global__ __launch_bounds__(256) void k_retest(TravParams p) {
     const uint32_t len = *p.retest_len;
     const uint32_t count = len < p.retest_cap ? len : p.retest_cap;
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < count; q += gridDim.x * blockDim.x) {
-        const int4 rec = p.retest[q];
+        const int4 rec = p.retest[2 * q], more = p.retest[2 * q + 1];
         const int64_t i = rec.x;
         const float *o = p.from + 3 * i, *e = p.to + 3 * i;
         const double ox = o[0], oy = o[1], oz = o[2], ex = e[0], ey = e[1], ez = e[2];
-        const int cand[3] = {rec.y, rec.z, rec.w};
+        const int cand[kUnsureMax] = {rec.y, rec.z, rec.w, more.x, more.y, more.z, more.w};
         int best = -1;
         double bu = 0.0, bv = 0.0, bt = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
+#pragma unroll 1
+        for (int k = 0; k < kUnsureMax; ++k) {
             const int id = cand[k];
             if (id < 0 || !valid_tri(p.F, p.nv, id) || (MODE == MODE_BOOL && best >= 0))
                 continue;

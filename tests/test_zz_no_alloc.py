@@ -69,8 +69,8 @@ def test_noalloc_with_a_segment_order_and_the_refusal():
         with pytest.raises(rsi.RSIError) as e:
             rsi.rsi_intersect_noalloc(mesh, big, big, out, mode="boolean")
         assert e.value.status == 6 and "scratch" in str(e.value)
-        # certified precision lists candidates too: 8,388,592 segments fit, one more does not
-        k = 8_388_593
+        # certified precision lists candidates too: 5,592,384 segments fit, one more does not
+        k = 5_592_385
         with pytest.raises(rsi.RSIError) as e:
             rsi.rsi_intersect_noalloc(mesh, big[:k], big[:k], {"hit": out["hit"][:k], "counters": out["counters"]},
                                       mode="boolean", precision="certified")
