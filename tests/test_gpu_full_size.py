@@ -99,3 +99,8 @@ def test_paper_scale_every_segment():
     _check_all("paper_scale", [("restructured", ("boolean", "first_hit", "barycentric", "intercept_count"), 0),
                                ("radix_tree", ("boolean", "first_hit"), 0),
                                ("restructured", ("boolean", "first_hit"), 2)])
+
+
+def test_precision_form_every_segment():
+    _check_all("precision", [("restructured", ("boolean", "first_hit", "barycentric", "intercept_count"), 0),
+                             ("radix_tree", ("boolean", "first_hit"), 0)])
