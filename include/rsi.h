@@ -147,10 +147,12 @@ typedef struct rsi_intersect_opts {
                              allow); 0 = the library default.  Fewer waves share a
                              CU's L1 cache among fewer tree paths. */
     int32_t node_width;   /* tree the first pass walks: 0 = the widest the mesh has
-                             (4 for build algorithms 0 and 2; binary for algorithm 1,
-                             the batched form and the proposal order), 2 = binary
-                             nodes, 4 = 4-wide nodes (RSI_E_ARG where not built).
-                             Results do not depend on it. */
+                             (4-wide for build algorithms 0 and 2 and for batches;
+                             binary for algorithm 1), 2 = binary nodes, 4 = 4-wide
+                             nodes (RSI_E_ARG where not built).  The proposal
+                             order walks a 4-wide tree of its own in which every
+                             bucket's subtree starts a node.  Results do not
+                             depend on it. */
 } rsi_intersect_opts;
 
 /* Output buffers (device pointers, caller-owned).  Required per mode:
@@ -365,7 +367,9 @@ rsi_status rsi_debug_certify(const float *rays_from, const float *rays_to, const
  * Learned subtree proposal.  A small MLP predicts, per segment, the depth-8
  * subtree ("bucket") of the tree that holds its first hit; rsi_intersect with
  * opts->proposal = 1 traverses that subtree first (and, in boolean mode, stops
- * at a sure hit there), then the rest of the tree without it.  The exact
+ * at a sure hit there), then the rest of the tree without it (on 4-wide nodes
+ * a second collapse, made when the proposal is created or loaded, keeps every
+ * bucket's subtree as a node of its own: 128 (N_t + 511) bytes more).  The exact
  * traversal and test decide every result, so results are identical to
  * proposal = 0; only the amount of work changes.
  * Network: inputs = the 6 end-point coordinates normalised to [-1, 1] over the
