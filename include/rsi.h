@@ -441,8 +441,9 @@ rsi_status rsi_proposal_load(rsi_mesh mesh, const char *path);
  * [vertex_offsets[m], vertex_offsets[m+1]) of the concatenated vertex array,
  * triangles [triangle_offsets[m], ...+1) whose indices are relative to its
  * own first vertex, and segments [ray_offsets[m], ...+1).  Keys are the mesh
- * id (6 bits) above a 57-bit Morton code (19 bits per axis of the mesh's own
- * box), so one sort, one radix tree and one bottom-up pass cover all meshes
+ * id (6 bits, bits 30..35 of the exported 64-bit keys) above a 30-bit Morton
+ * code (10 bits per axis of the mesh's own box), so one sort (five 8-bit
+ * passes), one radix tree and one bottom-up pass cover all meshes
  * and each mesh is one subtree.  The traversal takes (mesh, segment range)
  * items of up to 2048 segments from a queue.  Reported triangle indices are
  * relative to the segment's mesh.  rsi_batch_create allocates everything

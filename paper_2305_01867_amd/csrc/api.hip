@@ -819,6 +819,10 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     // the 4-wide tree (top slots, then one slot per binary internal node)
     const size_t sz_nodes4 = nt > 1 ? round_up(128 * (size_t)(nt - 1 + rsi::kTopSlots)) : 0;
     const size_t sz_roots4 = round_up(4 * (size_t)M) + round_up(4 * (size_t)rsi::kTopSlots);
+    // each XCD group's top and roots, and the mesh -> group map
+    const size_t sz_groups = nt > 1 ? round_up(sizeof(rsi::Node4) * rsi::kItemGroups * rsi::kTopSlots) +
+                                          round_up(4 * 64 * rsi::kItemGroups) + round_up(4 * (size_t)M)
+                                    : 0;
     const size_t sz_par = round_up(4 * (size_t)(nt > 0 ? 2 * nt - 1 : 1)), sz_cnt = round_up(4 * (size_t)(nt > 1 ? nt - 1 : 1));
     const size_t sz_tris = round_up(48 * (size_t)nt + 48), sz_small = 256;
     const size_t sz_tmp = round_up(rsi::sort_tmp_bytes(nt, 63));
@@ -827,7 +831,7 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     const size_t sz_items = round_up(16 * (size_t)(b.n_items + 1)) + round_up(4 * (rsi::kItemGroups + 1));
     const size_t sz_q = round_up(4 * (size_t)b.n_rays + 4) + 256;
     const size_t sz_order = round_up(rsi::ray_sort_ws_bytes(b.n_rays));
-    const size_t total = sz_V + sz_F + sz_keys + sz_ids + sz_nodes + sz_nodes4 + sz_roots4 + sz_par + sz_cnt +
+    const size_t total = sz_V + sz_F + sz_keys + sz_ids + sz_nodes + sz_nodes4 + sz_roots4 + sz_groups + sz_par + sz_cnt +
                          sz_tris + sz_small + sz_tmp + sz_off + sz_tm + sz_mb + sz_items + sz_q + sz_order;
     hipError_t e = hipMallocAsync(&bt->block, total, s);
     if (e != hipSuccess) {
@@ -851,6 +855,11 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     d.nodes4 = d.top4 ? d.top4 + rsi::kTopSlots : nullptr;
     b.roots4 = reinterpret_cast<int32_t *>(take(round_up(4 * (size_t)M)));
     b.slot_bin = reinterpret_cast<int32_t *>(take(round_up(4 * (size_t)rsi::kTopSlots)));
+    if (sz_groups) {
+        b.top4g = reinterpret_cast<rsi::Node4 *>(take(round_up(sizeof(rsi::Node4) * rsi::kItemGroups * rsi::kTopSlots)));
+        b.roots4g = reinterpret_cast<int32_t *>(take(round_up(4 * 64 * rsi::kItemGroups)));
+        b.mesh_group = reinterpret_cast<int32_t *>(take(round_up(4 * (size_t)M)));
+    }
     d.parent = reinterpret_cast<int32_t *>(take(sz_par));
     d.counters = reinterpret_cast<int32_t *>(take(sz_cnt));
     d.tris = reinterpret_cast<rsi::Tri *>(take(sz_tris));
@@ -890,6 +899,8 @@ rsi_status rsi_batch_create(int32_t n_meshes, const int64_t *vertex_offsets, con
     if (e == hipSuccess)
         e = hipMemcpyAsync(b.group_start, group_start.data(), 4 * (size_t)(rsi::kItemGroups + 1),
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && b.mesh_group)
+        e = hipMemcpyAsync(b.mesh_group, group_of.data(), 4 * (size_t)M, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);  // the host vectors go out of scope
     if (e != hipSuccess) {
@@ -985,6 +996,8 @@ rsi_status rsi_batch_intersect(rsi_batch batch, const float *rays_from, const fl
     a.n_meshes = b.M;
     a.mesh_root = b.roots;
     a.mesh_root4 = batch->dev.node_width == 4 ? b.roots4 : nullptr;
+    a.top4g = batch->dev.node_width == 4 ? b.top4g : nullptr;
+    a.roots4g = b.roots4g;
     a.mesh_toff = b.mesh_toff;
     a.ray_off = b.r_off;
     if (ray_sort != RSI_RAY_ORDER_INPUT) {

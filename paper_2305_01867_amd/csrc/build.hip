@@ -172,17 +172,18 @@ __global__ __launch_bounds__(256) void k_morton_batch(const float *__restrict__ 
     const int m = tri_mesh[t];
     const int32_t i0 = F[3 * t], i1 = F[3 * t + 1], i2 = F[3 * t + 2];
     if (i0 < 0 || i1 < 0 || i2 < 0) {  // marked invalid while copying
-        keys[t] = (uint64_t)m << 57;
+        keys[t] = (uint64_t)m << kBatchMortonBits;
         return;
     }
     const float *bb = mesh_bounds + 8 * m;
-    const float two_b = (float)(1u << 19), top = (float)((1u << 19) - 1u);
+    // 10 bits per axis of the mesh's own box, as the single-mesh 30-bit codes
+    const float two_b = (float)(1u << 10), top = (float)((1u << 10) - 1u);
     uint64_t key = 0;
     for (int a = 2; a >= 0; --a) {
         const float c = ((V[3 * (int64_t)i0 + a] + V[3 * (int64_t)i1 + a]) + V[3 * (int64_t)i2 + a]) / 3.0f;
         key = (key << 1) | spread3((uint64_t)quantise(c, bb[a], bb[3 + a] - bb[a], two_b, top));
     }
-    keys[t] = ((uint64_t)m << 57) | key;
+    keys[t] = ((uint64_t)m << kBatchMortonBits) | key;
 }
 
 // ---------------------------------------------------------- 3. radix sort
@@ -687,6 +688,18 @@ inline int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) /
 // ping-pong copies, the tile histograms and the scan partials.  An even
 // number of passes (key_bits 30 or 63 rounded up to 32 or 64) leaves the
 // result in (keys, ids).
+// After an odd number of passes the sorted pairs sit in the scratch buffers:
+// copy them back.
+template <typename K>
+__global__ void k_copy_pairs(const K *__restrict__ k_in, const int32_t *__restrict__ i_in, K *__restrict__ k_out,
+                             int32_t *__restrict__ i_out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        k_out[i] = k_in[i];
+        i_out[i] = i_in[i];
+    }
+}
+
 template <typename K>
 void sort_passes(K *keys, int32_t *ids, void *tmp, int64_t n, int key_bits, hipStream_t s) {
     K *keys_tmp = static_cast<K *>(tmp);
@@ -703,6 +716,8 @@ void sort_passes(K *keys, int32_t *ids, void *tmp, int64_t n, int key_bits, hipS
         K *tk = src_k; src_k = dst_k; dst_k = tk;
         int32_t *ti = src_i; src_i = dst_i; dst_i = ti;
     }
+    if (src_k != keys && n > 0)
+        k_copy_pairs<K><<<blocks_for(n, 256), 256, 0, s>>>(src_k, src_i, keys, ids, n);
 }
 
 size_t pass_tmp_bytes(int64_t n, size_t key_bytes) {
@@ -716,7 +731,7 @@ template <typename K>
 hipError_t build_from_keys(MeshDev &m, int key_bits, hipStream_t s) {
     const int64_t nt = m.nt;
     K *keys = static_cast<K *>(m.keys);
-    sort_passes<K>(keys, m.ids, m.sort_tmp, nt, key_bits, s);  // 4 or 8 passes: back in (keys, ids)
+    sort_passes<K>(keys, m.ids, m.sort_tmp, nt, key_bits, s);  // sorted pairs back in (keys, ids)
     if (m.algorithm == 1) {
         // the sort's scratch is free again: the exchange slots
         int32_t *other = static_cast<int32_t *>(m.sort_tmp);

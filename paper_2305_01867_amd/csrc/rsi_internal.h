@@ -121,6 +121,9 @@ struct MeshDev {
 // grouped, one group per XCD of the MI355X: the meshes are spread over the
 // groups by estimated cost, so each XCD's L2 holds the trees of a few meshes.
 constexpr int kItemGroups = 8;
+// Batched keys: the mesh id (6 bits, at most 64 meshes) above a 30-bit Morton
+// code over the mesh's own box, kept in 64-bit words.
+constexpr int kBatchMortonBits = 30;
 // Index in the traversal's queue words (after the queue length and the next
 // segment) of the first per-group item counter; the batch's queue area holds
 // them before its queue.
@@ -133,6 +136,9 @@ struct BatchDev {
     int32_t *roots = nullptr;                    // device [M] subtree root (INT32_MIN: empty)
     int32_t *roots4 = nullptr;                   // device [M] the same as 4-wide references
     int32_t *slot_bin = nullptr;                 // device [kTopSlots] binary node of each top slot
+    int32_t *mesh_group = nullptr;               // device [M] item group (XCD) of each mesh
+    Node4 *top4g = nullptr;                      // device [kItemGroups][kTopSlots] each group's meshes' top
+    int32_t *roots4g = nullptr;                  // device [kItemGroups][64] mesh roots as references in it
     int32_t *tri_mesh = nullptr;                 // device [nt]
     float *mesh_bounds = nullptr;                // device [M][8]
     int4 *items = nullptr;                       // device [n_items] (mesh, first, end, 0), grouped
@@ -225,6 +231,8 @@ struct TraverseArgs {
     int n_meshes = 0;
     const int32_t *mesh_root = nullptr;   // subtree root per mesh (INT32_MIN: empty)
     const int32_t *mesh_root4 = nullptr;  // the same in the 4-wide tree (NULL: binary nodes only)
+    const Node4 *top4g = nullptr;         // per XCD group: the top of its meshes (NULL: the combined top)
+    const int32_t *roots4g = nullptr;     // per XCD group: the mesh roots as references in it
     const int32_t *mesh_toff = nullptr;   // first triangle of each mesh
     const int32_t *ray_off = nullptr;     // [n_meshes + 1] first segment of each mesh
     // segment order: 0 input order, 1 Morton code of the midpoint, 2 direction

@@ -300,6 +300,12 @@ struct TravParams {
     int n_meshes;
     const int32_t *mesh_root;
     const int32_t *mesh_root4;  // the mesh roots as 4-wide references (first pass over 4-wide nodes)
+    // batched form, 4-wide, every top slot in LDS: each workgroup keeps the
+    // top of its XCD group's meshes (group blockIdx.x mod n_groups) instead
+    // of the combined tree's, with the mesh roots as references in it
+    const Node4 *top4g;
+    const int32_t *roots4g;
+    int top_group;
     const int32_t *mesh_toff;
     const int32_t *ray_off;
     const int32_t *order;  // segment at each processing position (NULL: input order)
@@ -412,12 +418,15 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     // 4-wide: the top of the tree in LDS, after the stacks (read-only once filled)
     const int ref_lim = WIDE ? n_internal + kTopSlots : n_internal;
     float4 *top_cache = reinterpret_cast<float4 *>(lds_stack + (p.stack_depth + 3) * stride);
+    const int group = p.n_groups > 0 ? (int)(blockIdx.x % p.n_groups) : 0;
     if (WIDE) {
-        const float4 *src = reinterpret_cast<const float4 *>(p.top4);
+        const Node4 *top = p.top_group ? p.top4g + (int64_t)group * kTopSlots : p.top4;
+        const float4 *src = reinterpret_cast<const float4 *>(top);
         for (int i = threadIdx.x; i < 8 * p.top_lds; i += stride)
             top_cache[i] = src[i];
         __syncthreads();
     }
+    const int32_t *roots4 = p.top_group ? p.roots4g + (int64_t)group * 64 : p.mesh_root4;
 
     // One mesh: each wave owns a contiguous range of segments and its lanes
     // draw from it.  Batched form: waves take (mesh, segment range) items from
@@ -554,7 +563,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                 // idles while work is left
 #pragma unroll 1
                 for (int t = 0; t < p.n_groups && item < 0; ++t) {
-                    const int g = (int)((blockIdx.x + t) % p.n_groups);
+                    const int g = (group + t) % p.n_groups;
                     if (groups_done & (1u << g))
                         continue;
                     uint32_t k = 0;
@@ -578,7 +587,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                 const int4 it = p.items[item];
                 cursor = it.y;
                 range_end = it.z;
-                cur_root = WIDE ? p.mesh_root4[it.x] : p.mesh_root[it.x];
+                cur_root = WIDE ? roots4[it.x] : p.mesh_root[it.x];
                 cur_toff = p.mesh_toff[it.x];
             } else {
                 items_left = false;
@@ -1632,6 +1641,9 @@ void launch_pass1(const TravParams &p, int block, hipStream_t s) {
         const int64_t slots = room > 0 ? room / (int64_t)sizeof(Node4) : 0;
         q.top_lds = (int)(slots < kTopSlots ? slots : kTopSlots);
     }
+    // a group's top replaces the combined one only when all of it is in LDS
+    // (a slot fetched from memory is read at the combined top's address)
+    q.top_group = (WIDE && p.items && p.top4g && q.top_lds == kTopSlots) ? 1 : 0;
     const size_t lds = stack_bytes + (size_t)q.top_lds * sizeof(Node4) + stage_bytes;
     void (*kern)(TravParams) = nullptr;
     if constexpr (MODE == MODE_COUNT)
@@ -1734,6 +1746,9 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.n_meshes = a.n_meshes;
     p.mesh_root = a.mesh_root;
     p.mesh_root4 = p.nodes4 ? a.mesh_root4 : nullptr;
+    p.top4g = p.nodes4 && a.items ? a.top4g : nullptr;
+    p.roots4g = p.top4g ? a.roots4g : nullptr;
+    p.top_group = 0;
     p.mesh_toff = a.mesh_toff;
     p.ray_off = a.ray_off;
     p.order = nullptr;

@@ -273,6 +273,85 @@ __global__ __launch_bounds__(kTopSlots) void k_top_cache(const Node4 *__restrict
         slot_bin[tid] = tid < b1 ? bidx[tid] : -1;
 }
 
+// Batched form: the top of each XCD group's meshes, breadth-first from their
+// roots (group g = blockIdx.x), laid out as k_top_cache lays out one tree's
+// top, and each mesh's root as a reference in it (a slot for the group's own
+// meshes, the node index + kTopSlots or a leaf reference for the others).
+__global__ __launch_bounds__(kTopSlots) void k_top_cache_group(const Node4 *__restrict__ nodes4,
+                                                               const int32_t *__restrict__ roots,
+                                                               const int32_t *__restrict__ mesh_group, int M,
+                                                               Node4 *__restrict__ top4g,
+                                                               int32_t *__restrict__ roots4g) {
+    constexpr int kWaves = kTopSlots / 64;
+    __shared__ int bidx[kTopSlots];
+    __shared__ int wave_sum[kWaves];
+    __shared__ int root_slot[64];
+    const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    Node4 *top4 = top4g + (int64_t)g * kTopSlots;
+    // the group's internal roots in mesh order take the first slots
+    if (w == 0) {
+        const bool mine = tid < M && mesh_group[tid] == g && roots[tid] >= 0;
+        const uint64_t all = __ballot(mine);  // the whole wave votes: not inside a lane branch
+        const int k = __popcll(all & (lane ? (~0ull >> (64 - lane)) : 0ull));
+        root_slot[tid] = mine ? k : -1;
+        if (mine)
+            bidx[k] = roots[tid];
+        if (lane == 0)
+            wave_sum[0] = __popcll(all);
+    }
+    __syncthreads();
+    int b0 = 0, b1 = wave_sum[0];
+    __syncthreads();
+    while (b0 < b1) {
+        const int i = b0 + tid;
+        Node4 nd;
+        int cnt = 0;
+        if (i < b1) {
+            nd = nodes4[bidx[i]];
+            cnt = (nd.child.x >= 0) + (nd.child.y >= 0) + (nd.child.z >= 0) + (nd.child.w >= 0);
+        }
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off);
+            incl += lane >= off ? t : 0;
+        }
+        if (lane == 63)
+            wave_sum[w] = incl;
+        __syncthreads();
+        int total = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            const int x = wave_sum[k];
+            incl += k < w ? x : 0;
+            total += x;
+        }
+        if (i < b1) {
+            int slot = b1 + incl - cnt;
+            int c[4] = {nd.child.x, nd.child.y, nd.child.z, nd.child.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (c[k] >= 0) {
+                    if (slot < kTopSlots) {
+                        bidx[slot] = c[k] - kTopSlots;
+                        c[k] = slot;
+                    }
+                    ++slot;
+                }
+            nd.child = make_int4(c[0], c[1], c[2], c[3]);
+            top4[i] = nd;
+        }
+        __syncthreads();  // bidx of the next level written, wave_sum read
+        b0 = b1;
+        b1 = b1 + total < kTopSlots ? b1 + total : kTopSlots;
+    }
+    if (tid < M) {
+        const int r = roots[tid];
+        const int sl = tid < 64 ? root_slot[tid] : -1;
+        roots4g[(int64_t)g * 64 + tid] = sl >= 0 ? sl : (r >= 0 ? r + kTopSlots : r);
+    }
+}
+
 __global__ void k_mark_frontier(const int32_t *__restrict__ bucket_ref, const int32_t *__restrict__ n_buckets,
                                 int32_t *flag, int64_t n_internal) {
     const int b = threadIdx.x;
@@ -296,15 +375,21 @@ __global__ void k_mark_mesh_roots(const int32_t *__restrict__ roots, int M, int3
 // 4-wide tree: its top slot if it has one, else binary index + kTopSlots;
 // a leaf keeps its leaf reference.
 // (The same for each mesh root of the batched form, n_buckets = NULL: count M.)
-__global__ void k_bucket_ref4(const int32_t *__restrict__ bucket_ref, const int32_t *__restrict__ n_buckets, int M,
-                              const int32_t *__restrict__ slot_bin, int32_t *__restrict__ ref4) {
+// One workgroup of kTopSlots threads: the slot map is staged in LDS first.
+__global__ __launch_bounds__(kTopSlots) void k_bucket_ref4(const int32_t *__restrict__ bucket_ref,
+                                                           const int32_t *__restrict__ n_buckets, int M,
+                                                           const int32_t *__restrict__ slot_bin,
+                                                           int32_t *__restrict__ ref4) {
+    __shared__ int bin[kTopSlots];
     const int b = threadIdx.x;
+    bin[b] = slot_bin[b];
+    __syncthreads();
     if (b >= (n_buckets ? *n_buckets : M))
         return;
     const int c = bucket_ref[b];
     int r = c >= 0 ? c + kTopSlots : c;
     for (int k = 0; k < kTopSlots; ++k)
-        r = c >= 0 && slot_bin[k] == c ? k : r;
+        r = c >= 0 && bin[k] == c ? k : r;
     ref4[b] = r;
 }
 
@@ -343,7 +428,7 @@ hipError_t launch_collapse_proposal(const MeshDev &m, Proposal &pr, hipStream_t 
     k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, pr.top4 + kTopSlots, pr.wide_flag, kFrontier, 0, pr.wide_queue,
                                       n_internal);
     k_top_cache<<<1, kTopSlots, 0, s>>>(pr.top4 + kTopSlots, pr.top4, pr.slot_bin);
-    k_bucket_ref4<<<1, kMlpOut, 0, s>>>(pr.bucket_ref, pr.dev_n_buckets, 0, pr.slot_bin, pr.bucket_ref4);
+    k_bucket_ref4<<<1, kTopSlots, 0, s>>>(pr.bucket_ref, pr.dev_n_buckets, 0, pr.slot_bin, pr.bucket_ref4);
     return hipGetLastError();
 }
 
@@ -370,7 +455,10 @@ hipError_t launch_collapse_batch(MeshDev &m, BatchDev &b, hipStream_t s) {
     k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, m.nodes4, L.tile_flag, kTileRoot | kMeshRoot, kTileRoot, L.queue,
                                       n_internal);
     k_top_cache<<<1, kTopSlots, 0, s>>>(m.nodes4, m.top4, b.slot_bin);
-    k_bucket_ref4<<<1, 64, 0, s>>>(b.roots, nullptr, b.M, b.slot_bin, b.roots4);
+    k_bucket_ref4<<<1, kTopSlots, 0, s>>>(b.roots, nullptr, b.M, b.slot_bin, b.roots4);
+    if (b.top4g)
+        k_top_cache_group<<<kItemGroups, kTopSlots, 0, s>>>(m.nodes4, b.roots, b.mesh_group, b.M, b.top4g,
+                                                            b.roots4g);
     const hipError_t e = hipGetLastError();
     m.node_width = e == hipSuccess ? 4 : 2;
     return e;

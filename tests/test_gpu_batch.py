@@ -49,10 +49,13 @@ def test_batch_equals_single_mesh_and_oracle():
     with rsi.rsi_batch_create(vo, to, ro) as b:
         rsi.rsi_batch_build(b, dev(V), dev(F))
         dO, dE = dev(O), dev(E)
-        for mode, prec, width in [(m, p, w) for m in MODES for p in ("certified", "plain") for w in (0, 2)]:
+        # 4-wide with each XCD group's top in LDS (1024-thread workgroups), 4-wide
+        # with the combined top (256 threads: not every slot fits), binary nodes
+        for mode, prec, width, block in [(m, p, w, bl) for m in MODES for p in ("certified", "plain")
+                                         for w, bl in ((0, 0), (0, 256), (2, 0))]:
             if True:
                 got = {k: host(v) for k, v in rsi.rsi_batch_intersect(b, dO, dE, mode=mode, precision=prec,
-                                                                      node_width=width).items()}
+                                                                      node_width=width, block=block).items()}
                 for m, (Vm, Fm, Om, Em) in enumerate(parts):
                     sl = slice(ro[m], ro[m + 1])
                     if len(Om) == 0:
@@ -62,7 +65,7 @@ def test_batch_equals_single_mesh_and_oracle():
                                                                         precision=prec).items()}
                     for k in one:
                         if k != "counters":
-                            assert np.array_equal(got[k][sl], one[k], equal_nan=True), (mode, prec, width, m, k)
+                            assert np.array_equal(got[k][sl], one[k], equal_nan=True), (mode, prec, width, block, m, k)
                     if prec == "certified":
                         hit, ids, uvt, _ = oracle.intersect(Vm, Fm, Om, Em) if len(Fm) else (
                             np.zeros(len(Om), np.uint8), np.full(len(Om), -1, np.int32), None, None)
@@ -80,7 +83,7 @@ def test_combined_tree_keeps_each_mesh_in_one_subtree():
         roots = host(rsi.rsi_batch_export(b, "mesh_roots"))
         counters = host(rsi.rsi_batch_export(b, "counters"))
     assert np.all(np.diff(keys.astype(np.float64)) >= 0)
-    mesh_of_key = (keys >> np.uint64(57)).astype(np.int64)
+    mesh_of_key = (keys >> np.uint64(30)).astype(np.int64)
     mesh_of_tri = np.searchsorted(to, np.arange(F.shape[0]), side="right") - 1
     assert np.array_equal(mesh_of_key, mesh_of_tri[ids])
     assert np.all(counters == 2)
