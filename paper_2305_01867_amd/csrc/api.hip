@@ -1060,13 +1060,14 @@ static rsi_status ensure_proposal(rsi_mesh mesh, hipStream_t s, uint64_t seed, b
     if (!pr.block) {
         const size_t f = round_up(4 * (size_t)rsi::kMlpParams);
         const size_t wb = round_up(2 * (size_t)rsi::kMlpWeights);
+        const size_t wbt = round_up(2 * 3 * (size_t)rsi::kMlpHidden * rsi::kMlpHidden);
         const size_t small = round_up(4 * 256) * 2 + 256;
         const size_t rk = round_up(4 * (size_t)d.nt), lbk = round_up((size_t)d.nt);
         // the proposal order's 4-wide tree, where the mesh has one
         const bool wide = d.node_width == 4 && d.nt > 1;
         const size_t w4 = wide ? sizeof(rsi::Node4) * (size_t)(rsi::kTopSlots + d.nt - 1) : 0;
         const size_t wsmall = wide ? round_up(4 * 256) + round_up(4 * rsi::kTopSlots) + 2 * rk : 0;
-        hipError_t e = hipMallocAsync(&pr.block, 4 * f + wb + small + rk + lbk + w4 + wsmall, s);
+        hipError_t e = hipMallocAsync(&pr.block, 4 * f + wb + wbt + small + rk + lbk + w4 + wsmall, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             pr.block = nullptr;
@@ -1078,6 +1079,7 @@ static rsi_status ensure_proposal(rsi_mesh mesh, hipStream_t s, uint64_t seed, b
         pr.m1 = reinterpret_cast<float *>(p); p += f;
         pr.m2 = reinterpret_cast<float *>(p); p += f;
         pr.Wb = reinterpret_cast<__bf16 *>(p); p += wb;
+        pr.WbT = reinterpret_cast<__bf16 *>(p); p += wbt;
         pr.bucket_ref = reinterpret_cast<int32_t *>(p); p += round_up(4 * 256);
         pr.bucket_first = reinterpret_cast<int32_t *>(p); p += round_up(4 * 256);
         pr.dev_n_buckets = reinterpret_cast<int32_t *>(p); p += 256;
@@ -1208,11 +1210,10 @@ rsi_status rsi_proposal_train(rsi_mesh mesh, const float *rays_from, const float
             const int64_t r0 = b * batch;
             const int rows = (int)(n_lab - r0 < batch ? n_lab - r0 : batch);
             // each batch adds (its mean loss) * rows / n_lab: the epoch's mean loss
+            const rsi::AdamStep step{lr, (int)(++pr.step)};
             e = rsi::proposal_batch_grad(mesh->dev, pr, rays_from, rays_to, seg, lab, r0, rows, pr.n_buckets,
                                          epoch_loss ? epoch_loss + ep : loss_sink, 1.0f / (float)n_lab, ws, s,
-                                         nullptr);
-            if (e == hipSuccess)
-                e = rsi::proposal_adam(pr, lr, (int)(++pr.step), s);
+                                         nullptr, &step);
         }
     }
     if (e != hipSuccess) {
@@ -1297,7 +1298,7 @@ rsi_status rsi_proposal_gradient(rsi_mesh mesh, const float *rays_from, const fl
     e = hipMemsetAsync(loss, 0, 4, s);
     if (e == hipSuccess)
         e = rsi::proposal_batch_grad(mesh->dev, pr, rays_from, rays_to, nullptr, labels, 0, (int)n_rays,
-                                     pr.n_buckets, loss, 0.0f, static_cast<char *>(ws), s, logits);
+                                     pr.n_buckets, loss, 0.0f, static_cast<char *>(ws), s, logits, nullptr);
     if (e == hipSuccess)
         e = hipMemcpyAsync(grad, pr.G, 4 * (size_t)rsi::kMlpParams, hipMemcpyDeviceToDevice, s);
     (void)hipFreeAsync(ws, s);

@@ -122,6 +122,8 @@ struct GemmArgs {
 };
 
 constexpr int kGT = 64, kGK = 32, kGPad = 8;
+constexpr int kSplitMax = 16;  // split-K chunks of a long contraction (the weight gradients)
+constexpr int kSplitRows = 512;  // rows per chunk of the weight gradients' split
 // k steps of kGK staged through LDS together, so a workgroup synchronises
 // once per kGSub * kGK of the contraction (each wave: 4 * kGSub MFMA per stage)
 constexpr int kGSub = 4;
@@ -254,12 +256,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int
             }
 }
 
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-    __shared__ __bf16 As[kGT][kGPitch];
-    __shared__ __bf16 Bs[kGT][kGPitch];  // stored [n][k]
-    gemm_tile(g, blockIdx.x, blockIdx.y, blockIdx.z, As, Bs);
-}
-
 // The four layers' weight gradients in one launch: z = layer x split chunk.
 struct GemmArgs4 {
     GemmArgs g[4];
@@ -269,140 +265,6 @@ __global__ __launch_bounds__(256) void k_gemm4(GemmArgs4 gs, int chunks) {
     __shared__ __bf16 Bs[kGT][kGPitch];
     const int layer = blockIdx.z / chunks;
     gemm_tile(gs.g[layer], blockIdx.x, blockIdx.y, blockIdx.z % chunks, As, Bs);
-}
-
-// Cf = the split-K partial sums added in chunk order (deterministic).
-__device__ __forceinline__ void reduce_split(const float *__restrict__ partial, int chunks, int M, int N,
-                                             float *__restrict__ Cf, int64_t c_m, int64_t c_n, int64_t i) {
-    const int64_t mn = (int64_t)M * N;
-    if (i >= mn)
-        return;
-    float s = 0.0f;
-    for (int z = 0; z < chunks; ++z)
-        s += partial[z * mn + i];
-    const int m = (int)(i / N), n = (int)(i % N);
-    Cf[m * c_m + n * c_n] = s;
-}
-
-__global__ __launch_bounds__(256) void k_gemm_reduce(const float *__restrict__ partial, int chunks, int M, int N,
-                                                     float *__restrict__ Cf, int64_t c_m, int64_t c_n) {
-    reduce_split(partial, chunks, M, N, Cf, c_m, c_n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-}
-
-__global__ __launch_bounds__(256) void k_gemm_reduce4(GemmArgs4 gs, int chunks) {
-    const GemmArgs &g = gs.g[blockIdx.y];
-    if (!g.partial)
-        return;
-    reduce_split(g.partial, chunks, g.M, g.N, g.Cf, g.c_m, g.c_n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-}
-
-// ------------------------------------------------- softmax cross-entropy
-// One row per wave: p = softmax(z over the first nb logits); the gradient of
-// the mean loss is (p - onehot(y)) / rows (0 for masked columns).  Writes the
-// row's loss times loss_scale to row_loss[row] (k_loss_sum adds them up).
-__global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z, const int32_t *__restrict__ y,
-                                                    int rows, int nb, float inv_rows, float loss_scale,
-                                                    __bf16 *__restrict__ dZ, float *__restrict__ row_loss) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= rows)
-        return;
-    const float *z = Z + (int64_t)row * kMlpOut;
-    float v[4];
-    float mx = -INFINITY;
-    for (int j = 0; j < 4; ++j) {
-        const int c = lane + 64 * j;
-        v[j] = c < nb ? z[c] : -INFINITY;
-        mx = fmaxf(mx, v[j]);
-    }
-    for (int off = 32; off > 0; off >>= 1)
-        mx = fmaxf(mx, __shfl_xor(mx, off));
-    float s = 0.0f;
-    for (int j = 0; j < 4; ++j)
-        s += (lane + 64 * j) < nb ? expf(v[j] - mx) : 0.0f;
-    for (int off = 32; off > 0; off >>= 1)
-        s += __shfl_xor(s, off);
-    const int label = y[row];
-    for (int j = 0; j < 4; ++j) {
-        const int c = lane + 64 * j;
-        float g = 0.0f;
-        if (c < nb)
-            g = (expf(v[j] - mx) / s - (c == label ? 1.0f : 0.0f)) * inv_rows;
-        dZ[(int64_t)row * kMlpOut + c] = (__bf16)g;
-    }
-    if (lane == 0)
-        row_loss[row] = label >= 0 && label < nb ? (logf(s) + mx - z[label]) * loss_scale : 0.0f;
-}
-
-// *loss += the sum of row_loss[0 .. rows) in a fixed order (one workgroup:
-// strided sums per lane, then a fixed tree), so the reported loss does not
-// depend on scheduling.
-__global__ __launch_bounds__(256) void k_loss_sum(const float *__restrict__ row_loss, int rows,
-                                                  float *__restrict__ loss) {
-    __shared__ float part[256];
-    float v = 0.0f;
-    for (int r = threadIdx.x; r < rows; r += 256)
-        v += row_loss[r];
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
-            part[threadIdx.x] += part[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        *loss += part[0];
-}
-
-// db[n] = sum over rows of dZ[row][n] (fp32 from bf16), in two fixed-order
-// stages: partial[b][n] over rows [64 b, 64 b + 64), then the partials in
-// order -- deterministic, and 64x more parallel than one pass.
-constexpr int kColRows = 64;
-
-// (blockIdx.y = layer: dZ and partial advance by rows x 256 and nblk x 256)
-__global__ __launch_bounds__(256) void k_col_partial(const __bf16 *__restrict__ dZ, int rows,
-                                                     float *__restrict__ partial) {
-    const int n = threadIdx.x, b = blockIdx.x;
-    dZ += (int64_t)blockIdx.y * rows * kMlpOut;
-    partial += (int64_t)blockIdx.y * gridDim.x * kMlpOut;
-    const int r1 = min(rows, (b + 1) * kColRows);
-    float s = 0.0f;
-#pragma unroll 16
-    for (int r = b * kColRows; r < r1; ++r)  // unrolled: the loads issue ahead of the in-order adds
-        s += (float)dZ[(int64_t)r * kMlpOut + n];
-    partial[(int64_t)b * kMlpOut + n] = s;
-}
-
-// (blockIdx.x = layer)
-__global__ __launch_bounds__(256) void k_col_final(const float *__restrict__ partial, int nblk,
-                                                   float *__restrict__ db) {
-    const int n = threadIdx.x;
-    partial += (int64_t)blockIdx.x * nblk * kMlpOut;
-    db += (int64_t)blockIdx.x * kMlpHidden;
-    float s = 0.0f;
-#pragma unroll 16
-    for (int b = 0; b < nblk; ++b)
-        s += partial[(int64_t)b * kMlpOut + n];
-    db[n] = s;
-}
-
-// Adam on the fp32 master parameters; refreshes the bf16 copy of the weights.
-__global__ __launch_bounds__(256) void k_adam(float *__restrict__ P, const float *__restrict__ G,
-                                              float *__restrict__ m1, float *__restrict__ m2,
-                                              __bf16 *__restrict__ Wb, int64_t n_params, int64_t n_weights,
-                                              float lr, float b1, float b2, float eps, float c1, float c2) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_params)
-        return;
-    const float g = G[i];
-    const float a = b1 * m1[i] + (1.0f - b1) * g;
-    const float b = b2 * m2[i] + (1.0f - b2) * g * g;
-    m1[i] = a;
-    m2[i] = b;
-    const float w = P[i] - lr * (a * c1) / (sqrtf(b * c2) + eps);
-    P[i] = w;
-    if (i < n_weights)
-        Wb[i] = (__bf16)w;
 }
 
 // Uniform(-a, a) initial weights from a counter-based hash (seed, index).
@@ -415,8 +277,34 @@ __device__ __forceinline__ uint32_t mix32(uint64_t x) {
     return (uint32_t)x;
 }
 
+// The bf16 weights are kept in MFMA fragment order: a layer with K inputs is
+// a sequence of 16-column x 32-k blocks (column tile major, then k step),
+// each 1 KB block laid out as the B operand's lanes take it (lane l: column
+// l % 16, k = 8 (l / 16) .. + 7), so one wave-wide 16-byte load reads one
+// whole block, eight full cache lines.
+__host__ __device__ constexpr int64_t frag_index(int col, int k, int K) {
+    return ((((int64_t)(col >> 4) * (K >> 5) + (k >> 5)) * 64 + (col & 15) + 16 * ((k & 31) >> 3)) << 3) + (k & 7);
+}
+
+// bf16 copies of weight i (layer l's W[out][in]): Wb in fragment order with
+// columns = outputs (the forward product), and for layers 2..4 WbT in
+// fragment order with columns = inputs (the backward product)
+__device__ __forceinline__ void store_weight(__bf16 *__restrict__ Wb, __bf16 *__restrict__ WbT, int64_t i, float w) {
+    const __bf16 h = (__bf16)w;
+    const int64_t first = (int64_t)kMlpOut * kMlpIn, hh = (int64_t)kMlpHidden * kMlpHidden;
+    if (i < first) {
+        Wb[frag_index((int)(i / kMlpIn), (int)(i % kMlpIn), kMlpIn)] = h;
+    } else {
+        const int64_t l = (i - first) / hh, j = (i - first) % hh;
+        const int o = (int)(j / kMlpHidden), in = (int)(j % kMlpHidden);
+        Wb[first + l * hh + frag_index(o, in, kMlpHidden)] = h;
+        WbT[l * hh + frag_index(in, o, kMlpHidden)] = h;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_init_params(float *__restrict__ P, __bf16 *__restrict__ Wb,
-                                                     float *__restrict__ m1, float *__restrict__ m2, uint64_t seed) {
+                                                     __bf16 *__restrict__ WbT, float *__restrict__ m1,
+                                                     float *__restrict__ m2, uint64_t seed) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kMlpParams)
         return;
@@ -428,7 +316,7 @@ __global__ __launch_bounds__(256) void k_init_params(float *__restrict__ P, __bf
         w = (2.0f * u - 1.0f) * a;
         if (i < (int64_t)kMlpOut * kMlpIn && (i % kMlpIn) >= kMlpFeat)
             w = 0.0f;  // padding features carry no weight
-        Wb[i] = (__bf16)w;
+        store_weight(Wb, WbT, i, w);
     }
     P[i] = w;
     m1[i] = 0.0f;
@@ -456,10 +344,11 @@ constexpr int kPThreads = 64 * kPWaves;
 constexpr int kPColTiles = kMlpHidden / 16 / kPWaves;  // 16-column tiles per wave
 constexpr int kPAhead = 2;                          // k steps the weight loads run ahead (1: 8.0 ms, 2: 7.6, 3: 7.6, 4: 7.7)
 
+template <int RT>
 __device__ __forceinline__ void tile_step(const __bf16 *__restrict__ xrow, int k0, const bf16x8 (&fb)[kPColTiles],
-                                          f32x4 (&acc)[kPRowTiles][kPColTiles]) {
+                                          f32x4 (&acc)[RT][kPColTiles]) {
 #pragma unroll
-    for (int a = 0; a < kPRowTiles; ++a) {
+    for (int a = 0; a < RT; ++a) {
         const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(xrow + 16 * a * kPPitch + k0);
 #pragma unroll
         for (int b = 0; b < kPColTiles; ++b)
@@ -471,32 +360,35 @@ __device__ __forceinline__ void tile_step(const __bf16 *__restrict__ xrow, int k
 // every step's weight fragments are registers of their own: step st + kPAhead's
 // loads are issued before step st multiplies and stay in flight across it,
 // with no register copy that would wait for them.
-template <int K>
+// RT row tiles of 16 (activations in LDS at pitch kPPitch), the wave's
+// kPColTiles column tiles, weight loads AHEAD k steps early.
+template <int K, int RT = kPRowTiles, int AHEAD = kPAhead>
 __device__ __forceinline__ void layer_tile(const __bf16 *__restrict__ Xin, const __bf16 *__restrict__ Wt, int wave,
-                                           int lane, f32x4 (&acc)[kPRowTiles][kPColTiles]) {
+                                           int lane, f32x4 (&acc)[RT][kPColTiles]) {
     static_assert(K % 32 == 0, "K must be a multiple of 32");
     constexpr int kSteps = K / 32;
 #pragma unroll
-    for (int a = 0; a < kPRowTiles; ++a)
+    for (int a = 0; a < RT; ++a)
 #pragma unroll
         for (int b = 0; b < kPColTiles; ++b)
             acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const int kq = 8 * (lane >> 4);
-    const __bf16 *wrow = Wt + (int64_t)(16 * kPColTiles * wave + (lane & 15)) * K + kq;
+    // the wave's first column tile, this lane's 16 bytes of each block
+    const __bf16 *wfrag = Wt + (int64_t)kPColTiles * wave * kSteps * 512 + 8 * lane;
     const __bf16 *xrow = Xin + (lane & 15) * kPPitch + kq;
     bf16x8 f[kSteps][kPColTiles];
 #pragma unroll
-    for (int st = 0; st < kPAhead && st < kSteps; ++st)
+    for (int st = 0; st < AHEAD && st < kSteps; ++st)
 #pragma unroll
         for (int b = 0; b < kPColTiles; ++b)
-            f[st][b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K + 32 * st);
+            f[st][b] = *reinterpret_cast<const bf16x8 *>(wfrag + (int64_t)(b * kSteps + st) * 512);
 #pragma unroll
     for (int st = 0; st < kSteps; ++st) {
-        if (st + kPAhead < kSteps)
+        if (st + AHEAD < kSteps)
 #pragma unroll
             for (int b = 0; b < kPColTiles; ++b)
-                f[st + kPAhead][b] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * b * K + 32 * (st + kPAhead));
-        tile_step(xrow, 32 * st, f[st], acc);
+                f[st + AHEAD][b] = *reinterpret_cast<const bf16x8 *>(wfrag + (int64_t)(b * kSteps + st + AHEAD) * 512);
+        tile_step<RT>(xrow, 32 * st, f[st], acc);
         __builtin_amdgcn_sched_barrier(0);  // keep each step's loads in its step: no hoisting past the register budget
     }
 }
@@ -616,6 +508,325 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(kPWav
 }
 
 constexpr size_t kProposeLds = (size_t)kPRows * kPPitch * sizeof(__bf16) + 2 * kPWaves * (size_t)kPRows * 4;
+
+// ------------------------------------------------ fused training pass
+// One workgroup per kTRows rows of a batch: the features, the four layers
+// forward, softmax cross-entropy and the chain of input gradients back to
+// the first layer, with the activations and gradients of the tile in LDS and
+// written out (bf16, column-major) for the weight gradients.  The layer
+// products run through layer_tile, the inference kernel's, so the logits
+// equal those of k_mlp_propose bit for bit.  A workgroup
+// also writes the column sums of each layer's gradient over its rows (the
+// bias gradients, added over the tiles in order by k_grad_finish) and the sum
+// of its rows' losses.  The backward products read the transposed copy of
+// the hidden weights, so both directions load 16 contiguous bytes per lane.
+constexpr int kTRows = 32;
+constexpr int kTRowTiles = kTRows / 16;
+constexpr int kTAhead = 4;
+static_assert(kTRows % 16 == 0 && kTRows <= 64, "whole row tiles; the loss sum reads one row per lane");
+
+struct TrainArgs {
+    const float *from, *to;
+    const int32_t *seg;  // segment of batch row r0 + r (NULL: the segment is r0 + r)
+    const int32_t *lab;  // label of batch row r0 + r
+    int64_t r0;
+    int rows, nb;
+    const float *bounds;
+    const __bf16 *Wb;    // [out][in] per layer
+    const __bf16 *WbT;   // layers 2..4 transposed, [in][out]
+    const float *bias;   // [4][256]
+    int64_t ld;          // rows rounded up to whole tiles: the row stride of the arrays below
+    __bf16 *X0;          // [224][ld]: the features, column-major
+    __bf16 *H;           // [3][256][ld]: the hidden activations, column-major
+    __bf16 *dZ;          // [4][256][ld]: gradients of the pre-activations, column-major
+    float *logits;       // [rows][256], or NULL
+    float *bias_part;    // [tiles][4][256]
+    float *loss_part;    // [tiles]
+    float inv_rows, loss_scale;
+};
+
+// LDS: the activations (the logits later take their place and more), the
+// gradients, the ReLU masks as wave ballots in the MFMA output layout, and
+// the per-wave column sums and row losses of the softmax.
+constexpr int kTMaskWords = kTRowTiles * kPColTiles * 4 * 4;  // (row tile, col tile, i, wave) per layer
+constexpr size_t kTActBytes = (size_t)kTRows * kPPitch * sizeof(__bf16);
+constexpr int kLPitch = kMlpOut + 16;  // logits row pitch (floats): four rows on disjoint LDS banks
+constexpr size_t kTLogitBytes = (size_t)kTRows * kLPitch * sizeof(float);
+static_assert(kTLogitBytes >= kTActBytes, "the logits take the activations' place");
+constexpr size_t kTrainLds = kTLogitBytes + kTActBytes + 3 * (size_t)kTMaskWords * sizeof(uint64_t) +
+                             4 * (size_t)kMlpOut * sizeof(float) + (size_t)kTRows * sizeof(float);
+
+// The tile's rows of an LDS array (pitch kPPitch, `cols` columns) into a
+// column-major global array T[col][ld] at rows t0 .. t0 + kTRows (padding
+// rows go out too: zero features, zero gradients), 16 bytes per lane, four
+// lanes per column: the weight-gradient product then reads both operands
+// contiguous along the rows.
+__device__ __forceinline__ void copy_cols(const __bf16 *S, __bf16 *T, int64_t ld, int t0, int cols, int tid) {
+    constexpr int kG = kTRows / 8;
+    for (int i = tid; i < cols * kG; i += 256) {
+        const int col = i / kG, g = i % kG;
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            v[j] = S[(8 * g + j) * kPPitch + col];
+        *reinterpret_cast<bf16x8 *>(T + (int64_t)col * ld + t0 + 8 * g) = v;
+    }
+}
+
+// Max / sum over the 16 lanes of a DPP row, every lane ending with the same
+// value: rotations by 8, 4, 2 and 1 within the row, each step adding two
+// operands that are equal up to order (so every lane rounds the same sums).
+__device__ __forceinline__ float dpp_ror(float v, int n) {
+    switch (n) {
+    case 8: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, false));
+    case 4: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xf, 0xf, false));
+    case 2: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xf, 0xf, false));
+    default: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, false));
+    }
+}
+__device__ __forceinline__ float row16_max(float v) {
+    v = fmaxf(v, dpp_ror(v, 8));
+    v = fmaxf(v, dpp_ror(v, 4));
+    v = fmaxf(v, dpp_ror(v, 2));
+    return fmaxf(v, dpp_ror(v, 1));
+}
+__device__ __forceinline__ float row16_sum(float v) {
+    v += dpp_ror(v, 8);
+    v += dpp_ror(v, 4);
+    v += dpp_ror(v, 2);
+    return v + dpp_ror(v, 1);
+}
+
+__global__ __launch_bounds__(256) void k_train_tile(TrainArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __bf16 *X = reinterpret_cast<__bf16 *>(lds_raw);                  // activations [kTRows][kPPitch]
+    float *L = reinterpret_cast<float *>(lds_raw);                     // logits [kTRows][256], over X
+    __bf16 *D = reinterpret_cast<__bf16 *>(lds_raw + kTLogitBytes);    // gradients [kTRows][kPPitch]
+    uint64_t *Msk = reinterpret_cast<uint64_t *>(lds_raw + kTLogitBytes + kTActBytes);  // [3][kTMaskWords]
+    float *csum = reinterpret_cast<float *>(Msk + 3 * kTMaskWords);   // [4 waves][256]
+    float *rl = csum + 4 * kMlpOut;                                    // [kTRows] row losses
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = blockIdx.x, t0 = tile * kTRows;
+    const int nrows = min(kTRows, a.rows - t0);
+    // features; rows past the batch are zero
+    for (int q = tid; q < kTRows * 7; q += 256) {
+        const int r = q / 7, part = q % 7;
+        __bf16 *row = X + r * kPPitch;
+        if (part == 6) {
+            for (int j = kMlpFeat; j < kMlpIn; ++j)
+                row[j] = (__bf16)0.0f;
+        } else if (r < nrows) {
+            const int64_t br = a.r0 + t0 + r;
+            const int64_t seg = a.seg ? a.seg[br] : br;
+            const float x = norm_coord(seg_coord(a.from, a.to, seg, part), a.bounds[part % 3], a.bounds[3 + part % 3]);
+            coord_features(x, part, row);
+        } else {
+            row[part] = (__bf16)0.0f;
+            for (int k = 0; k < 2 * kMlpBands; ++k)
+                row[6 + part * 2 * kMlpBands + k] = (__bf16)0.0f;
+        }
+    }
+    __syncthreads();
+    copy_cols(X, a.X0, a.ld, t0, kMlpIn, tid);
+    // forward: each layer's output over its input in X once every wave has read it
+    f32x4 acc[kTRowTiles][kPColTiles];
+#pragma unroll 1
+    for (int l = 0; l < 4; ++l) {
+        const int64_t woff = l == 0 ? 0 : (int64_t)kMlpOut * kMlpIn + (int64_t)(l - 1) * kMlpHidden * kMlpHidden;
+        if (l == 0)
+            layer_tile<kMlpIn, kTRowTiles, kTAhead>(X, a.Wb + woff, wave, lane, acc);
+        else
+            layer_tile<kMlpHidden, kTRowTiles, kTAhead>(X, a.Wb + woff, wave, lane, acc);
+        __syncthreads();
+        const float *bl = a.bias + l * kMlpHidden;
+#pragma unroll
+        for (int b = 0; b < kPColTiles; ++b) {
+            const int col = 16 * kPColTiles * wave + 16 * b + (lane & 15);
+            const float bv = bl[col];
+#pragma unroll
+            for (int t = 0; t < kTRowTiles; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * t + 4 * (lane >> 4) + i;
+                    const float v = acc[t][b][i] + bv;
+                    if (l < 3) {
+                        const __bf16 h = (__bf16)fmaxf(v, 0.0f);
+                        X[row * kPPitch + col] = h;
+                        // ReLU mask of the backward pass, kept in the layout its epilogue reads
+                        const uint64_t m = __ballot((float)h > 0.0f);
+                        if (lane == 0)
+                            Msk[l * kTMaskWords + ((t * kPColTiles + b) * 4 + i) * 4 + wave] = m;
+                    } else {
+                        L[row * kLPitch + col] = v;
+                    }
+                }
+        }
+        __syncthreads();
+        if (l < 3)
+            copy_cols(X, a.H + (int64_t)l * kMlpHidden * a.ld, a.ld, t0, kMlpHidden, tid);
+        else if (a.logits)
+            for (int i = tid; i < nrows * kMlpOut; i += 256)
+                a.logits[(int64_t)t0 * kMlpOut + i] = L[(i / kMlpOut) * kLPitch + i % kMlpOut];
+    }
+    // softmax cross-entropy: four rows of a wave at a time, 16 lanes (one DPP
+    // row) per row, lane l16 holding columns l16 + 16 j
+    const int g4 = lane >> 4, l16 = lane & 15;
+    float cs[16];  // this lane's column sums of the bf16 gradient over its rows
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        cs[j] = 0.0f;
+#pragma unroll
+    for (int p = 0; p < kTRows / 16; ++p) {
+        const int row = (kTRows / 4) * wave + 4 * p + g4;
+        const float *z = L + row * kLPitch;
+        float v[16];
+        float mx = -INFINITY;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int c = l16 + 16 * j;
+            v[j] = c < a.nb ? z[c] : -INFINITY;
+            mx = fmaxf(mx, v[j]);
+        }
+        mx = row16_max(mx);
+        float sum = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            v[j] = (l16 + 16 * j) < a.nb ? expf(v[j] - mx) : 0.0f;
+            sum += v[j];
+        }
+        sum = row16_sum(sum);
+        const bool valid = row < nrows;
+        const int label = valid ? a.lab[a.r0 + t0 + row] : -1;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int c = l16 + 16 * j;
+            const float g = valid && c < a.nb ? (v[j] / sum - (c == label ? 1.0f : 0.0f)) * a.inv_rows : 0.0f;
+            const __bf16 gb = (__bf16)g;
+            D[row * kPPitch + c] = gb;
+            cs[j] += (float)gb;
+        }
+        if (l16 == 0)
+            rl[row] = valid && label >= 0 && label < a.nb ? (logf(sum) + mx - z[label]) * a.loss_scale : 0.0f;
+    }
+    // the wave's column sums: add the four lane groups
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        float x = cs[j];
+        x += __shfl_xor(x, 16);
+        x += __shfl_xor(x, 32);
+        cs[j] = x;
+    }
+    if (lane < 16)
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            csum[wave * kMlpOut + l16 + 16 * j] = cs[j];
+    __syncthreads();
+    copy_cols(D, a.dZ + (int64_t)3 * kMlpOut * a.ld, a.ld, t0, kMlpOut, tid);
+    a.bias_part[((int64_t)tile * 4 + 3) * kMlpOut + tid] =
+        ((csum[tid] + csum[kMlpOut + tid]) + csum[2 * kMlpOut + tid]) + csum[3 * kMlpOut + tid];
+    if (wave == 0) {
+        float v = lane < kTRows ? rl[lane] : 0.0f;
+        for (int off = 32; off > 0; off >>= 1)
+            v += __shfl_xor(v, off);
+        if (lane == 0)
+            a.loss_part[tile] = v;
+    }
+    // backward: dZ(l - 1) = (dZ(l) W_l) where H_l > 0, in place in D; the
+    // column sums (bias gradients) from the registers, over the lanes that
+    // share a column
+#pragma unroll 1
+    for (int l = 3; l > 0; --l) {
+        layer_tile<kMlpHidden, kTRowTiles, kTAhead>(D, a.WbT + (int64_t)(l - 1) * kMlpHidden * kMlpHidden, wave,
+                                                    lane, acc);
+        __syncthreads();
+        const uint64_t *mk = Msk + (l - 1) * kTMaskWords;
+#pragma unroll
+        for (int b = 0; b < kPColTiles; ++b) {
+            const int col = 16 * kPColTiles * wave + 16 * b + (lane & 15);
+            float colsum = 0.0f;
+#pragma unroll
+            for (int t = 0; t < kTRowTiles; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * t + 4 * (lane >> 4) + i;
+                    const bool on = (mk[((t * kPColTiles + b) * 4 + i) * 4 + wave] >> lane) & 1ull;
+                    const __bf16 gb = (__bf16)(on ? acc[t][b][i] : 0.0f);
+                    D[row * kPPitch + col] = gb;
+                    colsum += (float)gb;
+                }
+            colsum += __shfl_xor(colsum, 16);
+            colsum += __shfl_xor(colsum, 32);
+            if (lane < 16)
+                a.bias_part[((int64_t)tile * 4 + (l - 1)) * kMlpOut + col] = colsum;
+        }
+        __syncthreads();
+        copy_cols(D, a.dZ + (int64_t)(l - 1) * kMlpOut * a.ld, a.ld, t0, kMlpOut, tid);
+    }
+}
+
+// The gradient of every parameter: a weight's split-K partial sums added in
+// chunk order (or the value already in G), a bias's tile sums added in tile
+// order; the loss parts added in tile order.  With adam set, the Adam step on
+// the fp32 master parameters and the bf16 copies follow.
+struct FinishArgs {
+    const float *split;  // [4][kSplitMax][256][256] partials, or NULL: the weight gradients are in G
+    int chunks;
+    const float *bias_part;
+    int tiles;
+    const float *loss_part;
+    float *loss;
+    float *G;
+    int adam;
+    float *P, *m1, *m2;
+    __bf16 *Wb, *WbT;
+    float lr, b1, b2, eps, c1, c2;
+};
+
+__global__ __launch_bounds__(256) void k_grad_finish(FinishArgs f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && f.loss) {
+        float sum = 0.0f;
+#pragma unroll 16
+        for (int t = 0; t < f.tiles; ++t)
+            sum += f.loss_part[t];
+        *f.loss += sum;
+    }
+    if (i >= kMlpParams)
+        return;
+    float g;
+    if (i < kMlpWeights) {
+        if (f.split) {
+            const int64_t first = (int64_t)kMlpOut * kMlpIn, hh = (int64_t)kMlpHidden * kMlpHidden;
+            const int l = i < first ? 0 : 1 + (int)((i - first) / hh);
+            const int64_t j = i < first ? i : (i - first) % hh;
+            const int64_t mn = l == 0 ? first : hh;
+            const float *pp = f.split + (int64_t)l * kSplitMax * kMlpOut * kMlpHidden + j;
+            g = 0.0f;
+#pragma unroll 4
+            for (int z = 0; z < f.chunks; ++z)
+                g += pp[z * mn];
+        } else {
+            g = f.G[i];
+        }
+    } else {
+        const int b = (int)(i - kMlpWeights), l = b / kMlpHidden, n = b % kMlpHidden;
+        g = 0.0f;
+#pragma unroll 16
+        for (int t = 0; t < f.tiles; ++t)
+            g += f.bias_part[((int64_t)t * 4 + l) * kMlpOut + n];
+    }
+    f.G[i] = g;
+    if (!f.adam)
+        return;
+    const float m = f.b1 * f.m1[i] + (1.0f - f.b1) * g;
+    const float v = f.b2 * f.m2[i] + (1.0f - f.b2) * g * g;
+    f.m1[i] = m;
+    f.m2[i] = v;
+    const float w = f.P[i] - f.lr * (m * f.c1) / (sqrtf(v * f.c2) + f.eps);
+    f.P[i] = w;
+    if (i < kMlpWeights)
+        store_weight(f.Wb, f.WbT, i, w);
+}
 
 // ------------------------------------------------ frontier and labels
 // Left-to-right frontier of the tree at depth 8: internal nodes at depth 8
@@ -789,32 +1000,21 @@ int operand_mode(const __bf16 *P, int64_t s_mn, int64_t s_k, int MN, int K) {
     return 0;
 }
 
-constexpr int kSplitMax = 16;  // split-K chunks of a long contraction (the weight gradients)
-
-// split: a buffer of kSplitMax * M * N floats for a split over K, or NULL
-// Operand layouts of g, and its split over K when `split` is given and the
-// contraction is long (raw sums, no epilogue); returns the number of chunks.
+// Operand layouts of g, and its split over K (rows) in chunks of about
+// kSplitRows when `split` (kSplitMax * M * N floats) is given and the
+// contraction spans more than one chunk (raw sums, no epilogue); returns the
+// number of chunks.
 int prepare_split(GemmArgs &g, float *split) {
     g.a_mode = operand_mode(g.A, g.a_m, g.a_k, g.M, g.K);
     g.b_mode = operand_mode(g.B, g.b_n, g.b_k, g.N, g.K);
     int chunks = 1;
-    if (split && g.K > 2 * 256 && !g.bias && !g.relu && !g.mask && !g.Cb && g.Cf) {
-        chunks = cdiv(g.K, 256) < kSplitMax ? cdiv(g.K, 256) : kSplitMax;
+    if (split && g.K > kSplitRows && !g.bias && !g.relu && !g.mask && !g.Cb && g.Cf) {
+        chunks = cdiv(g.K, kSplitRows) < kSplitMax ? cdiv(g.K, kSplitRows) : kSplitMax;
         g.k_chunk = cdiv(cdiv(g.K, chunks), kGStage) * kGStage;
         chunks = cdiv(g.K, g.k_chunk);
         g.partial = split;
     }
     return chunks;
-}
-
-void gemm(GemmArgs g, hipStream_t s, float *split = nullptr) {
-    const int chunks = prepare_split(g, split);
-    dim3 grid(cdiv(g.N, kGT), cdiv(g.M, kGT), chunks);
-    k_gemm<<<grid, 256, 0, s>>>(g);
-    if (g.partial) {
-        const int64_t mn = (int64_t)g.M * g.N;
-        k_gemm_reduce<<<cdiv(mn, 256), 256, 0, s>>>(g.partial, chunks, g.M, g.N, g.Cf, g.c_m, g.c_n);
-    }
 }
 
 }  // namespace
@@ -830,7 +1030,7 @@ hipError_t proposal_frontier(const MeshDev &m, Proposal &pr, hipStream_t s) {
 }
 
 hipError_t proposal_init(Proposal &pr, uint64_t seed, hipStream_t s) {
-    k_init_params<<<cdiv(kMlpParams, 256), 256, 0, s>>>(pr.P, pr.Wb, pr.m1, pr.m2, seed);
+    k_init_params<<<cdiv(kMlpParams, 256), 256, 0, s>>>(pr.P, pr.Wb, pr.WbT, pr.m1, pr.m2, seed);
     return hipGetLastError();
 }
 
@@ -862,108 +1062,113 @@ hipError_t proposal_predict(const MeshDev &m, const Proposal &pr, const float *f
 }
 
 // Forward + backward of one batch (rows segments listed in seg[r0..r0+rows),
-// labels lab[r0..]); writes the parameter gradient into pr.G and adds the
-// mean loss to *loss.  ws must hold kMlpBatchScratch(rows) bytes.
+// labels lab[r0..]) in three launches: k_train_tile (features, forward,
+// softmax cross-entropy, input gradients and bias / loss parts per tile of
+// kTRows rows), k_gemm4 (every layer's weight gradient, split over the rows)
+// and k_grad_finish (the sums in fixed order into pr.G, the loss, and with
+// `adam` the Adam step).  ws must hold proposal_batch_scratch(rows) bytes.
 hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from, const float *to,
                                const int32_t *seg, const int32_t *lab, int64_t r0, int rows, int nb, float *loss,
-                               float loss_scale, char *ws, hipStream_t s, float *logits_out) {
-    __bf16 *X0 = reinterpret_cast<__bf16 *>(ws);
-    __bf16 *H1 = X0 + (int64_t)rows * kMlpIn;
-    __bf16 *H2 = H1 + (int64_t)rows * kMlpHidden;
-    __bf16 *H3 = H2 + (int64_t)rows * kMlpHidden;
-    __bf16 *dZ0 = H3 + (int64_t)rows * kMlpHidden;  // dZ of layer l at dZ0 + l rows 256
-    float *Z4 = reinterpret_cast<float *>(dZ0 + 4 * (int64_t)rows * kMlpOut);
-    float *split = Z4 + (int64_t)rows * kMlpOut;  // 4 x kSplitMax x 256 x 256 partial sums of the weight gradients
-    const __bf16 *W1 = pr.Wb, *W2 = W1 + kMlpOut * kMlpIn, *W3 = W2 + kMlpHidden * kMlpHidden,
-                 *W4 = W3 + kMlpHidden * kMlpHidden;
-    const float *bias = pr.P + kMlpWeights;
+                               float loss_scale, char *ws, hipStream_t s, float *logits_out, const AdamStep *adam) {
+    const int tiles = cdiv(rows, kTRows);
+    const int64_t ld = (int64_t)tiles * kTRows;
+    __bf16 *X0 = reinterpret_cast<__bf16 *>(ws);           // [224][ld]
+    __bf16 *H = X0 + ld * kMlpIn;                          // [3][256][ld]
+    __bf16 *dZ0 = H + 3 * ld * kMlpHidden;                 // [4][256][ld]
+    float *split = reinterpret_cast<float *>(dZ0 + 4 * ld * kMlpOut);  // [4][kSplitMax][256][256]
+    float *bias_part = split + 4 * (int64_t)kSplitMax * kMlpOut * kMlpHidden;       // [tiles][4][256]
+    float *loss_part = bias_part + (int64_t)tiles * 4 * kMlpOut;                   // [tiles]
+    TrainArgs a{};
+    a.from = from;
+    a.to = to;
+    a.seg = seg;
+    a.lab = lab;
+    a.r0 = r0;
+    a.rows = rows;
+    a.nb = nb;
+    a.bounds = m.bounds;
+    a.Wb = pr.Wb;
+    a.WbT = pr.WbT;
+    a.bias = pr.P + kMlpWeights;
+    a.ld = ld;
+    a.X0 = X0;
+    a.H = H;
+    a.dZ = dZ0;
+    a.logits = logits_out;
+    a.bias_part = bias_part;
+    a.loss_part = loss_part;
+    a.inv_rows = 1.0f / rows;
+    a.loss_scale = loss_scale > 0.0f ? loss_scale : 1.0f / rows;
+    // above the default 64 KB of dynamic LDS: set per call (cheap on the
+    // host, right for whichever device is current)
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_train_tile),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrainLds);
+    if (e != hipSuccess)
+        return e;
+    k_train_tile<<<tiles, 256, kTrainLds, s>>>(a);
+    // every layer's weight gradient in one launch, split over the rows:
+    // dW[n][k] = sum_r dZ[r][n] H[r][k], both operands contiguous along r
+    // (padding rows add exact zeros: their gradients are zero); a batch of at
+    // most kSplitRows rows is not split: its sums go straight to the gradient
+    const __bf16 *ins[4] = {X0, H, H + ld * kMlpHidden, H + 2 * ld * kMlpHidden};
     float *G = pr.G;
-    float *gW1 = G, *gW2 = gW1 + kMlpOut * kMlpIn, *gW3 = gW2 + kMlpHidden * kMlpHidden,
-          *gW4 = gW3 + kMlpHidden * kMlpHidden, *gb = G + kMlpWeights;
-    auto dZ = [&](int l) { return dZ0 + (int64_t)l * rows * kMlpOut; };
-
-    k_features<<<cdiv((int64_t)rows * 7, 256), 256, 0, s>>>(from, to, seg, r0, rows, m.bounds, X0);
-    // forward: Z = H W (W stored [out][in]), ReLU on hidden layers
-    const __bf16 *ins[4] = {X0, H1, H2, H3};
-    __bf16 *outs[3] = {H1, H2, H3};
-    const __bf16 *Ws[4] = {W1, W2, W3, W4};
-    for (int l = 0; l < 4; ++l) {
-        const int K = l == 0 ? kMlpIn : kMlpHidden;
-        GemmArgs g{};
-        g.A = ins[l]; g.a_m = K; g.a_k = 1;
-        g.B = Ws[l]; g.b_k = 1; g.b_n = K;
-        g.M = rows; g.N = kMlpOut; g.K = K;
-        g.bias = bias + l * kMlpHidden;
-        g.relu = l < 3;
-        g.c_m = kMlpOut; g.c_n = 1;
-        if (l < 3) g.Cb = outs[l]; else g.Cf = logits_out ? logits_out : Z4;
-        gemm(g, s);
-    }
-    k_softmax_ce<<<cdiv(rows, 4), 256, 0, s>>>(logits_out ? logits_out : Z4, lab + r0, rows, nb, 1.0f / rows,
-                                              loss_scale > 0.0f ? loss_scale : 1.0f / rows, dZ(3), split);
-    k_loss_sum<<<1, 256, 0, s>>>(split, rows, loss);  // before the weight gradients reuse `split`
-    // backward, first the chain of input gradients: dZ(l - 1) = (dZ(l) W_l) masked by H_l > 0
-    for (int l = 3; l > 0; --l) {
-        GemmArgs h{};
-        h.A = dZ(l); h.a_m = kMlpOut; h.a_k = 1;
-        h.B = Ws[l]; h.b_k = kMlpHidden; h.b_n = 1;
-        h.M = rows; h.N = kMlpHidden; h.K = kMlpOut;
-        h.mask = ins[l]; h.mask_m = kMlpHidden; h.mask_n = 1;
-        h.Cb = dZ(l - 1); h.c_m = kMlpHidden; h.c_n = 1;
-        gemm(h, s);
-    }
-    // then every layer's weight gradient in one launch (split over the rows,
-    // the chunks added in order by one reduce launch) and every bias gradient
-    // in two: dW^T[n][k] = sum_r H[r][k] dZ[r][n]
-    float *gWs[4] = {gW1, gW2, gW3, gW4};
+    float *gWs[4] = {G, G + kMlpOut * kMlpIn, G + kMlpOut * kMlpIn + kMlpHidden * kMlpHidden,
+                     G + kMlpOut * kMlpIn + 2 * kMlpHidden * kMlpHidden};
     GemmArgs4 gs{};
     int chunks = 1;
     for (int l = 0; l < 4; ++l) {
         const int K = l == 0 ? kMlpIn : kMlpHidden;
         GemmArgs &g = gs.g[l];
-        g.A = dZ(l); g.a_m = 1; g.a_k = kMlpOut;
-        g.B = ins[l]; g.b_k = K; g.b_n = 1;
-        g.M = kMlpOut; g.N = K; g.K = rows;
+        g.A = dZ0 + (int64_t)l * kMlpOut * ld; g.a_m = ld; g.a_k = 1;
+        g.B = ins[l]; g.b_k = 1; g.b_n = ld;
+        g.M = kMlpOut; g.N = K; g.K = (int)ld;
         g.Cf = gWs[l]; g.c_m = K; g.c_n = 1;
         chunks = prepare_split(g, split + (int64_t)l * kSplitMax * kMlpOut * kMlpHidden);
     }
     k_gemm4<<<dim3(cdiv(kMlpHidden, kGT), cdiv(kMlpOut, kGT), 4 * chunks), 256, 0, s>>>(gs, chunks);
-    // a batch of at most 512 rows is not split (its sums go straight to the
-    // gradient, partial stays NULL): there is nothing to add up then
-    if (gs.g[0].partial)
-        k_gemm_reduce4<<<dim3(cdiv((int64_t)kMlpOut * kMlpHidden, 256), 4), 256, 0, s>>>(gs, chunks);
-    const int nblk = cdiv(rows, kColRows);
-    // (the split partial sums are spent by now: the bias partials go there)
-    k_col_partial<<<dim3(nblk, 4), kMlpOut, 0, s>>>(dZ0, rows, split);
-    k_col_final<<<4, kMlpOut, 0, s>>>(split, nblk, gb);
-    return hipGetLastError();
-}
-
-hipError_t proposal_adam(Proposal &pr, float lr, int step, hipStream_t s) {
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.0f / (1.0f - powf(b1, (float)step));
-    const float c2 = 1.0f / (1.0f - powf(b2, (float)step));
-    k_adam<<<cdiv(kMlpParams, 256), 256, 0, s>>>(pr.P, pr.G, pr.m1, pr.m2, pr.Wb, kMlpParams, kMlpWeights, lr, b1,
-                                                 b2, eps, c1, c2);
+    FinishArgs f{};
+    f.split = gs.g[0].partial ? split : nullptr;
+    f.chunks = chunks;
+    f.bias_part = bias_part;
+    f.tiles = tiles;
+    f.loss_part = loss_part;
+    f.loss = loss;
+    f.G = G;
+    if (adam) {
+        f.adam = 1;
+        f.P = pr.P;
+        f.m1 = pr.m1;
+        f.m2 = pr.m2;
+        f.Wb = pr.Wb;
+        f.WbT = pr.WbT;
+        f.lr = adam->lr;
+        f.b1 = 0.9f;
+        f.b2 = 0.999f;
+        f.eps = 1e-8f;
+        f.c1 = 1.0f / (1.0f - powf(f.b1, (float)adam->step));
+        f.c2 = 1.0f / (1.0f - powf(f.b2, (float)adam->step));
+    }
+    k_grad_finish<<<cdiv(kMlpParams, 256), 256, 0, s>>>(f);
     return hipGetLastError();
 }
 
 namespace {
-__global__ void k_params_to_bf16(const float *__restrict__ P, __bf16 *__restrict__ Wb) {
+__global__ void k_params_to_bf16(const float *__restrict__ P, __bf16 *__restrict__ Wb, __bf16 *__restrict__ WbT) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kMlpWeights)
-        Wb[i] = (__bf16)P[i];
+        store_weight(Wb, WbT, i, P[i]);
 }
 }  // namespace
 
 hipError_t proposal_set_params(Proposal &pr, hipStream_t s) {
-    k_params_to_bf16<<<cdiv(kMlpWeights, 256), 256, 0, s>>>(pr.P, pr.Wb);
+    k_params_to_bf16<<<cdiv(kMlpWeights, 256), 256, 0, s>>>(pr.P, pr.Wb, pr.WbT);
     return hipGetLastError();
 }
 
 size_t proposal_batch_scratch(int rows) {
-    return (size_t)rows * (kMlpIn + 3 * kMlpHidden + 4 * kMlpOut) * 2 + (size_t)rows * kMlpOut * 4 +
-           4 * (size_t)kSplitMax * kMlpOut * kMlpHidden * 4 + 256;
+    const size_t tiles = (size_t)cdiv(rows, kTRows);
+    return tiles * kTRows * (kMlpIn + 3 * kMlpHidden + 4 * kMlpOut) * 2 +
+           4 * (size_t)kSplitMax * kMlpOut * kMlpHidden * 4 + tiles * 4 * kMlpOut * 4 + tiles * 4 + 256;
 }
 
 hipError_t proposal_features(const MeshDev &m, const float *from, const float *to, int64_t n, __bf16 *X,

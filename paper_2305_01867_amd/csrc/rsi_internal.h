@@ -76,6 +76,7 @@ struct Proposal {
     float *G = nullptr;      // gradient [kMlpParams]
     float *m1 = nullptr, *m2 = nullptr;  // Adam moments
     __bf16 *Wb = nullptr;    // bf16 weights [kMlpWeights]
+    __bf16 *WbT = nullptr;   // bf16 hidden weights transposed (layers 2..4, [in][out]) for the backward pass
     int32_t *bucket_ref = nullptr;    // [256] frontier node reference per bucket
     int32_t *bucket_first = nullptr;  // [256] first sorted leaf of each bucket
     int32_t *dev_n_buckets = nullptr; // [1]
@@ -262,10 +263,16 @@ hipError_t proposal_labels(const MeshDev &m, Proposal &pr, const int32_t *tri_id
                            int32_t *label, uint32_t *count, int32_t *blk, hipStream_t s);
 hipError_t proposal_predict(const MeshDev &m, const Proposal &pr, const float *from, const float *to, int64_t n,
                             int nb, uint8_t *bucket, hipStream_t s);
+// One Adam step after a batch's gradient (step counts from 1).
+struct AdamStep {
+    float lr;
+    int step;
+};
+// The gradient of one batch into pr.G (the mean loss times rows x loss_scale
+// added to *loss), and with `adam` the parameter update.
 hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from, const float *to,
                                const int32_t *seg, const int32_t *lab, int64_t r0, int rows, int nb, float *loss,
-                               float loss_scale, char *ws, hipStream_t s, float *logits_out);
-hipError_t proposal_adam(Proposal &pr, float lr, int step, hipStream_t s);
+                               float loss_scale, char *ws, hipStream_t s, float *logits_out, const AdamStep *adam);
 size_t proposal_batch_scratch(int rows);
 hipError_t proposal_features(const MeshDev &m, const float *from, const float *to, int64_t n, __bf16 *X,
                              hipStream_t s);
