@@ -93,178 +93,110 @@ __global__ __launch_bounds__(256) void k_features(const float *__restrict__ from
     coord_features(x, c, row);
 }
 
-// ------------------------------------------------------------ tiled GEMM
-// C[m][n] = sum_k A(m, k) B(k, n) with arbitrary element strides, bf16 in,
-// fp32 accumulation; 64 x 64 tile per workgroup, 32 x 32 per wave, k steps of
-// 32 staged through LDS.  Epilogue: + bias[n], ReLU, times (mask(m, n) > 0),
-// stored as fp32 and / or bf16 with arbitrary strides.
-struct GemmArgs {
-    const __bf16 *A;
-    int64_t a_m, a_k;
-    const __bf16 *B;
-    int64_t b_k, b_n;
-    int M, N, K;
-    const float *bias;
-    int relu;
-    const __bf16 *mask;
-    int64_t mask_m, mask_n;
-    float *Cf;
-    __bf16 *Cb;
-    int64_t c_m, c_n;
-    // split over K: workgroup z covers k in [z k_chunk, (z + 1) k_chunk) and
-    // writes its raw sums to partial[z][M][N]; k_gemm_reduce adds them up
-    float *partial;
-    int k_chunk;
-    // operand layouts, set by gemm(): 0 element by element, 1 contiguous in
-    // k (16-byte loads along k), 2 contiguous in m / n (16-byte loads along
-    // m / n, transposed into LDS)
-    int a_mode, b_mode;
+// ------------------------------------------------- weight gradients
+// dW_l[n][k] = sum_r dZ_l[r][n] H_l[r][k] for the four layers in one launch:
+// workgroup z covers layer z / chunks over rows [c k_chunk, (c + 1) k_chunk)
+// of chunk c = z % chunks and a 128 x 128 tile of (n, k); four waves of
+// 64 x 64.  Both operands are the training pass's column-major arrays,
+// contiguous along r, staged through LDS kDStage rows at a time (the next
+// stage loads into registers while the current one multiplies); the sum over
+// r runs in r order.  A split writes raw partial sums [chunk][256][K_l],
+// added in chunk order by k_grad_finish; one chunk writes the gradient.
+constexpr int kSplitMax = 16;    // row chunks of the weight gradients at most
+constexpr int kSplitRows = 256;  // rows per chunk (a multiple of kDStage)
+constexpr int kDT = 128, kDStage = 128, kDPitch = kDStage + 8;
+constexpr size_t kDwLds = 2 * (size_t)kDT * kDPitch * sizeof(__bf16);
+
+struct DwArgs {
+    const __bf16 *A[4];  // dZ_l, [256][ld]
+    const __bf16 *B[4];  // the layer's input, [K_l][ld]
+    float *out[4];       // [chunks][256][K_l] partial sums, or the gradient (one chunk)
+    int64_t ld;
+    int k_chunk, chunks;
 };
 
-constexpr int kGT = 64, kGK = 32, kGPad = 8;
-constexpr int kSplitMax = 16;  // split-K chunks of a long contraction (the weight gradients)
-constexpr int kSplitRows = 512;  // rows per chunk of the weight gradients' split
-// k steps of kGK staged through LDS together, so a workgroup synchronises
-// once per kGSub * kGK of the contraction (each wave: 4 * kGSub MFMA per stage)
-constexpr int kGSub = 4;
-constexpr int kGStage = kGK * kGSub;
-constexpr int kGPitch = kGStage + kGPad;
-
-// One operand's 64 x 32 tile of this k step: each lane fetches 8 elements
-// (one 16-byte load in the vector layouts) into registers; put_tile stores
-// them into LDS as S[m or n][k].  Out-of-range elements are zero.
-__device__ __forceinline__ bf16x8 get_tile(const __bf16 *__restrict__ P, int64_t s_mn, int64_t s_k, int mode,
-                                           int mn0, int MN, int k0, int kend, int tid) {
-    bf16x8 v;
-    if (mode == 1) {
-        const int mn = tid >> 2, kk = (tid & 3) * 8;
-        if (mn0 + mn < MN && k0 + kk < kend)  // kend and kk are multiples of 8
-            v = *reinterpret_cast<const bf16x8 *>(P + (int64_t)(mn0 + mn) * s_mn + (k0 + kk));
+// rows [m0, m0 + 128) x r [r0, r0 + kDStage) of a [rows][ld] operand, 8 16-byte loads per lane
+__device__ __forceinline__ void dw_load(const __bf16 *__restrict__ P, int rows, int64_t ld, int m0, int r0, int rend,
+                                        int tid, bf16x8 (&v)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int idx = tid + 256 * q, m = idx >> 4, c = 8 * (idx & 15);
+        if (m0 + m < rows && r0 + c < rend)
+            v[q] = *reinterpret_cast<const bf16x8 *>(P + (int64_t)(m0 + m) * ld + r0 + c);
         else
-            v = bf16x8{};
-    } else if (mode == 2) {
-        const int kk = tid >> 3, mn = (tid & 7) * 8;
-        if (k0 + kk < kend && mn0 + mn < MN)  // MN and mn are multiples of 8
-            v = *reinterpret_cast<const bf16x8 *>(P + (int64_t)(k0 + kk) * s_k + (mn0 + mn));
-        else
-            v = bf16x8{};
-    } else {
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int idx = tid + 256 * r;
-            const int mn = idx / kGK, kk = idx % kGK;
-            const int gm = mn0 + mn, gk = k0 + kk;
-            v[r] = (gm < MN && gk < kend) ? P[gm * s_mn + gk * s_k] : (__bf16)0.0f;
-        }
-    }
-    return v;
-}
-
-// Stores one 64 x 32 tile (columns [c0, c0 + 32) of the stage) into S.
-__device__ __forceinline__ void put_tile(__bf16 (*S)[kGPitch], int c0, int mode, bf16x8 v, int tid) {
-    if (mode == 1) {
-        *reinterpret_cast<bf16x8 *>(&S[tid >> 2][c0 + (tid & 3) * 8]) = v;
-    } else if (mode == 2) {
-        const int kk = tid >> 3, mn = (tid & 7) * 8;
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            S[mn + i][c0 + kk] = v[i];
-    } else {
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int idx = tid + 256 * r;
-            S[idx / kGK][c0 + idx % kGK] = v[r];
-        }
+            v[q] = bf16x8{};
     }
 }
 
-// C = A B on MFMA: a 64 x 64 tile per workgroup, four waves of 32 x 32.  The
-// next k step's operand tiles load into registers while the current step
-// multiplies out of LDS; the sum over k runs in k order.
-__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int bz, __bf16 (*As)[kGPitch],
-                                          __bf16 (*Bs)[kGPitch]) {
+__device__ __forceinline__ void dw_store(__bf16 *S, int tid, const bf16x8 (&v)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int idx = tid + 256 * q;
+        *reinterpret_cast<bf16x8 *>(S + (idx >> 4) * kDPitch + 8 * (idx & 15)) = v[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dw(DwArgs d) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __bf16 *As = reinterpret_cast<__bf16 *>(lds_raw);  // [kDT][kDPitch]: n x r
+    __bf16 *Bs = As + kDT * kDPitch;                    // [kDT][kDPitch]: k x r
+    const int layer = blockIdx.z / d.chunks, chunk = blockIdx.z % d.chunks;
+    const int N = kMlpOut, K = layer == 0 ? kMlpIn : kMlpHidden;
+    const int n0 = blockIdx.y * kDT, k0 = blockIdx.x * kDT;
+    if (k0 >= K)
+        return;  // layer 1 has fewer inputs; uniform per workgroup
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = by * kGT, n0 = bx * kGT;
-    if (m0 >= g.M || n0 >= g.N)
-        return;  // a grouped launch covers the largest operand; uniform per workgroup
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int kb = g.partial ? bz * g.k_chunk : 0;
-    const int ke = g.partial ? min(g.K, kb + g.k_chunk) : g.K;
-    f32x4 acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
+    const int wn = (wave >> 1) * 64, wk = (wave & 1) * 64;
+    const int rb = chunk * d.k_chunk;
+    const int re = min((int)d.ld, rb + d.k_chunk);
+    const __bf16 *A = d.A[layer], *B = d.B[layer];
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
             acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // a stage: kGSub k steps of 32, loaded into registers while the previous
-    // stage multiplies (tiles past ke are zero)
-    bf16x8 va[kGSub], vb[kGSub];
-#pragma unroll
-    for (int j = 0; j < kGSub; ++j) {
-        va[j] = get_tile(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, kb + kGK * j, ke, tid);
-        vb[j] = get_tile(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, kb + kGK * j, ke, tid);
-    }
+    bf16x8 va[8], vb[8];
+    dw_load(A, N, d.ld, n0, rb, re, tid, va);
+    dw_load(B, K, d.ld, k0, rb, re, tid, vb);
     const int kq = 8 * (lane >> 4);
-    for (int k0 = kb; k0 < ke; k0 += kGStage) {
-        __syncthreads();  // the previous stage's reads of As / Bs are done
-#pragma unroll
-        for (int j = 0; j < kGSub; ++j) {
-            put_tile(As, kGK * j, g.a_mode, va[j], tid);
-            put_tile(Bs, kGK * j, g.b_mode, vb[j], tid);
-        }
+    for (int r0 = rb; r0 < re; r0 += kDStage) {
+        __syncthreads();  // the previous stage's reads are done
+        dw_store(As, tid, va);
+        dw_store(Bs, tid, vb);
         __syncthreads();
-        if (k0 + kGStage < ke) {
-#pragma unroll
-            for (int j = 0; j < kGSub; ++j) {
-                va[j] = get_tile(g.A, g.a_m, g.a_k, g.a_mode, m0, g.M, k0 + kGStage + kGK * j, ke, tid);
-                vb[j] = get_tile(g.B, g.b_n, g.b_k, g.b_mode, n0, g.N, k0 + kGStage + kGK * j, ke, tid);
-            }
+        if (r0 + kDStage < re) {
+            dw_load(A, N, d.ld, n0, r0 + kDStage, re, tid, va);
+            dw_load(B, K, d.ld, k0, r0 + kDStage, re, tid, vb);
         }
-        // the k steps in k order (the sum over k runs in the same order as
-        // with one step per stage); steps past ke hold zeros
-        const int steps = min(kGSub, (ke - k0 + kGK - 1) / kGK);
-        for (int j = 0; j < steps; ++j)
-            for (int a = 0; a < 2; ++a) {
-                const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * a + (lane & 15)][kGK * j + kq]);
-                for (int b = 0; b < 2; ++b) {
-                    const bf16x8 fb =
-                        *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * b + (lane & 15)][kGK * j + kq]);
-                    acc[a][b] = mfma16(fa, fb, acc[a][b]);
-                }
-            }
+        const int steps = min(kDStage, re - r0) / 32;
+        for (int j = 0; j < steps; ++j) {
+            bf16x8 fa[4], fb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                fa[a] = *reinterpret_cast<const bf16x8 *>(As + (wn + 16 * a + (lane & 15)) * kDPitch + 32 * j + kq);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                fb[b] = *reinterpret_cast<const bf16x8 *>(Bs + (wk + 16 * b + (lane & 15)) * kDPitch + 32 * j + kq);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = mfma16(fa[a], fb[b], acc[a][b]);
+        }
     }
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
+    float *out = d.out[layer] + (int64_t)chunk * N * K;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int m = m0 + wm + 16 * a + 4 * (lane >> 4) + i;
-                const int n = n0 + wn + 16 * b + (lane & 15);
-                if (m >= g.M || n >= g.N)
-                    continue;
-                float v = acc[a][b][i];
-                if (g.partial) {
-                    g.partial[((int64_t)bz * g.M + m) * g.N + n] = v;
-                    continue;
-                }
-                if (g.bias)
-                    v += g.bias[n];
-                if (g.relu)
-                    v = fmaxf(v, 0.0f);
-                if (g.mask && !((float)g.mask[m * g.mask_m + n * g.mask_n] > 0.0f))
-                    v = 0.0f;
-                if (g.Cf)
-                    g.Cf[m * g.c_m + n * g.c_n] = v;
-                if (g.Cb)
-                    g.Cb[m * g.c_m + n * g.c_n] = (__bf16)v;
+                const int n = n0 + wn + 16 * a + 4 * (lane >> 4) + i;
+                const int k = k0 + wk + 16 * b + (lane & 15);
+                if (n < N && k < K)
+                    out[(int64_t)n * K + k] = acc[a][b][i];
             }
-}
-
-// The four layers' weight gradients in one launch: z = layer x split chunk.
-struct GemmArgs4 {
-    GemmArgs g[4];
-};
-__global__ __launch_bounds__(256) void k_gemm4(GemmArgs4 gs, int chunks) {
-    __shared__ __bf16 As[kGT][kGPitch];
-    __shared__ __bf16 Bs[kGT][kGPitch];
-    const int layer = blockIdx.z / chunks;
-    gemm_tile(gs.g[layer], blockIdx.x, blockIdx.y, blockIdx.z % chunks, As, Bs);
 }
 
 // Uniform(-a, a) initial weights from a counter-based hash (seed, index).
@@ -390,6 +322,61 @@ __device__ __forceinline__ void layer_tile(const __bf16 *__restrict__ Xin, const
                 f[st + AHEAD][b] = *reinterpret_cast<const bf16x8 *>(wfrag + (int64_t)(b * kSteps + st + AHEAD) * 512);
         tile_step<RT>(xrow, 32 * st, f[st], acc);
         __builtin_amdgcn_sched_barrier(0);  // keep each step's loads in its step: no hoisting past the register budget
+    }
+}
+
+// layer_tile for a chain of layers: the first AHEAD k steps' fragments come
+// in pf, and the last AHEAD steps load the next layer's first AHEAD steps
+// (from Wn, with KN inputs; none when Wn is NULL) into pf, so a layer starts
+// without waiting on memory and the epilogue between two layers hides the
+// loads' latency.
+template <int KN, int AHEAD>
+__device__ __forceinline__ void prefetch_layer(const __bf16 *__restrict__ Wn, int wave, int lane,
+                                               bf16x8 (&pf)[AHEAD][kPColTiles]) {
+    constexpr int kStepsN = KN / 32;
+    const __bf16 *nfrag = Wn + (int64_t)kPColTiles * wave * kStepsN * 512 + 8 * lane;
+#pragma unroll
+    for (int st = 0; st < AHEAD; ++st)
+#pragma unroll
+        for (int b = 0; b < kPColTiles; ++b)
+            pf[st][b] = *reinterpret_cast<const bf16x8 *>(nfrag + (int64_t)(b * kStepsN + st) * 512);
+}
+
+template <int K, int KN, int RT, int AHEAD>
+__device__ __forceinline__ void layer_chain(const __bf16 *__restrict__ Xin, const __bf16 *__restrict__ Wt,
+                                            const __bf16 *__restrict__ Wn, int wave, int lane,
+                                            f32x4 (&acc)[RT][kPColTiles], bf16x8 (&pf)[AHEAD][kPColTiles]) {
+    constexpr int kSteps = K / 32, kStepsN = KN / 32;
+    static_assert(K % 32 == 0 && KN % 32 == 0 && AHEAD <= kSteps && AHEAD <= kStepsN, "whole k steps");
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int b = 0; b < kPColTiles; ++b)
+            acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int kq = 8 * (lane >> 4);
+    const __bf16 *wfrag = Wt + (int64_t)kPColTiles * wave * kSteps * 512 + 8 * lane;
+    const __bf16 *nfrag = Wn ? Wn + (int64_t)kPColTiles * wave * kStepsN * 512 + 8 * lane : nullptr;
+    const __bf16 *xrow = Xin + (lane & 15) * kPPitch + kq;
+    bf16x8 f[kSteps][kPColTiles];
+#pragma unroll
+    for (int st = 0; st < AHEAD; ++st)
+#pragma unroll
+        for (int b = 0; b < kPColTiles; ++b)
+            f[st][b] = pf[st][b];
+#pragma unroll
+    for (int st = 0; st < kSteps; ++st) {
+        if (st + AHEAD < kSteps) {
+#pragma unroll
+            for (int b = 0; b < kPColTiles; ++b)
+                f[st + AHEAD][b] = *reinterpret_cast<const bf16x8 *>(wfrag + (int64_t)(b * kSteps + st + AHEAD) * 512);
+        } else if (nfrag) {
+#pragma unroll
+            for (int b = 0; b < kPColTiles; ++b)
+                pf[st + AHEAD - kSteps][b] =
+                    *reinterpret_cast<const bf16x8 *>(nfrag + (int64_t)(b * kStepsN + st + AHEAD - kSteps) * 512);
+        }
+        tile_step<RT>(xrow, 32 * st, f[st], acc);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -630,19 +617,31 @@ __global__ __launch_bounds__(256) void k_train_tile(TrainArgs a) {
     copy_cols(X, a.X0, a.ld, t0, kMlpIn, tid);
     // forward: each layer's output over its input in X once every wave has read it
     f32x4 acc[kTRowTiles][kPColTiles];
+    bf16x8 pf[kTAhead][kPColTiles];  // the next layer's first k steps, loaded ahead
+    auto wlayer = [&](int l) -> const __bf16 * {  // forward l = 0..3, then backward l = 3..1 as 4..6
+        if (l == 0)
+            return a.Wb;
+        if (l < 4)
+            return a.Wb + (int64_t)kMlpOut * kMlpIn + (int64_t)(l - 1) * kMlpHidden * kMlpHidden;
+        return a.WbT + (int64_t)(6 - l) * kMlpHidden * kMlpHidden;
+    };
+    prefetch_layer<kMlpIn, kTAhead>(a.Wb, wave, lane, pf);
 #pragma unroll 1
     for (int l = 0; l < 4; ++l) {
-        const int64_t woff = l == 0 ? 0 : (int64_t)kMlpOut * kMlpIn + (int64_t)(l - 1) * kMlpHidden * kMlpHidden;
-        if (l == 0)
-            layer_tile<kMlpIn, kTRowTiles, kTAhead>(X, a.Wb + woff, wave, lane, acc);
-        else
-            layer_tile<kMlpHidden, kTRowTiles, kTAhead>(X, a.Wb + woff, wave, lane, acc);
-        __syncthreads();
         const float *bl = a.bias + l * kMlpHidden;
+        float bvs[kPColTiles];  // this layer's biases, loaded while it multiplies
+#pragma unroll
+        for (int b = 0; b < kPColTiles; ++b)
+            bvs[b] = bl[16 * kPColTiles * wave + 16 * b + (lane & 15)];
+        if (l == 0)
+            layer_chain<kMlpIn, kMlpHidden, kTRowTiles, kTAhead>(X, wlayer(0), wlayer(1), wave, lane, acc, pf);
+        else
+            layer_chain<kMlpHidden, kMlpHidden, kTRowTiles, kTAhead>(X, wlayer(l), wlayer(l + 1), wave, lane, acc, pf);
+        __syncthreads();
 #pragma unroll
         for (int b = 0; b < kPColTiles; ++b) {
             const int col = 16 * kPColTiles * wave + 16 * b + (lane & 15);
-            const float bv = bl[col];
+            const float bv = bvs[b];
 #pragma unroll
             for (int t = 0; t < kTRowTiles; ++t)
 #pragma unroll
@@ -736,8 +735,8 @@ __global__ __launch_bounds__(256) void k_train_tile(TrainArgs a) {
     // share a column
 #pragma unroll 1
     for (int l = 3; l > 0; --l) {
-        layer_tile<kMlpHidden, kTRowTiles, kTAhead>(D, a.WbT + (int64_t)(l - 1) * kMlpHidden * kMlpHidden, wave,
-                                                    lane, acc);
+        layer_chain<kMlpHidden, kMlpHidden, kTRowTiles, kTAhead>(D, wlayer(7 - l), l > 1 ? wlayer(8 - l) : nullptr,
+                                                                 wave, lane, acc, pf);
         __syncthreads();
         const uint64_t *mk = Msk + (l - 1) * kTMaskWords;
 #pragma unroll
@@ -786,7 +785,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(FinishArgs f) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && f.loss) {
         float sum = 0.0f;
-#pragma unroll 16
+#pragma unroll 32
         for (int t = 0; t < f.tiles; ++t)
             sum += f.loss_part[t];
         *f.loss += sum;
@@ -811,7 +810,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(FinishArgs f) {
     } else {
         const int b = (int)(i - kMlpWeights), l = b / kMlpHidden, n = b % kMlpHidden;
         g = 0.0f;
-#pragma unroll 16
+#pragma unroll 32
         for (int t = 0; t < f.tiles; ++t)
             g += f.bias_part[((int64_t)t * 4 + l) * kMlpOut + n];
     }
@@ -989,34 +988,6 @@ __global__ __launch_bounds__(256) void k_labels(const int32_t *__restrict__ tri_
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-// Operand layout for k_gemm's loads: 16-byte loads need 8 contiguous
-// elements at 16-byte aligned addresses.
-int operand_mode(const __bf16 *P, int64_t s_mn, int64_t s_k, int MN, int K) {
-    const bool al = (reinterpret_cast<uintptr_t>(P) & 15) == 0;
-    if (al && s_k == 1 && s_mn % 8 == 0 && K % 8 == 0)
-        return 1;
-    if (al && s_mn == 1 && s_k % 8 == 0 && MN % 8 == 0)
-        return 2;
-    return 0;
-}
-
-// Operand layouts of g, and its split over K (rows) in chunks of about
-// kSplitRows when `split` (kSplitMax * M * N floats) is given and the
-// contraction spans more than one chunk (raw sums, no epilogue); returns the
-// number of chunks.
-int prepare_split(GemmArgs &g, float *split) {
-    g.a_mode = operand_mode(g.A, g.a_m, g.a_k, g.M, g.K);
-    g.b_mode = operand_mode(g.B, g.b_n, g.b_k, g.N, g.K);
-    int chunks = 1;
-    if (split && g.K > kSplitRows && !g.bias && !g.relu && !g.mask && !g.Cb && g.Cf) {
-        chunks = cdiv(g.K, kSplitRows) < kSplitMax ? cdiv(g.K, kSplitRows) : kSplitMax;
-        g.k_chunk = cdiv(cdiv(g.K, chunks), kGStage) * kGStage;
-        chunks = cdiv(g.K, g.k_chunk);
-        g.partial = split;
-    }
-    return chunks;
-}
-
 }  // namespace
 
 // ===================================================================== host
@@ -1106,29 +1077,32 @@ hipError_t proposal_batch_grad(const MeshDev &m, Proposal &pr, const float *from
     if (e != hipSuccess)
         return e;
     k_train_tile<<<tiles, 256, kTrainLds, s>>>(a);
-    // every layer's weight gradient in one launch, split over the rows:
-    // dW[n][k] = sum_r dZ[r][n] H[r][k], both operands contiguous along r
-    // (padding rows add exact zeros: their gradients are zero); a batch of at
-    // most kSplitRows rows is not split: its sums go straight to the gradient
-    const __bf16 *ins[4] = {X0, H, H + ld * kMlpHidden, H + 2 * ld * kMlpHidden};
+    // every layer's weight gradient in one launch, split over the rows (a
+    // batch of at most kSplitRows rows is not split: its sums go straight to
+    // the gradient); padding rows add exact zeros, their gradients being zero
     float *G = pr.G;
-    float *gWs[4] = {G, G + kMlpOut * kMlpIn, G + kMlpOut * kMlpIn + kMlpHidden * kMlpHidden,
-                     G + kMlpOut * kMlpIn + 2 * kMlpHidden * kMlpHidden};
-    GemmArgs4 gs{};
-    int chunks = 1;
+    DwArgs dw{};
+    dw.ld = ld;
+    dw.chunks = ld > kSplitRows ? cdiv(ld, kSplitRows) : 1;
+    if (dw.chunks > kSplitMax)
+        dw.chunks = kSplitMax;
+    dw.k_chunk = cdiv(cdiv(ld, dw.chunks), kDStage) * kDStage;
+    dw.chunks = cdiv(ld, dw.k_chunk);
+    const bool split_k = dw.chunks > 1;
     for (int l = 0; l < 4; ++l) {
-        const int K = l == 0 ? kMlpIn : kMlpHidden;
-        GemmArgs &g = gs.g[l];
-        g.A = dZ0 + (int64_t)l * kMlpOut * ld; g.a_m = ld; g.a_k = 1;
-        g.B = ins[l]; g.b_k = 1; g.b_n = ld;
-        g.M = kMlpOut; g.N = K; g.K = (int)ld;
-        g.Cf = gWs[l]; g.c_m = K; g.c_n = 1;
-        chunks = prepare_split(g, split + (int64_t)l * kSplitMax * kMlpOut * kMlpHidden);
+        const int64_t woff = l == 0 ? 0 : (int64_t)kMlpOut * kMlpIn + (int64_t)(l - 1) * kMlpHidden * kMlpHidden;
+        dw.A[l] = dZ0 + (int64_t)l * kMlpOut * ld;
+        dw.B[l] = l == 0 ? X0 : H + (int64_t)(l - 1) * kMlpHidden * ld;
+        dw.out[l] = split_k ? split + (int64_t)l * kSplitMax * kMlpOut * kMlpHidden : G + woff;
     }
-    k_gemm4<<<dim3(cdiv(kMlpHidden, kGT), cdiv(kMlpOut, kGT), 4 * chunks), 256, 0, s>>>(gs, chunks);
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dw), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kDwLds);
+    if (e != hipSuccess)
+        return e;
+    k_dw<<<dim3(cdiv(kMlpHidden, kDT), cdiv(kMlpOut, kDT), 4 * dw.chunks), 256, kDwLds, s>>>(dw);
     FinishArgs f{};
-    f.split = gs.g[0].partial ? split : nullptr;
-    f.chunks = chunks;
+    f.split = split_k ? split : nullptr;
+    f.chunks = dw.chunks;
     f.bias_part = bias_part;
     f.tiles = tiles;
     f.loss_part = loss_part;
