@@ -210,8 +210,7 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices,
  * ever culled) the segment misses; test each reached triangle.  Boolean mode
  * stops at the first hit; the other modes keep the nearest and skip boxes that
  * begin beyond it.  n_rays == 0 does nothing.  Limit: n_rays < 2^31.
- * Temporary device memory (4 n_rays + 64 bytes, plus 8 n_rays in CERTIFIED
- * precision outside the intercept-count mode, plus what a proposal or a
+ * Temporary device memory (4 n_rays + 64 bytes, plus what a proposal or a
  * segment order needs) is allocated and freed stream-ordered on `stream`.
  */
 rsi_status rsi_intersect(rsi_mesh mesh, const float *rays_from, const float *rays_to,
@@ -225,13 +224,11 @@ rsi_status rsi_intersect(rsi_mesh mesh, const float *rays_from, const float *ray
  * rsi_intersect; the caller still provides the inputs and outputs.  The
  * temporary memory comes from one 64 MiB device array of the library instead
  * of an allocation, so the call allocates nothing (no hipMalloc / hipFree of
- * any kind).  It needs 4 n_rays + 64 bytes rounded up to 256, plus 32 bytes
- * per four segments (rounded up to 256) in CERTIFIED precision outside the
- * intercept-count mode, plus n_rays rounded up to 256 with opts->proposal =
- * 1, plus 16 n_rays with a segment order (ray_sort != 0): at most 16,777,200
- * segments in input order in PLAIN precision (or the intercept-count mode)
- * and 5,592,384 in CERTIFIED precision, without the proposal.  A call
- * needing more returns RSI_E_CAPACITY before any GPU work.  Every GPU the library runs on holds its own copy of the array until
+ * any kind).  It needs 4 n_rays + 64 bytes rounded up to 256, plus n_rays
+ * rounded up to 256 with opts->proposal = 1, plus 16 n_rays with a segment
+ * order (ray_sort != 0): at most 16,777,200 segments in input order without
+ * the proposal, in either precision.  A call needing more returns
+ * RSI_E_CAPACITY before any GPU work.  Every GPU the library runs on holds its own copy of the array until
  * the process ends; the array's address on the current device is looked up
  * the first time this is called there.  All calls on one GPU share that
  * array: calls that may overlap on one GPU (different streams without

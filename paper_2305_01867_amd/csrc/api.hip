@@ -462,12 +462,9 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *ws = nullptr;
     const size_t q_bytes = (4 * (size_t)n + 64 + 255) & ~size_t(255);
-    // certified precision (not the count mode): the candidate list, 32 B per record for up to n / 4 segments
-    const bool listed = precision == RSI_PRECISION_CERTIFIED && mode != RSI_MODE_INTERCEPT_COUNT && !stats;
-    const size_t r_bytes = listed ? round_up(32 * (size_t)rsi::retest_cap_for(n)) : 0;
     const size_t b_bytes = use_prop ? ((size_t)n + 511) & ~size_t(255) : 0;
     const bool sorted = ray_sort != RSI_RAY_ORDER_INPUT && n > 1 && mesh->dev.nt > 0;
-    const size_t ws_bytes = q_bytes + r_bytes + b_bytes + (sorted ? rsi::ray_sort_ws_bytes(n) : 0);
+    const size_t ws_bytes = q_bytes + b_bytes + (sorted ? rsi::ray_sort_ws_bytes(n) : 0);
     const bool own_ws = scratch_ptr == nullptr;
     hipError_t e = hipSuccess;
     if (own_ws) {
@@ -481,9 +478,8 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
         if (ws_bytes > scratch_cap)
             return fail(RSI_E_CAPACITY, "this call needs " + std::to_string(ws_bytes) +
                                             " bytes of scratch, more than the " + std::to_string(scratch_cap) +
-                                            " the no-allocation entry point holds (4 bytes per segment, 8 more "
-                                            "in certified precision, 1 more with the proposal and 16 more with "
-                                            "a segment order)");
+                                            " the no-allocation entry point holds (4 bytes per segment, 1 more "
+                                            "with the proposal and 16 more with a segment order)");
         ws = scratch_ptr;
     }
     rsi::TraverseArgs a;
@@ -499,17 +495,13 @@ static rsi_status run_rays(rsi_mesh mesh, const float *from, const float *to, in
     uint64_t *ws_counters = reinterpret_cast<uint64_t *>(static_cast<char *>(ws));
     a.queue_len = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + 32);
     a.queue = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + 64);
-    if (listed) {
-        a.retest = reinterpret_cast<int4 *>(static_cast<char *>(ws) + q_bytes);
-        a.retest_cap = (uint32_t)rsi::retest_cap_for(n);
-    }
     if (sorted) {
         a.ray_sort = ray_sort;
         a.key_bounds = mesh->dev.bounds;
-        a.sort_ws = static_cast<char *>(ws) + q_bytes + r_bytes + b_bytes;
+        a.sort_ws = static_cast<char *>(ws) + q_bytes + b_bytes;
     }
     if (use_prop) {
-        uint8_t *bucket = static_cast<uint8_t *>(ws) + q_bytes + r_bytes;
+        uint8_t *bucket = static_cast<uint8_t *>(ws) + q_bytes;
         e = rsi::proposal_predict(mesh->dev, mesh->dev.prop, from, to, n, mesh->dev.prop.n_buckets, bucket, s);
         if (e != hipSuccess) {
             if (own_ws)

@@ -216,10 +216,7 @@ struct TraverseArgs {
     int32_t *count = nullptr;      // intercept-count mode
     uint64_t *counters = nullptr;  // [4] device
     int32_t *queue = nullptr;      // [n] device
-    uint32_t *queue_len = nullptr; // [3] device (inside counters workspace): queue length, next segment,
-                                   // listed segments
-    int4 *retest = nullptr;        // [retest_cap] certified segments decided from listed candidates
-    uint32_t retest_cap = 0;
+    uint32_t *queue_len = nullptr; // [2] device (inside counters workspace): queue length, next segment
     uint32_t *visits = nullptr;    // stats only
     uint32_t *tests = nullptr;     // stats only
     const uint8_t *bucket = nullptr;      // proposal per segment (NULL: none)
@@ -243,8 +240,6 @@ struct TraverseArgs {
     void *sort_ws = nullptr;              // ray_sort != 0: ray_sort_ws_bytes(n) bytes
 };
 size_t ray_sort_ws_bytes(int64_t n);
-// Records of the certified candidate list for n segments (a quarter of them).
-inline int64_t retest_cap_for(int64_t n) { return (n + 3) / 4; }
 hipError_t launch_debug_certify(const float *from, const float *to, const float *corners, int64_t n, float *vals,
                                 int32_t *cls, hipStream_t s);
 hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t s);

@@ -11,12 +11,16 @@
 //   CERTIFIED  each predicate X comes with a proven bound B(X) on its distance
 //              from the exact value and from the binary64 value; |X| > B(X)
 //              fixes the sign of the binary64 result, so the pair is a sure
-//              hit or a sure miss.  Otherwise the pair is "unsure".  Nearest-hit
-//              choice uses proven intervals around the binary64 t.
-// A segment whose result is unsure, or whose path outgrows the LDS stack, is
-// appended to a queue and finished by pass 2 (k_finish): a deep private stack
-// and, in CERTIFIED precision, the binary64 test with the oracle's operation
-// order (no contraction, correctly rounded division) on every candidate.
+//              hit or a sure miss.  Otherwise the pair is "unsure" and the
+//              lane decides it at once with the binary64 test in the
+//              oracle's operation order (no contraction, correctly rounded
+//              division).  Nearest-hit choice uses proven intervals around
+//              the binary64 t, and the binary64 t themselves where two
+//              intervals overlap.
+// A segment whose path outgrows the LDS stack (or, in count mode, whose list
+// of distinct t overflows or holds nearly equal ones) is appended to a queue
+// and finished by pass 2 (k_finish): a deep private stack and, in CERTIFIED
+// precision, the binary64 test on every candidate.
 //
 // Box test: the slab test on each child box widened by eta = 2^-20 max(|coord|)
 // of the segment and mesh.  That margin exceeds every rounding of the slab
@@ -310,9 +314,6 @@ struct TravParams {
     const int32_t *ray_off;
     const int32_t *order;  // segment at each processing position (NULL: input order)
     int stage_ok;          // boolean results may be staged per wave (4-byte aligned output)
-    int4 *retest;          // certified, one mesh: (segment, candidate ids) decided after pass 1, or NULL
-    uint32_t *retest_len;  // records appended (may exceed retest_cap: those went to the second pass)
-    uint32_t retest_cap;
     int deep_cap;          // second pass: entries of a lane's private stack (<= kDeepStack)
     int wave_cap;          // second pass: entries of a wave's shared stack (<= its LDS array)
 };
@@ -323,28 +324,6 @@ __device__ __forceinline__ void enqueue(const TravParams &p, int64_t i, int why)
     atomicAdd(p.counters + why, 1ull);
 }
 
-// A certified segment whose answer hangs only on a few listed candidates
-// (unsure pairs, and in the nearest-hit modes the best sure hit): appended
-// for k_retest, which decides them in binary64.  False when the list is full
-// (the segment then goes to the second pass).
-// A record is two int4: (segment, c0, c1, c2), (c3, c4, c5, c6), candidate
-// ids or -1.
-__device__ __forceinline__ bool retest_push(const TravParams &p, int4 a, int4 b) {
-    if (!p.retest)
-        return false;
-    const uint32_t slot = atomicAdd(p.retest_len, 1u);
-    if (slot >= p.retest_cap)
-        return false;
-    p.retest[2 * slot] = a;
-    p.retest[2 * slot + 1] = b;
-    atomicAdd(p.counters, 1ull);  // re-decided in binary64
-    return true;
-}
-// unsure pairs a lane lists for k_retest: seven (boolean), or six beside the
-// best sure hit (a segment aimed at a vertex meets the triangles around it)
-constexpr int kUnsureMax = 7;
-template <int MODE>
-constexpr int kUnsureSlots = MODE == MODE_BOOL ? 7 : 6;
 
 // Pointers into LDS by address space, so reads of the LDS copy of the tree's
 // top compile to ds_read and are not merged with the global path.
@@ -522,25 +501,17 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     float tlimit = 1.0f;
     int best_id = -1;
     float best_t = INFINITY, best_lo = INFINITY, best_hi = INFINITY, best_u = 0.0f, best_v = 0.0f;
-    bool found = false, unsure = false, flagged = false, overflow = false;
-    // certified: the unsure pairs met so far (input triangle ids), for k_retest
-    int uns[kUnsureMax];
-#pragma unroll
-    for (int k = 0; k < kUnsureMax; ++k)
-        uns[k] = -1;
-    int n_uns = 0;
-    auto note_unsure = [&](int id) {
-#pragma unroll
-        for (int k = 0; k < kUnsureMax; ++k)
-            if (k == n_uns)
-                uns[k] = id;
-        ++n_uns;
-    };
+    // certified nearest hit: its binary64 t when computed (it decided a tie)
+    bool best_exact = false;
+    double best_t64 = 0.0;
+    bool found = false, flagged = false, overflow = false;
     uint32_t n_nodes = 0, n_tests = 0;
     int steps = 0;
     int phase = 1, skip = kDone;  // kDone never equals a child reference
     bool best_late = false;       // best hit found in phase 1 (a proposal miss)
     uint32_t n_late = 0;          // this lane's proposal misses, summed per wave at exit
+    uint32_t n_redecided = 0;     // boolean, certified: pairs of this segment decided in binary64
+    uint32_t seg_redecided = 0;   // this lane's segments with such a pair, summed per wave at exit
     // count mode: the distinct t found so far -- binary32 values (plain), or
     // intervals that each hold one hit's binary64 t (certified): disjoint
     // intervals hold distinct values, so only overlapping ones need the exact
@@ -611,12 +582,10 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                     tlimit = 1.0f;
                     best_id = -1;
                     best_t = best_lo = best_hi = INFINITY;
+                    best_exact = false;
                     best_u = best_v = 0.0f;
-                    found = unsure = flagged = overflow = false;
-#pragma unroll
-                    for (int k = 0; k < kUnsureMax; ++k)
-                        uns[k] = -1;
-                    n_uns = 0;
+                    found = flagged = overflow = false;
+                    n_redecided = 0;
                     n_nodes = n_tests = 0;
                     nk = 0;
                     list_full = false;
@@ -891,34 +860,69 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                     float lo = 0.0f, hi = 0.0f;
                     const int c = classify(m, tri, r, lo, hi);
                     if (MODE == MODE_BOOL) {
-                        if (c == kHit) {
+                        bool hit = c == kHit;
+                        if (c == kUnsure) {
+                            // decided here in binary64, in the oracle's
+                            // operation order: a segment aimed at an edge or a
+                            // vertex would otherwise search on for a sure hit
+                            // through everything its box overlaps
+                            ++n_redecided;
+                            if (valid_tri(p.F, p.nv, id)) {
+                                const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
+                                hit = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, id).hit;
+                            }
+                        }
+                        if (hit) {
                             found = true;
                             best_late = phase == 1;
                             ref = kDone;
-                        } else if (c == kUnsure) {
-                            unsure = true;
-                            note_unsure(id);
                         }
-                    } else if (c == kUnsure) {
-                        // go on and list it (the answer is then the nearest of
-                        // the listed pairs and the best sure hit, in binary64),
-                        // or hand the segment to the second pass
-                        if (p.retest && n_uns < kUnsureSlots<MODE>) {
-                            note_unsure(id);
-                        } else {
-                            flagged = true;
-                            ref = kDone;
+                    } else {
+                        // an unsure pair is decided here in binary64, in the
+                        // oracle's operation order; a hit then takes part
+                        // like a sure one, its interval holding the exact t
+                        bool hit = c == kHit, exact = false;
+                        double t64 = 0.0;
+                        const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
+                        if (c == kUnsure) {
+                            ++n_redecided;
+                            hit = false;
+                            if (valid_tri(p.F, p.nv, id)) {
+                                const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, id);
+                                hit = h.hit;
+                                exact = true;
+                                t64 = h.t;
+                                lo = __double2float_rd(h.t);
+                                hi = __double2float_ru(h.t);
+                            }
                         }
-                    } else if (c == kHit) {
-                        if (best_id < 0 || hi < best_lo) {
+                        if (hit && !(best_id < 0 || hi < best_lo) && !(lo > best_hi)) {
+                            // the intervals overlap: compare the binary64 t
+                            // themselves (both pairs are binary64 hits), ties
+                            // to the smaller triangle id, as the oracle
+                            if (!exact) {
+                                t64 = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, id).t;
+                                exact = true;
+                            }
+                            if (!best_exact) {
+                                best_t64 = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, best_id).t;
+                                best_exact = true;
+                            }
+                            ++n_redecided;
+                            hit = t64 < best_t64 || (t64 == best_t64 && id < best_id);
+                            lo = __double2float_rd(t64);
+                            hi = __double2float_ru(t64);
+                        } else if (hit && best_id >= 0 && !(hi < best_lo)) {
+                            hit = false;  // beyond the best hit
+                        }
+                        if (hit) {
                             best_lo = lo;
                             best_hi = hi;
                             best_id = id;
+                            best_exact = exact;
+                            best_t64 = t64;
                             best_late = phase == 1;
                             tlimit = fminf(tlimit, hi * (1.0f + 0x1p-20f));
-                        } else if (!(lo > best_hi)) {
-                            flagged = true;  // intervals overlap: order not certain
-                            ref = kDone;
                         }
                     }
                 }
@@ -960,32 +964,28 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
                 // pass writes its result after this kernel
                 if (!found && overflow)
                     enqueue(p, ray, 1);
-                else if (!found && CERT && unsure &&
-                         !(n_uns <= kUnsureSlots<MODE> &&
-                           retest_push(p, make_int4((int)ray, uns[0], uns[1], uns[2]),
-                                       make_int4(uns[3], uns[4], uns[5], uns[6]))))
-                    enqueue(p, ray, 0);
+                seg_redecided += n_redecided > 0 ? 1u : 0u;
                 put_hit(ray, found ? 1u : 0u);
-            } else if (overflow) {
-                enqueue(p, ray, 1);
-            } else if (CERT && flagged) {
-                enqueue(p, ray, 0);
-            } else if (CERT && n_uns > 0) {
-                if (!retest_push(p, make_int4((int)ray, best_id, uns[0], uns[1]),
-                                 make_int4(uns[2], uns[3], uns[4], uns[5])))
-                    enqueue(p, ray, 0);
-            } else if (CERT && MODE == MODE_BARY && best_id >= 0) {
-                if (p.bary_after) {  // (u, v, t) after both passes, a lane per segment
-                    if (p.out.hit)
-                        p.out.hit[ray] = 1;
-                    p.out.id[ray] = best_id - lane_toff;
-                } else {
-                    const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
-                    const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, best_id);
-                    write_out(p.out, ray, MODE, best_id - lane_toff, (float)h.u, (float)h.v, (float)h.t);
-                }
             } else {
-                write_out(p.out, ray, MODE, best_id >= 0 ? best_id - lane_toff : -1, best_u, best_v, best_t);
+                if (CERT && n_redecided > 0 && !flagged)
+                    ++seg_redecided;  // (a flagged segment is counted when queued)
+                if (overflow) {
+                    enqueue(p, ray, 1);
+                } else if (CERT && flagged) {
+                    enqueue(p, ray, 0);
+                } else if (CERT && MODE == MODE_BARY && best_id >= 0) {
+                    if (p.bary_after) {  // (u, v, t) after both passes, a lane per segment
+                        if (p.out.hit)
+                            p.out.hit[ray] = 1;
+                        p.out.id[ray] = best_id - lane_toff;
+                    } else {
+                        const float *o = p.from + 3 * ray, *e = p.to + 3 * ray;
+                        const MT64 h = mt64(o[0], o[1], o[2], e[0], e[1], e[2], p.V, p.F, best_id);
+                        write_out(p.out, ray, MODE, best_id - lane_toff, (float)h.u, (float)h.v, (float)h.t);
+                    }
+                } else {
+                    write_out(p.out, ray, MODE, best_id >= 0 ? best_id - lane_toff : -1, best_u, best_v, best_t);
+                }
             }
             ray = -1;
         }
@@ -1003,6 +1003,14 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
             stage_flush();
         if (win_base < range_end)
             stage_flush();
+    }
+    if (MODE != MODE_COUNT && CERT && !STATS) {
+        // segments with a pair decided in binary64 in this pass, one atomic per wave
+        uint32_t w = seg_redecided;
+        for (int off = 32; off > 0; off >>= 1)
+            w += __shfl_xor(w, off);
+        if (lane == 0 && w)
+            atomicAdd(p.counters, (unsigned long long)w);
     }
     if (PROP && !STATS) {
         // one atomic per wave: a shared counter across eight XCDs is costly
@@ -1442,48 +1450,6 @@ __device__ void finish_lane(const TravParams &p, int64_t i, int *stk) {
     f.write(p, i, toff);
 }
 
-// The listed segments of a certified first pass: each one's answer is
-// decided by its listed candidates alone (every other candidate it reached
-// was a proven binary32 miss, or -- in the nearest-hit modes -- a sure hit
-// no nearer than the listed best sure hit), each tested in binary64 with the
-// oracle's operation order.  A lane per segment.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_retest(TravParams p) {
-    const uint32_t len = *p.retest_len;
-    const uint32_t count = len < p.retest_cap ? len : p.retest_cap;
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < count; q += gridDim.x * blockDim.x) {
-        const int4 rec = p.retest[2 * q], more = p.retest[2 * q + 1];
-        const int64_t i = rec.x;
-        const float *o = p.from + 3 * i, *e = p.to + 3 * i;
-        const double ox = o[0], oy = o[1], oz = o[2], ex = e[0], ey = e[1], ez = e[2];
-        const int cand[kUnsureMax] = {rec.y, rec.z, rec.w, more.x, more.y, more.z, more.w};
-        int best = -1;
-        double bu = 0.0, bv = 0.0, bt = 0.0;
-#pragma unroll 1
-        for (int k = 0; k < kUnsureMax; ++k) {
-            const int id = cand[k];
-            if (id < 0 || !valid_tri(p.F, p.nv, id) || (MODE == MODE_BOOL && best >= 0))
-                continue;
-            const MT64 h = mt64(ox, oy, oz, ex, ey, ez, p.V, p.F, id);
-            if (h.hit && (best < 0 || h.t < bt || (h.t == bt && id < best))) {
-                best = id;
-                bu = h.u;
-                bv = h.v;
-                bt = h.t;
-            }
-        }
-        if (MODE == MODE_BOOL) {
-            p.out.hit[i] = best >= 0 ? 1 : 0;
-        } else if (p.bary_after && best >= 0) {  // (u, v, t) follow from the id after both passes
-            if (p.out.hit)
-                p.out.hit[i] = 1;
-            p.out.id[i] = best;
-        } else {  // a miss (NaN u, v, t), or the values themselves
-            write_out(p.out, i, MODE, best, (float)bu, (float)bv, (float)bt);
-        }
-    }
-}
-
 template <int MODE, bool CERT>
 __global__ __launch_bounds__(kFinishThreads) void k_finish(TravParams p) {
     __shared__ int deep[kWaveCap<MODE>];
@@ -1563,8 +1529,8 @@ __global__ void k_ray_keys(const float *__restrict__ from, const float *__restri
 }
 
 __global__ void k_reset(uint32_t *queue_len, unsigned long long *counters, int n_groups) {
-    if (threadIdx.x < 3)
-        queue_len[threadIdx.x] = 0;  // queue length, next segment of pass 1, listed segments
+    if (threadIdx.x < 2)
+        queue_len[threadIdx.x] = 0;  // queue length, next segment of pass 1
     if (threadIdx.x < n_groups)
         queue_len[kGroupNext + threadIdx.x] = 0;  // next item of each group
     if (threadIdx.x < 4)
@@ -1753,11 +1719,6 @@ TravParams make_params(const MeshDev &m, const TraverseArgs &a) {
     p.ray_off = a.ray_off;
     p.order = nullptr;
     p.stage_ok = (reinterpret_cast<uintptr_t>(a.hit) & 3u) == 0 ? 1 : 0;
-    // the candidate list: certified, one mesh, modes other than the count
-    const bool listed = a.certified && a.retest && a.items == nullptr && a.mode != MODE_COUNT;
-    p.retest = listed ? a.retest : nullptr;
-    p.retest_len = a.queue_len + 2;
-    p.retest_cap = listed ? a.retest_cap : 0;
     p.deep_cap = kDeepStack;
     p.wave_cap = a.mode == MODE_COUNT ? kWaveCap<MODE_COUNT> : kWaveCap<MODE_BOOL>;
     // RSI_DEBUG_PASS2_STACK=k (2..kDeepStack) shrinks both second-pass stacks
@@ -1807,16 +1768,6 @@ hipError_t launch_intersect(const MeshDev &m, const TraverseArgs &a, hipStream_t
     if (e != hipSuccess)
         return e;
     dispatch_pass1<false>(p, a.mode, a.certified != 0, a.block, s);
-    if (p.retest) {  // the listed segments, a lane each
-        const int64_t want = ((int64_t)p.retest_cap + 255) / 256;
-        const int grid_r = (int)(want < 1024 ? (want < 1 ? 1 : want) : 1024);
-        if (a.mode == MODE_BOOL)
-            k_retest<MODE_BOOL><<<grid_r, 256, 0, s>>>(p);
-        else if (a.mode == MODE_FIRST)
-            k_retest<MODE_FIRST><<<grid_r, 256, 0, s>>>(p);
-        else
-            k_retest<MODE_BARY><<<grid_r, 256, 0, s>>>(p);
-    }
     // enough blocks for one per segment of a short queue; a long queue is
     // taken 64 segments per block (count mode: a wave per segment, with
     // small blocks that fit many per CU)

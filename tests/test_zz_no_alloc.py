@@ -69,10 +69,14 @@ def test_noalloc_with_a_segment_order_and_the_refusal():
         with pytest.raises(rsi.RSIError) as e:
             rsi.rsi_intersect_noalloc(mesh, big, big, out, mode="boolean")
         assert e.value.status == 6 and "scratch" in str(e.value)
-        # certified precision lists candidates too: 5,592,384 segments fit, one more does not
-        k = 5_592_385
+        # certified precision needs no more scratch: refused at the same size
+        with pytest.raises(rsi.RSIError) as e:
+            rsi.rsi_intersect_noalloc(mesh, big, big, out, mode="boolean", precision="certified")
+        assert e.value.status == 6
+        # a segment order needs about 16 bytes more per segment: 4,000,000 do not fit
+        k = 4_000_000
         with pytest.raises(rsi.RSIError) as e:
             rsi.rsi_intersect_noalloc(mesh, big[:k], big[:k], {"hit": out["hit"][:k], "counters": out["counters"]},
-                                      mode="boolean", precision="certified")
+                                      mode="boolean", precision="certified", ray_sort="midpoint")
         assert e.value.status == 6
         assert int(host(out["hit"]).max()) == 0
