@@ -329,12 +329,8 @@ rsi_status rsi_build(const float *vertices, int64_t n_vertices, const int32_t *t
     d.sort_tmp = take(sz_tmp);
     d.bytes = (int64_t)total;
 
-    if (n_vertices > 0)
-        e = hipMemcpyAsync(d.V, vertices, 12 * (size_t)n_vertices, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d.F, triangles, 12 * (size_t)nt, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess)
-        e = rsi::launch_build(d, vertices, triangles, s, sz_tmp);
+    // the build's first kernels copy the vertices and triangles into the mesh
+    e = rsi::launch_build(d, vertices, triangles, s, sz_tmp);
     if (e != hipSuccess) {
         rsi_destroy(m);
         return fail_hip(e, "rsi_build launch");

@@ -57,13 +57,19 @@ __device__ __forceinline__ void block_minmax(float lo[3], float hi[3]) {
     }
 }
 
+// (also copies the caller's vertices into the mesh's own array, and clears
+// the build flags)
 __global__ __launch_bounds__(1024) void k_mesh_bounds_part(const float *__restrict__ V, int64_t nv,
-                                                           float *__restrict__ partial) {
+                                                           float *__restrict__ partial, float *__restrict__ V_copy,
+                                                           int32_t *__restrict__ flags) {
+    if (blockIdx.x == 0 && threadIdx.x < 4)
+        flags[threadIdx.x] = 0;
     float lo[3] = {INFINITY, INFINITY, INFINITY};
     float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
         for (int a = 0; a < 3; ++a) {
             const float x = V[3 * i + a];
+            V_copy[3 * i + a] = x;
             lo[a] = fminf(lo[a], x);
             hi[a] = fmaxf(hi[a], x);
         }
@@ -128,17 +134,22 @@ __device__ __forceinline__ uint32_t quantise(float c, float lo, float ext, float
     return x > 0.0f ? (uint32_t)floorf(fminf(x, top)) : 0u;
 }
 
+// (also copies the caller's triangles into the mesh's own array)
 template <typename K>
 __global__ __launch_bounds__(256) void k_morton(const float *__restrict__ V, int64_t nv,
                                                 const int32_t *__restrict__ F, int64_t nt,
                                                 const float *__restrict__ bounds, K *__restrict__ keys,
-                                                int32_t *__restrict__ ids, int32_t *__restrict__ flags) {
+                                                int32_t *__restrict__ ids, int32_t *__restrict__ flags,
+                                                int32_t *__restrict__ F_copy) {
 #pragma clang fp contract(off)
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt)
         return;
     constexpr int b = sizeof(K) == 4 ? 10 : 21;
     const int32_t i0 = F[3 * t], i1 = F[3 * t + 1], i2 = F[3 * t + 2];
+    F_copy[3 * t] = i0;
+    F_copy[3 * t + 1] = i1;
+    F_copy[3 * t + 2] = i2;
     ids[t] = (int32_t)t;
     if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
         atomicOr(flags, 1);
@@ -157,8 +168,8 @@ __global__ __launch_bounds__(256) void k_morton(const float *__restrict__ V, int
     keys[t] = key;
 }
 
-// Batched form: the key of a triangle of mesh m is m (6 bits) above a 57-bit
-// Morton code (19 bits per axis) of its centroid normalised to mesh m's box,
+// Batched form: the key of a triangle of mesh m is m (6 bits) above a 30-bit
+// Morton code (10 bits per axis) of its centroid normalised to mesh m's box,
 // so each mesh's triangles are contiguous after the sort and form one subtree.
 __global__ __launch_bounds__(256) void k_morton_batch(const float *__restrict__ V, const int32_t *__restrict__ F,
                                                       const int32_t *__restrict__ tri_mesh, int64_t nt,
@@ -377,11 +388,14 @@ __device__ __forceinline__ int prefix(const K *__restrict__ k, int n, int i, K k
 
 // Also lists the bottom-up tiles: the largest subtrees with at most kBoxTile
 // leaves (children of larger nodes, or the root itself), wave-aggregated into
-// tiles[0 .. *n_tiles).
+// tiles[0 .. *n_tiles); and flags each internal node of at most kBoxTile
+// leaves with kTileRootFlag (the 4-wide collapse above the tiles stops at the
+// first flagged nodes from the root, which are the tiles).
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_tree(const K *__restrict__ keys, int n, Node *__restrict__ nodes,
                                                     int32_t *__restrict__ parent, int32_t *__restrict__ counters,
-                                                    int32_t *__restrict__ tiles, int32_t *__restrict__ n_tiles) {
+                                                    int32_t *__restrict__ tiles, int32_t *__restrict__ n_tiles,
+                                                    int32_t *__restrict__ tile_flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1)
         return;
@@ -413,6 +427,7 @@ __global__ __launch_bounds__(256) void k_radix_tree(const K *__restrict__ keys, 
     parent[left >= 0 ? left : (n - 1) + ~left] = i;
     parent[right >= 0 ? right : (n - 1) + ~right] = i;
     counters[i] = 0;
+    tile_flag[i] = hi - lo + 1 <= kBoxTile ? kTileRootFlag : 0;
     if (i == 0)
         parent[0] = -1;
 
@@ -750,7 +765,7 @@ hipError_t build_from_keys(MeshDev &m, int key_bits, hipStream_t s) {
     if (nt >= 2) {
         k_zero_i32<<<1, 64, 0, s>>>(n_tiles, 1);
         k_radix_tree<K><<<blocks_for(nt - 1, 256), 256, 0, s>>>(keys, (int)nt, m.nodes, m.parent, m.counters, tiles,
-                                                                n_tiles);
+                                                                n_tiles, L.tile_flag);
     } else {
         k_single_tile<<<1, 1, 0, s>>>(tiles, n_tiles);
     }
@@ -766,10 +781,10 @@ hipError_t build_from_keys(MeshDev &m, int key_bits, hipStream_t s) {
 }
 
 template <typename K>
-hipError_t build_typed(MeshDev &m, hipStream_t s) {
+hipError_t build_typed(MeshDev &m, const int32_t *F_in, hipStream_t s) {
     const int64_t nt = m.nt;
-    k_morton<K><<<blocks_for(nt, 256), 256, 0, s>>>(m.V, m.nv, m.F, nt, m.bounds, static_cast<K *>(m.keys), m.ids,
-                                                    m.flags);
+    k_morton<K><<<blocks_for(nt, 256), 256, 0, s>>>(m.V, m.nv, F_in, nt, m.bounds, static_cast<K *>(m.keys), m.ids,
+                                                    m.flags, m.F);
     return build_from_keys<K>(m, m.morton_bits, s);
 }
 
@@ -807,15 +822,15 @@ hipError_t sort_u32_pairs(uint32_t *keys, int32_t *ids, void *tmp, int64_t n, hi
 
 hipError_t build_from_keys64(MeshDev &m, int key_bits, hipStream_t s) { return build_from_keys<uint64_t>(m, key_bits, s); }
 
-hipError_t launch_build(MeshDev &m, const float *, const int32_t *, hipStream_t s, size_t) {
-    k_zero_i32<<<1, 64, 0, s>>>(m.flags, 4);
-    // the sort scratch is free until the keys are sorted
+hipError_t launch_build(MeshDev &m, const float *V_in, const int32_t *F_in, hipStream_t s, size_t) {
+    // the sort scratch is free until the keys are sorted; the first kernels
+    // also copy the caller's vertices and triangles into the mesh
     const int64_t want = (m.nv + 1023) / 1024;
     const int parts = (int)(want < 1 ? 1 : (want < kBoundsParts ? want : kBoundsParts));
     float *partial = static_cast<float *>(m.sort_tmp);
-    k_mesh_bounds_part<<<parts, 1024, 0, s>>>(m.V, m.nv, partial);
+    k_mesh_bounds_part<<<parts, 1024, 0, s>>>(V_in, m.nv, partial, m.V, m.flags);
     k_mesh_bounds_final<<<1, kBoundsParts, 0, s>>>(partial, parts, m.bounds);
-    hipError_t e = m.morton_bits > 32 ? build_typed<uint64_t>(m, s) : build_typed<uint32_t>(m, s);
+    hipError_t e = m.morton_bits > 32 ? build_typed<uint64_t>(m, F_in, s) : build_typed<uint32_t>(m, F_in, s);
     if (e == hipSuccess && m.algorithm == 2)
         e = launch_restructure(m, kRestructureRounds, s);
     if (e == hipSuccess && m.algorithm != 1 && m.nodes4)

@@ -18,8 +18,10 @@
 // tile (a subtree of at most 1024 leaves, listed by the radix-tree kernel)
 // into LDS in one step, restructures it height by height (the nodes of one
 // height compacted onto consecutive lanes, a treelet optimised per node), and
-// writes it back; one workgroup then does the same for the nodes above the tiles, with
-// the tiles as fixed leaves.  No cross-workgroup synchronisation at all.
+// writes it back.  No cross-workgroup synchronisation at all.  The few nodes
+// above the tiles are left as the radix tree made them: restructuring them too
+// (one more workgroup, the tiles as fixed leaves) cost more build time than it
+// saved traversal time at every measured mesh size, 32 K to 526 K triangles.
 //
 // After restructuring, an internal node's leaves are no longer a contiguous
 // range of sorted positions: words 14 / 15 of a node then hold the smallest
@@ -32,7 +34,6 @@ namespace {
 constexpr int kTile = 1024;            // leaves per tile
 constexpr int kThreads = 512;          // lanes per workgroup (256 VGPRs per lane, no spills)
 constexpr int kTreelet = 4;            // leaves per treelet (the optimisation runs in one lane's registers)
-constexpr int kMaxLevels = 130;        // > deepest radix tree (97) + treelet growth
 constexpr float kCostNode = 1.2f;      // SAH weight of a node visit (one 64-B node, two box tests)
 constexpr float kCostTri = 1.0f;       // SAH weight of a triangle test
 
@@ -50,14 +51,13 @@ struct TileLds {
     int height[kTile];         // 1 + the larger child height (a leaf is 0)
     int order[kTile];          // internal nodes by rising height
     int h_start[kTile + 2];    // order[h_start[h] .. h_start[h + 1]) have height h
-    int lf_ref[kTile];         // global reference of local leaf j (a leaf ~k, or a fixed subtree)
+    int lf_ref[kTile];         // global reference of local leaf j (a leaf ~k)
     float lf_box[6][kTile];
     float lf_cost[kTile];
     int lf_count[kTile];
     int lf_lo[kTile], lf_hi[kTile];
     int lf_parent[kTile];
-    int lvl_start[kMaxLevels + 2];  // breadth-first load of the top tree
-    int n_in, n_lf, root, overflow, max_height;
+    int n_in, n_lf, root, max_height;
 };
 
 __device__ __forceinline__ float half_area(float x0, float y0, float z0, float x1, float y1, float z1) {
@@ -376,76 +376,6 @@ __device__ __forceinline__ void restructure_local(TileLds &T, int rounds) {
     }
 }
 
-template <typename Stop, typename LeafCost>
-__device__ void load_tree(TileLds &T, const Node *__restrict__ nodes, int root, Stop stop, LeafCost leaf_cost) {
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        T.n_in = 1;
-        T.n_lf = 0;
-        T.overflow = 0;
-        T.root = 0;
-        T.in_slot[0] = root;
-        T.in_parent[0] = -1;
-        T.lvl_start[0] = 0;
-        T.lvl_start[1] = 1;
-    }
-    __syncthreads();
-    // the root's own box: the union of its children's boxes
-    for (int lv = 0; lv < kMaxLevels; ++lv) {
-        const int b0 = T.lvl_start[lv], b1 = T.lvl_start[lv + 1];
-        if (b0 == b1 || T.overflow)
-            break;
-        for (int j = b0 + tid; j < b1; j += blockDim.x) {
-            const Node *nd = nodes + T.in_slot[j];
-            const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
-            const int4 refs = nd->refs;
-            const float cb[2][6] = {{L.x, L.z, Z.x, L.y, L.w, Z.y}, {R.x, R.z, Z.z, R.y, R.w, Z.w}};
-            if (j == 0)
-                for (int a = 0; a < 3; ++a) {
-                    T.in_box[a][0] = fminf(cb[0][a], cb[1][a]);
-                    T.in_box[3 + a][0] = fmaxf(cb[0][3 + a], cb[1][3 + a]);
-                }
-            const int child[2] = {refs.x, refs.y};
-            for (int side = 0; side < 2; ++side) {
-                const int c = child[side];
-                if (c >= 0 && !stop(c)) {
-                    const int id = atomicAdd(&T.n_in, 1);
-                    if (id >= kTile) {
-                        T.overflow = 1;
-                        continue;
-                    }
-                    T.in_slot[id] = c;
-                    T.in_parent[id] = j;
-                    for (int a = 0; a < 6; ++a)
-                        T.in_box[a][id] = cb[side][a];
-                    T.in_child[side][j] = id;
-                } else {
-                    const int id = atomicAdd(&T.n_lf, 1);
-                    if (id >= kTile) {
-                        T.overflow = 1;
-                        continue;
-                    }
-                    T.lf_ref[id] = c;
-                    for (int a = 0; a < 6; ++a)
-                        T.lf_box[a][id] = cb[side][a];
-                    int count, lo, hi;
-                    const float cost = leaf_cost(c, cb[side], count, lo, hi);
-                    T.lf_cost[id] = cost;
-                    T.lf_count[id] = count;
-                    T.lf_lo[id] = lo;
-                    T.lf_hi[id] = hi;
-                    T.lf_parent[id] = j;
-                    T.in_child[side][j] = ~id;
-                }
-            }
-        }
-        __syncthreads();
-        if (tid == 0)
-            T.lvl_start[lv + 2] = T.n_in < kTile ? T.n_in : kTile;
-        __syncthreads();
-    }
-}
-
 // Write the local tree back: node words, parents; returns nothing.  Block-wide.
 // Load the radix-tree subtree rooted at internal node c in one parallel
 // step.  In the radix-tree numbering a subtree over sorted leaves [a, b] is
@@ -495,7 +425,6 @@ __device__ void load_tile(TileLds &T, const Node *__restrict__ nodes, int c) {
         T.n_in = n_in;
         T.n_lf = n_in ? n_in + 1 : 0;
         T.root = c - base;
-        T.overflow = 0;
     }
     __syncthreads();
 }
@@ -530,8 +459,7 @@ __device__ void store_tree(const TileLds &T, Node *nodes, int32_t *parent, int n
 // One workgroup per tile of the radix-tree kernel's list.
 __global__ __launch_bounds__(kThreads) void k_restructure_tiles(Node *nodes, int32_t *parent, int n,
                                                              const int32_t *__restrict__ tiles,
-                                                             const int32_t *__restrict__ n_tiles,
-                                                             float *__restrict__ tile_cost, int rounds) {
+                                                             const int32_t *__restrict__ n_tiles, int rounds) {
     extern __shared__ char lds[];
     TileLds &T = *reinterpret_cast<TileLds *>(lds);
     const int total = *n_tiles;
@@ -542,39 +470,8 @@ __global__ __launch_bounds__(kThreads) void k_restructure_tiles(Node *nodes, int
         load_tile(T, nodes, c);
         restructure_local(T, rounds);
         store_tree(T, nodes, parent, n);
-        if (threadIdx.x == 0)
-            tile_cost[c] = T.n_in ? T.in_cost[T.root] : 0.0f;
         __syncthreads();  // LDS is reused by the next tile
     }
-}
-
-// One workgroup: the nodes above the tiles (more than kTile leaves each),
-// with the tiles as fixed leaves.  Skipped when they do not fit in LDS.
-__global__ __launch_bounds__(kThreads) void k_restructure_top(Node *nodes, int32_t *parent, int n,
-                                                           const float *__restrict__ tile_cost, int rounds) {
-    extern __shared__ char lds[];
-    TileLds &T = *reinterpret_cast<TileLds *>(lds);
-    const Node *cn = nodes;
-    auto count_of = [cn](int c) { return c < 0 ? 1 : cn[c].refs.w - cn[c].refs.z + 1; };
-    if (count_of(0) <= kTile)
-        return;  // the whole tree is one tile
-    auto stop = [count_of](int c) { return count_of(c) <= kTile; };
-    auto leaf_cost = [cn, tile_cost](int ref, const float *b, int &count, int &lo, int &hi) {
-        if (ref < 0) {
-            count = 1;
-            lo = hi = ~ref;
-            return tri_cost(b);
-        }
-        lo = cn[ref].refs.z;
-        hi = cn[ref].refs.w;
-        count = hi - lo + 1;
-        return tile_cost[ref];
-    };
-    load_tree(T, nodes, 0, stop, leaf_cost);
-    if (T.overflow)
-        return;
-    restructure_local(T, rounds);
-    store_tree(T, nodes, parent, n);
 }
 
 }  // namespace
@@ -587,15 +484,11 @@ hipError_t launch_restructure(MeshDev &m, int rounds, hipStream_t s) {
     const BuildLists L = build_lists(m.sort_tmp, m.nt);  // the radix-tree kernel's tile list
     int32_t *n_tiles = L.n_tiles;
     int32_t *tiles = L.tiles;
-    float *tile_cost = L.tile_cost;
     const size_t lds = sizeof(TileLds);
     // above the default 64 KB of dynamic LDS: set per call (cheap on the host,
     // and right for whichever device is current; no shared flag between threads)
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_restructure_tiles),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_restructure_top),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
     int dev = 0, cus = 256;
@@ -603,8 +496,7 @@ hipError_t launch_restructure(MeshDev &m, int rounds, hipStream_t s) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t want = (m.nt + kTile - 1) / kTile * 2;  // tiles hold up to kTile leaves, usually fewer
     const int grid = (int)(want < cus ? want : cus);
-    k_restructure_tiles<<<grid, kThreads, lds, s>>>(m.nodes, m.parent, (int)m.nt, tiles, n_tiles, tile_cost, rounds);
-    k_restructure_top<<<1, kThreads, lds, s>>>(m.nodes, m.parent, (int)m.nt, tile_cost, rounds);
+    k_restructure_tiles<<<grid, kThreads, lds, s>>>(m.nodes, m.parent, (int)m.nt, tiles, n_tiles, rounds);
     return hipGetLastError();
 }
 

@@ -165,25 +165,25 @@ hipError_t launch_collapse(MeshDev &m, hipStream_t s);  // wide.hip: the 4-wide 
 hipError_t launch_collapse_proposal(const MeshDev &m, Proposal &pr, hipStream_t s);  // ... of the proposal order
 
 // Lists kept in a mesh's sort scratch once the sort is done: the tile count
-// and tile list of the radix-tree kernel (subtrees of at most 1024 leaves),
-// a cost per tile (restructuring), a node queue and a flag per internal node
-// (4-wide collapse).
+// and tile list of the radix-tree kernel (subtrees of at most 1024 leaves), a
+// node queue and a flag per internal node (4-wide collapse).
 struct BuildLists {
     int32_t *n_tiles, *tiles;
-    float *tile_cost;
     int32_t *queue, *tile_flag;
 };
+// tile_flag bit of the internal nodes with at most 1024 leaves (set by the
+// radix-tree kernel; the tiles are the topmost of them)
+constexpr int32_t kTileRootFlag = 1;
 inline int64_t round64(int64_t n) { return (n + 63) & ~int64_t(63); }
 inline BuildLists build_lists(void *sort_tmp, int64_t nt) {
     BuildLists L;
     L.n_tiles = static_cast<int32_t *>(sort_tmp);
     L.tiles = L.n_tiles + 64;
-    L.tile_cost = reinterpret_cast<float *>(L.tiles + round64(nt));
-    L.queue = reinterpret_cast<int32_t *>(L.tile_cost + round64(nt));
+    L.queue = L.tiles + round64(nt);
     L.tile_flag = L.queue + round64(nt);
     return L;
 }
-inline size_t build_lists_bytes(int64_t nt) { return 4 * (64 + 4 * (size_t)round64(nt)); }
+inline size_t build_lists_bytes(int64_t nt) { return 4 * (64 + 3 * (size_t)round64(nt)); }
 size_t restructure_lds_bytes();
 // Stable sort of (32-bit key, id) pairs in place; tmp holds sort_u32_tmp_bytes(n).
 size_t sort_u32_tmp_bytes(int64_t n);

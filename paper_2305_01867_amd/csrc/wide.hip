@@ -127,15 +127,6 @@ __global__ void k_clear_flags(int32_t *flag, int64_t n) {
         flag[i] = 0;
 }
 
-__global__ void k_mark_tiles(const int32_t *__restrict__ tiles, const int32_t *__restrict__ n_tiles, int32_t *flag,
-                             int64_t n_internal) {
-    const int total = *n_tiles;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-        const int c = tiles[e];
-        if (c >= 0 && c < n_internal)
-            flag[c] = 1;
-    }
-}
 
 // One workgroup per tile: breadth-first from the tile root, a lane per
 // 4-wide node of the current level.
@@ -179,7 +170,7 @@ __global__ __launch_bounds__(256) void k_collapse_tiles(const Node *__restrict__
 // opened, started by the tile workgroups), or the whole tree with the
 // frontier of the learned proposal flagged kFrontier (each frontier node
 // starts a 4-wide node, so the proposal order can start and skip it).
-constexpr int kTileRoot = 1, kFrontier = 2, kMeshRoot = 4;
+constexpr int kTileRoot = kTileRootFlag, kFrontier = 2, kMeshRoot = 4;
 __global__ __launch_bounds__(1024) void k_collapse_top(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
                                                        const int32_t *__restrict__ flag, int no_open, int no_start,
                                                        int32_t *queue, int64_t n_internal) {
@@ -400,9 +391,7 @@ hipError_t launch_collapse(MeshDev &m, hipStream_t s) {
         return hipSuccess;  // one leaf: nothing to collapse
     const int64_t n_internal = m.nt - 1;
     const BuildLists L = build_lists(m.sort_tmp, m.nt);
-    const int blocks = (int)((n_internal + 255) / 256);
-    k_clear_flags<<<blocks, 256, 0, s>>>(L.tile_flag, n_internal);
-    k_mark_tiles<<<blocks, 256, 0, s>>>(L.tiles, L.n_tiles, L.tile_flag, n_internal);
+    // (the radix-tree kernel flagged the tiles' nodes)
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -442,9 +431,7 @@ hipError_t launch_collapse_batch(MeshDev &m, BatchDev &b, hipStream_t s) {
     }
     const int64_t n_internal = m.nt - 1;
     const BuildLists L = build_lists(m.sort_tmp, m.nt);
-    const int blocks = (int)((n_internal + 255) / 256);
-    k_clear_flags<<<blocks, 256, 0, s>>>(L.tile_flag, n_internal);
-    k_mark_tiles<<<blocks, 256, 0, s>>>(L.tiles, L.n_tiles, L.tile_flag, n_internal);
+    // (the radix-tree kernel flagged the tiles' nodes)
     k_mark_mesh_roots<<<1, 64, 0, s>>>(b.roots, b.M, L.tile_flag, n_internal);
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
