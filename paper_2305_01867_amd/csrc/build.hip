@@ -21,6 +21,10 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 2048 keys per tile
 constexpr int kRadix = 256;
+// Up to this many tiles (131,072 keys) a pass is one launch: every scatter
+// workgroup derives its own offsets from the whole (small) histogram and adds
+// its keys to the next pass's histogram as it places them.
+constexpr int kSmallSortTiles = 64;
 constexpr int kBoxTile = 1024;  // leaves per bottom-up workgroup (one per lane)
 constexpr int kNoTile = INT32_MIN;  // never a child reference (leaves are ~k with k < 2^30)
 constexpr int kRestructureRounds = 2;  // treelet restructuring passes of algorithm 2
@@ -200,10 +204,13 @@ __global__ __launch_bounds__(256) void k_morton_batch(const float *__restrict__ 
 // ---------------------------------------------------------- 3. radix sort
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const K *__restrict__ keys, int64_t n, int shift,
-                                                            int ntiles, uint32_t *__restrict__ hist) {
+                                                            int ntiles, uint32_t *__restrict__ hist,
+                                                            uint32_t *__restrict__ clear) {
     __shared__ uint32_t h[kRadix];
     const int tid = threadIdx.x, tile = blockIdx.x;
     h[tid] = 0;
+    if (clear)  // one-launch passes: the histogram the first pass adds to
+        clear[(int64_t)tid * ntiles + tile] = 0u;
     __syncthreads();
     const int64_t base = (int64_t)tile * kSortTile;
 #pragma unroll
@@ -358,6 +365,85 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const K *__restri
                 pos += wcnt[w][digit];
             kout[pos] = key;
             iout[pos] = id;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < kSortThreads / 64; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// One pass of a small sort in one launch.  hist holds this pass's per-tile
+// digit counts (digit-major); each workgroup sums them into its own offsets
+// (digits below, then earlier tiles of its digit), scatters its tile like
+// k_sort_scatter, and counts each placed key's next digit into hist_next at
+// the tile its new position falls in.  hist_clear (the histogram two passes
+// on) is zeroed here: nothing reads or adds to it during this pass.
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_pass_small(const K *__restrict__ kin,
+                                                                  const int32_t *__restrict__ iin,
+                                                                  K *__restrict__ kout, int32_t *__restrict__ iout,
+                                                                  int64_t n, int shift, int ntiles,
+                                                                  const uint32_t *__restrict__ hist,
+                                                                  uint32_t *__restrict__ hist_next,
+                                                                  uint32_t *__restrict__ hist_clear, int next) {
+    __shared__ uint32_t run[kRadix];
+    __shared__ uint32_t base[kRadix];
+    __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
+    __shared__ uint32_t wsum[kSortThreads / 64];
+    const int tid = threadIdx.x, tile = blockIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    uint32_t earlier = 0, total = 0;
+    const uint32_t *h = hist + (int64_t)tid * ntiles;
+    for (int t = 0; t < ntiles; ++t) {
+        const uint32_t v = h[t];
+        earlier += t < tile ? v : 0u;
+        total += v;
+    }
+    uint32_t all;
+    base[tid] = block_excl_scan(total, wsum, all) + earlier;
+    hist_clear[(int64_t)tid * ntiles + tile] = 0u;
+    run[tid] = 0;
+    for (int w = 0; w < kSortThreads / 64; ++w)
+        wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t t0 = (int64_t)tile * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t idx = t0 + r * kSortThreads + tid;
+        const bool valid = idx < n;
+        K key = 0;
+        int32_t id = 0;
+        uint32_t digit = 0;
+        if (valid) {
+            key = kin[idx];
+            id = iin[idx];
+            digit = (uint32_t)(key >> shift) & 0xffu;
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (digit >> bit) & 1u;
+            const uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0)
+            wcnt[wave][digit] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[digit] + run[digit] + rank;
+            for (int w = 0; w < wave; ++w)
+                pos += wcnt[w][digit];
+            kout[pos] = key;
+            iout[pos] = id;
+            if (next)
+                atomicAdd(hist_next + (int64_t)((uint32_t)(key >> (shift + 8)) & 0xffu) * ntiles + pos / kSortTile,
+                          1u);
         }
         __syncthreads();
         uint32_t add = 0;
@@ -699,12 +785,8 @@ __global__ void k_zero_i32(int32_t *p, int n) {
 
 inline int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
 
-// Stable LSD passes over (keys, ids) with 8-bit digits; tmp holds the
-// ping-pong copies, the tile histograms and the scan partials.  An even
-// number of passes (key_bits 30 or 63 rounded up to 32 or 64) leaves the
-// result in (keys, ids).
-// After an odd number of passes the sorted pairs sit in the scratch buffers:
-// copy them back.
+// After an odd number of sort passes the sorted pairs sit in the scratch
+// buffers: copy them back.
 template <typename K>
 __global__ void k_copy_pairs(const K *__restrict__ k_in, const int32_t *__restrict__ i_in, K *__restrict__ k_out,
                              int32_t *__restrict__ i_out, int64_t n) {
@@ -715,6 +797,12 @@ __global__ void k_copy_pairs(const K *__restrict__ k_in, const int32_t *__restri
     }
 }
 
+// Stable LSD passes over (keys, ids) with 8-bit digits; tmp holds the
+// ping-pong copies, the tile histograms and the scan partials.  Up to
+// kSmallSortTiles tiles a pass is one launch; above that, a histogram, a scan
+// and a scatter.  An even number of passes (key_bits 30 or 63 rounded up to
+// 32 or 64) leaves the result in (keys, ids); an odd one (the batched form's
+// 36-bit keys) ends with a copy back.
 template <typename K>
 void sort_passes(K *keys, int32_t *ids, void *tmp, int64_t n, int key_bits, hipStream_t s) {
     K *keys_tmp = static_cast<K *>(tmp);
@@ -724,12 +812,29 @@ void sort_passes(K *keys, int32_t *ids, void *tmp, int64_t n, int key_bits, hipS
     uint32_t *partial = hist + (int64_t)kRadix * ntiles;
     K *src_k = keys, *dst_k = keys_tmp;
     int32_t *src_i = ids, *dst_i = ids_tmp;
-    for (int shift = 0; shift < key_bits; shift += 8) {
-        k_sort_hist<K><<<ntiles, kSortThreads, 0, s>>>(src_k, n, shift, ntiles, hist);
-        scan_hist(hist, (int64_t)kRadix * ntiles, partial, s);
-        k_sort_scatter<K><<<ntiles, kSortThreads, 0, s>>>(src_k, src_i, dst_k, dst_i, n, shift, ntiles, hist);
-        K *tk = src_k; src_k = dst_k; dst_k = tk;
-        int32_t *ti = src_i; src_i = dst_i; dst_i = ti;
+    if (n <= 1)
+        return;  // nothing to order
+    if (ntiles <= kSmallSortTiles) {
+        // three histograms in turn: read by this pass, added to for the next,
+        // cleared for the one after
+        const int64_t hl = (int64_t)kRadix * ntiles;
+        uint32_t *H[3] = {hist, hist + hl, hist + 2 * hl};
+        k_sort_hist<K><<<ntiles, kSortThreads, 0, s>>>(src_k, n, 0, ntiles, H[0], H[1]);
+        for (int shift = 0, pass = 0; shift < key_bits; shift += 8, ++pass) {
+            k_sort_pass_small<K><<<ntiles, kSortThreads, 0, s>>>(src_k, src_i, dst_k, dst_i, n, shift, ntiles,
+                                                                  H[pass % 3], H[(pass + 1) % 3], H[(pass + 2) % 3],
+                                                                  shift + 8 < key_bits ? 1 : 0);
+            K *tk = src_k; src_k = dst_k; dst_k = tk;
+            int32_t *ti = src_i; src_i = dst_i; dst_i = ti;
+        }
+    } else {
+        for (int shift = 0; shift < key_bits; shift += 8) {
+            k_sort_hist<K><<<ntiles, kSortThreads, 0, s>>>(src_k, n, shift, ntiles, hist, nullptr);
+            scan_hist(hist, (int64_t)kRadix * ntiles, partial, s);
+            k_sort_scatter<K><<<ntiles, kSortThreads, 0, s>>>(src_k, src_i, dst_k, dst_i, n, shift, ntiles, hist);
+            K *tk = src_k; src_k = dst_k; dst_k = tk;
+            int32_t *ti = src_i; src_i = dst_i; dst_i = ti;
+        }
     }
     if (src_k != keys && n > 0)
         k_copy_pairs<K><<<blocks_for(n, 256), 256, 0, s>>>(src_k, src_i, keys, ids, n);
@@ -737,7 +842,8 @@ void sort_passes(K *keys, int32_t *ids, void *tmp, int64_t n, int key_bits, hipS
 
 size_t pass_tmp_bytes(int64_t n, size_t key_bytes) {
     const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
-    return key_bytes * n + 4 * n + 4 * (size_t)kRadix * ntiles + 4 * 1024 + 256;
+    const int64_t hists = ntiles <= kSmallSortTiles ? 3 : 1;  // one-launch passes keep three
+    return key_bytes * n + 4 * n + 4 * (size_t)kRadix * ntiles * hists + 4 * 1024 + 256;
 }
 
 // Sort (key, id), build the radix tree and fill the boxes bottom-up, for keys
