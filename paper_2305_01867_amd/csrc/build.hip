@@ -316,38 +316,33 @@ void scan_hist(uint32_t *hist, int64_t len, uint32_t *partial, hipStream_t s) {
     k_scan_apply<<<g, 1024, 0, s>>>(hist, len, seg, partial);
 }
 
-// Stable scatter of one tile.  Rounds of 256 consecutive keys are ranked in
-// order: inside a wave by matching the 8 digit bits with ballots, across the
-// four waves and earlier rounds through per-digit LDS counts.
+// Stable scatter of one tile.  Its keys are loaded at once (eight per
+// lane), then ranked in rounds of 256 consecutive keys: inside a wave by
+// matching the 8 digit bits with ballots, across the four waves and earlier
+// rounds through per-digit LDS counts.  base[d] is where the tile's keys of
+// digit d start; run and wcnt start at zero.  With hist_next, each placed
+// key's next digit is counted at the tile its new position falls in.
 template <typename K>
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const K *__restrict__ kin,
-                                                               const int32_t *__restrict__ iin,
-                                                               K *__restrict__ kout, int32_t *__restrict__ iout,
-                                                               int64_t n, int shift, int ntiles,
-                                                               const uint32_t *__restrict__ offs) {
-    __shared__ uint32_t run[kRadix];
-    __shared__ uint32_t base[kRadix];
-    __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
-    const int tid = threadIdx.x, tile = blockIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    run[tid] = 0;
-    base[tid] = offs[(int64_t)tid * ntiles + tile];
-    for (int w = 0; w < kSortThreads / 64; ++w)
-        wcnt[w][tid] = 0;
-    __syncthreads();
+__device__ __forceinline__ void scatter_tile(const K *__restrict__ kin, const int32_t *__restrict__ iin,
+                                             K *__restrict__ kout, int32_t *__restrict__ iout, int64_t n,
+                                             int shift, int tile, uint32_t *run, const uint32_t *base,
+                                             uint32_t (*wcnt)[kRadix], uint32_t *__restrict__ hist_next,
+                                             int ntiles) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t t0 = (int64_t)tile * kSortTile;
+    K key[kSortItems];
+    int32_t id[kSortItems];
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t idx = t0 + r * kSortThreads + tid;
-        const bool valid = idx < n;
-        K key = 0;
-        int32_t id = 0;
-        uint32_t digit = 0;
-        if (valid) {
-            key = kin[idx];
-            id = iin[idx];
-            digit = (uint32_t)(key >> shift) & 0xffu;
-        }
+        key[r] = idx < n ? kin[idx] : K(0);
+        id[r] = idx < n ? iin[idx] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const bool valid = t0 + r * kSortThreads + tid < n;
+        const uint32_t digit = valid ? (uint32_t)(key[r] >> shift) & 0xffu : 0u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
@@ -363,8 +358,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const K *__restri
             uint32_t pos = base[digit] + run[digit] + rank;
             for (int w = 0; w < wave; ++w)
                 pos += wcnt[w][digit];
-            kout[pos] = key;
-            iout[pos] = id;
+            kout[pos] = key[r];
+            iout[pos] = id[r];
+            if (hist_next)
+                atomicAdd(hist_next + (int64_t)((uint32_t)(key[r] >> (shift + 8)) & 0xffu) * ntiles + pos / kSortTile,
+                          1u);
         }
         __syncthreads();
         uint32_t add = 0;
@@ -377,12 +375,31 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const K *__restri
     }
 }
 
+// One scatter pass over scanned tile histograms (offs: digit-major, exclusive).
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const K *__restrict__ kin,
+                                                               const int32_t *__restrict__ iin,
+                                                               K *__restrict__ kout, int32_t *__restrict__ iout,
+                                                               int64_t n, int shift, int ntiles,
+                                                               const uint32_t *__restrict__ offs) {
+    __shared__ uint32_t run[kRadix];
+    __shared__ uint32_t base[kRadix];
+    __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
+    const int tid = threadIdx.x, tile = blockIdx.x;
+    run[tid] = 0;
+    base[tid] = offs[(int64_t)tid * ntiles + tile];
+    for (int w = 0; w < kSortThreads / 64; ++w)
+        wcnt[w][tid] = 0;
+    __syncthreads();
+    scatter_tile<K>(kin, iin, kout, iout, n, shift, tile, run, base, wcnt, nullptr, ntiles);
+}
+
 // One pass of a small sort in one launch.  hist holds this pass's per-tile
 // digit counts (digit-major); each workgroup sums them into its own offsets
-// (digits below, then earlier tiles of its digit), scatters its tile like
-// k_sort_scatter, and counts each placed key's next digit into hist_next at
-// the tile its new position falls in.  hist_clear (the histogram two passes
-// on) is zeroed here: nothing reads or adds to it during this pass.
+// (digits below, then earlier tiles of its digit) and scatters its tile,
+// counting the next digit into hist_next (null after the last pass).
+// hist_clear (the histogram two passes on) is zeroed here: nothing reads or
+// adds to it during this pass.
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_sort_pass_small(const K *__restrict__ kin,
                                                                   const int32_t *__restrict__ iin,
@@ -390,13 +407,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass_small(const K *__res
                                                                   int64_t n, int shift, int ntiles,
                                                                   const uint32_t *__restrict__ hist,
                                                                   uint32_t *__restrict__ hist_next,
-                                                                  uint32_t *__restrict__ hist_clear, int next) {
+                                                                  uint32_t *__restrict__ hist_clear) {
     __shared__ uint32_t run[kRadix];
     __shared__ uint32_t base[kRadix];
     __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
     __shared__ uint32_t wsum[kSortThreads / 64];
     const int tid = threadIdx.x, tile = blockIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
     uint32_t earlier = 0, total = 0;
     const uint32_t *h = hist + (int64_t)tid * ntiles;
     for (int t = 0; t < ntiles; ++t) {
@@ -411,49 +427,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass_small(const K *__res
     for (int w = 0; w < kSortThreads / 64; ++w)
         wcnt[w][tid] = 0;
     __syncthreads();
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t t0 = (int64_t)tile * kSortTile;
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t idx = t0 + r * kSortThreads + tid;
-        const bool valid = idx < n;
-        K key = 0;
-        int32_t id = 0;
-        uint32_t digit = 0;
-        if (valid) {
-            key = kin[idx];
-            id = iin[idx];
-            digit = (uint32_t)(key >> shift) & 0xffu;
-        }
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const bool set = (digit >> bit) & 1u;
-            const uint64_t m = __ballot(set);
-            peers &= set ? m : ~m;
-        }
-        const uint32_t rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0)
-            wcnt[wave][digit] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = base[digit] + run[digit] + rank;
-            for (int w = 0; w < wave; ++w)
-                pos += wcnt[w][digit];
-            kout[pos] = key;
-            iout[pos] = id;
-            if (next)
-                atomicAdd(hist_next + (int64_t)((uint32_t)(key >> (shift + 8)) & 0xffu) * ntiles + pos / kSortTile,
-                          1u);
-        }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < kSortThreads / 64; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
-        }
-        run[tid] += add;
-        __syncthreads();
-    }
+    scatter_tile<K>(kin, iin, kout, iout, n, shift, tile, run, base, wcnt, hist_next, ntiles);
 }
 
 // ---------------------------------------------------------- 4. radix tree
@@ -822,8 +796,8 @@ void sort_passes(K *keys, int32_t *ids, void *tmp, int64_t n, int key_bits, hipS
         k_sort_hist<K><<<ntiles, kSortThreads, 0, s>>>(src_k, n, 0, ntiles, H[0], H[1]);
         for (int shift = 0, pass = 0; shift < key_bits; shift += 8, ++pass) {
             k_sort_pass_small<K><<<ntiles, kSortThreads, 0, s>>>(src_k, src_i, dst_k, dst_i, n, shift, ntiles,
-                                                                  H[pass % 3], H[(pass + 1) % 3], H[(pass + 2) % 3],
-                                                                  shift + 8 < key_bits ? 1 : 0);
+                                                                  H[pass % 3], shift + 8 < key_bits ? H[(pass + 1) % 3] : nullptr,
+                                                                  H[(pass + 2) % 3]);
             K *tk = src_k; src_k = dst_k; dst_k = tk;
             int32_t *ti = src_i; src_i = dst_i; dst_i = ti;
         }

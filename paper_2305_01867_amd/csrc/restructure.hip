@@ -37,27 +37,24 @@ constexpr int kTreelet = 4;            // leaves per treelet (the optimisation r
 constexpr float kCostNode = 1.2f;      // SAH weight of a node visit (one 64-B node, two box tests)
 constexpr float kCostTri = 1.0f;       // SAH weight of a triangle test
 
-// LDS image of one (sub)tree.  Local internal node 0 is the root.  A local
-// child reference is >= 0 for a local internal node and ~j for local leaf j.
+// LDS image of one (sub)tree, nodes and leaves in one index space: a local
+// reference c below kTile is internal node c (local ids are offsets from the
+// tile's first internal node), c >= kTile is leaf c - kTile.  Every per-node
+// quantity is then one LDS read, whichever kind the reference is.
 struct TileLds {
-    int in_child[2][kTile];
-    int in_slot[kTile];        // global internal node index
-    float in_box[6][kTile];    // own box: lo xyz, hi xyz
-    float in_cost[kTile];      // SAH cost of the subtree
-    int in_count[kTile];       // leaves below
-    int in_lo[kTile], in_hi[kTile];  // smallest / largest sorted leaf below
-    int in_parent[kTile];      // local parent, -1 at the root
-    int arrive[kTile + 2];     // arrivals of the height climb, then per-height counters
-    int height[kTile];         // 1 + the larger child height (a leaf is 0)
-    int order[kTile];          // internal nodes by rising height
-    int h_start[kTile + 2];    // order[h_start[h] .. h_start[h + 1]) have height h
-    int lf_ref[kTile];         // global reference of local leaf j (a leaf ~k)
-    float lf_box[6][kTile];
-    float lf_cost[kTile];
-    int lf_count[kTile];
-    int lf_lo[kTile], lf_hi[kTile];
-    int lf_parent[kTile];
-    int n_in, n_lf, root, max_height;
+    int child[2][kTile];         // local references of internal node j's children
+    int slot[kTile];             // global internal node index of internal node j
+    int lf_ref[kTile];           // global reference of leaf k (a leaf ~g)
+    float box[6][2 * kTile];     // own box of reference c: lo xyz, hi xyz
+    float cost[2 * kTile];       // SAH cost of the subtree
+    int count[2 * kTile];        // leaves below
+    int lo[2 * kTile], hi[2 * kTile];  // smallest / largest sorted leaf below
+    int parent[2 * kTile];       // local parent (internal), -1 at the root
+    int arrive[kTile + 2];       // arrivals of the height climb, then per-height counters
+    int height[kTile];           // 1 + the larger child height (a leaf is 0)
+    int order[kTile];            // internal nodes by rising height
+    int h_start[kTile + 2];      // order[h_start[h] .. h_start[h + 1]) have height h
+    int n_in, n_lf, max_height;
 };
 
 __device__ __forceinline__ float half_area(float x0, float y0, float z0, float x1, float y1, float z1) {
@@ -65,39 +62,17 @@ __device__ __forceinline__ float half_area(float x0, float y0, float z0, float x
     return dx * dy + dy * dz + dz * dx;  // half the surface area; the common factor 2 cancels in comparisons
 }
 
-__device__ __forceinline__ float tri_cost(const float *b) {
-    return kCostTri * half_area(b[0], b[1], b[2], b[3], b[4], b[5]);
+__device__ __forceinline__ float box_area(const TileLds &T, int c) {
+    return half_area(T.box[0][c], T.box[1][c], T.box[2][c], T.box[3][c], T.box[4][c], T.box[5][c]);
 }
-
-// Box / cost / count / leaf span of a local reference.
-__device__ __forceinline__ float ref_box(const TileLds &T, int r, int a) {
-    return r >= 0 ? T.in_box[a][r] : T.lf_box[a][~r];
-}
-__device__ __forceinline__ float ref_cost(const TileLds &T, int r) { return r >= 0 ? T.in_cost[r] : T.lf_cost[~r]; }
-__device__ __forceinline__ int ref_count(const TileLds &T, int r) { return r >= 0 ? T.in_count[r] : T.lf_count[~r]; }
-__device__ __forceinline__ int ref_lo(const TileLds &T, int r) { return r >= 0 ? T.in_lo[r] : T.lf_lo[~r]; }
-__device__ __forceinline__ int ref_hi(const TileLds &T, int r) { return r >= 0 ? T.in_hi[r] : T.lf_hi[~r]; }
 
 // Cost, count and leaf span of internal node j from its children.
-__device__ __forceinline__ float node_cost(const TileLds &T, int j) {
-    return kCostNode * half_area(T.in_box[0][j], T.in_box[1][j], T.in_box[2][j], T.in_box[3][j], T.in_box[4][j],
-                                 T.in_box[5][j]) +
-           ref_cost(T, T.in_child[0][j]) + ref_cost(T, T.in_child[1][j]);
-}
-
 __device__ __forceinline__ void refresh_node(TileLds &T, int j) {
-    const int c0 = T.in_child[0][j], c1 = T.in_child[1][j];
-    T.in_cost[j] = node_cost(T, j);
-    T.in_count[j] = ref_count(T, c0) + ref_count(T, c1);
-    T.in_lo[j] = min(ref_lo(T, c0), ref_lo(T, c1));
-    T.in_hi[j] = max(ref_hi(T, c0), ref_hi(T, c1));
-}
-
-__device__ __forceinline__ void set_parent(TileLds &T, int ref, int j) {
-    if (ref >= 0)
-        T.in_parent[ref] = j;
-    else
-        T.lf_parent[~ref] = j;
+    const int c0 = T.child[0][j], c1 = T.child[1][j];
+    T.cost[j] = kCostNode * box_area(T, j) + T.cost[c0] + T.cost[c1];
+    T.count[j] = T.count[c0] + T.count[c1];
+    T.lo[j] = min(T.lo[c0], T.lo[c1]);
+    T.hi[j] = max(T.hi[c0], T.hi[c1]);
 }
 
 // Splits of the subsets of four treelet leaves: {subset, part holding the
@@ -115,8 +90,9 @@ __device__ constexpr unsigned char kSplits[kSplitCount][3] = {
 // known at compile time (all in registers), and rewires the (at most three)
 // internal nodes when that is cheaper than the current shape.
 __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
-    int leaf[4] = {T.in_child[0][p], T.in_child[1][p], 0, 0};
+    int leaf[4] = {T.child[0][p], T.child[1][p], 0, 0};
     int inner[3] = {p, -1, -1};
+    const float now = T.cost[p];
     int m = 2;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -125,9 +101,8 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const int r = leaf[i];
-            if (i < m && r >= 0) {
-                const float a = half_area(T.in_box[0][r], T.in_box[1][r], T.in_box[2][r], T.in_box[3][r],
-                                          T.in_box[4][r], T.in_box[5][r]);
+            if (i < m && r < kTile) {
+                const float a = box_area(T, r);
                 if (a > best_a) {
                     best_a = a;
                     best = i;
@@ -140,7 +115,7 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
 #pragma unroll
         for (int i = 1; i < 3; ++i)
             r = best == i ? leaf[i] : r;
-        const int c0 = T.in_child[0][r], c1 = T.in_child[1][r];
+        const int c0 = T.child[0][r], c1 = T.child[1][r];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             leaf[i] = i == best ? c0 : leaf[i];
@@ -153,43 +128,41 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
     }
     if (m < 3)
         return;  // both children are leaves: one shape only
-    // the treelet leaves' box, cost, leaf count and leaf span, read once
-    float lb[4][6], lc[4];
-    int ln[4], llo[4], lhi[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = i < m ? leaf[i] : leaf[0];
-#pragma unroll
-        for (int a = 0; a < 6; ++a)
-            lb[i][a] = ref_box(T, r, a);
-        lc[i] = ref_cost(T, r);
-        ln[i] = ref_count(T, r);
-        llo[i] = ref_lo(T, r);
-        lhi[i] = ref_hi(T, r);
-    }
-    const int full = (1 << m) - 1;
-    float area[16], cost[16], best_sum[16];
+    // every subset's box, leaf count and leaf span, each from the subset
+    // without its lowest leaf (with three leaves the fourth repeats the first
+    // and only subsets of the first three are used)
+    float sb[16][6], area[16];
+    int sn[16], slo[16], shi[16];
+    float cost[16], best_sum[16];
     int split[16];
 #pragma unroll
     for (int S = 1; S < 16; ++S) {
-        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        const int i = __builtin_ctz(S), R = S & (S - 1);
+        const int r = i < m ? leaf[i] : leaf[0];
+        if (R == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if ((S >> i) & 1)
+            for (int a = 0; a < 6; ++a)
+                sb[S][a] = T.box[a][r];
+            sn[S] = T.count[r];
+            slo[S] = T.lo[r];
+            shi[S] = T.hi[r];
+            cost[S] = T.cost[r];
+        } else {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    b[a] = fminf(b[a], lb[i][a]);
-                    b[3 + a] = fmaxf(b[3 + a], lb[i][3 + a]);
-                }
-        area[S] = half_area(b[0], b[1], b[2], b[3], b[4], b[5]);
-        cost[S] = best_sum[S] = INFINITY;
+            for (int a = 0; a < 3; ++a) {
+                sb[S][a] = fminf(sb[R][a], sb[1 << i][a]);
+                sb[S][3 + a] = fmaxf(sb[R][3 + a], sb[1 << i][3 + a]);
+            }
+            sn[S] = sn[R] + sn[1 << i];
+            slo[S] = min(slo[R], slo[1 << i]);
+            shi[S] = max(shi[R], shi[1 << i]);
+            cost[S] = INFINITY;
+        }
+        area[S] = half_area(sb[S][0], sb[S][1], sb[S][2], sb[S][3], sb[S][4], sb[S][5]);
+        best_sum[S] = INFINITY;
         split[S] = 0;
     }
-    area[0] = cost[0] = 0.0f;
-    split[0] = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        cost[1 << i] = lc[i];
+    cost[0] = 0.0f;
     // every split (S, P | S^P) of a subset S of two or more leaves, with P
     // holding S's lowest leaf so each unordered pair appears once, listed by
     // subset size so a subset's parts are done before it; the flag marks a
@@ -205,7 +178,7 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
         if (kSplits[e][2])
             cost[S] = kCostNode * area[S] + best_sum[S];
     }
-    const float now = T.in_cost[p];
+    const int full = (1 << m) - 1;
     const float best_cost = m == 4 ? cost[15] : cost[7];
     if (!(best_cost < now * (1.0f - 1e-6f)))
         return;
@@ -250,32 +223,18 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
                 child1 = __builtin_popcount(Q) == 1 ? leaf[__builtin_ctz(Q)] : node[Q];
             }
         }
-        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-        int count = 0, lo = INT32_MAX, hi = INT32_MIN;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if ((S >> i) & 1) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    b[a] = fminf(b[a], lb[i][a]);
-                    b[3 + a] = fmaxf(b[3 + a], lb[i][3 + a]);
-                }
-                count += ln[i];
-                lo = min(lo, llo[i]);
-                hi = max(hi, lhi[i]);
-            }
         const int j = node[S];
-        T.in_child[0][j] = child0;
-        T.in_child[1][j] = child1;
-        set_parent(T, child0, j);
-        set_parent(T, child1, j);
+        T.child[0][j] = child0;
+        T.child[1][j] = child1;
+        T.parent[child0] = j;
+        T.parent[child1] = j;
 #pragma unroll
         for (int a = 0; a < 6; ++a)
-            T.in_box[a][j] = b[a];
-        T.in_cost[j] = cost[S];
-        T.in_count[j] = count;
-        T.in_lo[j] = lo;
-        T.in_hi[j] = hi;
+            T.box[a][j] = sb[S][a];
+        T.cost[j] = cost[S];
+        T.count[j] = sn[S];
+        T.lo[j] = slo[S];
+        T.hi[j] = shi[S];
     }
 }
 
@@ -291,16 +250,16 @@ __device__ __forceinline__ void local_heights(TileLds &T) {
         T.max_height = 0;
     __syncthreads();
     for (int k = threadIdx.x; k < T.n_lf; k += blockDim.x) {
-        int j = T.lf_parent[k];
+        int j = T.parent[kTile + k];
         for (int step = 0; j >= 0 && step < T.n_in; ++step) {  // a climb is at most n_in nodes long
             if (__hip_atomic_fetch_add(&T.arrive[j], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
                 break;  // the other subtree is still on its way
-            const int c0 = T.in_child[0][j], c1 = T.in_child[1][j];
-            const int h = 1 + max(c0 >= 0 ? T.height[c0] : 0, c1 >= 0 ? T.height[c1] : 0);
+            const int c0 = T.child[0][j], c1 = T.child[1][j];
+            const int h = 1 + max(c0 < kTile ? T.height[c0] : 0, c1 < kTile ? T.height[c1] : 0);
             T.height[j] = h;
-            if (T.in_parent[j] < 0)
+            if (T.parent[j] < 0)
                 T.max_height = h;  // the local root is the highest node
-            j = T.in_parent[j];
+            j = T.parent[j];
         }
     }
     __syncthreads();
@@ -368,7 +327,7 @@ __device__ __forceinline__ void restructure_local(TileLds &T, int rounds) {
             for (int i = T.h_start[h] + threadIdx.x; i < e; i += blockDim.x) {
                 const int j = T.order[i];
                 refresh_node(T, j);
-                if (T.in_count[j] >= kTreelet)
+                if (T.count[j] >= kTreelet)
                     optimize_treelet(T, j);
             }
             __syncthreads();
@@ -391,60 +350,48 @@ __device__ void load_tile(TileLds &T, const Node *__restrict__ nodes, int c) {
         const float4 L = nd->xy_left, R = nd->xy_right, Z = nd->z_both;
         const int4 refs = nd->refs;
         const float cb[2][6] = {{L.x, L.z, Z.x, L.y, L.w, Z.y}, {R.x, R.z, Z.z, R.y, R.w, Z.w}};
-        T.in_slot[j] = base + j;
+        T.slot[j] = base + j;
         const int child[2] = {refs.x, refs.y};
         for (int side = 0; side < 2; ++side) {
             const int g = child[side];
-            if (g >= 0) {
-                const int id = g - base;
-                T.in_parent[id] = j;
-                for (int e = 0; e < 6; ++e)
-                    T.in_box[e][id] = cb[side][e];
-                T.in_child[side][j] = id;
-            } else {
-                const int id = ~g - a;
-                T.lf_ref[id] = g;
-                T.lf_parent[id] = j;
-                for (int e = 0; e < 6; ++e)
-                    T.lf_box[e][id] = cb[side][e];
-                T.lf_cost[id] = tri_cost(cb[side]);
-                T.lf_count[id] = 1;
-                T.lf_lo[id] = T.lf_hi[id] = ~g;
-                T.in_child[side][j] = ~id;
+            const int id = g >= 0 ? g - base : kTile + (~g - a);
+            T.parent[id] = j;
+            for (int e = 0; e < 6; ++e)
+                T.box[e][id] = cb[side][e];
+            if (g < 0) {
+                T.lf_ref[id - kTile] = g;
+                T.cost[id] = kCostTri * half_area(cb[side][0], cb[side][1], cb[side][2], cb[side][3], cb[side][4],
+                                                  cb[side][5]);
+                T.count[id] = 1;
+                T.lo[id] = T.hi[id] = ~g;
             }
+            T.child[side][j] = id;
         }
         if (base + j == c) {
-            T.in_parent[j] = -1;
+            T.parent[j] = -1;
             for (int e = 0; e < 3; ++e) {
-                T.in_box[e][j] = fminf(cb[0][e], cb[1][e]);
-                T.in_box[3 + e][j] = fmaxf(cb[0][3 + e], cb[1][3 + e]);
+                T.box[e][j] = fminf(cb[0][e], cb[1][e]);
+                T.box[3 + e][j] = fmaxf(cb[0][3 + e], cb[1][3 + e]);
             }
         }
     }
     if (threadIdx.x == 0) {
         T.n_in = n_in;
         T.n_lf = n_in ? n_in + 1 : 0;
-        T.root = c - base;
     }
     __syncthreads();
 }
 
 __device__ void store_tree(const TileLds &T, Node *nodes, int32_t *parent, int n) {
     for (int j = threadIdx.x; j < T.n_in; j += blockDim.x) {
-        const int g = T.in_slot[j];
+        const int g = T.slot[j];
         int gref[2];
         float b[2][6];
         for (int side = 0; side < 2; ++side) {
-            const int c = T.in_child[side][j];
-            if (c >= 0) {
-                gref[side] = T.in_slot[c];
-                for (int a = 0; a < 6; ++a)
-                    b[side][a] = T.in_box[a][c];
-            } else {
-                gref[side] = T.lf_ref[~c];
-                for (int a = 0; a < 6; ++a)
-                    b[side][a] = T.lf_box[a][~c];
-            }
+            const int c = T.child[side][j];
+            gref[side] = c < kTile ? T.slot[c] : T.lf_ref[c - kTile];
+            for (int a = 0; a < 6; ++a)
+                b[side][a] = T.box[a][c];
             const int pslot = gref[side] >= 0 ? gref[side] : (n - 1) + ~gref[side];
             parent[pslot] = g;
         }
@@ -452,7 +399,7 @@ __device__ void store_tree(const TileLds &T, Node *nodes, int32_t *parent, int n
         nd->xy_left = make_float4(b[0][0], b[0][3], b[0][1], b[0][4]);
         nd->xy_right = make_float4(b[1][0], b[1][3], b[1][1], b[1][4]);
         nd->z_both = make_float4(b[0][2], b[0][5], b[1][2], b[1][5]);
-        nd->refs = make_int4(gref[0], gref[1], T.in_lo[j], T.in_hi[j]);
+        nd->refs = make_int4(gref[0], gref[1], T.lo[j], T.hi[j]);
     }
 }
 
