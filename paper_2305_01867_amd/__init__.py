@@ -260,14 +260,19 @@ def rsi_intersect(mesh: Mesh, rays_from: torch.Tensor, rays_to: torch.Tensor, mo
     dev = rays_from.device
     out = dict(out or {})
     if mode == "boolean":
-        out.setdefault("hit", torch.empty(n, dtype=torch.uint8, device=dev))
+        if "hit" not in out:
+            out["hit"] = torch.empty(n, dtype=torch.uint8, device=dev)
     elif mode == "intercept_count":
-        out.setdefault("count", torch.empty(n, dtype=torch.int32, device=dev))
+        if "count" not in out:
+            out["count"] = torch.empty(n, dtype=torch.int32, device=dev)
     else:
-        out.setdefault("tri_id", torch.empty(n, dtype=torch.int32, device=dev))
+        if "tri_id" not in out:
+            out["tri_id"] = torch.empty(n, dtype=torch.int32, device=dev)
     if mode == "barycentric":
-        out.setdefault("uvt", torch.empty((n, 3), dtype=torch.float32, device=dev))
-    out.setdefault("counters", torch.zeros(4, dtype=torch.int64, device=dev))
+        if "uvt" not in out:
+            out["uvt"] = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    if "counters" not in out:
+        out["counters"] = torch.empty(4, dtype=torch.int64, device=dev)
     spec = {"hit": (torch.uint8, None), "tri_id": (torch.int32, None), "uvt": (torch.float32, 3),
             "count": (torch.int32, None), "counters": (torch.int64, None)}
     for k, t in out.items():
@@ -595,14 +600,19 @@ def rsi_batch_intersect(batch: Batch, rays_from, rays_to, mode: str = "boolean",
     dev = rays_from.device
     out = dict(out or {})
     if mode == "boolean":
-        out.setdefault("hit", torch.empty(n, dtype=torch.uint8, device=dev))
+        if "hit" not in out:
+            out["hit"] = torch.empty(n, dtype=torch.uint8, device=dev)
     elif mode == "intercept_count":
-        out.setdefault("count", torch.empty(n, dtype=torch.int32, device=dev))
+        if "count" not in out:
+            out["count"] = torch.empty(n, dtype=torch.int32, device=dev)
     else:
-        out.setdefault("tri_id", torch.empty(n, dtype=torch.int32, device=dev))
+        if "tri_id" not in out:
+            out["tri_id"] = torch.empty(n, dtype=torch.int32, device=dev)
     if mode == "barycentric":
-        out.setdefault("uvt", torch.empty((n, 3), dtype=torch.float32, device=dev))
-    out.setdefault("counters", torch.zeros(4, dtype=torch.int64, device=dev))
+        if "uvt" not in out:
+            out["uvt"] = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    if "counters" not in out:
+        out["counters"] = torch.empty(4, dtype=torch.int64, device=dev)
 
     def ptr(k):
         return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p()

@@ -11,9 +11,9 @@
 //
 // Work split as in the bottom-up pass: one workgroup per tile (a subtree of
 // at most 1024 leaves listed by the radix-tree kernel), breadth-first from
-// the tile root with the queue in LDS; one workgroup for the nodes above the
-// tiles, which never opens a tile root (every tile root starts a 4-wide node
-// of its own).  Treelet restructuring keeps every tile root and its leaves,
+// the tile root with the queue in LDS; one more workgroup of the same launch
+// for the nodes above the tiles, which never opens a tile root (every tile
+// root starts a 4-wide node of its own).  Treelet restructuring keeps every tile root and its leaves,
 // so the same tile list serves both builds.
 #include "rsi_internal.h"
 
@@ -128,40 +128,30 @@ __global__ void k_clear_flags(int32_t *flag, int64_t n) {
 }
 
 
-// One workgroup per tile: breadth-first from the tile root, a lane per
-// 4-wide node of the current level.
-__global__ __launch_bounds__(256) void k_collapse_tiles(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
-                                                        const int32_t *__restrict__ tiles,
-                                                        const int32_t *__restrict__ n_tiles,
-                                                        const int32_t *__restrict__ flag, int no_open) {
-    __shared__ int q[kTileQueue];
-    __shared__ int qn;
-    const int total = *n_tiles;
-    for (int e = blockIdx.x; e < total; e += gridDim.x) {
-        const int c = tiles[e];
-        if (c < 0)
-            continue;  // a one-leaf tile: no internal node
-        if (threadIdx.x == 0) {
-            q[0] = c;
-            qn = 1;
+// One workgroup's tile: breadth-first from the tile root c, a lane per 4-wide
+// node of the current level, the queue in LDS.
+__device__ void collapse_tile(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4, int c,
+                              const int32_t *__restrict__ flag, int no_open, int *q, int &qn) {
+    if (threadIdx.x == 0) {
+        q[0] = c;
+        qn = 1;
+    }
+    __syncthreads();
+    int b0 = 0, b1 = 1;
+    while (b0 < b1) {
+        for (int i = b0 + (int)threadIdx.x; i < b1; i += blockDim.x) {
+            int kids[4];
+            const int nk = collapse_node(nodes, nodes4, q[i], flag, no_open, 0, kids);
+            for (int k = 0; k < nk; ++k) {
+                const int slot = atomicAdd(&qn, 1);
+                if (slot < kTileQueue)
+                    q[slot] = kids[k];
+            }
         }
         __syncthreads();
-        int b0 = 0, b1 = 1;
-        while (b0 < b1) {
-            for (int i = b0 + (int)threadIdx.x; i < b1; i += blockDim.x) {
-                int kids[4];
-                const int nk = collapse_node(nodes, nodes4, q[i], flag, no_open, 0, kids);
-                for (int k = 0; k < nk; ++k) {
-                    const int slot = atomicAdd(&qn, 1);
-                    if (slot < kTileQueue)
-                        q[slot] = kids[k];
-                }
-            }
-            __syncthreads();
-            b0 = b1;
-            b1 = qn < kTileQueue ? qn : kTileQueue;
-            __syncthreads();  // every lane has read qn before the next level appends
-        }
+        b0 = b1;
+        b1 = qn < kTileQueue ? qn : kTileQueue;
+        __syncthreads();  // every lane has read qn before the next level appends
     }
 }
 
@@ -171,10 +161,9 @@ __global__ __launch_bounds__(256) void k_collapse_tiles(const Node *__restrict__
 // frontier of the learned proposal flagged kFrontier (each frontier node
 // starts a 4-wide node, so the proposal order can start and skip it).
 constexpr int kTileRoot = kTileRootFlag, kFrontier = 2, kMeshRoot = 4;
-__global__ __launch_bounds__(1024) void k_collapse_top(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
-                                                       const int32_t *__restrict__ flag, int no_open, int no_start,
-                                                       int32_t *queue, int64_t n_internal) {
-    __shared__ int qn;
+__device__ void collapse_from_root(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
+                                   const int32_t *__restrict__ flag, int no_open, int no_start, int32_t *queue,
+                                   int64_t n_internal, int &qn) {
     if (flag[0] & no_start)
         return;  // the whole tree is one tile
     if (threadIdx.x == 0) {
@@ -198,6 +187,40 @@ __global__ __launch_bounds__(1024) void k_collapse_top(const Node *__restrict__ 
         b1 = qn < n_internal ? qn : (int)n_internal;
         __syncthreads();
     }
+}
+
+// The tiles and the nodes above them in one launch: the last workgroup takes
+// the nodes above the tiles, the others the tiles in turn.  The two parts
+// write disjoint nodes (a tile root is never opened from above).  tile_no_open
+// marks the nodes a tile never opens (0: none).
+__global__ __launch_bounds__(256) void k_collapse(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
+                                                  const int32_t *__restrict__ tiles,
+                                                  const int32_t *__restrict__ n_tiles,
+                                                  const int32_t *__restrict__ flag, int tile_no_open,
+                                                  int top_no_open, int32_t *queue, int64_t n_internal) {
+    __shared__ int q[kTileQueue];
+    __shared__ int qn;
+    if (blockIdx.x == gridDim.x - 1) {
+        collapse_from_root(nodes, nodes4, flag, top_no_open, kTileRoot, queue, n_internal, qn);
+        return;
+    }
+    const int32_t *tile_flag = tile_no_open ? flag : nullptr;
+    const int total = *n_tiles;
+    for (int e = blockIdx.x; e < total; e += gridDim.x - 1) {
+        const int c = tiles[e];
+        if (c < 0)
+            continue;  // a one-leaf tile: no internal node
+        collapse_tile(nodes, nodes4, c, tile_flag, tile_no_open, q, qn);
+    }
+}
+
+// The whole tree from the root in one workgroup (the learned proposal's
+// collapse: a one-off set-up, not on the hot path).
+__global__ __launch_bounds__(1024) void k_collapse_top(const Node *__restrict__ nodes, Node4 *__restrict__ nodes4,
+                                                       const int32_t *__restrict__ flag, int no_open, int no_start,
+                                                       int32_t *queue, int64_t n_internal) {
+    __shared__ int qn;
+    collapse_from_root(nodes, nodes4, flag, no_open, no_start, queue, n_internal, qn);
 }
 
 // One workgroup: the first kTopSlots 4-wide nodes in breadth-first order from
@@ -396,9 +419,9 @@ hipError_t launch_collapse(MeshDev &m, hipStream_t s) {
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t want = (m.nt + 1023) / 1024 * 2;  // tiles hold up to 1024 leaves, usually fewer
-    const int grid = (int)(want < 4 * cus ? want : 4 * cus);
-    k_collapse_tiles<<<grid, 256, 0, s>>>(m.nodes, m.nodes4, L.tiles, L.n_tiles, nullptr, 0);
-    k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, m.nodes4, L.tile_flag, kTileRoot, kTileRoot, L.queue, n_internal);
+    const int grid = (int)(want < 4 * cus ? want : 4 * cus) + 1;  // + the nodes above the tiles
+    k_collapse<<<grid, 256, 0, s>>>(m.nodes, m.nodes4, L.tiles, L.n_tiles, L.tile_flag, 0, kTileRoot, L.queue,
+                                    n_internal);
     k_top_cache<<<1, kTopSlots, 0, s>>>(m.nodes4, m.top4, nullptr);
     const hipError_t e = hipGetLastError();
     if (e == hipSuccess)
@@ -437,10 +460,9 @@ hipError_t launch_collapse_batch(MeshDev &m, BatchDev &b, hipStream_t s) {
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t want = (m.nt + 1023) / 1024 * 2;
-    const int grid = (int)(want < 4 * cus ? want : 4 * cus);
-    k_collapse_tiles<<<grid, 256, 0, s>>>(m.nodes, m.nodes4, L.tiles, L.n_tiles, L.tile_flag, kMeshRoot);
-    k_collapse_top<<<1, 1024, 0, s>>>(m.nodes, m.nodes4, L.tile_flag, kTileRoot | kMeshRoot, kTileRoot, L.queue,
-                                      n_internal);
+    const int grid = (int)(want < 4 * cus ? want : 4 * cus) + 1;  // + the nodes above the tiles
+    k_collapse<<<grid, 256, 0, s>>>(m.nodes, m.nodes4, L.tiles, L.n_tiles, L.tile_flag, kMeshRoot,
+                                    kTileRoot | kMeshRoot, L.queue, n_internal);
     k_top_cache<<<1, kTopSlots, 0, s>>>(m.nodes4, m.top4, b.slot_bin);
     k_bucket_ref4<<<1, kTopSlots, 0, s>>>(b.roots, nullptr, b.M, b.slot_bin, b.roots4);
     if (b.top4g)
