@@ -89,10 +89,15 @@ __device__ constexpr unsigned char kSplits[kSplitCount][3] = {
 // least-cost topology over the 15 leaf subsets with every subset and split
 // known at compile time (all in registers), and rewires the (at most three)
 // internal nodes when that is cheaper than the current shape.
-__device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
-    int leaf[4] = {T.child[0][p], T.child[1][p], 0, 0};
-    int inner[3] = {p, -1, -1};
-    const float now = T.cost[p];
+// The treelet at p (children c0, c1): opens the largest-area internal leaf
+// twice; returns the number of treelet leaves (2 to 4) in leaf[], with the
+// opened nodes in inner[1..] (inner[0] = p).
+__device__ __forceinline__ int open_treelet(const TileLds &T, int p, int c0, int c1, int leaf[4], int inner[3]) {
+    leaf[0] = c0;
+    leaf[1] = c1;
+    leaf[2] = leaf[3] = 0;
+    inner[0] = p;
+    inner[1] = inner[2] = -1;
     int m = 2;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -115,17 +120,24 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
 #pragma unroll
         for (int i = 1; i < 3; ++i)
             r = best == i ? leaf[i] : r;
-        const int c0 = T.child[0][r], c1 = T.child[1][r];
+        const int d0 = T.child[0][r], d1 = T.child[1][r];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            leaf[i] = i == best ? c0 : leaf[i];
-            leaf[i] = i == m ? c1 : leaf[i];
+            leaf[i] = i == best ? d0 : leaf[i];
+            leaf[i] = i == m ? d1 : leaf[i];
         }
 #pragma unroll
         for (int i = 1; i < 3; ++i)
             inner[i] = i == m - 1 ? r : inner[i];
         ++m;
     }
+    return m;
+}
+
+__device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
+    int leaf[4], inner[3];
+    const float now = T.cost[p];
+    const int m = open_treelet(T, p, T.child[0][p], T.child[1][p], leaf, inner);
     if (m < 3)
         return;  // both children are leaves: one shape only
     // every subset's box, leaf count and leaf span, each from the subset
@@ -238,6 +250,166 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
     }
 }
 
+// The same step for a level with few nodes: kGroup lanes of one wave share
+// the node p, and lane g takes the leaf subset S = g.  Each lane unions its
+// subset's boxes; a pair's cost follows from its leaves, a triple's from the
+// pairs of the lanes that own them (shuffles), and every lane evaluates the
+// whole set's splits, so the choice is the same in each.  The splits are
+// tried in the order of kSplits with the same strict comparison, so the
+// topology is the one the single-lane search picks.  base is the group's
+// first lane in the wave; control flow is uniform over the group.
+constexpr int kGroup = 16;
+
+__device__ __forceinline__ void treelet_group(TileLds &T, int p, int g, int base) {
+    const int c0 = T.child[0][p], c1 = T.child[1][p];
+    const float now = kCostNode * box_area(T, p) + T.cost[c0] + T.cost[c1];
+    const int cnt = T.count[c0] + T.count[c1];
+    if (g == 0) {  // refresh p
+        T.cost[p] = now;
+        T.count[p] = cnt;
+        T.lo[p] = min(T.lo[c0], T.lo[c1]);
+        T.hi[p] = max(T.hi[c0], T.hi[c1]);
+    }
+    if (cnt < kTreelet)
+        return;
+    int leaf[4], inner[3];
+    const int m = open_treelet(T, p, c0, c1, leaf, inner);
+    if (m < 3)
+        return;
+    // this lane's subset (with three leaves the fourth repeats the first; only
+    // subsets of the first three are used then)
+    const int S = g;
+    float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    float lc[4];
+    int n = 0, lo = INT32_MAX, hi = INT32_MIN;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = i < m ? leaf[i] : leaf[0];
+        lc[i] = T.cost[r];
+        if ((S >> i) & 1) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                b[a] = fminf(b[a], T.box[a][r]);
+                b[3 + a] = fmaxf(b[3 + a], T.box[3 + a][r]);
+            }
+            n += T.count[r];
+            lo = min(lo, T.lo[r]);
+            hi = max(hi, T.hi[r]);
+        }
+    }
+    const float area = half_area(b[0], b[1], b[2], b[3], b[4], b[5]);
+    const int pc = __builtin_popcount(S);
+    // the subset's leaves in rising order (a < e1 < e2 where present)
+    const int a = __builtin_ctz(S | 16), R = S & (S - 1);
+    const int e1 = __builtin_ctz(R | 16), e2 = __builtin_ctz((R & (R - 1)) | 16);
+    float c = INFINITY;
+    int split = 0;
+    if (pc == 1) {
+        c = lc[a];
+    } else if (pc == 2) {
+        const float sum = lc[a] + lc[e1 & 3];
+        c = kCostNode * area + sum;
+        split = 1 << a;
+    }
+    // triples: {a} | {e1, e2}, {a, e1} | {e2}, {a, e2} | {e1}
+    {
+        const int pa = 1 << (a & 3), p1 = 1 << (e1 & 3), p2 = 1 << (e2 & 3);
+        const float v1 = __shfl(c, base + (p1 | p2), 64);
+        const float v2 = __shfl(c, base + (pa | p1), 64);
+        const float v3 = __shfl(c, base + (pa | p2), 64);
+        if (pc == 3) {
+            float best = lc[a & 3] + v1;
+            int P = pa;
+            const float s2 = v2 + lc[e2 & 3];
+            if (s2 < best) {
+                best = s2;
+                P = pa | p1;
+            }
+            const float s3 = v3 + lc[e1 & 3];
+            if (s3 < best) {
+                best = s3;
+                P = pa | p2;
+            }
+            c = kCostNode * area + best;
+            split = P;
+        }
+    }
+    // the whole set, evaluated in every lane: the cost of each part from its lane
+    float ck[16];
+#pragma unroll
+    for (int k = 3; k < 16; ++k)
+        if (__builtin_popcount(k) >= 2)
+            ck[k] = __shfl(c, base + k, 64);
+    int full, Pf;
+    float best_cost;
+    if (m == 4) {
+        const float s[7] = {lc[0] + ck[14], ck[3] + ck[12], ck[5] + ck[10], ck[7] + lc[3],
+                            ck[9] + ck[6], ck[11] + lc[2], ck[13] + lc[1]};
+        const int P7[7] = {1, 3, 5, 7, 9, 11, 13};
+        float best = s[0];
+        int P = 1;
+#pragma unroll
+        for (int k = 1; k < 7; ++k)
+            if (s[k] < best) {
+                best = s[k];
+                P = P7[k];
+            }
+        best_cost = kCostNode * __shfl(area, base + 15, 64) + best;
+        full = 15;
+        Pf = P;
+        if (S == 15) {
+            c = best_cost;
+            split = P;
+        }
+    } else {
+        best_cost = ck[7];
+        full = 7;
+        Pf = __shfl(split, base + 7, 64);
+    }
+    const int Xs = __shfl(split, base + (__builtin_popcount(Pf) == 3 ? Pf : (full ^ Pf)), 64);
+    if (!(best_cost < now * (1.0f - 1e-6f)))
+        return;
+    // the internal subsets of the chosen topology: the whole set, its parts
+    // of two or more leaves, and the parts of a triple among them
+    const int Qf = full ^ Pf;
+    int used = 1 << full;
+    used |= __builtin_popcount(Pf) >= 2 ? 1 << Pf : 0;
+    used |= __builtin_popcount(Qf) >= 2 ? 1 << Qf : 0;
+    const int X = __builtin_popcount(Pf) == 3 ? Pf : (__builtin_popcount(Qf) == 3 ? Qf : 0);
+    if (X) {
+        const int Px = Xs, Qx = X ^ Xs;
+        used |= __builtin_popcount(Px) >= 2 ? 1 << Px : 0;
+        used |= __builtin_popcount(Qx) >= 2 ? 1 << Qx : 0;
+    }
+    // node ids: the whole set keeps p, the others take the opened nodes by
+    // falling subset index
+    const int others = used & ~(1 << full);
+    auto ref_of = [&](int U) {
+        if (__builtin_popcount(U) == 1) {
+            const int i = __builtin_ctz(U);
+            return i == 0 ? leaf[0] : (i == 1 ? leaf[1] : (i == 2 ? leaf[2] : leaf[3]));
+        }
+        if (U == full)
+            return p;
+        return __builtin_popcount(others >> (U + 1)) == 0 ? inner[1] : inner[2];
+    };
+    if ((used >> S) & 1) {
+        const int j = ref_of(S);
+        const int child0 = ref_of(split), child1 = ref_of(S ^ split);
+        T.child[0][j] = child0;
+        T.child[1][j] = child1;
+        T.parent[child0] = j;
+        T.parent[child1] = j;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            T.box[k][j] = b[k];
+        T.cost[j] = c;
+        T.count[j] = n;
+        T.lo[j] = lo;
+        T.hi[j] = hi;
+    }
+}
+
 // Heights of the local internal nodes by a bottom-up climb, one lane per
 // leaf: the second lane to reach a node finds both child heights final.
 // Integer work only, so the divergence of the climb costs little.
@@ -323,12 +495,20 @@ __device__ __forceinline__ void restructure_local(TileLds &T, int rounds) {
         order_by_height(T);
         const int H = T.max_height;
         for (int h = 1; h <= H; ++h) {
-            const int e = T.h_start[h + 1];
-            for (int i = T.h_start[h] + threadIdx.x; i < e; i += blockDim.x) {
-                const int j = T.order[i];
-                refresh_node(T, j);
-                if (T.count[j] >= kTreelet)
-                    optimize_treelet(T, j);
+            const int b = T.h_start[h], e = T.h_start[h + 1];
+            if ((e - b) * kGroup <= (int)blockDim.x) {
+                // few nodes (the upper levels, where the search's latency
+                // adds up level by level): a lane group per node
+                const int g = threadIdx.x / kGroup;
+                if (b + g < e)
+                    treelet_group(T, T.order[b + g], threadIdx.x & (kGroup - 1), threadIdx.x & 63 & ~(kGroup - 1));
+            } else {
+                for (int i = b + threadIdx.x; i < e; i += blockDim.x) {
+                    const int j = T.order[i];
+                    refresh_node(T, j);
+                    if (T.count[j] >= kTreelet)
+                        optimize_treelet(T, j);
+                }
             }
             __syncthreads();
         }
