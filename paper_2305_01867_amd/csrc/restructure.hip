@@ -256,8 +256,10 @@ __device__ __forceinline__ void optimize_treelet(TileLds &T, int p) {
 // pairs of the lanes that own them (shuffles), and every lane evaluates the
 // whole set's splits, so the choice is the same in each.  The splits are
 // tried in the order of kSplits with the same strict comparison, so the
-// topology is the one the single-lane search picks.  base is the group's
-// first lane in the wave; control flow is uniform over the group.
+// choice is the single-lane search's up to rounding order (the compiler may
+// fuse the cost sums differently; a near tie can then go the other way).
+// base is the group's first lane in the wave; control flow is uniform over
+// the group.
 constexpr int kGroup = 16;
 
 __device__ __forceinline__ void treelet_group(TileLds &T, int p, int g, int base) {
