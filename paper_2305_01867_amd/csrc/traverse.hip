@@ -370,6 +370,10 @@ constexpr int kPend = 2;
 // fewer waves than registers allow share the CU's L1 among fewer tree paths.
 constexpr int kDefaultWavesPerCU = 16;
 constexpr int kDone = INT32_MIN;  // nothing left for the lane's segment
+// One mesh: the share of the segments handed out in chunks at the end of the
+// launch (1/kTailDiv of them), and the chunk size.
+constexpr int64_t kTailDiv = 8;
+constexpr int kTailChunk = 64;
 
 // Boolean results of one mesh in input order are staged per wave in LDS and
 // written out a window of kStageWin segments at a time (whole lines instead
@@ -415,11 +419,16 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     // boolean results staged in LDS (one mesh, input order, 4-byte aligned output)
     const bool stage = MODE == MODE_BOOL && !STATS && !batch && p.order == nullptr && p.stage_ok;
-    int64_t cursor = batch ? 0 : p.n * wave_id / waves;
-    int64_t range_end = batch ? 0 : p.n * (wave_id + 1) / waves;
+    // One mesh: the first segments are split evenly over the waves; the rest
+    // (1/kTailDiv, from a multiple of 4) is a pool of kTailChunk-segment chunks
+    // that waves take in turn once their own share is handed out, so the waves
+    // whose shares cost more do not hold up the end of the launch.
+    const int64_t n_static = batch ? 0 : (p.n - p.n / kTailDiv) & ~int64_t(3);
+    int64_t cursor = batch ? 0 : n_static * wave_id / waves;
+    int64_t range_end = batch ? 0 : n_static * (wave_id + 1) / waves;
     if (stage) {  // ranges start at multiples of 4
         cursor &= ~int64_t(3);
-        range_end = wave_id + 1 == waves ? p.n : (range_end & ~int64_t(3));
+        range_end = wave_id + 1 == waves ? n_static : (range_end & ~int64_t(3));
     }
     uint32_t *stage_w = nullptr;  // this wave's two windows
     int64_t win_base = cursor;    // first segment of the older window
@@ -469,7 +478,7 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
             p.out.hit[i] = (uint8_t)v;
         }
     };
-    bool items_left = batch;
+    bool items_left = batch || n_static < p.n;  // batch items, or the pool's chunks
     uint32_t groups_done = 0;  // item groups found empty (wave-uniform)
     int cur_root = p.root, cur_toff = 0;
     int lane_root = p.root, lane_toff = 0;  // of the lane's current segment
@@ -525,7 +534,32 @@ __device__ __forceinline__ void traverse_pass1(TravParams p, int *lds_stack) {
     for (;;) {
         // ---- refill idle lanes
         const uint64_t idle = __ballot(ray < 0);
-        if (items_left && cursor >= range_end && idle) {
+        if (!batch && items_left && cursor >= range_end && idle) {
+            uint32_t k = 0;
+            if (lane == 0)
+                k = atomicAdd(p.next_ray, 1u);
+            k = __shfl(k, 0);
+            const int64_t start = n_static + (int64_t)k * kTailChunk;
+            if (start < p.n) {
+                if (stage) {
+                    // what the old range left in its windows goes out (against
+                    // the old range end); then the windows start at the chunk.
+                    // Segments of the old range still in flight come before
+                    // it, so they are written straight out when they finish.
+                    if (win_base < range_end)
+                        stage_flush();
+                    if (win_base < range_end)
+                        stage_flush();
+                    win_base = start;
+                    win_old = 0;
+                }
+                cursor = start;
+                range_end = start + kTailChunk < p.n ? start + kTailChunk : p.n;
+            } else {
+                items_left = false;
+            }
+        }
+        if (batch && items_left && cursor >= range_end && idle) {
             int item = -1;
             if (p.group_start) {
                 // items are grouped by XCD (workgroups are spread over the
