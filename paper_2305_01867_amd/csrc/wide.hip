@@ -389,22 +389,28 @@ __global__ void k_mark_mesh_roots(const int32_t *__restrict__ roots, int M, int3
 // 4-wide tree: its top slot if it has one, else binary index + kTopSlots;
 // a leaf keeps its leaf reference.
 // (The same for each mesh root of the batched form, n_buckets = NULL: count M.)
-// One workgroup of kTopSlots threads: the slot map is staged in LDS first.
+// One workgroup of kTopSlots threads: the buckets' references are staged in
+// LDS, then each slot claims the buckets whose node it holds (at most
+// kTopSlots buckets or meshes).
 __global__ __launch_bounds__(kTopSlots) void k_bucket_ref4(const int32_t *__restrict__ bucket_ref,
                                                            const int32_t *__restrict__ n_buckets, int M,
                                                            const int32_t *__restrict__ slot_bin,
                                                            int32_t *__restrict__ ref4) {
-    __shared__ int bin[kTopSlots];
-    const int b = threadIdx.x;
-    bin[b] = slot_bin[b];
-    __syncthreads();
-    if (b >= (n_buckets ? *n_buckets : M))
-        return;
-    const int c = bucket_ref[b];
-    int r = c >= 0 ? c + kTopSlots : c;
-    for (int k = 0; k < kTopSlots; ++k)
-        r = c >= 0 && bin[k] == c ? k : r;
-    ref4[b] = r;
+    __shared__ int ref[kTopSlots];  // each bucket's binary reference
+    const int t = threadIdx.x;
+    const int n_raw = n_buckets ? *n_buckets : M;
+    const int n = n_raw < kTopSlots ? n_raw : kTopSlots;
+    const int c = t < n ? bucket_ref[t] : -1;
+    ref[t] = c;
+    if (t < n)
+        ref4[t] = c >= 0 ? c + kTopSlots : c;  // by default the node itself (not in the top)
+    __syncthreads();  // the defaults are written before any slot claims a bucket
+    // slot t claims the buckets whose node it holds (each slot holds one node)
+    const int mine = slot_bin[t];
+    if (mine >= 0)
+        for (int b = 0; b < n; ++b)
+            if (ref[b] == mine)
+                ref4[b] = t;
 }
 
 }  // namespace
