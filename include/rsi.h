@@ -172,7 +172,11 @@ typedef struct rsi_outputs {
                            was not in the proposed bucket (proposal misses), [3] count-mode
                            segments with more distinct hits than a lane keeps in registers
                            (11 in CERTIFIED precision, 12 in PLAIN), finished by the second
-                           pass.  Zeroed by the call before it counts. */
+                           pass.  Zeroed by the call before it counts.  [0] and [1] depend
+                           on the order in which a wave's lanes reach their leaves, and the
+                           last segments of a launch go to whichever waves are free first,
+                           so these two may vary slightly from call to call; the results
+                           never do. */
     int32_t *count;     /* [N_r] intercept-count mode: distinct intersections, 0 on a miss */
 } rsi_outputs;
 

@@ -371,8 +371,10 @@ constexpr int kPend = 2;
 constexpr int kDefaultWavesPerCU = 16;
 constexpr int kDone = INT32_MIN;  // nothing left for the lane's segment
 // One mesh: the share of the segments handed out in chunks at the end of the
-// launch (1/kTailDiv of them), and the chunk size.
-constexpr int64_t kTailDiv = 8;
+// launch (1/kTailDiv of them), and the chunk size.  At the paper's scale a
+// sixth measured best (a quarter, an eighth, a tenth, a twelfth and a
+// sixteenth all ended later).
+constexpr int64_t kTailDiv = 6;
 constexpr int kTailChunk = 64;
 
 // Boolean results of one mesh in input order are staged per wave in LDS and

@@ -35,6 +35,15 @@ def _same(a, b, key):
     x, y = host(a[key]), host(b[key])
     if key == "uvt":
         return np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    if key == "counters":
+        # [2] and [3] follow from each segment's answer and hits; [0] (pairs
+        # decided in binary64) and [1] (stack overflows) also depend on when a
+        # wave's lanes reach their held leaves, and the last chunks of a
+        # launch go to whichever waves are free first, so these two may differ
+        # from call to call: both calls must have zeroed and counted them
+        n_max = max(len(host(v)) for k, v in a.items() if k != "counters")
+        return (np.array_equal(x[2:], y[2:]) and np.all((x[:2] >= 0) & (x[:2] <= n_max))
+                and np.all((y[:2] >= 0) & (y[:2] <= n_max)))
     return np.array_equal(x, y)
 
 
