@@ -446,7 +446,7 @@ rsi_status rsi_proposal_load(rsi_mesh mesh, const char *path);
  * code (10 bits per axis of the mesh's own box), so one sort (five 8-bit
  * passes), one radix tree and one bottom-up pass cover all meshes
  * and each mesh is one subtree.  The traversal takes (mesh, segment range)
- * items of up to 2048 segments from a queue.  Reported triangle indices are
+ * items of up to 512 segments from a queue.  Reported triangle indices are
  * relative to the segment's mesh.  rsi_batch_create allocates everything
  * (including ~16 B per segment for the optional segment ordering);
  * rsi_batch_build and rsi_batch_intersect allocate nothing and never wait, so
