@@ -302,6 +302,28 @@ __global__ __launch_bounds__(1024) void k_scan_apply(uint32_t *__restrict__ hist
     }
 }
 
+// The tile histograms of a large sort, one row of ntiles per digit: workgroup
+// d scans row d in place (exclusive) and writes its total to totals[d]; the
+// scatter adds the digits below from those totals.  One launch instead of
+// a three-step scan of the whole histogram.
+__global__ __launch_bounds__(1024) void k_scan_rows(uint32_t *__restrict__ hist, int64_t ntiles,
+                                                    uint32_t *__restrict__ totals) {
+    __shared__ uint32_t wsum[16];
+    uint32_t *row = hist + (int64_t)blockIdx.x * ntiles;
+    uint32_t run = 0;
+    for (int64_t r = 0; r < ntiles; r += blockDim.x) {
+        const int64_t i = r + threadIdx.x;
+        const uint32_t v = i < ntiles ? row[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan(v, wsum, total);
+        if (i < ntiles)
+            row[i] = run + ex;
+        run += total;
+    }
+    if (threadIdx.x == 0)
+        totals[blockIdx.x] = run;
+}
+
 // Exclusive scan of hist[0..len); partial holds 1024 entries.
 void scan_hist(uint32_t *hist, int64_t len, uint32_t *partial, hipStream_t s) {
     if (len <= 32768) {
@@ -375,19 +397,24 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ kin, const in
     }
 }
 
-// One scatter pass over scanned tile histograms (offs: digit-major, exclusive).
+// One scatter pass over tile histograms scanned per digit (offs: digit-major,
+// exclusive within each digit's row; totals: each digit's count).
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const K *__restrict__ kin,
                                                                const int32_t *__restrict__ iin,
                                                                K *__restrict__ kout, int32_t *__restrict__ iout,
                                                                int64_t n, int shift, int ntiles,
-                                                               const uint32_t *__restrict__ offs) {
+                                                               const uint32_t *__restrict__ offs,
+                                                               const uint32_t *__restrict__ totals) {
     __shared__ uint32_t run[kRadix];
     __shared__ uint32_t base[kRadix];
     __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
+    __shared__ uint32_t wsum[kSortThreads / 64];
     const int tid = threadIdx.x, tile = blockIdx.x;
+    uint32_t all;
+    const uint32_t below = block_excl_scan(totals[tid], wsum, all);  // keys of the digits below
     run[tid] = 0;
-    base[tid] = offs[(int64_t)tid * ntiles + tile];
+    base[tid] = below + offs[(int64_t)tid * ntiles + tile];
     for (int w = 0; w < kSortThreads / 64; ++w)
         wcnt[w][tid] = 0;
     __syncthreads();
@@ -774,7 +801,7 @@ __global__ void k_copy_pairs(const K *__restrict__ k_in, const int32_t *__restri
 // Stable LSD passes over (keys, ids) with 8-bit digits; tmp holds the
 // ping-pong copies, the tile histograms and the scan partials.  Up to
 // kSmallSortTiles tiles a pass is one launch; above that, a histogram, a scan
-// and a scatter.  An even number of passes (key_bits 30 or 63 rounded up to
+// of each digit's row and a scatter.  An even number of passes (key_bits 30 or 63 rounded up to
 // 32 or 64) leaves the result in (keys, ids); an odd one (the batched form's
 // 36-bit keys) ends with a copy back.
 template <typename K>
@@ -804,8 +831,9 @@ void sort_passes(K *keys, int32_t *ids, void *tmp, int64_t n, int key_bits, hipS
     } else {
         for (int shift = 0; shift < key_bits; shift += 8) {
             k_sort_hist<K><<<ntiles, kSortThreads, 0, s>>>(src_k, n, shift, ntiles, hist, nullptr);
-            scan_hist(hist, (int64_t)kRadix * ntiles, partial, s);
-            k_sort_scatter<K><<<ntiles, kSortThreads, 0, s>>>(src_k, src_i, dst_k, dst_i, n, shift, ntiles, hist);
+            k_scan_rows<<<kRadix, 1024, 0, s>>>(hist, ntiles, partial);
+            k_sort_scatter<K><<<ntiles, kSortThreads, 0, s>>>(src_k, src_i, dst_k, dst_i, n, shift, ntiles, hist,
+                                                               partial);
             K *tk = src_k; src_k = dst_k; dst_k = tk;
             int32_t *ti = src_i; src_i = dst_i; dst_i = ti;
         }
